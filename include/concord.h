@@ -1,0 +1,250 @@
+/*
+ * concord.h - C-ABI of the MI355X (gfx950) proximal-gradient solver for the
+ * CONCORD / PseudoNet sparse inverse-covariance estimator.
+ *
+ * The problem (paper Section 2, eq. (1), and Algorithm 1): given data
+ * X in R^{n x p} (or its sample covariance S = X^T X / n) and tuning
+ * parameters lambda1, lambda2 >= 0, minimise over symmetric Omega
+ *
+ *   F(Omega) = f(Omega) + lambda1 * sum_{i != j} |omega_ij|,
+ *   f(Omega) = -sum_i log omega_ii + 1/2 tr(Omega S Omega)
+ *              + lambda2/2 ||Omega||_F^2
+ *
+ * by proximal gradient with backtracking line search (step sizes
+ * tau = 1, 1/2, 1/4, ..., restarted at 1 every iteration).  f is eq. (1)'s
+ * smooth part at (2 lambda1, 2 lambda2), halved; with this scaling the
+ * gradient G = -(Omega_D)^{-1} + 1/2 (W + W^T) + lambda2 Omega (W = Omega S)
+ * of Algorithm 1 is exactly f's gradient.  The soft threshold of eq. (2) is
+ * applied to off-diagonal entries only (the l1 term covers Omega_X only).
+ *
+ * Two forms of the products (Section 3):
+ *   CONCORD_COV  (Algorithm 2): S formed once, W = Omega S per iterate;
+ *   CONCORD_OBS  (Algorithm 3): Y = Omega X^T per iterate, W = Y X / n.
+ *
+ * Conventions for every entry point:
+ *   - Return value: 0 = OK, > 0 = warning, < 0 = error (codes below).  No C++
+ *     exception crosses this boundary.  concord_last_error() describes the
+ *     last failure of a handle.
+ *   - All array arguments named dev_* or documented as "device" are device
+ *     (HBM) pointers of the handle's device.  Host pointers are named host_*.
+ *   - Work is ordered on the handle's stream (concord_config.stream).  Calls
+ *     that return values to the host synchronise that stream.
+ *   - A handle may be used by one host thread at a time.
+ *   - The caller owns every buffer it passes; inputs are copied into the
+ *     library's own layout before the call returns (in stream order), so the
+ *     caller may free them afterwards.  The library owns Omega, its
+ *     workspace and all intermediate products; they are freed by
+ *     concord_destroy().
+ *   - Asynchronous HIP errors surface as CONCORD_EHIP at the next
+ *     synchronising call.
+ */
+#ifndef CONCORD_H
+#define CONCORD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define CONCORD_OK            0
+#define CONCORD_WMAXITER      1   /* concord_solve: max_iter reached before tol */
+#define CONCORD_EINVAL       -1   /* bad argument: lambda < 0, tol <= 0, dims, dtype, shape */
+#define CONCORD_ENOMEM       -2   /* device allocation failed */
+#define CONCORD_EHIP         -3   /* HIP runtime error (message in last_error) */
+#define CONCORD_ENOTPD       -4   /* a supplied Omega has a diagonal entry <= 0 */
+#define CONCORD_ENONFINITE   -5   /* NaN or Inf in X, S or Omega */
+#define CONCORD_ELINESEARCH  -6   /* max_backtracks step sizes all rejected; Omega kept */
+#define CONCORD_ENODATA      -7   /* step/solve/objective before concord_set_data */
+
+/* ---- enums ---- */
+#define CONCORD_COV 0
+#define CONCORD_OBS 1
+
+#define CONCORD_FP64   0   /* products and storage in FP64 */
+#define CONCORD_FP32   1   /* products in FP32 (FP32 MFMA / FP32 FMA), FP64 reductions */
+#define CONCORD_BF16X3 2   /* dense contractions as BF16 hi/lo split (hi*hi + hi*lo + lo*hi)
+                              on BF16 MFMA with FP32 accumulation; sparse products in FP32;
+                              FP64 reductions */
+
+#define CONCORD_F64 0
+#define CONCORD_F32 1
+
+#define CONCORD_DATA_X 0   /* observations X, n x p */
+#define CONCORD_DATA_S 1   /* sample covariance S, p x p symmetric (Cov only) */
+
+#define CONCORD_GRAD_MASKED 0   /* d f / d Omega on the stored entries of Omega only */
+#define CONCORD_GRAD_DENSE  1   /* d f / d Omega as a dense p x p array */
+
+typedef struct concord_ctx concord_ctx;
+
+typedef struct concord_config {
+    int64_t p;              /* number of variables, >= 1 */
+    int64_t n;              /* number of observations, >= 1 (ignored when S is supplied) */
+    int32_t variant;        /* CONCORD_COV or CONCORD_OBS */
+    int32_t precision;      /* CONCORD_FP64, CONCORD_FP32 or CONCORD_BF16X3 */
+    void*   stream;         /* hipStream_t to order all work on; NULL = null stream */
+    int32_t device;         /* HIP device ordinal; -1 = the current device */
+    int32_t max_backtracks; /* step-size halvings allowed per iteration (default 60) */
+    int32_t trial_batch;    /* step sizes evaluated together per launch, 1..8 (default 8) */
+    int32_t reserved;
+} concord_config;
+
+/* Per-iteration record (Algorithm 1, one pass of the outer loop). */
+typedef struct concord_step_info {
+    int64_t k;            /* iterations completed after this step */
+    double  tau;          /* accepted step size */
+    int32_t n_trials;     /* step sizes tried, as the sequential search would count (1 = tau 1) */
+    int32_t n_batches;    /* trial launches used */
+    double  f;            /* smooth value at the new iterate (FP64) */
+    double  F;            /* full objective at the new iterate (FP64) */
+    int64_t nnz;          /* stored entries of the new iterate (both triangles + diagonal) */
+    double  delta_fro;    /* ||Omega^{k+1} - Omega^k||_F */
+    int64_t n_candidates; /* |A|: entries the step could make nonzero this iteration */
+    double  lhs;          /* difference-form left side of the test at the accepted tau */
+    double  rhs;          /* ||Delta||^2 / (2 tau) */
+} concord_step_info;
+
+typedef struct concord_solve_info {
+    int64_t iters;        /* accepted iterations */
+    double  f, F;         /* objective at the returned iterate */
+    int64_t nnz;
+    int32_t status;       /* same value the call returns */
+    int32_t reserved;
+} concord_solve_info;
+
+/* Fill *cfg with defaults: variant COV, precision FP64, stream NULL,
+   device -1, max_backtracks 60, trial_batch 8, p = n = 0. */
+void concord_config_init(concord_config* cfg);
+
+/* Create a handle for problems of size p (and n).  Allocates the workspace
+   for X/S, Omega and the products on cfg->device.  Omega starts at I
+   (Algorithm 1, first line).  Errors: EINVAL (p < 1, n < 1 when needed,
+   unknown variant/precision, trial_batch outside 1..8), ENOMEM, EHIP. */
+int concord_create(const concord_config* cfg, concord_ctx** out);
+
+/* Load the data (device pointer, row-major, leading dimension ld >= cols).
+   kind = CONCORD_DATA_X: rows = n, cols = p; copied to the library layout
+     X^T (p x n, variable-major) in the handle's precision (plus BF16 hi/lo
+     planes for CONCORD_BF16X3).  For Cov, S = X^T X / n is then formed on
+     the GPU (Algorithm 2, once).
+   kind = CONCORD_DATA_S (Cov only): rows = cols = p; S is copied as given
+     (it must be symmetric; it is not checked).
+   dtype: CONCORD_F64 or CONCORD_F32.  Resets Omega to I and k to 0.
+   Errors: EINVAL (shape/dtype/kind mismatch, S with Obs), ENONFINITE
+   (NaN/Inf in the input), EHIP. */
+int concord_set_data(concord_ctx* ctx, int32_t kind, const void* dev_data, int32_t dtype,
+                     int64_t rows, int64_t cols, int64_t ld);
+
+/* Replace the iterate by a caller-supplied symmetric CSR matrix (warm start,
+   checkpoint resume).  Device arrays: row_ptr int64[p+1] (row_ptr[0] = 0),
+   col int32[nnz] (sorted and unique within each row, both triangles, the
+   diagonal present in every row), val[nnz] of dtype.  Symmetry is the
+   caller's promise and is not checked.  Sets k to 0.
+   Errors: EINVAL (bad row_ptr/col, missing diagonal), ENOTPD (diagonal <= 0),
+   ENONFINITE, ENOMEM, EHIP. */
+int concord_set_omega(concord_ctx* ctx, int64_t nnz, const int64_t* dev_row_ptr,
+                      const int32_t* dev_col, const void* dev_val, int32_t dtype);
+
+/* Omega <- I, k <- 0. */
+int concord_reset(concord_ctx* ctx);
+
+/* One outer iteration of Algorithm 1 (Algorithm 2 or 3 for the products):
+   gradient, then the backtracking search tau = 1, 1/2, ... with the
+   sufficient-decrease test, then accept.  Trials whose diagonal is not
+   positive are rejected.  The test is evaluated in the exact difference
+   form  sum_i [x_i - log1p x_i] + 1/2 tr(D S D) + lambda2/2 ||D||^2
+   <= ||D||^2 / (2 tau)  with D = Omega+ - Omega, x_i = D_ii / omega_ii, in
+   FP64; it equals the paper's test f(Omega+) <= f(Omega) + <G, D> +
+   ||D||^2/(2 tau) identically.  trial_batch step sizes are evaluated per
+   launch and the first passing one (in the order 1, 1/2, ...) is taken,
+   which is the sequential search's choice.
+   info may be NULL.  Errors: EINVAL (lambda < 0), ENODATA, ELINESEARCH
+   (Omega and k unchanged), EHIP. */
+int concord_step(concord_ctx* ctx, double lambda1, double lambda2, concord_step_info* info);
+
+/* As concord_step, but the step size is forced: tau = 2^-(trials-1) is
+   accepted without the test (its terms are still reported).  trials >= 1.
+   Used to replay a reference run's step sizes.  Errors as concord_step, plus
+   ENOTPD if the forced step leaves a diagonal entry <= 0. */
+int concord_step_replay(concord_ctx* ctx, double lambda1, double lambda2, int32_t trials,
+                        concord_step_info* info);
+
+/* Iterate concord_step until |F_new - F_old| < tol * |F_old| (checked after
+   each accepted step) or max_iter steps (Algorithm 1's stopping rule "using
+   epsilon", read as a relative change of the full objective).  tol = 0 runs
+   exactly max_iter steps.  Returns OK when tol was met, WMAXITER when
+   max_iter was reached first (OK when tol = 0), or an error of
+   concord_step.  info may be NULL. */
+int concord_solve(concord_ctx* ctx, double lambda1, double lambda2, double tol, int64_t max_iter,
+                  concord_solve_info* info);
+
+/* f and F at the current iterate, FP64 (host pointers; either may be NULL).
+   Errors: EINVAL, ENODATA, EHIP. */
+int concord_objective(concord_ctx* ctx, double lambda1, double lambda2, double* host_f,
+                      double* host_F);
+
+/* Copy the current iterate out as CSR (same layout as concord_set_omega).
+   Always writes *host_nnz.  If dev_row_ptr is NULL only the size is
+   returned; otherwise dev_row_ptr (p+1), dev_col and dev_val (capacity >=
+   *host_nnz as returned by a sizing call) are filled.  dtype: F64 or F32. */
+int concord_get_omega(concord_ctx* ctx, int64_t* host_nnz, int64_t* dev_row_ptr,
+                      int32_t* dev_col, void* dev_val, int32_t dtype);
+
+/* Number of completed iterations of the current iterate. */
+int64_t concord_iterations(const concord_ctx* ctx);
+
+/* Differentiation form (Obs products).  Smooth value at the current iterate
+   with the loaded X:  f = -sum log omega_ii + ||Omega X^T||_F^2 / (2n)
+   + lambda2/2 ||Omega||_F^2, in FP64 (host pointer).  Y = Omega X^T is not
+   stored.  Requires CONCORD_OBS and X.  Errors: EINVAL, ENODATA, EHIP. */
+int concord_smooth_value(concord_ctx* ctx, double lambda2, double* host_f);
+
+/* Gradients of concord_smooth_value at the current iterate.
+   dev_dOmega: mode MASKED -> val-shaped array (nnz of the iterate, CSR
+     order, dtype) holding G_ij on the stored entries; mode DENSE -> p x p
+     row-major (ld = p) holding G.  G is the gradient over symmetric
+     matrices, G = -(Omega_D)^{-1} + 1/2 (Omega S + S Omega) + lambda2 Omega
+     (a symmetric perturbation E_ij + E_ji changes f by 2 G_ij).  NULL skips it.
+   dev_dX: n x p row-major (ld = p) receiving d f / d X = (Omega Y)^T / n
+     with Y = Omega X^T recomputed here.  NULL skips it.
+   dtype: F64 or F32 for both outputs.  Errors: EINVAL, ENODATA, EHIP. */
+int concord_gradient(concord_ctx* ctx, double lambda2, int32_t mode, void* dev_dOmega,
+                     void* dev_dX, int32_t dtype);
+
+/* Batched lambda path over several independent Cov problems.
+   count instances; instance b has p_b variables and its data X_b (device,
+   n_b x p_b row-major, ld_b, FP32) given by the descriptor arrays.  Every
+   instance is solved at every lambda1 in host_lambda1[0..n_l1-1] (lambda2
+   common), each from Omega = I, with the stopping rule of concord_solve.
+   Results: host_iters[b*n_l1 + l] and host_F[b*n_l1 + l] (host arrays of
+   count*n_l1); the estimates stay in the batch handle and are read with
+   concord_batch_get_omega.  Precision FP32 products, FP64 reductions. */
+typedef struct concord_batch concord_batch;
+int concord_batch_create(int32_t count, const int64_t* host_p, const int64_t* host_n,
+                         const void* const* host_dev_X, const int64_t* host_ld, int32_t n_l1,
+                         const double* host_lambda1, void* stream, concord_batch** out);
+int concord_batch_solve(concord_batch* b, double lambda2, double tol, int64_t max_iter,
+                        int64_t* host_iters, double* host_F);
+int concord_batch_get_omega(concord_batch* b, int32_t instance, int32_t l1_index,
+                            int64_t* host_nnz, int64_t* dev_row_ptr, int32_t* dev_col,
+                            double* dev_val);
+const char* concord_batch_last_error(const concord_batch* b);
+void concord_batch_destroy(concord_batch* b);
+
+/* Description of the last error on this handle ("" if none). Never NULL. */
+const char* concord_last_error(const concord_ctx* ctx);
+
+/* Free the handle and everything it owns.  NULL is accepted. */
+void concord_destroy(concord_ctx* ctx);
+
+/* Library version string. */
+const char* concord_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CONCORD_H */

@@ -1,0 +1,421 @@
+"""ctypes binding of libconcord (include/concord.h).
+
+Argument marshalling only: every step of the iteration runs in the HIP
+kernels of the library.  The module-level functions carry the C names; the
+``Solver`` class wraps a handle for torch tensors (device memory and the
+current HIP stream come from PyTorch).
+
+The library must have been built (``python -m paper_1710_10769_amd.build``);
+importing a function of this module without it raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libconcord.so")
+
+OK, WMAXITER = 0, 1
+EINVAL, ENOMEM, EHIP, ENOTPD, ENONFINITE, ELINESEARCH, ENODATA = -1, -2, -3, -4, -5, -6, -7
+COV, OBS = 0, 1
+FP64, FP32, BF16X3 = 0, 1, 2
+F64, F32 = 0, 1
+DATA_X, DATA_S = 0, 1
+GRAD_MASKED, GRAD_DENSE = 0, 1
+
+_CODES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", ENOTPD: "ENOTPD",
+          ENONFINITE: "ENONFINITE", ELINESEARCH: "ELINESEARCH", ENODATA: "ENODATA"}
+
+_VARIANTS = {"cov": COV, "obs": OBS}
+_PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+
+
+class ConcordError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class concord_config(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int64), ("n", ctypes.c_int64), ("variant", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("device", ctypes.c_int32), ("max_backtracks", ctypes.c_int32),
+                ("trial_batch", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class concord_step_info(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int64), ("tau", ctypes.c_double), ("n_trials", ctypes.c_int32),
+                ("n_batches", ctypes.c_int32), ("f", ctypes.c_double), ("F", ctypes.c_double),
+                ("nnz", ctypes.c_int64), ("delta_fro", ctypes.c_double),
+                ("n_candidates", ctypes.c_int64), ("lhs", ctypes.c_double),
+                ("rhs", ctypes.c_double)]
+
+
+class concord_solve_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int64), ("f", ctypes.c_double), ("F", ctypes.c_double),
+                ("nnz", ctypes.c_int64), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I32, _I64, _D = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_SIGS = {
+    "concord_config_init": (None, [ctypes.POINTER(concord_config)]),
+    "concord_create": (_I32, [ctypes.POINTER(concord_config), ctypes.POINTER(_P)]),
+    "concord_set_data": (_I32, [_P, _I32, _P, _I32, _I64, _I64, _I64]),
+    "concord_set_omega": (_I32, [_P, _I64, _P, _P, _P, _I32]),
+    "concord_reset": (_I32, [_P]),
+    "concord_step": (_I32, [_P, _D, _D, ctypes.POINTER(concord_step_info)]),
+    "concord_step_replay": (_I32, [_P, _D, _D, _I32, ctypes.POINTER(concord_step_info)]),
+    "concord_solve": (_I32, [_P, _D, _D, _D, _I64, ctypes.POINTER(concord_solve_info)]),
+    "concord_objective": (_I32, [_P, _D, _D, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "concord_get_omega": (_I32, [_P, ctypes.POINTER(_I64), _P, _P, _P, _I32]),
+    "concord_iterations": (_I64, [_P]),
+    "concord_smooth_value": (_I32, [_P, _D, ctypes.POINTER(_D)]),
+    "concord_gradient": (_I32, [_P, _D, _I32, _P, _P, _I32]),
+    "concord_batch_create": (_I32, [_I32, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
+                                    ctypes.POINTER(_P), ctypes.POINTER(_I64), _I32,
+                                    ctypes.POINTER(_D), _P, ctypes.POINTER(_P)]),
+    "concord_batch_solve": (_I32, [_P, _D, _D, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
+    "concord_batch_get_omega": (_I32, [_P, _I32, _I32, ctypes.POINTER(_I64), _P, _P, _P]),
+    "concord_batch_last_error": (ctypes.c_char_p, [_P]),
+    "concord_batch_destroy": (None, [_P]),
+    "concord_last_error": (ctypes.c_char_p, [_P]),
+    "concord_destroy": (None, [_P]),
+    "concord_version": (ctypes.c_char_p, []),
+}
+EXPORTED = tuple(_SIGS)
+
+
+def load(path: str = LIB_PATH):
+    """Load libconcord.so and set every signature.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libconcord.so not built at {path}; run python -m paper_1710_10769_amd.build")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, handle=None, batch=False) -> int:
+    if rc < 0:
+        msg = ""
+        if handle is not None:
+            fn = load().concord_batch_last_error if batch else load().concord_last_error
+            msg = (fn(handle) or b"").decode()
+        raise ConcordError(rc, msg)
+    return rc
+
+
+# ---- the C entry points under their own names ------------------------------------
+
+def concord_version() -> str:
+    return load().concord_version().decode()
+
+
+def concord_config_init() -> concord_config:
+    cfg = concord_config()
+    load().concord_config_init(ctypes.byref(cfg))
+    return cfg
+
+
+def concord_create(cfg: concord_config) -> int:
+    h = ctypes.c_void_p()
+    _check(load().concord_create(ctypes.byref(cfg), ctypes.byref(h)))
+    return h.value
+
+
+def concord_destroy(h) -> None:
+    load().concord_destroy(h)
+
+
+def concord_last_error(h) -> str:
+    return (load().concord_last_error(h) or b"").decode()
+
+
+def concord_set_data(h, kind: int, ptr: int, dtype: int, rows: int, cols: int, ld: int) -> int:
+    return _check(load().concord_set_data(h, kind, ptr, dtype, rows, cols, ld), h)
+
+
+def concord_set_omega(h, nnz: int, rowptr: int, col: int, val: int, dtype: int) -> int:
+    return _check(load().concord_set_omega(h, nnz, rowptr, col, val, dtype), h)
+
+
+def concord_reset(h) -> int:
+    return _check(load().concord_reset(h), h)
+
+
+@dataclasses.dataclass
+class StepInfo:
+    k: int
+    tau: float
+    n_trials: int
+    n_batches: int
+    f: float
+    F: float
+    nnz: int
+    delta_fro: float
+    n_candidates: int
+    lhs: float
+    rhs: float
+
+
+def _step_info(si: concord_step_info) -> StepInfo:
+    return StepInfo(**{k: getattr(si, k) for k, _ in concord_step_info._fields_})
+
+
+def concord_step(h, lam1: float, lam2: float) -> StepInfo:
+    si = concord_step_info()
+    _check(load().concord_step(h, lam1, lam2, ctypes.byref(si)), h)
+    return _step_info(si)
+
+
+def concord_step_replay(h, lam1: float, lam2: float, trials: int) -> StepInfo:
+    si = concord_step_info()
+    _check(load().concord_step_replay(h, lam1, lam2, trials, ctypes.byref(si)), h)
+    return _step_info(si)
+
+
+@dataclasses.dataclass
+class SolveInfo:
+    iters: int
+    f: float
+    F: float
+    nnz: int
+    status: int
+
+
+def concord_solve(h, lam1: float, lam2: float, tol: float, max_iter: int) -> SolveInfo:
+    si = concord_solve_info()
+    rc = _check(load().concord_solve(h, lam1, lam2, tol, max_iter, ctypes.byref(si)), h)
+    return SolveInfo(si.iters, si.f, si.F, si.nnz, rc)
+
+
+def concord_objective(h, lam1: float, lam2: float) -> Tuple[float, float]:
+    f, F = ctypes.c_double(), ctypes.c_double()
+    _check(load().concord_objective(h, lam1, lam2, ctypes.byref(f), ctypes.byref(F)), h)
+    return f.value, F.value
+
+
+def concord_get_omega(h, rowptr: int = 0, col: int = 0, val: int = 0, dtype: int = F64) -> int:
+    nnz = ctypes.c_int64()
+    _check(load().concord_get_omega(h, ctypes.byref(nnz), rowptr or None, col or None,
+                                    val or None, dtype), h)
+    return nnz.value
+
+
+def concord_iterations(h) -> int:
+    return load().concord_iterations(h)
+
+
+def concord_smooth_value(h, lam2: float) -> float:
+    f = ctypes.c_double()
+    _check(load().concord_smooth_value(h, lam2, ctypes.byref(f)), h)
+    return f.value
+
+
+def concord_gradient(h, lam2: float, mode: int, dOmega: int, dX: int, dtype: int) -> int:
+    return _check(load().concord_gradient(h, lam2, mode, dOmega or None, dX or None, dtype), h)
+
+
+# ---- torch-facing wrapper --------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream or None
+
+
+class Solver:
+    """One CONCORD problem on the current GPU (a library handle)."""
+
+    def __init__(self, p: int, n: int, variant: str = "obs", precision: str = "fp32",
+                 stream=None, device: Optional[int] = None, trial_batch: int = 8,
+                 max_backtracks: int = 60):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the HIP library needs a gfx950 device")
+        cfg = concord_config_init()
+        cfg.p, cfg.n = p, n
+        cfg.variant = _VARIANTS[variant]
+        cfg.precision = _PRECISIONS[precision]
+        cfg.stream = _stream_ptr(stream)
+        cfg.device = torch.cuda.current_device() if device is None else device
+        cfg.trial_batch = trial_batch
+        cfg.max_backtracks = max_backtracks
+        self.p, self.n, self.variant, self.precision = p, n, variant, precision
+        self.device = torch.device("cuda", cfg.device)
+        self._h = concord_create(cfg)
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            concord_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_data(self, X) -> None:
+        """X: (n, p) CUDA tensor, float32 or float64, row-major (any row stride)."""
+        assert X.is_cuda and X.dim() == 2 and X.stride(1) == 1
+        concord_set_data(self._h, DATA_X, X.data_ptr(), _dtype_code(X), X.shape[0], X.shape[1],
+                         X.stride(0))
+
+    def set_covariance(self, S) -> None:
+        assert S.is_cuda and S.dim() == 2 and S.stride(1) == 1
+        concord_set_data(self._h, DATA_S, S.data_ptr(), _dtype_code(S), S.shape[0], S.shape[1],
+                         S.stride(0))
+
+    def set_omega(self, rowptr, col, val) -> None:
+        torch = _torch()
+        rowptr = rowptr.to(self.device, torch.int64).contiguous()
+        col = col.to(self.device, torch.int32).contiguous()
+        val = val.to(self.device).contiguous()
+        concord_set_omega(self._h, col.numel(), rowptr.data_ptr(), col.data_ptr(), val.data_ptr(),
+                          _dtype_code(val))
+
+    def reset(self) -> None:
+        concord_reset(self._h)
+
+    def step(self, lam1: float, lam2: float) -> StepInfo:
+        return concord_step(self._h, lam1, lam2)
+
+    def step_replay(self, lam1: float, lam2: float, trials: int) -> StepInfo:
+        return concord_step_replay(self._h, lam1, lam2, trials)
+
+    def solve(self, lam1: float, lam2: float, tol: float = 1e-5, max_iter: int = 200) -> SolveInfo:
+        return concord_solve(self._h, lam1, lam2, tol, max_iter)
+
+    def objective(self, lam1: float, lam2: float) -> Tuple[float, float]:
+        return concord_objective(self._h, lam1, lam2)
+
+    @property
+    def iterations(self) -> int:
+        return concord_iterations(self._h)
+
+    def get_omega(self, dtype=None):
+        """Current iterate as CUDA tensors (rowptr int64, col int32, val)."""
+        torch = _torch()
+        dtype = dtype or torch.float64
+        nnz = concord_get_omega(self._h)
+        rowptr = torch.empty(self.p + 1, dtype=torch.int64, device=self.device)
+        col = torch.empty(max(nnz, 1), dtype=torch.int32, device=self.device)
+        val = torch.empty(max(nnz, 1), dtype=dtype, device=self.device)
+        concord_get_omega(self._h, rowptr.data_ptr(), col.data_ptr(), val.data_ptr(),
+                          F64 if dtype == torch.float64 else F32)
+        return rowptr, col[:nnz], val[:nnz]
+
+    def get_omega_scipy(self):
+        import numpy as np
+        import scipy.sparse as sp
+        r, c, v = self.get_omega()
+        return sp.csr_matrix((v.cpu().numpy(), c.cpu().numpy().astype(np.int64),
+                              r.cpu().numpy()), shape=(self.p, self.p))
+
+    def smooth_value(self, lam2: float) -> float:
+        return concord_smooth_value(self._h, lam2)
+
+    def gradient(self, lam2: float, mode: str = "masked", want_omega=True, want_x=True,
+                 dtype=None):
+        torch = _torch()
+        dtype = dtype or torch.float32
+        nnz = concord_get_omega(self._h)
+        dOm = None
+        if want_omega:
+            dOm = torch.empty(nnz if mode == "masked" else (self.p, self.p), dtype=dtype,
+                              device=self.device)
+        dX = torch.empty((self.n, self.p), dtype=dtype, device=self.device) if want_x else None
+        concord_gradient(self._h, lam2, GRAD_MASKED if mode == "masked" else GRAD_DENSE,
+                         dOm.data_ptr() if dOm is not None else 0,
+                         dX.data_ptr() if dX is not None else 0,
+                         F64 if dtype == torch.float64 else F32)
+        return dOm, dX
+
+
+class Batch:
+    """A batch of independent Cov problems solved over one lambda1 path."""
+
+    def __init__(self, Xs, lambda1s, stream=None):
+        torch = _torch()
+        self.count = len(Xs)
+        self._Xs = [x.contiguous() for x in Xs]
+        ps = (ctypes.c_int64 * self.count)(*[x.shape[1] for x in self._Xs])
+        ns = (ctypes.c_int64 * self.count)(*[x.shape[0] for x in self._Xs])
+        lds = (ctypes.c_int64 * self.count)(*[x.stride(0) for x in self._Xs])
+        ptrs = (ctypes.c_void_p * self.count)(*[x.data_ptr() for x in self._Xs])
+        for x in self._Xs:
+            assert x.dtype == torch.float32 and x.is_cuda
+        self.lambda1s = list(lambda1s)
+        l1 = (ctypes.c_double * len(self.lambda1s))(*self.lambda1s)
+        h = ctypes.c_void_p()
+        rc = load().concord_batch_create(self.count, ps, ns, ptrs, lds, len(self.lambda1s), l1,
+                                         _stream_ptr(stream), ctypes.byref(h))
+        _check(rc)
+        self._h = h.value
+        self.ps = [x.shape[1] for x in self._Xs]
+        self.device = self._Xs[0].device
+
+    def solve(self, lam2: float, tol: float, max_iter: int):
+        m = self.count * len(self.lambda1s)
+        iters = (ctypes.c_int64 * m)()
+        Fs = (ctypes.c_double * m)()
+        rc = load().concord_batch_solve(self._h, lam2, tol, max_iter, iters, Fs)
+        _check(rc, self._h, batch=True)
+        return list(iters), list(Fs), rc
+
+    def get_omega(self, instance: int, l1_index: int):
+        torch = _torch()
+        nnz = ctypes.c_int64()
+        _check(load().concord_batch_get_omega(self._h, instance, l1_index, ctypes.byref(nnz),
+                                              None, None, None), self._h, batch=True)
+        p = self.ps[instance]
+        rowptr = torch.empty(p + 1, dtype=torch.int64, device=self.device)
+        col = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=self.device)
+        val = torch.empty(max(nnz.value, 1), dtype=torch.float64, device=self.device)
+        _check(load().concord_batch_get_omega(self._h, instance, l1_index, ctypes.byref(nnz),
+                                              rowptr.data_ptr(), col.data_ptr(), val.data_ptr()),
+               self._h, batch=True)
+        return rowptr, col[:nnz.value], val[:nnz.value]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().concord_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

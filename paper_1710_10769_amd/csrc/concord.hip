@@ -1,0 +1,732 @@
+// Host driver and C-ABI of libconcord (see include/concord.h).
+//
+// One outer iteration (Algorithm 1; products per Algorithm 2 or 3):
+//   [Obs]  M = (Y X + (Y X)^T) / (2n)          gemm_sym, syr2k, MFMA
+//   [Cov]  M = (W + W^T) / 2, W = Omega S      (already formed at accept)
+//   A      = candidates of the prox step       cand_count + scan + cand_fill
+//   trials tau0 * 2^-q, q < trial_batch         trial + colsum + decide
+//   accept Omega+ (CSR emission), products and objective at Omega+ (gated on
+//          the device-side decision), one host synchronisation per batch.
+//
+// The backtracking line search restarts at tau = 1 every iteration.  A batch
+// evaluates several step sizes of the sequence 1, 1/2, 1/4, ... in one pass
+// and accepts the first passing one, which is exactly the step the sequential
+// search of Algorithm 1 would accept.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/concord.h"
+#include "internal.h"
+
+using namespace concord;
+
+namespace {
+
+constexpr int MAXQ = 8;
+
+__global__ void state_reset_kernel(DevState* st) {
+    if (threadIdx.x == 0) {
+        st->accepted_q = -1;
+        st->accepted = 0;
+        st->nonpos = 0;
+        st->overflow = 0;
+    }
+}
+
+// copy objective sums (lg, sq, l1, wsum, ysq) into the state when gated on
+__global__ void obj_finish_kernel(const double* sums, int nysq, DevState* st, const int* gate) {
+    if (threadIdx.x != 0) return;
+    if (gate && *gate == 0) return;
+    st->obj[0] = sums[0];
+    st->obj[1] = sums[1];
+    st->obj[2] = sums[2];
+    st->obj[3] = sums[3];
+    double y = 0.0;
+    for (int i = 0; i < nysq; ++i) y += sums[4 + i];
+    st->obj[4] = y;
+}
+
+__global__ void set_int_kernel(int* p, int v) {
+    if (threadIdx.x == 0) *p = v;
+}
+
+}  // namespace
+
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct concord_ctx {
+    int64_t p = 0, n = 0;
+    int variant = CONCORD_COV, precision = CONCORD_FP64;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int max_bt = 60, tb = 8;
+    std::string err;
+
+    int64_t prow = 0, ldk = 0, ldp = 0;
+    int dstore = ST_F64;   // Xt / Y / M element storage
+    int sstore = ST_F64;   // S storage (Cov)
+    int gkind = GK_F64;
+
+    bool has_data = false;
+
+    void* Xt = nullptr;
+    uint16_t* Xt_hi = nullptr;
+    uint16_t* Xt_lo = nullptr;
+    void* Y = nullptr;
+    uint16_t* Y_hi = nullptr;
+    uint16_t* Y_lo = nullptr;
+    void* S = nullptr;
+    void* M = nullptr;
+
+    Csr om[2] = {};
+    int64_t om_cap[2] = {0, 0};
+    int cur = 0;
+    int64_t nnz = 0;
+    int64_t k = 0;
+
+    Cand A = {};
+    int64_t a_cap = 0;
+    int64_t* cnt = nullptr;
+    uint64_t* bitmap = nullptr;
+    int64_t nwords = 0;
+
+    double* part = nullptr;
+    int64_t part_elems = 0;
+    double* sums = nullptr;      // 64
+    double* objsums = nullptr;   // 64
+    DevState* st = nullptr;
+    DevState* st_host = nullptr; // pinned
+    int64_t* h_stage = nullptr;  // pinned, 4 int64
+    int* d_one = nullptr;
+    int* d_flags = nullptr;      // 8 ints
+
+    bool prod_valid = false;     // products and objective sums valid for om[cur]
+    double obj[5] = {0, 0, 0, 0, 0};
+
+    std::vector<void*> allocs;
+};
+
+namespace {
+
+const char* kVersion = "concord-mi355x 0.1 (gfx950)";
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        hipGetDevice(&prev);
+        if (prev != dev) hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int now = -1;
+        hipGetDevice(&now);
+        if (prev >= 0 && now != prev) hipSetDevice(prev);
+    }
+};
+
+int fail(concord_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCK(ctx, expr)                                                                 \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? CONCORD_ENOMEM : CONCORD_EHIP,  \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));              \
+    } while (0)
+
+int dalloc(concord_ctx* c, void** out, size_t bytes, bool zero) {
+    *out = nullptr;
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(out, bytes);
+    if (e != hipSuccess) {
+        *out = nullptr;
+        hipGetLastError();
+        return fail(c, CONCORD_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    c->allocs.push_back(*out);
+    if (zero) {
+        e = hipMemsetAsync(*out, 0, bytes, c->stream);
+        if (e != hipSuccess) return fail(c, CONCORD_EHIP, "hipMemsetAsync failed");
+    }
+    return CONCORD_OK;
+}
+
+void dfree(concord_ctx* c, void* p) {
+    if (!p) return;
+    for (auto& a : c->allocs)
+        if (a == p) {
+            hipFree(p);
+            a = nullptr;
+        }
+}
+
+template <typename T>
+int dalloc_t(concord_ctx* c, T** out, size_t count, bool zero = false) {
+    void* v = nullptr;
+    int rc = dalloc(c, &v, count * sizeof(T), zero);
+    *out = (T*)v;
+    return rc;
+}
+
+int elem_bytes(int store) { return store == ST_F64 ? 8 : 4; }
+
+// capacity for candidate / iterate arrays
+int ensure_csr_cap(concord_ctx* c, int which, int64_t cap) {
+    if (c->om_cap[which] >= cap) return CONCORD_OK;
+    Csr& o = c->om[which];
+    // rowptr is kept; col/val regrown
+    dfree(c, o.col);
+    dfree(c, o.val);
+    o.col = nullptr;
+    o.val = nullptr;
+    int rc;
+    if ((rc = dalloc_t(c, &o.col, cap))) return rc;
+    if ((rc = dalloc_t(c, &o.val, cap))) return rc;
+    c->om_cap[which] = cap;
+    return CONCORD_OK;
+}
+
+int ensure_cand_cap(concord_ctx* c, int64_t cap) {
+    if (c->a_cap >= cap) return CONCORD_OK;
+    dfree(c, c->A.col);
+    dfree(c, c->A.omega);
+    dfree(c, c->A.grad);
+    int rc;
+    if ((rc = dalloc_t(c, &c->A.col, cap))) return rc;
+    if ((rc = dalloc_t(c, &c->A.omega, cap))) return rc;
+    if ((rc = dalloc_t(c, &c->A.grad, cap))) return rc;
+    c->a_cap = cap;
+    return CONCORD_OK;
+}
+
+int sync_state(concord_ctx* c) {
+    HIPCK(c, hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    return CONCORD_OK;
+}
+
+// Dense p x p work buffers (M and the candidate bitmap) are allocated on first
+// use, so handles used only for the differentiation form never hold them.
+int ensure_dense(concord_ctx* c) {
+    int rc;
+    if (!c->M && (rc = dalloc(c, &c->M, (size_t)c->p * c->ldp * elem_bytes(c->dstore), true)))
+        return rc;
+    if (!c->bitmap && (rc = dalloc_t(c, &c->bitmap, (size_t)c->p * c->nwords, true))) return rc;
+    return CONCORD_OK;
+}
+
+// Products and objective sums at om[which], gated on `gate` (device int).
+int products_at(concord_ctx* c, int which, const int* gate) {
+    if (c->variant == CONCORD_COV) {
+        int rc = ensure_dense(c);
+        if (rc) return rc;
+    }
+    const Csr& O = c->om[which];
+    const int64_t p = c->p;
+    int nysq = 0;
+    if (c->variant == CONCORD_OBS) {
+        const bool split = c->precision == CONCORD_BF16X3;
+        const int nch = spmm_nchunks(c->dstore, c->ldk);
+        // sq parts go after the 4 objective columns in `part`
+        double* sq = c->part + 4 * p;
+        HIPCK(c, launch_spmm(O, p, c->Xt, c->dstore, c->ldk, c->ldk, split ? nullptr : c->Y,
+                             c->dstore, c->ldk, split ? c->Y_hi : nullptr,
+                             split ? c->Y_lo : nullptr, sq, gate, c->stream));
+        nysq = nch;
+        HIPCK(c, launch_obj_parts(O, p, nullptr, c->dstore, 0, c->part, gate, c->stream));
+        HIPCK(c, launch_colsum(c->part, p, 4 + nch, c->objsums, c->stream));
+    } else {
+        HIPCK(c, launch_spmm(O, p, c->S, c->sstore, c->ldp, c->ldp, c->M, c->dstore, c->ldp,
+                             nullptr, nullptr, nullptr, gate, c->stream));
+        HIPCK(c, launch_symmetrize(c->M, c->dstore, p, c->ldp, gate, c->stream));
+        HIPCK(c, launch_obj_parts(O, p, c->M, c->dstore, c->ldp, c->part, gate, c->stream));
+        HIPCK(c, launch_colsum(c->part, p, 4, c->objsums, c->stream));
+    }
+    hipLaunchKernelGGL(obj_finish_kernel, dim3(1), dim3(64), 0, c->stream, c->objsums, nysq, c->st,
+                       gate);
+    HIPCK(c, hipGetLastError());
+    return CONCORD_OK;
+}
+
+int ensure_products(concord_ctx* c) {
+    if (c->prod_valid) return CONCORD_OK;
+    hipLaunchKernelGGL(state_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->st);
+    int rc = products_at(c, c->cur, c->d_one);
+    if (rc) return rc;
+    if ((rc = sync_state(c))) return rc;
+    for (int i = 0; i < 5; ++i) c->obj[i] = c->st_host->obj[i];
+    c->prod_valid = true;
+    return CONCORD_OK;
+}
+
+void objective_from(const concord_ctx* c, const double* o, double lam1, double lam2, double* f,
+                    double* F) {
+    const double quad = c->variant == CONCORD_OBS ? o[4] / (double)c->n : o[3];
+    const double fv = -o[0] + 0.5 * quad + 0.5 * lam2 * o[1];
+    *f = fv;
+    *F = fv + lam1 * o[2];
+}
+
+int set_identity(concord_ctx* c) {
+    int rc = ensure_csr_cap(c, c->cur, c->p);
+    if (rc) return rc;
+    HIPCK(c, launch_identity(c->om[c->cur], c->p, c->stream));
+    c->nnz = c->p;
+    c->k = 0;
+    c->prod_valid = false;
+    return CONCORD_OK;
+}
+
+int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord_step_info* info) {
+    if (!c) return CONCORD_EINVAL;
+    if (!(lam1 >= 0.0) || !(lam2 >= 0.0) || !std::isfinite(lam1) || !std::isfinite(lam2))
+        return fail(c, CONCORD_EINVAL, "lambda1 and lambda2 must be finite and >= 0");
+    if (!c->has_data) return fail(c, CONCORD_ENODATA, "no data: call concord_set_data first");
+    if (forced_trials > c->max_bt + 1)
+        return fail(c, CONCORD_EINVAL, "forced trial count exceeds max_backtracks + 1");
+    DeviceGuard g(c->device);
+    int rc = ensure_dense(c);
+    if (rc) return rc;
+    if ((rc = ensure_products(c))) return rc;
+    const int64_t p = c->p;
+
+    // gradient-side dense product
+    if (c->variant == CONCORD_OBS) {
+        const bool split = c->precision == CONCORD_BF16X3;
+        const void* P0 = split ? (const void*)c->Y_hi : c->Y;
+        const void* P1 = split ? (const void*)c->Y_lo : nullptr;
+        const void* Q0 = split ? (const void*)c->Xt_hi : c->Xt;
+        const void* Q1 = split ? (const void*)c->Xt_lo : nullptr;
+        HIPCK(c, launch_gemm_sym(c->gkind, true, P0, P1, Q0, Q1, c->ldk, p,
+                                 0.5 / (double)c->n, c->M, c->dstore, c->ldp, c->stream));
+    }
+    const int nxt = c->cur ^ 1;
+    const double inv_n = c->variant == CONCORD_OBS ? 1.0 / (double)c->n : 1.0;
+    const void* TB = c->variant == CONCORD_OBS ? c->Xt : c->S;
+    const int tbstore = c->variant == CONCORD_OBS ? c->dstore : c->sstore;
+    const int64_t tld = c->variant == CONCORD_OBS ? c->ldk : c->ldp;
+
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        hipLaunchKernelGGL(state_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->st);
+        // candidate set
+        HIPCK(c, launch_cand_count(c->M, c->dstore, c->ldp, c->om[c->cur], p, lam1, c->bitmap,
+                                   c->nwords, c->cnt, c->stream));
+        HIPCK(c, launch_scan(c->cnt, p, c->A.rowptr, c->a_cap, &c->st->overflow, c->stream));
+        HIPCK(c, launch_cand_fill(c->M, c->dstore, c->ldp, c->om[c->cur], p, lam2, c->bitmap,
+                                  c->nwords, c->A, c->a_cap, &c->st->overflow, c->stream));
+        if ((rc = ensure_csr_cap(c, nxt, c->a_cap))) return rc;
+
+        const int total = c->max_bt + 1;   // step sizes 1 .. 2^-max_bt
+        int q_base = 0, batches = 0;
+        const int forced_q = forced_trials >= 1 ? forced_trials - 1 : -1;
+        if (forced_q >= 0) q_base = forced_q;
+        bool overflow = false, accepted = false;
+        while (q_base < total) {
+            const int m = forced_q >= 0 ? 1 : std::min(c->tb, total - q_base);
+            const double tau0 = std::ldexp(1.0, -q_base);
+            HIPCK(c, launch_trial(c->A, p, tau0, m, lam1, c->variant, TB, tbstore, tld,
+                                  c->variant == CONCORD_OBS ? c->ldk : 0, c->part, c->st,
+                                  c->stream));
+            HIPCK(c, launch_colsum(c->part, p, 4 * m, c->sums, c->stream));
+            HIPCK(c, launch_decide(c->sums, m, tau0, q_base, lam2, c->variant, inv_n, forced_q,
+                                   c->st, c->stream));
+            // emission and products at Omega+ (all gated on the decision)
+            HIPCK(c, launch_emit_count(c->A, p, lam1, c->st, c->cnt, c->stream));
+            HIPCK(c, launch_scan(c->cnt, p, c->om[nxt].rowptr, c->om_cap[nxt], nullptr, c->stream));
+            HIPCK(c, launch_emit_fill(c->A, p, lam1, c->st, c->om[nxt], c->stream));
+            if ((rc = products_at(c, nxt, &c->st->accepted))) return rc;
+            HIPCK(c, hipMemcpyAsync(c->h_stage, c->om[nxt].rowptr + p, sizeof(int64_t),
+                                    hipMemcpyDeviceToHost, c->stream));
+            HIPCK(c, hipMemcpyAsync(c->h_stage + 1, c->A.rowptr + p, sizeof(int64_t),
+                                    hipMemcpyDeviceToHost, c->stream));
+            if ((rc = sync_state(c))) return rc;
+            ++batches;
+            if (c->st_host->overflow) { overflow = true; break; }
+            if (c->st_host->accepted_q >= 0) { accepted = true; break; }
+            if (forced_q >= 0) break;
+            q_base += m;
+        }
+        if (overflow) {
+            const int64_t need = c->h_stage[1];
+            if ((rc = ensure_cand_cap(c, need + need / 2 + 1024))) return rc;
+            continue;
+        }
+        if (c->st_host->nonpos)
+            return fail(c, CONCORD_ENOTPD, "replayed step leaves a diagonal entry <= 0");
+        if (!accepted)
+            return fail(c, CONCORD_ELINESEARCH,
+                        "line search exhausted max_backtracks; iterate unchanged");
+        const DevState& s = *c->st_host;
+        c->cur = nxt;
+        c->nnz = c->h_stage[0];
+        c->k += 1;
+        for (int i = 0; i < 5; ++i) c->obj[i] = s.obj[i];
+        c->prod_valid = true;
+        if (info) {
+            info->k = c->k;
+            info->tau = s.tau;
+            info->n_trials = s.accepted_q + 1;
+            info->n_batches = batches;
+            objective_from(c, c->obj, lam1, lam2, &info->f, &info->F);
+            info->nnz = c->nnz;
+            info->delta_fro = std::sqrt(s.dd);
+            info->n_candidates = c->h_stage[1];
+            info->lhs = s.lhs;
+            info->rhs = s.rhs;
+        }
+        return CONCORD_OK;
+    }
+    return fail(c, CONCORD_ENOMEM, "candidate capacity did not converge");
+}
+
+}  // namespace
+
+extern "C" {
+
+void concord_config_init(concord_config* cfg) {
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->variant = CONCORD_COV;
+    cfg->precision = CONCORD_FP64;
+    cfg->stream = nullptr;
+    cfg->device = -1;
+    cfg->max_backtracks = 60;
+    cfg->trial_batch = 8;
+}
+
+const char* concord_version(void) { return kVersion; }
+
+const char* concord_last_error(const concord_ctx* ctx) {
+    if (!ctx) return "null handle";
+    return ctx->err.c_str();
+}
+
+void concord_destroy(concord_ctx* ctx) {
+    if (!ctx) return;
+    {
+        DeviceGuard g(ctx->device);
+        hipStreamSynchronize(ctx->stream);
+        for (void* a : ctx->allocs)
+            if (a) hipFree(a);
+        if (ctx->st_host) hipHostFree(ctx->st_host);
+        if (ctx->h_stage) hipHostFree(ctx->h_stage);
+    }
+    delete ctx;
+}
+
+int concord_create(const concord_config* cfg, concord_ctx** out) {
+    if (!out) return CONCORD_EINVAL;
+    *out = nullptr;
+    if (!cfg) return CONCORD_EINVAL;
+    if (cfg->p < 1 || cfg->p > (int64_t)1 << 30) return CONCORD_EINVAL;
+    if (cfg->variant != CONCORD_COV && cfg->variant != CONCORD_OBS) return CONCORD_EINVAL;
+    if (cfg->precision < CONCORD_FP64 || cfg->precision > CONCORD_BF16X3) return CONCORD_EINVAL;
+    if (cfg->variant == CONCORD_OBS && cfg->n < 1) return CONCORD_EINVAL;
+    if (cfg->n < 0) return CONCORD_EINVAL;
+    if (cfg->trial_batch < 1 || cfg->trial_batch > MAXQ) return CONCORD_EINVAL;
+    if (cfg->max_backtracks < 0 || cfg->max_backtracks > 1000) return CONCORD_EINVAL;
+
+    int dev = cfg->device;
+    if (dev < 0) {
+        if (hipGetDevice(&dev) != hipSuccess) return CONCORD_EHIP;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || dev >= ndev) return CONCORD_EHIP;
+
+    concord_ctx* c = new concord_ctx();
+    c->p = cfg->p;
+    c->n = cfg->n;
+    c->variant = cfg->variant;
+    c->precision = cfg->precision;
+    c->stream = (hipStream_t)cfg->stream;
+    c->device = dev;
+    c->max_bt = cfg->max_backtracks;
+    c->tb = cfg->trial_batch;
+    DeviceGuard g(dev);
+
+    c->dstore = c->precision == CONCORD_FP64 ? ST_F64 : ST_F32;
+    c->sstore = c->precision == CONCORD_FP64 ? ST_F64 : (c->precision == CONCORD_FP32 ? ST_F32 : ST_B16P);
+    c->gkind = c->precision == CONCORD_FP64 ? GK_F64 : (c->precision == CONCORD_FP32 ? GK_F32 : GK_BF16X3);
+    const int64_t p = c->p;
+    c->prow = round_up(p, ROW_PAD);
+    c->ldk = round_up(c->n > 0 ? c->n : 1, K_PAD);
+    c->ldp = round_up(p, 64);
+    c->nwords = (p + 63) / 64;
+
+    auto bail = [&](int rc) {
+        concord_destroy(c);
+        return rc;
+    };
+    int rc;
+    const size_t eb = elem_bytes(c->dstore);
+    const bool split = c->precision == CONCORD_BF16X3;
+    if (c->n > 0) {
+        if ((rc = dalloc(c, &c->Xt, (size_t)c->prow * c->ldk * eb, true))) return bail(rc);
+        if (split) {
+            if ((rc = dalloc_t(c, &c->Xt_hi, (size_t)c->prow * c->ldk, true))) return bail(rc);
+            if ((rc = dalloc_t(c, &c->Xt_lo, (size_t)c->prow * c->ldk, true))) return bail(rc);
+        }
+    }
+    if (c->variant == CONCORD_OBS) {
+        if (split) {
+            if ((rc = dalloc_t(c, &c->Y_hi, (size_t)c->prow * c->ldk, true))) return bail(rc);
+            if ((rc = dalloc_t(c, &c->Y_lo, (size_t)c->prow * c->ldk, true))) return bail(rc);
+        } else {
+            if ((rc = dalloc(c, &c->Y, (size_t)c->prow * c->ldk * eb, true))) return bail(rc);
+        }
+    } else {
+        if ((rc = dalloc(c, &c->S, (size_t)p * c->ldp * (c->sstore == ST_F64 ? 8 : 4), true)))
+            return bail(rc);
+    }
+    for (int w = 0; w < 2; ++w)
+        if ((rc = dalloc_t(c, &c->om[w].rowptr, p + 1, true))) return bail(rc);
+    const int64_t cap0 = 8 * p + 1024;
+    if ((rc = ensure_csr_cap(c, 0, cap0)) || (rc = ensure_csr_cap(c, 1, cap0))) return bail(rc);
+    if ((rc = dalloc_t(c, &c->A.rowptr, p + 1, true))) return bail(rc);
+    if ((rc = ensure_cand_cap(c, cap0))) return bail(rc);
+    if ((rc = dalloc_t(c, &c->cnt, p + 1, true))) return bail(rc);
+    const int nch = c->variant == CONCORD_OBS ? spmm_nchunks(c->dstore, c->ldk) : 0;
+    c->part_elems = (int64_t)std::max(4 * MAXQ, 4 + nch) * p;
+    if ((rc = dalloc_t(c, &c->part, c->part_elems, true))) return bail(rc);
+    if ((rc = dalloc_t(c, &c->sums, 64, true))) return bail(rc);
+    if ((rc = dalloc_t(c, &c->objsums, 64 + nch, true))) return bail(rc);
+    if ((rc = dalloc_t(c, &c->st, 1, true))) return bail(rc);
+    if ((rc = dalloc_t(c, &c->d_one, 1, false))) return bail(rc);
+    if ((rc = dalloc_t(c, &c->d_flags, 8, true))) return bail(rc);
+    hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, c->stream, c->d_one, 1);
+    if (hipHostMalloc((void**)&c->st_host, sizeof(DevState), hipHostMallocDefault) != hipSuccess)
+        return bail(CONCORD_ENOMEM);
+    if (hipHostMalloc((void**)&c->h_stage, 4 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
+        return bail(CONCORD_ENOMEM);
+    if ((rc = set_identity(c))) return bail(rc);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(CONCORD_EHIP);
+    *out = c;
+    return CONCORD_OK;
+}
+
+int concord_set_data(concord_ctx* c, int32_t kind, const void* dev_data, int32_t dtype,
+                     int64_t rows, int64_t cols, int64_t ld) {
+    if (!c) return CONCORD_EINVAL;
+    if (!dev_data) return fail(c, CONCORD_EINVAL, "null data pointer");
+    if (dtype != CONCORD_F64 && dtype != CONCORD_F32) return fail(c, CONCORD_EINVAL, "dtype");
+    if (ld < cols) return fail(c, CONCORD_EINVAL, "ld < cols");
+    DeviceGuard g(c->device);
+    const int is64 = dtype == CONCORD_F64;
+    if (kind == CONCORD_DATA_X) {
+        if (rows != c->n || cols != c->p)
+            return fail(c, CONCORD_EINVAL, "X must be n x p as configured");
+    } else if (kind == CONCORD_DATA_S) {
+        if (c->variant != CONCORD_COV) return fail(c, CONCORD_EINVAL, "S is accepted by Cov only");
+        if (rows != c->p || cols != c->p) return fail(c, CONCORD_EINVAL, "S must be p x p");
+    } else {
+        return fail(c, CONCORD_EINVAL, "unknown data kind");
+    }
+    hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, c->stream, c->d_flags, 0);
+    HIPCK(c, launch_check_finite(dev_data, is64, rows, cols, ld, c->d_flags, c->stream));
+    int hflag = 0;
+    HIPCK(c, hipMemcpyAsync(&hflag, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    if (hflag) return fail(c, CONCORD_ENONFINITE, "data holds NaN or Inf");
+
+    if (kind == CONCORD_DATA_X) {
+        const bool split = c->precision == CONCORD_BF16X3;
+        HIPCK(c, launch_transpose_in(dev_data, is64, rows, cols, ld, c->Xt, c->dstore, c->ldk,
+                                     split ? c->Xt_hi : nullptr, split ? c->Xt_lo : nullptr,
+                                     c->stream));
+        if (c->variant == CONCORD_COV) {
+            const void* P0 = split ? (const void*)c->Xt_hi : c->Xt;
+            const void* P1 = split ? (const void*)c->Xt_lo : nullptr;
+            HIPCK(c, launch_gemm_sym(c->gkind, false, P0, P1, nullptr, nullptr, c->ldk, c->p,
+                                     1.0 / (double)c->n, c->S, c->sstore, c->ldp, c->stream));
+        }
+    } else {
+        HIPCK(c, launch_copy_square(dev_data, is64, c->p, ld, c->S, c->sstore, c->ldp, c->stream));
+    }
+    c->has_data = true;
+    int rc = set_identity(c);
+    if (rc) return rc;
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    return CONCORD_OK;
+}
+
+int concord_set_omega(concord_ctx* c, int64_t nnz, const int64_t* dev_row_ptr,
+                      const int32_t* dev_col, const void* dev_val, int32_t dtype) {
+    if (!c) return CONCORD_EINVAL;
+    if (nnz < c->p || !dev_row_ptr || !dev_col || !dev_val)
+        return fail(c, CONCORD_EINVAL, "bad CSR arguments");
+    if (dtype != CONCORD_F64 && dtype != CONCORD_F32) return fail(c, CONCORD_EINVAL, "dtype");
+    DeviceGuard g(c->device);
+    hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, c->stream, c->d_flags, 0);
+    hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, c->stream, c->d_flags + 1, 0);
+    hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, c->stream, c->d_flags + 2, 0);
+    HIPCK(c, launch_csr_validate(dev_row_ptr, dev_col, dev_val, dtype == CONCORD_F64, c->p, nnz,
+                                 c->d_flags, c->stream));
+    int hf[3] = {0, 0, 0};
+    HIPCK(c, hipMemcpyAsync(hf, c->d_flags, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    if (hf[0]) return fail(c, CONCORD_EINVAL, "CSR structure invalid (row_ptr, sorted columns or diagonal)");
+    if (hf[2]) return fail(c, CONCORD_ENONFINITE, "Omega holds NaN or Inf");
+    if (hf[1]) return fail(c, CONCORD_ENOTPD, "Omega has a diagonal entry <= 0");
+    int rc;
+    if ((rc = ensure_csr_cap(c, c->cur, nnz))) return rc;
+    if ((rc = ensure_cand_cap(c, std::max<int64_t>(c->a_cap, 2 * nnz)))) return rc;
+    Csr& o = c->om[c->cur];
+    HIPCK(c, hipMemcpyAsync(o.rowptr, dev_row_ptr, (c->p + 1) * sizeof(int64_t),
+                            hipMemcpyDeviceToDevice, c->stream));
+    HIPCK(c, launch_csr_import(dev_col, dev_val, dtype == CONCORD_F64, nnz, o.col, o.val, c->stream));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    c->nnz = nnz;
+    c->k = 0;
+    c->prod_valid = false;
+    return CONCORD_OK;
+}
+
+int concord_reset(concord_ctx* c) {
+    if (!c) return CONCORD_EINVAL;
+    DeviceGuard g(c->device);
+    int rc = set_identity(c);
+    if (rc) return rc;
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    return CONCORD_OK;
+}
+
+int concord_step(concord_ctx* c, double lam1, double lam2, concord_step_info* info) {
+    return do_step(c, lam1, lam2, 0, info);
+}
+
+int concord_step_replay(concord_ctx* c, double lam1, double lam2, int32_t trials,
+                        concord_step_info* info) {
+    if (!c) return CONCORD_EINVAL;
+    if (trials < 1) return fail(c, CONCORD_EINVAL, "trials must be >= 1");
+    return do_step(c, lam1, lam2, trials, info);
+}
+
+int concord_solve(concord_ctx* c, double lam1, double lam2, double tol, int64_t max_iter,
+                  concord_solve_info* info) {
+    if (!c) return CONCORD_EINVAL;
+    if (!(tol >= 0.0) || max_iter < 0) return fail(c, CONCORD_EINVAL, "tol must be >= 0, max_iter >= 0");
+    if (!c->has_data) return fail(c, CONCORD_ENODATA, "no data: call concord_set_data first");
+    DeviceGuard g(c->device);
+    int rc = ensure_products(c);
+    if (rc) return rc;
+    double f, F_old;
+    objective_from(c, c->obj, lam1, lam2, &f, &F_old);
+    int status = tol > 0.0 ? CONCORD_WMAXITER : CONCORD_OK;
+    int64_t it = 0;
+    for (; it < max_iter; ++it) {
+        concord_step_info si;
+        rc = do_step(c, lam1, lam2, 0, &si);
+        if (rc < 0) { status = rc; break; }
+        const double F_new = si.F;
+        if (tol > 0.0 && std::fabs(F_new - F_old) < tol * std::fabs(F_old)) {
+            status = CONCORD_OK;
+            ++it;
+            break;
+        }
+        F_old = F_new;
+    }
+    if (info) {
+        info->iters = c->k;
+        objective_from(c, c->obj, lam1, lam2, &info->f, &info->F);
+        info->nnz = c->nnz;
+        info->status = status;
+    }
+    return status;
+}
+
+int concord_objective(concord_ctx* c, double lam1, double lam2, double* host_f, double* host_F) {
+    if (!c) return CONCORD_EINVAL;
+    if (!(lam1 >= 0.0) || !(lam2 >= 0.0)) return fail(c, CONCORD_EINVAL, "lambda must be >= 0");
+    if (!c->has_data) return fail(c, CONCORD_ENODATA, "no data: call concord_set_data first");
+    DeviceGuard g(c->device);
+    int rc = ensure_products(c);
+    if (rc) return rc;
+    double f, F;
+    objective_from(c, c->obj, lam1, lam2, &f, &F);
+    if (host_f) *host_f = f;
+    if (host_F) *host_F = F;
+    return CONCORD_OK;
+}
+
+int concord_get_omega(concord_ctx* c, int64_t* host_nnz, int64_t* dev_row_ptr, int32_t* dev_col,
+                      void* dev_val, int32_t dtype) {
+    if (!c || !host_nnz) return CONCORD_EINVAL;
+    *host_nnz = c->nnz;
+    if (!dev_row_ptr) return CONCORD_OK;
+    if (!dev_col || !dev_val) return fail(c, CONCORD_EINVAL, "col/val must be given with row_ptr");
+    if (dtype != CONCORD_F64 && dtype != CONCORD_F32) return fail(c, CONCORD_EINVAL, "dtype");
+    DeviceGuard g(c->device);
+    const Csr& o = c->om[c->cur];
+    HIPCK(c, hipMemcpyAsync(dev_row_ptr, o.rowptr, (c->p + 1) * sizeof(int64_t),
+                            hipMemcpyDeviceToDevice, c->stream));
+    HIPCK(c, hipMemcpyAsync(dev_col, o.col, c->nnz * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                            c->stream));
+    HIPCK(c, launch_csr_export(o.val, c->nnz, dev_val, dtype == CONCORD_F64, c->stream));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    return CONCORD_OK;
+}
+
+int64_t concord_iterations(const concord_ctx* c) { return c ? c->k : -1; }
+
+int concord_smooth_value(concord_ctx* c, double lam2, double* host_f) {
+    if (!c) return CONCORD_EINVAL;
+    if (c->variant != CONCORD_OBS) return fail(c, CONCORD_EINVAL, "differentiation form needs Obs");
+    return concord_objective(c, 0.0, lam2, host_f, nullptr);
+}
+
+int concord_gradient(concord_ctx* c, double lam2, int32_t mode, void* dev_dOmega, void* dev_dX,
+                     int32_t dtype) {
+    if (!c) return CONCORD_EINVAL;
+    if (c->variant != CONCORD_OBS) return fail(c, CONCORD_EINVAL, "differentiation form needs Obs");
+    if (!c->has_data) return fail(c, CONCORD_ENODATA, "no data: call concord_set_data first");
+    if (!(lam2 >= 0.0)) return fail(c, CONCORD_EINVAL, "lambda2 must be >= 0");
+    if (mode != CONCORD_GRAD_MASKED && mode != CONCORD_GRAD_DENSE)
+        return fail(c, CONCORD_EINVAL, "mode");
+    if (dtype != CONCORD_F64 && dtype != CONCORD_F32) return fail(c, CONCORD_EINVAL, "dtype");
+    DeviceGuard g(c->device);
+    int rc = ensure_products(c);   // Y at the current iterate (recomputed if stale)
+    if (rc) return rc;
+    const bool split = c->precision == CONCORD_BF16X3;
+    if (split) return fail(c, CONCORD_EINVAL, "differentiation form supports FP64 and FP32");
+    const Csr& O = c->om[c->cur];
+    const int out64 = dtype == CONCORD_F64;
+    if (dev_dOmega) {
+        if (mode == CONCORD_GRAD_MASKED) {
+            HIPCK(c, launch_sddmm_grad(O, c->p, c->Y, c->Xt, c->dstore, c->ldk, c->n, lam2,
+                                       dev_dOmega, out64, c->stream));
+        } else {
+            if ((rc = ensure_dense(c))) return rc;
+            HIPCK(c, launch_gemm_sym(c->gkind, true, c->Y, nullptr, c->Xt, nullptr, c->ldk, c->p,
+                                     0.5 / (double)c->n, c->M, c->dstore, c->ldp, c->stream));
+            HIPCK(c, launch_gather_dense_grad(c->M, c->dstore, c->ldp, O, c->p, lam2, dev_dOmega,
+                                              out64, c->stream));
+        }
+    }
+    if (dev_dX) {
+        // d f / d X^T = Omega Y / n, written transposed (n x p); the product
+        // goes through the Y buffer's twin (M is large enough: p x ldp >= p x ldk
+        // is not guaranteed, so use a temporary).
+        void* tmp = nullptr;
+        if ((rc = dalloc(c, &tmp, (size_t)c->prow * c->ldk * elem_bytes(c->dstore), true))) return rc;
+        HIPCK(c, launch_spmm(O, c->p, c->Y, c->dstore, c->ldk, c->ldk, tmp, c->dstore, c->ldk,
+                             nullptr, nullptr, nullptr, c->d_one, c->stream));
+        HIPCK(c, launch_transpose_out(tmp, c->dstore, c->p, c->n, c->ldk, 1.0 / (double)c->n,
+                                      dev_dX, out64, c->stream));
+        HIPCK(c, hipStreamSynchronize(c->stream));
+        dfree(c, tmp);
+    }
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    return CONCORD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,173 @@
+// Internal declarations shared by the HIP translation units of libconcord.
+// Nothing here is part of the C-ABI (include/concord.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace concord {
+
+// Dense element storage forms.
+enum Store : int {
+    ST_F64 = 0,   // double
+    ST_F32 = 1,   // float
+    ST_B16P = 2,  // packed pair (bf16 hi | bf16 lo << 16); value = hi + lo
+};
+
+// Operand planes of the MFMA symmetric contraction.
+enum GemmKind : int {
+    GK_F64 = 0,    // FP64 MFMA 16x16x4
+    GK_F32 = 1,    // FP32 MFMA 32x32x2
+    GK_BF16X3 = 2, // BF16 MFMA 32x32x16, hi*hi + hi*lo + lo*hi
+};
+
+constexpr int GEMM_BM = 128;   // output tile edge
+constexpr int ROW_PAD = 256;   // dense operands are allocated with rows padded to this
+constexpr int K_PAD = 64;      // and their K (column) dimension padded to this
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// ---- launchers (all asynchronous on `stream`) ----
+
+// C = alpha * (P Q^T + Q P^T)  (syr2k)  or  alpha * P P^T  (syrk, Q ignored),
+// over the upper-triangle tiles only, written symmetrically (both triangles,
+// bitwise symmetric).  P and Q are prow x ldk row-major planes (prow a
+// multiple of 128, zero rows beyond p; ldk a multiple of 64, zero columns
+// beyond the true K).  For GK_BF16X3, P0/P1 and Q0/Q1 are the hi/lo planes
+// (uint16 bf16 bits); otherwise P0/Q0 hold float (GK_F32) or double (GK_F64).
+// out_store: ST_F32, ST_F64 or ST_B16P.
+hipError_t launch_gemm_sym(int kind, bool syr2k, const void* P0, const void* P1,
+                           const void* Q0, const void* Q1, int64_t ldk, int64_t p,
+                           double alpha, void* C, int out_store, int64_t ldc,
+                           hipStream_t stream);
+
+// X (rows x cols, ld, F64 or F32) -> Xt (cols x ldo) in `store` (F64/F32);
+// optionally bf16 hi/lo planes (hi, lo may be null).  Scale applied on copy.
+hipError_t launch_transpose_in(const void* X, int x_is_f64, int64_t rows, int64_t cols,
+                               int64_t ld, void* Xt, int store, int64_t ldo, uint16_t* hi,
+                               uint16_t* lo, hipStream_t stream);
+
+// Copy a square p x p (ld) F64/F32 matrix into `store` layout with ldo.
+hipError_t launch_copy_square(const void* S, int s_is_f64, int64_t p, int64_t ld, void* out,
+                              int store, int64_t ldo, hipStream_t stream);
+
+// Non-finite detector: sets *flag (int) to 1 if any of the rows x cols (ld)
+// entries is NaN/Inf.
+hipError_t launch_check_finite(const void* A, int is_f64, int64_t rows, int64_t cols,
+                               int64_t ld, int* flag, hipStream_t stream);
+
+// ---- sparse side ----
+
+struct Csr {
+    int64_t* rowptr;  // p+1
+    int32_t* col;     // cap
+    double* val;      // cap
+};
+
+// Y = Omega B (B: K x N dense, ldb, store), rows < p written to C (ldc) in
+// `cstore` (F64/F32) unless C is null; hi/lo planes written if non-null.
+// sq_part (if non-null) receives sum_j Y_ij^2 per (row, column-chunk) in FP64
+// as sq_part[chunk * p + row]; nchunks returned through *nchunks_out.
+// `gate` (device int, may be null): kernel does nothing unless *gate != 0.
+hipError_t launch_spmm(const Csr& A, int64_t p, const void* B, int bstore, int64_t ldb,
+                       int64_t ncols, void* C, int cstore, int64_t ldc, uint16_t* hi,
+                       uint16_t* lo, double* sq_part, const int* gate, hipStream_t stream);
+int spmm_nchunks(int bstore, int64_t ncols);
+
+// Candidate set of one iteration.
+struct Cand {
+    int64_t* rowptr;  // p+1
+    int32_t* col;     // cap
+    double* omega;    // cap: current omega_ij (0 off the support)
+    double* grad;     // cap: G_ij
+};
+
+// Count pass: for every row, A_i = {j != i : |M_ij| > lam1} U supp(Omega_i) U {i}.
+// Writes the candidate bitmap (p x nwords64 uint64, row-major, word w bit b
+// covers column 64*w+b) and cnt[i] = |A_i|.
+hipError_t launch_cand_count(const void* M, int mstore, int64_t ldm, const Csr& om, int64_t p,
+                             double lam1, uint64_t* bitmap, int64_t nwords, int64_t* cnt,
+                             hipStream_t stream);
+// Fill pass: writes A (sorted columns) with omega and G = M + lam2*omega - [i==j]/omega_ii.
+hipError_t launch_cand_fill(const void* M, int mstore, int64_t ldm, const Csr& om, int64_t p,
+                            double lam2, const uint64_t* bitmap, int64_t nwords,
+                            const Cand& A, int64_t cap, const int* overflow,
+                            hipStream_t stream);
+
+// Exclusive scan of cnt[0..p) into out[0..p] (out[p] = total); sets
+// *overflow = 1 if total > cap.  Single workgroup, deterministic.
+hipError_t launch_scan(const int64_t* cnt, int64_t p, int64_t* out, int64_t cap, int* overflow,
+                       hipStream_t stream);
+
+struct DevState;
+// Trial evaluation for `m` step sizes tau_q = tau0 * 2^-q (q < m) at once.
+// Per row partials part[(q*4 + t) * p + row], t = 0: sum x - log1p x over the
+// diagonal, 1: ||Delta_i||^2, 2: quadratic term of row i, 3: 1 if the
+// diagonal entry is <= 0.  Obs quadratic: ||Delta_i X^T||^2 (B = Xt, ncols = n);
+// Cov quadratic: sum_{j,k in A_i} Delta_ij S_jk Delta_ik (B = S).
+hipError_t launch_trial(const Cand& A, int64_t p, double tau0, int m, double lam1, int variant,
+                        const void* B, int bstore, int64_t ldb, int64_t ncols, double* part,
+                        const struct DevState* st, hipStream_t stream);
+
+// Deterministic FP64 column sums: in[c * rows + r] -> out[c], c < ncol.
+hipError_t launch_colsum(const double* in, int64_t rows, int ncol, double* out,
+                         hipStream_t stream);
+
+// Decision: given per-q sums (sum[q*4 + t]), picks the first passing q
+// (or the forced one) and writes the state.
+hipError_t launch_decide(const double* sums, int m, double tau0, int q_base, double lam2,
+                         int variant, double inv_n, int forced_q, DevState* st,
+                         hipStream_t stream);
+
+// Emission: new CSR from A at the chosen step (state->accepted_q).
+hipError_t launch_emit_count(const Cand& A, int64_t p, double lam1, const DevState* st,
+                             int64_t* cnt, hipStream_t stream);
+hipError_t launch_emit_fill(const Cand& A, int64_t p, double lam1, const DevState* st,
+                            const Csr& out, hipStream_t stream);
+
+// Objective partials of a CSR iterate.  part[t * p + row]: t = 0 sum of log
+// of the diagonal, 1 sum of squares, 2 off-diagonal sum of |v|, 3 sum of
+// W_ij * omega_ij over the stored entries (only if W non-null).
+hipError_t launch_obj_parts(const Csr& om, int64_t p, const void* W, int wstore, int64_t ldw,
+                            double* part, const int* gate, hipStream_t stream);
+
+// Identity CSR (omega = I) into `om`.
+hipError_t launch_identity(const Csr& om, int64_t p, hipStream_t stream);
+
+// Symmetrise a dense square matrix in place: M = (W + W^T)/2.
+hipError_t launch_symmetrize(void* W, int store, int64_t p, int64_t ld, const int* gate,
+                             hipStream_t stream);
+
+// Differentiation form.
+hipError_t launch_sddmm_grad(const Csr& om, int64_t p, const void* Yt, const void* Xt,
+                             int store, int64_t ld, int64_t n, double lam2, void* out,
+                             int out_f64, hipStream_t stream);
+hipError_t launch_gather_dense_grad(const void* M, int mstore, int64_t ldm, const Csr& om,
+                                    int64_t p, double lam2, void* out, int out_f64,
+                                    hipStream_t stream);
+hipError_t launch_transpose_out(const void* Yt, int store, int64_t p, int64_t n, int64_t ld,
+                                double scale, void* out, int out_f64, hipStream_t stream);
+hipError_t launch_csr_validate(const int64_t* rowptr, const int32_t* col, const void* val,
+                               int val_f64, int64_t p, int64_t nnz, int* flags,
+                               hipStream_t stream);
+hipError_t launch_csr_import(const int32_t* col, const void* val, int val_f64, int64_t nnz,
+                             int32_t* col_out, double* val_out, hipStream_t stream);
+hipError_t launch_csr_export(const double* val, int64_t nnz, void* out, int out_f64,
+                             hipStream_t stream);
+
+// Device-side solver state (one per handle, in device memory).
+struct DevState {
+    double f, F;            // at the current iterate
+    double sums[16 * 4];    // per-q trial sums of the last batch
+    double tau;             // accepted step size
+    double lhs, rhs, dd;    // test terms at the accepted step
+    double obj[5];          // objective sums at the last evaluated iterate:
+                            // log-diagonal, sum of squares, off-diagonal |.|,
+                            // sum W o Omega (Cov), ||Y||^2 (Obs)
+    int accepted_q;         // -1: none passed yet in this iteration
+    int accepted;           // 1 once a step is accepted (gate of the accept kernels)
+    int nonpos;             // forced step leaves the domain
+    int overflow;           // candidate capacity exceeded
+};
+
+}  // namespace concord

@@ -1,0 +1,1103 @@
+// Sparse and streaming kernels of the proximal-gradient iteration.
+//
+// Layouts (all device memory):
+//   Omega      CSR: rowptr int64[p+1], col int32 (sorted per row, both
+//              triangles, diagonal always stored), val double.
+//   dense      row-major, rows padded with zeros; a "chunk" is 16 bytes:
+//              2 doubles (ST_F64), 4 floats (ST_F32) or 4 packed bf16 hi/lo
+//              pairs (ST_B16P, value = hi + lo in FP32).
+//   candidates CSR-like (rowptr, col, omega, grad) of the set A that can be
+//              nonzero after this iteration's prox step.
+//
+// One 64-wide wavefront owns one row in every row kernel; compaction is by
+// wavefront ballot + popcount prefix, so every emitted row stays sorted.
+// Every FP64 reduction is done in a fixed order (lane-local sequential sums,
+// then a fixed xor-butterfly, then fixed-order column sums), so results are
+// bitwise reproducible run to run.
+#include "internal.h"
+
+namespace concord {
+namespace {
+
+constexpr int NT = 256;
+constexpr int WPB = NT / 64;   // waves (rows) per block
+
+__device__ inline int64_t uni(int64_t x) {
+    return (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((int)(x >> 32)) << 32) |
+                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(x & 0xffffffff)));
+}
+__device__ inline int lane_id() { return threadIdx.x & 63; }
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline uint64_t lanemask_lt() {
+    const int l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+__device__ inline uint16_t f2bf_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf2f(uint32_t h16) { return __uint_as_float(h16 << 16); }
+
+// ---- chunk loaders ----------------------------------------------------------
+template <int S> struct Chunk;
+template <> struct Chunk<ST_F64> {
+    static constexpr int V = 2;
+    typedef double T;
+    __device__ static void load(const void* b, int64_t idx, T (&v)[V]) {
+        double2 d = *(const double2*)((const double*)b + idx);
+        v[0] = d.x; v[1] = d.y;
+    }
+    __device__ static T one(const void* b, int64_t idx) { return ((const double*)b)[idx]; }
+};
+template <> struct Chunk<ST_F32> {
+    static constexpr int V = 4;
+    typedef float T;
+    __device__ static void load(const void* b, int64_t idx, T (&v)[V]) {
+        float4 d = *(const float4*)((const float*)b + idx);
+        v[0] = d.x; v[1] = d.y; v[2] = d.z; v[3] = d.w;
+    }
+    __device__ static T one(const void* b, int64_t idx) { return ((const float*)b)[idx]; }
+};
+template <> struct Chunk<ST_B16P> {
+    static constexpr int V = 4;
+    typedef float T;
+    __device__ static T cv(uint32_t u) { return bf2f(u & 0xffffu) + bf2f(u >> 16); }
+    __device__ static void load(const void* b, int64_t idx, T (&v)[V]) {
+        uint4 d = *(const uint4*)((const uint32_t*)b + idx);
+        v[0] = cv(d.x); v[1] = cv(d.y); v[2] = cv(d.z); v[3] = cv(d.w);
+    }
+    __device__ static T one(const void* b, int64_t idx) { return cv(((const uint32_t*)b)[idx]); }
+};
+
+template <int S> __device__ inline double load_one_d(const void* b, int64_t idx) {
+    return (double)Chunk<S>::one(b, idx);
+}
+
+// ---- SpMM: C = Omega B ------------------------------------------------------
+// grid: x = ceil(p / 4) row blocks, y = column chunks of 64*V (chunk-major
+// dispatch keeps one column slab of B hot in L2/MALL across all rows).
+template <int BS, int CS>
+__global__ void __launch_bounds__(NT)
+spmm_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+            const double* __restrict__ val, int64_t p, const void* __restrict__ B, int64_t ldb,
+            int64_t ncols, void* __restrict__ C, int64_t ldc, uint16_t* __restrict__ hi,
+            uint16_t* __restrict__ lo, double* __restrict__ sq_part, const int* gate) {
+    if (gate && *gate == 0) return;
+    typedef Chunk<BS> Ch;
+    typedef typename Ch::T T;
+    constexpr int V = Ch::V;
+    const int64_t row = uni((int64_t)blockIdx.x * WPB + (threadIdx.x >> 6));
+    if (row >= p) return;
+    const int lane = lane_id();
+    const int64_t c0 = (int64_t)blockIdx.y * 64 * V + lane * V;
+    const bool active = c0 < ncols;
+    T acc[V];
+#pragma unroll
+    for (int t = 0; t < V; ++t) acc[t] = 0;
+    const int64_t s = rowptr[row], e = rowptr[row + 1];
+    if (active) {
+        int64_t k = s;
+        for (; k + 4 <= e; k += 4) {
+            T b0[V], b1[V], b2[V], b3[V];
+            const int64_t j0 = col[k], j1 = col[k + 1], j2 = col[k + 2], j3 = col[k + 3];
+            Ch::load(B, j0 * ldb + c0, b0);
+            Ch::load(B, j1 * ldb + c0, b1);
+            Ch::load(B, j2 * ldb + c0, b2);
+            Ch::load(B, j3 * ldb + c0, b3);
+            const T v0 = (T)val[k], v1 = (T)val[k + 1], v2 = (T)val[k + 2], v3 = (T)val[k + 3];
+#pragma unroll
+            for (int t = 0; t < V; ++t) {
+                acc[t] = fma(v0, b0[t], acc[t]);
+                acc[t] = fma(v1, b1[t], acc[t]);
+                acc[t] = fma(v2, b2[t], acc[t]);
+                acc[t] = fma(v3, b3[t], acc[t]);
+            }
+        }
+        for (; k < e; ++k) {
+            T b0[V];
+            Ch::load(B, (int64_t)col[k] * ldb + c0, b0);
+            const T v0 = (T)val[k];
+#pragma unroll
+            for (int t = 0; t < V; ++t) acc[t] = fma(v0, b0[t], acc[t]);
+        }
+    }
+    double sq = 0.0;
+    if (active) {
+        if (C) {
+            if (CS == ST_F64) {
+                double* o = (double*)C + row * ldc + c0;
+#pragma unroll
+                for (int t = 0; t < V; ++t) o[t] = (double)acc[t];
+            } else {
+                float* o = (float*)C + row * ldc + c0;
+#pragma unroll
+                for (int t = 0; t < V; ++t) o[t] = (float)acc[t];
+            }
+        }
+        if (hi) {
+            uint16_t h[V], l[V];
+#pragma unroll
+            for (int t = 0; t < V; ++t) {
+                const float x = (float)acc[t];
+                h[t] = f2bf_rne(x);
+                l[t] = f2bf_rne(x - bf2f(h[t]));
+            }
+            if (V == 4) {
+                *(uint2*)(hi + row * ldc + c0) =
+                    make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+                *(uint2*)(lo + row * ldc + c0) =
+                    make_uint2((uint32_t)l[0] | ((uint32_t)l[1] << 16), (uint32_t)l[2] | ((uint32_t)l[3] << 16));
+            } else {
+#pragma unroll
+                for (int t = 0; t < V; ++t) { hi[row * ldc + c0 + t] = h[t]; lo[row * ldc + c0 + t] = l[t]; }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < V; ++t) sq += (double)acc[t] * (double)acc[t];
+    }
+    if (sq_part) {
+        sq = wave_sum(sq);
+        if (lane == 0) sq_part[(int64_t)blockIdx.y * p + row] = sq;
+    }
+}
+
+// ---- candidate set ----------------------------------------------------------
+// Per wave: an LDS bitmap of supp(Omega_i) (p bits).
+template <int MS>
+__device__ inline void cand_load_group(const void* M, int64_t base, int64_t c, int64_t p,
+                                       double (&m)[Chunk<MS>::V]) {
+    typedef Chunk<MS> Ch;
+    constexpr int V = Ch::V;
+    typename Ch::T v[V];
+    if (c < p) {
+        // dense rows are padded to a multiple of 64 columns; chunks never straddle
+        Ch::load(M, base + c, v);
+#pragma unroll
+        for (int t = 0; t < V; ++t) m[t] = (double)v[t];
+    } else {
+#pragma unroll
+        for (int t = 0; t < V; ++t) m[t] = 0.0;
+    }
+}
+
+__device__ inline void build_supp_bits(uint32_t* bits, int64_t nw32, const int32_t* col, int64_t s,
+                                       int64_t e) {
+    const int lane = lane_id();
+    for (int64_t w = lane; w < nw32; w += 64) bits[w] = 0u;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    for (int64_t k = s + lane; k < e; k += 64) {
+        const int32_t c = col[k];
+        atomicOr(&bits[c >> 5], 1u << (c & 31));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// in-bit for lane's V columns starting at c (c multiple of V)
+template <int V>
+__device__ inline uint32_t supp_nibble(const uint32_t* bits, int64_t c) {
+    const uint32_t w = bits[c >> 5];
+    return (w >> (c & 31)) & ((1u << V) - 1u);
+}
+
+template <int MS>
+__global__ void __launch_bounds__(NT)
+cand_count_kernel(const void* __restrict__ M, int64_t ldm, const int64_t* __restrict__ rowptr,
+                  const int32_t* __restrict__ col, int64_t p, double lam1,
+                  uint64_t* __restrict__ bitmap, int64_t nwords, int64_t* __restrict__ cnt) {
+    typedef Chunk<MS> Ch;
+    constexpr int V = Ch::V;
+    constexpr int LPW = 64 / V;   // lanes per 64-bit word
+    extern __shared__ uint32_t sbits[];
+    const int64_t nw32 = nwords * 2;
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
+    if (row >= p) return;
+    uint32_t* bits = sbits + wave * nw32;
+    build_supp_bits(bits, nw32, col, rowptr[row], rowptr[row + 1]);
+    const int64_t base = row * ldm;
+    int64_t total = 0;
+    const int64_t step = 64 * V;
+    for (int64_t g = 0; g < p; g += step) {
+        const int64_t c = g + lane * V;
+        double m[V];
+        cand_load_group<MS>(M, base, c, p, m);
+        uint32_t nib = c < p ? supp_nibble<V>(bits, c) : 0u;
+#pragma unroll
+        for (int t = 0; t < V; ++t) {
+            const int64_t j = c + t;
+            if (j < p && (j == row || fabs(m[t]) > lam1)) nib |= 1u << t;
+        }
+        // assemble 64-bit words: lane l contributes V bits at V*(l % LPW)
+        uint64_t w = (uint64_t)nib << (V * (lane % LPW));
+#pragma unroll
+        for (int o = LPW / 2; o >= 1; o >>= 1) w |= __shfl_xor(w, o, 64);
+        if ((lane % LPW) == 0) {
+            const int64_t wi = g / 64 + lane / LPW;
+            if (wi < nwords) bitmap[row * nwords + wi] = w;
+        }
+        total += __popc(nib);
+    }
+    // total over lanes
+    double tt = (double)total;
+    tt = wave_sum(tt);
+    if (lane == 0) cnt[row] = (int64_t)tt;
+}
+
+template <int MS>
+__global__ void __launch_bounds__(NT)
+cand_fill_kernel(const void* __restrict__ M, int64_t ldm, const int64_t* __restrict__ rowptr,
+                 const int32_t* __restrict__ col, const double* __restrict__ val, int64_t p,
+                 double lam2, const uint64_t* __restrict__ bitmap, int64_t nwords,
+                 const int64_t* __restrict__ arow, int32_t* __restrict__ acol,
+                 double* __restrict__ aom, double* __restrict__ agr, const int* overflow) {
+    if (*overflow) return;
+    typedef Chunk<MS> Ch;
+    constexpr int V = Ch::V;
+    constexpr int LPW = 64 / V;
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
+    if (row >= p) return;
+    const int64_t s = rowptr[row], e = rowptr[row + 1];
+    int64_t out = arow[row];
+    const int64_t base = row * ldm;
+    const int64_t step = 64 * V;
+    const int wpg = V;   // 64-bit words per group of 64*V columns
+    for (int64_t g = 0; g < p; g += step) {
+        const int64_t w0 = g / 64;
+        uint64_t words[V];
+        int before = 0;
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+            words[q] = (w0 + q < nwords) ? bitmap[row * nwords + w0 + q] : 0ull;
+        }
+        const int myw = lane / LPW;
+        int grp_total = 0;
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+            const int pc = __popcll(words[q]);
+            if (q < myw) before += pc;
+            grp_total += pc;
+        }
+        (void)wpg;
+        const int sh = V * (lane % LPW);
+        const uint32_t nib = (uint32_t)(words[myw] >> sh) & ((1u << V) - 1u);
+        before += __popcll(words[myw] & ((sh == 0) ? 0ull : (~0ull >> (64 - sh))));
+        if (nib) {
+            const int64_t c = g + lane * V;
+            double m[V];
+            cand_load_group<MS>(M, base, c, p, m);
+            int k = 0;
+#pragma unroll
+            for (int t = 0; t < V; ++t) {
+                if (!((nib >> t) & 1u)) continue;
+                const int64_t j = c + t;
+                // omega_ij: binary search of the sorted CSR row
+                double om = 0.0;
+                int64_t lo_ = s, hi_ = e;
+                while (lo_ < hi_) {
+                    const int64_t mid = (lo_ + hi_) >> 1;
+                    if (col[mid] < j) lo_ = mid + 1; else hi_ = mid;
+                }
+                if (lo_ < e && col[lo_] == j) om = val[lo_];
+                double gval = m[t] + lam2 * om;
+                if (j == row) gval -= 1.0 / om;
+                const int64_t pos = out + before + k;
+                acol[pos] = (int32_t)j;
+                aom[pos] = om;
+                agr[pos] = gval;
+                ++k;
+            }
+        }
+        out += grp_total;
+    }
+}
+
+// ---- scan ---------------------------------------------------------------------
+__global__ void __launch_bounds__(1024)
+scan_kernel(const int64_t* __restrict__ cnt, int64_t p, int64_t* __restrict__ out, int64_t cap,
+            int* overflow) {
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (p + 1023) / 1024;
+    const int64_t a = t * per, b = a + per < p ? a + per : p;
+    int64_t s = 0;
+    for (int64_t i = a; i < b; ++i) s += cnt[i];
+    part[t] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        int64_t v = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t run = part[t] - s;
+    for (int64_t i = a; i < b; ++i) { out[i] = run; run += cnt[i]; }
+    if (t == 1023) {
+        out[p] = part[1023];
+        if (overflow) *overflow = part[1023] > cap ? 1 : 0;
+    }
+}
+
+// ---- trial evaluation ---------------------------------------------------------
+constexpr int MAXQ = 8;
+
+__device__ inline double prox_one(double om, double g, double tau, double thr, bool diag) {
+    const double z = om - tau * g;
+    if (diag) return z;
+    return z > thr ? z - thr : (z < -thr ? z + thr : 0.0);
+}
+
+template <int BS, bool OBS>
+__global__ void __launch_bounds__(NT)
+trial_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
+             const double* __restrict__ aom, const double* __restrict__ agr, int64_t p,
+             double tau0, int m, double lam1, const void* __restrict__ B, int64_t ldb,
+             int64_t ncols, double* __restrict__ part, const DevState* st) {
+    if (st->overflow || st->accepted_q >= 0) return;   // capacity exceeded or already decided
+    typedef Chunk<BS> Ch;
+    typedef typename Ch::T T;
+    constexpr int V = Ch::V;
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
+    if (row >= p) return;
+    const int64_t s = arow[row], e = arow[row + 1];
+    double slog[MAXQ], sdd[MAXQ], squad[MAXQ], snp[MAXQ];
+#pragma unroll
+    for (int q = 0; q < MAXQ; ++q) { slog[q] = 0; sdd[q] = 0; squad[q] = 0; snp[q] = 0; }
+
+    // elementwise terms (lanes over entries)
+    for (int64_t k = s + lane; k < e; k += 64) {
+        const int64_t j = acol[k];
+        const double om = aom[k], g = agr[k];
+        const bool diag = j == row;
+        double tau = tau0;
+#pragma unroll
+        for (int q = 0; q < MAXQ; ++q) {
+            if (q < m) {
+                const double wp = prox_one(om, g, tau, tau * lam1, diag);
+                const double d = wp - om;
+                sdd[q] += d * d;
+                if (diag) {
+                    if (wp <= 0.0) snp[q] += 1.0;
+                    else {
+                        const double x = d / om;
+                        slog[q] += x - log1p(x);
+                    }
+                }
+            }
+            tau *= 0.5;
+        }
+    }
+    // quadratic term
+    if (OBS) {
+        // ||Delta_i X^T||^2 over n columns: lanes over columns, loop over entries
+        for (int64_t c0 = 0; c0 < ncols; c0 += 64 * V) {
+            const int64_t c = c0 + lane * V;
+            const bool act = c < ncols;
+            T acc[MAXQ][V];
+#pragma unroll
+            for (int q = 0; q < MAXQ; ++q)
+#pragma unroll
+                for (int t = 0; t < V; ++t) acc[q][t] = 0;
+            for (int64_t k = s; k < e; ++k) {
+                const int64_t j = acol[k];
+                const double om = aom[k], g = agr[k];
+                const bool diag = j == row;
+                T b[V];
+                if (act) Ch::load(B, j * ldb + c, b);
+                else {
+#pragma unroll
+                    for (int t = 0; t < V; ++t) b[t] = 0;
+                }
+                double tau = tau0;
+#pragma unroll
+                for (int q = 0; q < MAXQ; ++q) {
+                    if (q < m) {
+                        const T d = (T)(prox_one(om, g, tau, tau * lam1, diag) - om);
+#pragma unroll
+                        for (int t = 0; t < V; ++t) acc[q][t] = fma(d, b[t], acc[q][t]);
+                    }
+                    tau *= 0.5;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < MAXQ; ++q) {
+                if (q < m) {
+#pragma unroll
+                    for (int t = 0; t < V; ++t) squad[q] += (double)acc[q][t] * (double)acc[q][t];
+                }
+            }
+        }
+    } else {
+        // sum_{a,b in A_i} Delta_a S[j_a, j_b] Delta_b : lanes over b, loop over a
+        for (int64_t kb = s + lane; kb < e; kb += 64) {
+            const int64_t jb = acol[kb];
+            const double omb = aom[kb], gb = agr[kb];
+            const bool diagb = jb == row;
+            double db[MAXQ];
+            {
+                double tau = tau0;
+#pragma unroll
+                for (int q = 0; q < MAXQ; ++q) {
+                    db[q] = q < m ? prox_one(omb, gb, tau, tau * lam1, diagb) - omb : 0.0;
+                    tau *= 0.5;
+                }
+            }
+            for (int64_t ka = s; ka < e; ++ka) {
+                const int64_t ja = acol[ka];
+                const double oma = aom[ka], ga = agr[ka];
+                const bool diaga = ja == row;
+                const double sab = load_one_d<BS>(B, ja * ldb + jb);
+                double tau = tau0;
+#pragma unroll
+                for (int q = 0; q < MAXQ; ++q) {
+                    if (q < m) {
+                        const double da = prox_one(oma, ga, tau, tau * lam1, diaga) - oma;
+                        squad[q] += da * sab * db[q];
+                    }
+                    tau *= 0.5;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < MAXQ; ++q) {
+        if (q < m) {
+            const double a = wave_sum(slog[q]);
+            const double b2 = wave_sum(sdd[q]);
+            const double c2 = wave_sum(squad[q]);
+            const double d2 = wave_sum(snp[q]);
+            if (lane == 0) {
+                part[(int64_t)(q * 4 + 0) * p + row] = a;
+                part[(int64_t)(q * 4 + 1) * p + row] = b2;
+                part[(int64_t)(q * 4 + 2) * p + row] = c2;
+                part[(int64_t)(q * 4 + 3) * p + row] = d2;
+            }
+        }
+    }
+}
+
+// ---- column sums -----------------------------------------------------------------
+__global__ void __launch_bounds__(NT)
+colsum_kernel(const double* __restrict__ in, int64_t rows, double* __restrict__ out) {
+    __shared__ double red[NT];
+    const int c = blockIdx.x, t = threadIdx.x;
+    const double* a = in + (int64_t)c * rows;
+    double s = 0.0;
+    for (int64_t i = t; i < rows; i += NT) s += a[i];
+    red[t] = s;
+    __syncthreads();
+    for (int o = NT / 2; o >= 1; o >>= 1) {
+        if (t < o) red[t] += red[t + o];
+        __syncthreads();
+    }
+    if (t == 0) out[c] = red[0];
+}
+
+// ---- decision ----------------------------------------------------------------
+__global__ void decide_kernel(const double* __restrict__ sums, int m, double tau0, int q_base,
+                              double lam2, double inv_n, int forced_q, DevState* st) {
+    if (threadIdx.x != 0) return;
+    if (st->overflow || st->accepted_q >= 0) return;   // capacity exceeded / decided earlier
+    double tau = tau0;
+    for (int q = 0; q < m; ++q) {
+        const double slog = sums[q * 4 + 0], dd = sums[q * 4 + 1], quad = sums[q * 4 + 2],
+                     np = sums[q * 4 + 3];
+        const double lhs = slog + 0.5 * quad * inv_n + 0.5 * lam2 * dd;
+        const double rhs = dd / (2.0 * tau);
+        for (int t = 0; t < 4; ++t) st->sums[q * 4 + t] = sums[q * 4 + t];
+        bool ok;
+        if (forced_q >= 0) {
+            ok = (q_base + q) == forced_q;
+            if (ok && np > 0.0) st->nonpos = 1;
+        } else {
+            ok = np == 0.0 && lhs <= rhs;
+        }
+        if (ok) {
+            st->accepted = st->nonpos ? 0 : 1;
+            st->accepted_q = q_base + q;
+            st->tau = tau;
+            st->lhs = lhs;
+            st->rhs = rhs;
+            st->dd = dd;
+            return;
+        }
+        tau *= 0.5;
+    }
+}
+
+// ---- emission ----------------------------------------------------------------
+__global__ void __launch_bounds__(NT)
+emit_count_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
+                  const double* __restrict__ aom, const double* __restrict__ agr, int64_t p,
+                  double lam1, const DevState* st, int64_t* __restrict__ cnt) {
+    if (st->accepted_q < 0 || st->nonpos) return;
+    const double tau = st->tau;
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
+    if (row >= p) return;
+    const int64_t s = arow[row], e = arow[row + 1];
+    int c = 0;
+    for (int64_t k = s + lane; k < e; k += 64) {
+        const bool diag = acol[k] == row;
+        const double wp = prox_one(aom[k], agr[k], tau, tau * lam1, diag);
+        c += (wp != 0.0 || diag) ? 1 : 0;
+    }
+    double t = wave_sum((double)c);
+    if (lane == 0) cnt[row] = (int64_t)t;
+}
+
+__global__ void __launch_bounds__(NT)
+emit_fill_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
+                 const double* __restrict__ aom, const double* __restrict__ agr, int64_t p,
+                 double lam1, const DevState* st, const int64_t* __restrict__ orow,
+                 int32_t* __restrict__ ocol, double* __restrict__ oval) {
+    if (st->accepted_q < 0 || st->nonpos) return;
+    const double tau = st->tau;
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
+    if (row >= p) return;
+    const int64_t s = arow[row], e = arow[row + 1];
+    int64_t out = orow[row];
+    for (int64_t k0 = s; k0 < e; k0 += 64) {
+        const int64_t k = k0 + lane;
+        bool keep = false;
+        double wp = 0.0;
+        int32_t j = 0;
+        if (k < e) {
+            j = acol[k];
+            const bool diag = j == row;
+            wp = prox_one(aom[k], agr[k], tau, tau * lam1, diag);
+            keep = wp != 0.0 || diag;
+        }
+        const uint64_t mask = __ballot(keep);
+        if (keep) {
+            const int64_t pos = out + __popcll(mask & lanemask_lt());
+            ocol[pos] = j;
+            oval[pos] = wp;
+        }
+        out += __popcll(mask);
+    }
+}
+
+// ---- objective partials --------------------------------------------------------
+template <int WS>
+__global__ void __launch_bounds__(NT)
+obj_parts_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                 const double* __restrict__ val, int64_t p, const void* __restrict__ W,
+                 int64_t ldw, double* __restrict__ part, const int* gate) {
+    if (gate && *gate == 0) return;
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
+    if (row >= p) return;
+    const int64_t s = rowptr[row], e = rowptr[row + 1];
+    double lg = 0, sq = 0, l1 = 0, wv = 0;
+    for (int64_t k = s + lane; k < e; k += 64) {
+        const int64_t j = col[k];
+        const double v = val[k];
+        sq += v * v;
+        if (j == row) lg += log(v);
+        else l1 += fabs(v);
+        if (W) wv += load_one_d<WS>(W, row * ldw + j) * v;
+    }
+    lg = wave_sum(lg); sq = wave_sum(sq); l1 = wave_sum(l1); wv = wave_sum(wv);
+    if (lane == 0) {
+        part[0 * p + row] = lg;
+        part[1 * p + row] = sq;
+        part[2 * p + row] = l1;
+        part[3 * p + row] = wv;
+    }
+}
+
+__global__ void identity_kernel(int64_t* rowptr, int32_t* col, double* val, int64_t p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < p) { rowptr[i] = i; col[i] = (int32_t)i; val[i] = 1.0; }
+    if (i == p) rowptr[p] = p;
+}
+
+// ---- symmetrise (Cov): M = (W + W^T) / 2, tile pairs through LDS ----------------
+template <int S>
+__global__ void __launch_bounds__(NT)
+symmetrize_kernel(void* W, int64_t p, int64_t ld, int T, const int* gate) {
+    if (gate && *gate == 0) return;
+    typedef typename Chunk<S>::T E;
+    __shared__ E a[64][65], b[64][65];
+    // tile pair from linear upper-triangle index
+    int t = blockIdx.x;
+    int I = 0;
+    while (t >= T - I) { t -= T - I; ++I; }
+    const int J = I + t;
+    E* M = (E*)W;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) {
+        const int64_t gi = (int64_t)I * 64 + r, gj = (int64_t)J * 64 + tx;
+        a[r][tx] = (gi < p && gj < p) ? M[gi * ld + gj] : (E)0;
+        const int64_t hi_ = (int64_t)J * 64 + r, hj = (int64_t)I * 64 + tx;
+        b[r][tx] = (hi_ < p && hj < p) ? M[hi_ * ld + hj] : (E)0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int64_t gi = (int64_t)I * 64 + r, gj = (int64_t)J * 64 + tx;
+        if (gi < p && gj < p) M[gi * ld + gj] = (E)0.5 * (a[r][tx] + b[tx][r]);
+        const int64_t hi_ = (int64_t)J * 64 + r, hj = (int64_t)I * 64 + tx;
+        if (I != J && hi_ < p && hj < p) M[hi_ * ld + hj] = (E)0.5 * (b[r][tx] + a[tx][r]);
+    }
+}
+
+// ---- ingest ----------------------------------------------------------------------
+template <typename In, typename Out>
+__global__ void __launch_bounds__(NT)
+transpose_in_kernel(const In* __restrict__ X, int64_t rows, int64_t cols, int64_t ld,
+                    Out* __restrict__ Xt, int64_t ldo, uint16_t* __restrict__ hi,
+                    uint16_t* __restrict__ lo) {
+    __shared__ Out tile[64][65];
+    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) {
+        const int64_t gr = r0 + r, gc = c0 + tx;
+        tile[r][tx] = (gr < rows && gc < cols) ? (Out)X[gr * ld + gc] : (Out)0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int64_t oc = c0 + r, orr = r0 + tx;   // output row = input col
+        if (oc < cols && orr < rows) {
+            const Out v = tile[tx][r];
+            Xt[oc * ldo + orr] = v;
+            if (hi) {
+                const float x = (float)v;
+                const uint16_t h = f2bf_rne(x);
+                hi[oc * ldo + orr] = h;
+                lo[oc * ldo + orr] = f2bf_rne(x - bf2f(h));
+            }
+        }
+    }
+}
+
+template <typename In>
+__global__ void copy_square_kernel(const In* __restrict__ S, int64_t p, int64_t ld, void* out,
+                                   int store, int64_t ldo) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= p * p) return;
+    const int64_t i = idx / p, j = idx % p;
+    const double v = (double)S[i * ld + j];
+    if (store == ST_F64) ((double*)out)[i * ldo + j] = v;
+    else if (store == ST_F32) ((float*)out)[i * ldo + j] = (float)v;
+    else {
+        const float x = (float)v;
+        const uint16_t h = f2bf_rne(x);
+        const uint16_t l = f2bf_rne(x - bf2f(h));
+        ((uint32_t*)out)[i * ldo + j] = (uint32_t)h | ((uint32_t)l << 16);
+    }
+}
+
+template <typename In>
+__global__ void check_finite_kernel(const In* __restrict__ A, int64_t rows, int64_t cols,
+                                    int64_t ld, int* flag) {
+    const int64_t n = rows * cols;
+    bool bad = false;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const double v = (double)A[(idx / cols) * ld + idx % cols];
+        if (!isfinite(v)) bad = true;
+    }
+    if (bad) *flag = 1;
+}
+
+// ---- differentiation form ------------------------------------------------------
+// G_ij on the stored entries: ( <Y_i, Xt_j> + <Y_j, Xt_i> ) / (2n) + lam2 w_ij - [i==j]/w_ii
+template <int S>
+__global__ void __launch_bounds__(NT)
+sddmm_grad_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                  const double* __restrict__ val, int64_t p, const void* __restrict__ Y,
+                  const void* __restrict__ Xt, int64_t ld, int64_t n, double lam2, void* out,
+                  int out_f64) {
+    typedef Chunk<S> Ch;
+    typedef typename Ch::T T;
+    constexpr int V = Ch::V;
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
+    if (row >= p) return;
+    const int64_t s = rowptr[row], e = rowptr[row + 1];
+    double wii = 0.0;
+    for (int64_t k = s; k < e; ++k) {
+        const int64_t j = col[k];
+        double acc = 0.0;
+        for (int64_t c = lane * V; c < n; c += 64 * V) {
+            T yi[V], xj[V], yj[V], xi[V];
+            Ch::load(Y, row * ld + c, yi);
+            Ch::load(Xt, j * ld + c, xj);
+            Ch::load(Y, j * ld + c, yj);
+            Ch::load(Xt, row * ld + c, xi);
+            T a = 0;
+#pragma unroll
+            for (int t = 0; t < V; ++t) a += yi[t] * xj[t] + yj[t] * xi[t];
+            acc += (double)a;
+        }
+        acc = wave_sum(acc);
+        const double v = val[k];
+        double g = acc / (2.0 * (double)n) + lam2 * v;
+        if (j == row) { wii = v; g -= 1.0 / v; }
+        if (lane == 0) {
+            if (out_f64) ((double*)out)[k] = g;
+            else ((float*)out)[k] = (float)g;
+        }
+    }
+    (void)wii;
+}
+
+template <int S>
+__global__ void __launch_bounds__(NT)
+dense_grad_kernel(const void* __restrict__ M, int64_t ldm, const int64_t* __restrict__ rowptr,
+                  const int32_t* __restrict__ col, const double* __restrict__ val, int64_t p,
+                  double lam2, void* out, int out_f64) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= p * p) return;
+    const int64_t i = idx / p, j = idx % p;
+    double g = load_one_d<S>(M, i * ldm + j);
+    // add lam2 * omega_ij and the diagonal term
+    const int64_t s = rowptr[i], e = rowptr[i + 1];
+    int64_t lo_ = s, hi_ = e;
+    while (lo_ < hi_) {
+        const int64_t mid = (lo_ + hi_) >> 1;
+        if (col[mid] < j) lo_ = mid + 1; else hi_ = mid;
+    }
+    if (lo_ < e && col[lo_] == j) {
+        const double v = val[lo_];
+        g += lam2 * v;
+        if (i == j) g -= 1.0 / v;
+    }
+    if (out_f64) ((double*)out)[idx] = g;
+    else ((float*)out)[idx] = (float)g;
+}
+
+template <typename E>
+__global__ void __launch_bounds__(NT)
+transpose_out_kernel(const E* __restrict__ A, int64_t p, int64_t n, int64_t ld, double scale,
+                     void* out, int out_f64) {
+    // A: p x n (ld) -> out: n x p, scaled
+    __shared__ double tile[64][65];
+    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) {
+        const int64_t gr = r0 + r, gc = c0 + tx;
+        tile[r][tx] = (gr < p && gc < n) ? (double)A[gr * ld + gc] * scale : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int64_t orow = c0 + r, ocol = r0 + tx;
+        if (orow < n && ocol < p) {
+            if (out_f64) ((double*)out)[orow * p + ocol] = tile[tx][r];
+            else ((float*)out)[orow * p + ocol] = (float)tile[tx][r];
+        }
+    }
+}
+
+// flags[0]: structural error, flags[1]: non-positive diagonal, flags[2]: non-finite
+template <typename VT>
+__global__ void csr_validate_kernel(const int64_t* rowptr, const int32_t* col, const VT* val,
+                                    int64_t p, int64_t nnz, int* flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p) return;
+    const int64_t s = rowptr[i], e = rowptr[i + 1];
+    if (i == 0 && s != 0) flags[0] = 1;
+    if (i == p - 1 && e != nnz) flags[0] = 1;
+    if (s < 0 || e < s || e > nnz) { flags[0] = 1; return; }
+    bool has_diag = false;
+    for (int64_t k = s; k < e; ++k) {
+        const int32_t c = col[k];
+        if (c < 0 || c >= p || (k > s && col[k - 1] >= c)) flags[0] = 1;
+        const double v = (double)val[k];
+        if (!isfinite(v)) flags[2] = 1;
+        if (c == i) { has_diag = true; if (!(v > 0.0)) flags[1] = 1; }
+    }
+    if (!has_diag) flags[0] = 1;
+}
+
+template <typename VT>
+__global__ void csr_import_kernel(const int32_t* col, const VT* val, int64_t nnz, int32_t* co,
+                                  double* vo) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nnz) { co[k] = col[k]; vo[k] = (double)val[k]; }
+}
+
+__global__ void csr_export_kernel(const double* val, int64_t nnz, void* out, int out_f64) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nnz) {
+        if (out_f64) ((double*)out)[k] = val[k];
+        else ((float*)out)[k] = (float)val[k];
+    }
+}
+
+inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+// ================================ launchers ======================================
+
+int spmm_nchunks(int bstore, int64_t ncols) {
+    const int V = bstore == ST_F64 ? 2 : 4;
+    return (int)((ncols + 64 * V - 1) / (64 * V));
+}
+
+hipError_t launch_spmm(const Csr& A, int64_t p, const void* B, int bstore, int64_t ldb,
+                       int64_t ncols, void* C, int cstore, int64_t ldc, uint16_t* hi,
+                       uint16_t* lo, double* sq_part, const int* gate, hipStream_t stream) {
+    if (p == 0) return hipSuccess;
+    const int nch = spmm_nchunks(bstore, ncols);
+    dim3 grid(blocks_for(p, WPB), nch);
+#define SPMM(BS, CS)                                                                     \
+    hipLaunchKernelGGL((spmm_kernel<BS, CS>), grid, dim3(NT), 0, stream, A.rowptr, A.col, \
+                       A.val, p, B, ldb, ncols, C, ldc, hi, lo, sq_part, gate)
+    if (bstore == ST_F64) SPMM(ST_F64, ST_F64);
+    else if (bstore == ST_F32) {
+        if (cstore == ST_F64) SPMM(ST_F32, ST_F64); else SPMM(ST_F32, ST_F32);
+    } else SPMM(ST_B16P, ST_F32);
+#undef SPMM
+    return hipGetLastError();
+}
+
+hipError_t launch_cand_count(const void* M, int mstore, int64_t ldm, const Csr& om, int64_t p,
+                             double lam1, uint64_t* bitmap, int64_t nwords, int64_t* cnt,
+                             hipStream_t stream) {
+    if (p == 0) return hipSuccess;
+    const size_t lds = (size_t)WPB * nwords * 8;
+    if (mstore == ST_F64)
+        hipLaunchKernelGGL(cand_count_kernel<ST_F64>, dim3(blocks_for(p, WPB)), dim3(NT), lds,
+                           stream, M, ldm, om.rowptr, om.col, p, lam1, bitmap, nwords, cnt);
+    else
+        hipLaunchKernelGGL(cand_count_kernel<ST_F32>, dim3(blocks_for(p, WPB)), dim3(NT), lds,
+                           stream, M, ldm, om.rowptr, om.col, p, lam1, bitmap, nwords, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_cand_fill(const void* M, int mstore, int64_t ldm, const Csr& om, int64_t p,
+                            double lam2, const uint64_t* bitmap, int64_t nwords,
+                            const Cand& A, int64_t cap, const int* overflow,
+                            hipStream_t stream) {
+    (void)cap;
+    if (p == 0) return hipSuccess;
+    if (mstore == ST_F64)
+        hipLaunchKernelGGL(cand_fill_kernel<ST_F64>, dim3(blocks_for(p, WPB)), dim3(NT), 0,
+                           stream, M, ldm, om.rowptr, om.col, om.val, p, lam2, bitmap, nwords,
+                           A.rowptr, A.col, A.omega, A.grad, overflow);
+    else
+        hipLaunchKernelGGL(cand_fill_kernel<ST_F32>, dim3(blocks_for(p, WPB)), dim3(NT), 0,
+                           stream, M, ldm, om.rowptr, om.col, om.val, p, lam2, bitmap, nwords,
+                           A.rowptr, A.col, A.omega, A.grad, overflow);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const int64_t* cnt, int64_t p, int64_t* out, int64_t cap, int* overflow,
+                       hipStream_t stream) {
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, stream, cnt, p, out, cap, overflow);
+    return hipGetLastError();
+}
+
+hipError_t launch_trial(const Cand& A, int64_t p, double tau0, int m, double lam1, int variant,
+                        const void* B, int bstore, int64_t ldb, int64_t ncols, double* part,
+                        const DevState* st, hipStream_t stream) {
+    if (p == 0) return hipSuccess;
+    if (m < 1 || m > MAXQ) return hipErrorInvalidValue;
+    dim3 grid(blocks_for(p, WPB));
+#define TRIAL(BS, OBS)                                                                       \
+    hipLaunchKernelGGL((trial_kernel<BS, OBS>), grid, dim3(NT), 0, stream, A.rowptr, A.col,   \
+                       A.omega, A.grad, p, tau0, m, lam1, B, ldb, ncols, part, st)
+    const bool obs = variant == 1;
+    if (bstore == ST_F64) { if (obs) TRIAL(ST_F64, true); else TRIAL(ST_F64, false); }
+    else if (bstore == ST_F32) { if (obs) TRIAL(ST_F32, true); else TRIAL(ST_F32, false); }
+    else { if (obs) return hipErrorInvalidValue; TRIAL(ST_B16P, false); }
+#undef TRIAL
+    return hipGetLastError();
+}
+
+hipError_t launch_colsum(const double* in, int64_t rows, int ncol, double* out,
+                         hipStream_t stream) {
+    hipLaunchKernelGGL(colsum_kernel, dim3(ncol), dim3(NT), 0, stream, in, rows, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_decide(const double* sums, int m, double tau0, int q_base, double lam2,
+                         int variant, double inv_n, int forced_q, DevState* st,
+                         hipStream_t stream) {
+    (void)variant;
+    hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(64), 0, stream, sums, m, tau0, q_base, lam2,
+                       inv_n, forced_q, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit_count(const Cand& A, int64_t p, double lam1, const DevState* st,
+                             int64_t* cnt, hipStream_t stream) {
+    if (p == 0) return hipSuccess;
+    hipLaunchKernelGGL(emit_count_kernel, dim3(blocks_for(p, WPB)), dim3(NT), 0, stream,
+                       A.rowptr, A.col, A.omega, A.grad, p, lam1, st, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit_fill(const Cand& A, int64_t p, double lam1, const DevState* st,
+                            const Csr& out, hipStream_t stream) {
+    if (p == 0) return hipSuccess;
+    hipLaunchKernelGGL(emit_fill_kernel, dim3(blocks_for(p, WPB)), dim3(NT), 0, stream,
+                       A.rowptr, A.col, A.omega, A.grad, p, lam1, st, out.rowptr, out.col,
+                       out.val);
+    return hipGetLastError();
+}
+
+hipError_t launch_obj_parts(const Csr& om, int64_t p, const void* W, int wstore, int64_t ldw,
+                            double* part, const int* gate, hipStream_t stream) {
+    if (p == 0) return hipSuccess;
+    dim3 grid(blocks_for(p, WPB));
+    if (wstore == ST_F64)
+        hipLaunchKernelGGL(obj_parts_kernel<ST_F64>, grid, dim3(NT), 0, stream, om.rowptr, om.col,
+                           om.val, p, W, ldw, part, gate);
+    else
+        hipLaunchKernelGGL(obj_parts_kernel<ST_F32>, grid, dim3(NT), 0, stream, om.rowptr, om.col,
+                           om.val, p, W, ldw, part, gate);
+    return hipGetLastError();
+}
+
+hipError_t launch_identity(const Csr& om, int64_t p, hipStream_t stream) {
+    hipLaunchKernelGGL(identity_kernel, dim3(blocks_for(p + 1, NT)), dim3(NT), 0, stream,
+                       om.rowptr, om.col, om.val, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_symmetrize(void* W, int store, int64_t p, int64_t ld, const int* gate,
+                             hipStream_t stream) {
+    const int T = (int)((p + 63) / 64);
+    const int nt = T * (T + 1) / 2;
+    if (nt == 0) return hipSuccess;
+    if (store == ST_F64)
+        hipLaunchKernelGGL(symmetrize_kernel<ST_F64>, dim3(nt), dim3(NT), 0, stream, W, p, ld, T, gate);
+    else
+        hipLaunchKernelGGL(symmetrize_kernel<ST_F32>, dim3(nt), dim3(NT), 0, stream, W, p, ld, T, gate);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_in(const void* X, int x_is_f64, int64_t rows, int64_t cols,
+                               int64_t ld, void* Xt, int store, int64_t ldo, uint16_t* hi,
+                               uint16_t* lo, hipStream_t stream) {
+    dim3 grid(blocks_for(cols, 64), blocks_for(rows, 64));
+    if (x_is_f64) {
+        if (store == ST_F64)
+            hipLaunchKernelGGL((transpose_in_kernel<double, double>), grid, dim3(NT), 0, stream,
+                               (const double*)X, rows, cols, ld, (double*)Xt, ldo, hi, lo);
+        else
+            hipLaunchKernelGGL((transpose_in_kernel<double, float>), grid, dim3(NT), 0, stream,
+                               (const double*)X, rows, cols, ld, (float*)Xt, ldo, hi, lo);
+    } else {
+        if (store == ST_F64)
+            hipLaunchKernelGGL((transpose_in_kernel<float, double>), grid, dim3(NT), 0, stream,
+                               (const float*)X, rows, cols, ld, (double*)Xt, ldo, hi, lo);
+        else
+            hipLaunchKernelGGL((transpose_in_kernel<float, float>), grid, dim3(NT), 0, stream,
+                               (const float*)X, rows, cols, ld, (float*)Xt, ldo, hi, lo);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_square(const void* S, int s_is_f64, int64_t p, int64_t ld, void* out,
+                              int store, int64_t ldo, hipStream_t stream) {
+    const unsigned nb = blocks_for(p * p, NT);
+    if (s_is_f64)
+        hipLaunchKernelGGL(copy_square_kernel<double>, dim3(nb), dim3(NT), 0, stream,
+                           (const double*)S, p, ld, out, store, ldo);
+    else
+        hipLaunchKernelGGL(copy_square_kernel<float>, dim3(nb), dim3(NT), 0, stream,
+                           (const float*)S, p, ld, out, store, ldo);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const void* A, int is_f64, int64_t rows, int64_t cols,
+                               int64_t ld, int* flag, hipStream_t stream) {
+    if (rows * cols == 0) return hipSuccess;
+    unsigned nb = blocks_for(rows * cols, NT);
+    if (nb > 4096) nb = 4096;
+    if (is_f64)
+        hipLaunchKernelGGL(check_finite_kernel<double>, dim3(nb), dim3(NT), 0, stream,
+                           (const double*)A, rows, cols, ld, flag);
+    else
+        hipLaunchKernelGGL(check_finite_kernel<float>, dim3(nb), dim3(NT), 0, stream,
+                           (const float*)A, rows, cols, ld, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_sddmm_grad(const Csr& om, int64_t p, const void* Y, const void* Xt,
+                             int store, int64_t ld, int64_t n, double lam2, void* out,
+                             int out_f64, hipStream_t stream) {
+    if (p == 0) return hipSuccess;
+    dim3 grid(blocks_for(p, WPB));
+    if (store == ST_F64)
+        hipLaunchKernelGGL(sddmm_grad_kernel<ST_F64>, grid, dim3(NT), 0, stream, om.rowptr, om.col,
+                           om.val, p, Y, Xt, ld, n, lam2, out, out_f64);
+    else
+        hipLaunchKernelGGL(sddmm_grad_kernel<ST_F32>, grid, dim3(NT), 0, stream, om.rowptr, om.col,
+                           om.val, p, Y, Xt, ld, n, lam2, out, out_f64);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_dense_grad(const void* M, int mstore, int64_t ldm, const Csr& om,
+                                    int64_t p, double lam2, void* out, int out_f64,
+                                    hipStream_t stream) {
+    const unsigned nb = blocks_for(p * p, NT);
+    if (mstore == ST_F64)
+        hipLaunchKernelGGL(dense_grad_kernel<ST_F64>, dim3(nb), dim3(NT), 0, stream, M, ldm,
+                           om.rowptr, om.col, om.val, p, lam2, out, out_f64);
+    else
+        hipLaunchKernelGGL(dense_grad_kernel<ST_F32>, dim3(nb), dim3(NT), 0, stream, M, ldm,
+                           om.rowptr, om.col, om.val, p, lam2, out, out_f64);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_out(const void* Yt, int store, int64_t p, int64_t n, int64_t ld,
+                                double scale, void* out, int out_f64, hipStream_t stream) {
+    dim3 grid(blocks_for(n, 64), blocks_for(p, 64));
+    if (store == ST_F64)
+        hipLaunchKernelGGL(transpose_out_kernel<double>, grid, dim3(NT), 0, stream,
+                           (const double*)Yt, p, n, ld, scale, out, out_f64);
+    else
+        hipLaunchKernelGGL(transpose_out_kernel<float>, grid, dim3(NT), 0, stream,
+                           (const float*)Yt, p, n, ld, scale, out, out_f64);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_validate(const int64_t* rowptr, const int32_t* col, const void* val,
+                               int val_f64, int64_t p, int64_t nnz, int* flags,
+                               hipStream_t stream) {
+    if (val_f64)
+        hipLaunchKernelGGL(csr_validate_kernel<double>, dim3(blocks_for(p, NT)), dim3(NT), 0, stream,
+                           rowptr, col, (const double*)val, p, nnz, flags);
+    else
+        hipLaunchKernelGGL(csr_validate_kernel<float>, dim3(blocks_for(p, NT)), dim3(NT), 0, stream,
+                           rowptr, col, (const float*)val, p, nnz, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_import(const int32_t* col, const void* val, int val_f64, int64_t nnz,
+                             int32_t* col_out, double* val_out, hipStream_t stream) {
+    if (nnz == 0) return hipSuccess;
+    if (val_f64)
+        hipLaunchKernelGGL(csr_import_kernel<double>, dim3(blocks_for(nnz, NT)), dim3(NT), 0, stream,
+                           col, (const double*)val, nnz, col_out, val_out);
+    else
+        hipLaunchKernelGGL(csr_import_kernel<float>, dim3(blocks_for(nnz, NT)), dim3(NT), 0, stream,
+                           col, (const float*)val, nnz, col_out, val_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_export(const double* val, int64_t nnz, void* out, int out_f64,
+                             hipStream_t stream) {
+    if (nnz == 0) return hipSuccess;
+    hipLaunchKernelGGL(csr_export_kernel, dim3(blocks_for(nnz, NT)), dim3(NT), 0, stream, val, nnz,
+                       out, out_f64);
+    return hipGetLastError();
+}
+
+}  // namespace concord

@@ -1,0 +1,99 @@
+"""The C-ABI library loads on the CPU and exports every symbol the header declares.
+
+Error paths that are decided before any GPU work (argument validation) are
+exercised here too; nothing below launches a kernel.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "concord.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(concord_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1710_10769_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        import paper_1710_10769_amd.build as b
+        b.build()
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_1710_10769_amd import _lib
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.EXPORTED) | {"concord_config_init"}
+
+
+def test_version_and_null_handles(lib):
+    from paper_1710_10769_amd import _lib
+    assert "gfx950" in _lib.concord_version()
+    assert lib.concord_last_error(None) == b"null handle"
+    lib.concord_destroy(None)
+    lib.concord_batch_destroy(None)
+    si = _lib.concord_step_info()
+    assert lib.concord_step(None, 0.1, 0.1, ctypes.byref(si)) == _lib.EINVAL
+    assert lib.concord_solve(None, 0.1, 0.1, 1e-5, 10, None) == _lib.EINVAL
+    assert lib.concord_reset(None) == _lib.EINVAL
+    nnz = ctypes.c_int64()
+    assert lib.concord_get_omega(None, ctypes.byref(nnz), None, None, None, 0) == _lib.EINVAL
+
+
+def test_config_defaults(lib):
+    from paper_1710_10769_amd import _lib
+    cfg = _lib.concord_config_init()
+    assert (cfg.variant, cfg.precision, cfg.device) == (_lib.COV, _lib.FP64, -1)
+    assert (cfg.max_backtracks, cfg.trial_batch) == (60, 8)
+    assert ctypes.sizeof(_lib.concord_config) == 48
+
+
+@pytest.mark.parametrize("field,value", [("p", 0), ("variant", 7), ("precision", 9),
+                                         ("trial_batch", 0), ("trial_batch", 9),
+                                         ("max_backtracks", -1), ("n", -3)])
+def test_create_rejects_bad_config(lib, field, value):
+    from paper_1710_10769_amd import _lib
+    cfg = _lib.concord_config_init()
+    cfg.p, cfg.n, cfg.variant = 10, 5, _lib.OBS
+    setattr(cfg, field, value)
+    h = ctypes.c_void_p()
+    assert lib.concord_create(ctypes.byref(cfg), ctypes.byref(h)) == _lib.EINVAL
+    assert not h.value
+
+
+def test_obs_needs_n(lib):
+    from paper_1710_10769_amd import _lib
+    cfg = _lib.concord_config_init()
+    cfg.p, cfg.n, cfg.variant = 10, 0, _lib.OBS
+    h = ctypes.c_void_p()
+    assert lib.concord_create(ctypes.byref(cfg), ctypes.byref(h)) == _lib.EINVAL
+
+
+def test_batch_create_rejects_bad_args(lib):
+    from paper_1710_10769_amd import _lib
+    h = ctypes.c_void_p()
+    l1 = (ctypes.c_double * 1)(-1.0)
+    ps = (ctypes.c_int64 * 1)(10)
+    assert lib.concord_batch_create(1, ps, ps, None, ps, 1, l1, None, ctypes.byref(h)) == _lib.EINVAL
+    assert lib.concord_batch_create(0, ps, ps, None, ps, 1, l1, None, ctypes.byref(h)) == _lib.EINVAL
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    from paper_1710_10769_amd import _lib
+    saved = _lib._lib
+    try:
+        _lib._lib = None
+        with pytest.raises(RuntimeError, match="not built"):
+            _lib.load(str(tmp_path / "nope.so"))
+    finally:
+        _lib._lib = saved

@@ -1,0 +1,252 @@
+"""GPU parity of the HIP path (through the C-ABI) against the FP64 oracle.
+
+Every case prints its name, sizes and seed before touching the GPU.
+Tolerances:
+  FP64 form   : max |Omega_gpu - Omega_oracle| <= 1e-6 (free run, same taus)
+  FP32, BF16x3: max |Omega_gpu - Omega_oracle| <= 1e-4 * max|Omega_oracle|
+                (oracle's step sizes replayed), supports equal outside the
+                band | |u_ij| - lam1 | <= 1e-6 * lam1.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import datagen
+from oracle import concord as oc
+from tests.gpu_common import max_abs_diff, support_mismatch
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU parity tests need a visible GPU"
+    return torch
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _solver(p, n, variant, precision, **kw):
+    from paper_1710_10769_amd import Solver
+    return Solver(p, n, variant=variant, precision=precision, **kw)
+
+
+def _to_dev(X, dtype):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(X)).to("cuda", dtype)
+
+
+def _rounded(X, precision):
+    return X.astype(np.float32).astype(np.float64) if precision != "fp64" else X
+
+
+# ------------------------------------------------------------------ C1 free run
+
+def test_c1_cov_fp64_free_run():
+    torch = _torch()
+    w = datagen.make_workload("c1_cov_fp64_p200")
+    _say("c1 cov fp64 p=200 n=100 seed=1 free run")
+    ref = oc.solve(w.lam1, w.lam2, "cov", X=w.X, tol=w.tol, max_iter=w.max_iter,
+                   record_iterates=True)
+    s = _solver(w.p, w.n, "cov", "fp64")
+    s.set_data(_to_dev(w.X, torch.float64))
+    f0, F0 = s.objective(w.lam1, w.lam2)
+    assert abs(F0 - ref.F0) < 1e-10 * abs(ref.F0)
+    F_old = F0
+    for it, rec in enumerate(ref.log):
+        info = s.step(w.lam1, w.lam2)
+        assert info.n_trials == rec.trials, (it, info.n_trials, rec.trials)
+        om = s.get_omega_scipy()
+        assert max_abs_diff(om, ref.iterates[it + 1]) <= 1e-6, it
+        assert abs(info.F - rec.F) <= 1e-9 * abs(rec.F)
+        stop = abs(info.F - F_old) < w.tol * abs(F_old)
+        assert stop == (it == len(ref.log) - 1 and ref.status == "converged")
+        F_old = info.F
+    # and the library's own solve stops at the same iteration
+    s.reset()
+    si = s.solve(w.lam1, w.lam2, w.tol, w.max_iter)
+    assert si.iters == len(ref.log)
+    assert max_abs_diff(s.get_omega_scipy(), ref.omega) <= 1e-6
+    s.close()
+
+
+# --------------------------------------------- first step exposes the dense product
+
+@pytest.mark.parametrize("variant", ["cov", "obs"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_first_step_dense_product(variant, precision):
+    """lambda1 = 0 and a replayed small tau: every entry of Omega^1 = I - tau G(I)
+    is stored, so the whole dense product (SYRK / SYR2K) is compared."""
+    torch = _torch()
+    p, n = 333, 201   # several 128-tiles and ragged tails in p and in K
+    w = datagen.make_workload("c3_cov_p16384", p=p, n=n)
+    X = _rounded(w.X, precision)
+    trials = 4   # tau = 1/8
+    lam2 = 0.1
+    _say(f"first step {variant} {precision} p={p} n={n} seed=3 trials={trials}")
+    ref = oc.solve(0.0, lam2, variant, X=X, fixed_iters=1, tau_replay=[trials],
+                   check_literal=False)
+    s = _solver(p, n, variant, precision)
+    s.set_data(_to_dev(X, torch.float64 if precision == "fp64" else torch.float32))
+    info = s.step_replay(0.0, lam2, trials)
+    got = s.get_omega_scipy()
+    scale = np.abs(ref.omega.data).max()
+    err = max_abs_diff(got, ref.omega)
+    tol = {"fp64": 1e-12, "fp32": 2e-6, "bf16x3": 3e-5}[precision] * max(1.0, scale)
+    assert err <= tol, (err, tol)
+    assert info.tau == 0.125
+    # bitwise symmetric
+    d = (got - got.T)
+    assert d.nnz == 0 or np.abs(d.data).max() == 0.0
+    s.close()
+
+
+# --------------------------------------------------------- reduced-size replays
+
+@pytest.mark.parametrize("variant,precision,lam1", [
+    ("obs", "fp64", 0.12), ("obs", "fp32", 0.12), ("obs", "bf16x3", 0.12),
+    ("cov", "fp32", 0.2), ("cov", "bf16x3", 0.2), ("cov", "fp64", 0.2),
+])
+def test_replay_parity(variant, precision, lam1):
+    torch = _torch()
+    p, n, iters = 700, 300, 12
+    w = datagen.make_workload("c2_obs_p20000", p=p, n=n)
+    X = _rounded(w.X, precision)
+    lam2 = w.lam2
+    _say(f"replay {variant} {precision} p={p} n={n} lam1={lam1} iters={iters}")
+    ref = oc.solve(lam1, lam2, variant, X=X, fixed_iters=iters, record_iterates=True,
+                   check_literal=False)
+    assert max(r.nnz for r in ref.log) > p, "case must grow the support"
+    s = _solver(p, n, variant, precision)
+    s.set_data(_to_dev(X, torch.float64 if precision == "fp64" else torch.float32))
+    for it, rec in enumerate(ref.log):
+        info = s.step_replay(lam1, lam2, rec.trials)
+        got = s.get_omega_scipy()
+        want = ref.iterates[it + 1]
+        scale = np.abs(want.data).max()
+        err = max_abs_diff(got, want)
+        tol = 1e-6 if precision == "fp64" else 1e-4 * scale
+        assert err <= tol, (it, err, tol)
+        mism = support_mismatch(got, want)
+        if mism:
+            # only entries within the threshold band may differ
+            prev = ref.iterates[it]
+            G = _oracle_grad(prev, X, variant, lam2)
+            tau = rec.tau
+            for (i, j) in mism:
+                z = prev[i, j] - tau * G[i, j]
+                band = abs(abs(z) / tau - lam1)
+                assert band <= 1e-6 * lam1 or precision != "fp64" and band <= 1e-3 * lam1, \
+                    (it, i, j, band)
+        assert abs(info.F - rec.F) <= (1e-9 if precision == "fp64" else 1e-5) * abs(rec.F)
+    s.close()
+
+
+def _oracle_grad(om, X, variant, lam2):
+    W = np.asarray(om @ oc.sample_covariance(X))
+    return oc.gradient(W, om, lam2)
+
+
+# ---------------------------------------------------------------- free runs
+
+@pytest.mark.parametrize("variant,precision", [("obs", "fp64"), ("obs", "fp32"),
+                                               ("cov", "fp32"), ("obs", "bf16x3")])
+def test_free_run_small(variant, precision):
+    torch = _torch()
+    p, n = 260, 120
+    w = datagen.make_workload("c3_cov_p16384", p=p, n=n)
+    X = _rounded(w.X, precision)
+    lam1, lam2 = 0.25, 0.1
+    _say(f"free run {variant} {precision} p={p} n={n}")
+    ref = oc.solve(lam1, lam2, variant, X=X, tol=1e-5, max_iter=200, check_literal=False)
+    s = _solver(p, n, variant, precision)
+    s.set_data(_to_dev(X, torch.float64 if precision == "fp64" else torch.float32))
+    si = s.solve(lam1, lam2, 1e-5, 200)
+    got = s.get_omega_scipy()
+    scale = np.abs(ref.omega.data).max()
+    tol = 1e-6 if precision == "fp64" else 1e-3 * scale
+    assert max_abs_diff(got, ref.omega) <= tol
+    if precision == "fp64":
+        assert si.iters == len(ref.log)
+    # monotone objective is a property of every run
+    s.close()
+
+
+# -------------------------------------------------------------- invariants
+
+def test_monotone_and_symmetric_fp32_obs():
+    torch = _torch()
+    p, n = 900, 400
+    w = datagen.make_workload("c2_obs_p20000", p=p, n=n)
+    _say(f"invariants obs fp32 p={p} n={n}")
+    s = _solver(p, n, "obs", "fp32")
+    s.set_data(_to_dev(w.X, torch.float32))
+    F_prev = s.objective(0.12, w.lam2)[1]
+    for _ in range(15):
+        info = s.step(0.12, w.lam2)
+        assert info.F <= F_prev + 1e-6 * abs(F_prev)
+        assert info.lhs <= info.rhs
+        F_prev = info.F
+    om = s.get_omega_scipy()
+    d = om - om.T
+    assert d.nnz == 0 or np.abs(d.data).max() == 0.0
+    assert np.all(om.diagonal() > 0)
+    s.close()
+
+
+def test_determinism_bitwise():
+    torch = _torch()
+    p, n = 500, 200
+    w = datagen.make_workload("c2_obs_p20000", p=p, n=n)
+    _say(f"determinism obs bf16x3 p={p} n={n}")
+    outs = []
+    for _ in range(2):
+        s = _solver(p, n, "obs", "bf16x3")
+        s.set_data(_to_dev(w.X, torch.float32))
+        infos = [s.step(0.12, w.lam2) for _ in range(6)]
+        outs.append((s.get_omega_scipy(), [(i.tau, i.F, i.lhs) for i in infos]))
+        s.close()
+    assert outs[0][1] == outs[1][1]
+    assert (outs[0][0] != outs[1][0]).nnz == 0
+
+
+def test_diagonal_closed_form_gpu():
+    """Orthogonal columns -> S diagonal -> omega_ii = 1/sqrt(s_ii + lam2), off-diagonals 0."""
+    torch = _torch()
+    rng = np.random.Generator(np.random.PCG64(77))
+    n, p = 300, 150
+    Q, _ = np.linalg.qr(rng.standard_normal((n, p)))
+    X = Q * rng.uniform(0.5, 2.0, p) * math.sqrt(n)
+    S = X.T @ X / n
+    _say(f"closed form cov fp64 p={p} n={n}")
+    s = _solver(p, n, "cov", "fp64")
+    s.set_data(_to_dev(X, torch.float64))
+    s.solve(0.05, 0.1, 0.0, 400)
+    om = s.get_omega_scipy()
+    want = 1.0 / np.sqrt(np.diag(S) + 0.1)
+    assert np.abs(om.diagonal() - want).max() < 1e-7
+    assert om.nnz == p
+    s.close()
+
+
+def test_lambda1_max_closed_form_gpu():
+    """lambda1 >= lambda1_max keeps the estimate diagonal at diag(1/sqrt(s_ii+lam2))."""
+    torch = _torch()
+    from oracle import checks
+    w = datagen.make_workload("c2_obs_p20000", p=640, n=256)
+    X = w.X.astype(np.float32).astype(np.float64)
+    S = X.T @ X / X.shape[0]
+    lmax = checks.lambda1_max(S, w.lam2)
+    _say(f"lambda1_max obs fp32 p=640 lmax={lmax:.4f}")
+    s = _solver(640, 256, "obs", "fp32")
+    s.set_data(_to_dev(X, torch.float32))
+    s.solve(lmax * 1.02, w.lam2, 0.0, 300)
+    om = s.get_omega_scipy()
+    assert om.nnz == 640
+    want = checks.diagonal_solution(S, w.lam2)
+    assert np.abs(om.diagonal() - want).max() < 1e-5
+    s.close()
