@@ -1,0 +1,162 @@
+#!/usr/bin/env python
+"""Throughput of the CONCORD proximal-gradient iteration on one MI355X.
+
+Workload: the Obs form (Y = Omega X^T, gradient from Y X / n) at p = 20,000
+variables, n = 5,000 observations; true Omega0 random with 10 off-diagonal
+nonzeros per row, values +-U[0.1, 0.3], diagonal = row abs-sum + 0.1; rows of
+X ~ N(0, Omega0^{-1}), columns standardised; lambda1 = 0.4, lambda2 = 0.05.
+
+A step is one outer iteration of the method: the dense gradient contraction
+(MFMA), the candidate set, the batched step-size trials with the
+sufficient-decrease test, CSR emission of the accepted iterate and the
+product refresh Y = Omega X^T with the objective sums.  Inputs are resident in
+HBM before the timed region.  Both precision forms are timed (BF16 hi/lo split
+and plain FP32); ``value`` is the BF16-split form.
+
+Prints one JSON line.  --gpus N with N > 1 is not supported (one GPU).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "prox-grad iters/sec + HBM/MFMA roofline fraction at p=20k; BF16-split vs FP32"
+PEAK_TFLOPS = {"bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def run_form(torch, X32, p, n, lam1, lam2, form, steps, warmup):
+    from paper_1710_10769_amd import Solver
+    s = Solver(p, n, variant="obs", precision=form)
+    s.set_data(X32)
+    log(f"{form}: warmup {warmup} steps")
+    for _ in range(warmup):
+        s.step(lam1, lam2)
+    s.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [s.step(lam1, lam2) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = s.profile()
+    s.set_profiling(False)
+    log(f"{form}: {steps} steps in {t1 - t0:.3f} s")
+    om = s.get_omega_scipy()
+    s.close()
+    sec = t1 - t0
+    dense_ms, dense_n = prof["dense"]
+    gemm_ms = dense_ms / max(dense_n, 1)
+    flops = 2.0 * n * p * p   # algorithmic flops of Y X / n per iteration
+    achieved = flops / (gemm_ms * 1e-3) / 1e12
+    res = {
+        "value": steps / sec,
+        "ms_per_step": sec / steps * 1e3,
+        "kernel_ms_per_step": {k: v[0] / steps for k, v in prof.items()},
+        "dense_kernel_avg_ms": gemm_ms,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[form],
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[form], "traffic": None},
+        "trials_per_step": sum(i.n_trials for i in infos) / steps,
+        "final_F": infos[-1].F,
+        "final_nnz": infos[-1].nnz,
+    }
+    return res, om
+
+
+def cpu_baseline(X64, lam1, lam2):
+    """The FP64 oracle, untuned, on one full-size outer iteration of the workload."""
+    import numpy as np  # noqa: F401
+    import threadpoolctl
+    from oracle import concord as oc
+    t0 = time.perf_counter()
+    oc.solve(lam1, lam2, "obs", X=X64, fixed_iters=1, check_literal=False)
+    sec = time.perf_counter() - t0
+    threads = max((i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()), default=1)
+    return {"value": 1.0 / sec, "unit": "iters/s", "cores": int(threads), "kind": "oracle",
+            "sample": "1 outer iteration at the full workload size (p=20000, n=5000), FP64 "
+                      "NumPy/SciPy; dense BLAS multithreaded, sparse products single-threaded",
+            "seconds": sec}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--forms", default="bf16x3,fp32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--p", type=int, default=20000)
+    ap.add_argument("--n", type=int, default=5000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "layout is a design, not a build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import datagen
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    p, n = args.p, args.n
+    log(f"generating workload p={p} n={n}")
+    t0 = time.perf_counter()
+    w = datagen.make_workload("c2_obs_p20000", p=p, n=n, backend="torch", device="cuda")
+    log(f"generated in {time.perf_counter() - t0:.1f} s")
+    X32 = torch.from_numpy(w.X.astype(np.float32)).to("cuda")
+    forms = [f for f in args.forms.split(",") if f]
+    out = {}
+    oms = {}
+    for form in forms:
+        out[form], oms[form] = run_form(torch, X32, p, n, w.lam1, w.lam2, form, args.steps,
+                                        args.warmup)
+    head = forms[0]
+    line = {
+        "metric": METRIC,
+        "value": out[head]["value"],
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": out[head]["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": head,
+        "data": "synthetic",
+        "config": {"workload": f"obs_random_deg10_standardized_p{p}_n{n}", "p": p, "n": n,
+                   "lam1": w.lam1, "lam2": w.lam2, "variant": "obs", "precision": head,
+                   "trial_batch": 8},
+        "roofline": out[head]["roofline"],
+    }
+    for f in forms[1:]:
+        line[f] = {k: out[f][k] for k in ("value", "ms_per_step", "roofline", "dense_kernel_avg_ms")}
+        line[f"{head}_over_{f}"] = out[head]["value"] / out[f]["value"]
+        a, b = oms[head], oms[f]
+        d = a - b
+        scale = float(np.abs(b.data).max())
+        line[f"final_omega_maxdiff_rel_{head}_vs_{f}"] = (float(np.abs(d.data).max()) if d.nnz else 0.0) / scale
+    line["kernel_ms_per_step"] = out[head]["kernel_ms_per_step"]
+    line["dense_kernel_avg_ms"] = out[head]["dense_kernel_avg_ms"]
+    line["trials_per_step"] = out[head]["trials_per_step"]
+    line["final_nnz"] = out[head]["final_nnz"]
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, 1 iteration)")
+        X64 = w.X.astype(np.float32).astype(np.float64)
+        del w
+        line["cpu_baseline"] = cpu_baseline(X64, 0.4, 0.05)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

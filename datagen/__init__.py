@@ -111,20 +111,33 @@ def sample_cholesky(omega0: sp.spmatrix, n: int, rng: np.random.Generator,
     z = rng.standard_normal((n, p))
     dense = omega0.toarray()
     if backend == "torch":
-        import torch
-        dev = torch.device(device or "cpu")
-        A = torch.from_numpy(dense).to(dev)
-        L = torch.linalg.cholesky(A)
-        # X = Z L^{-1}  <=>  X^T = L^{-T} Z^T
-        Zt = torch.from_numpy(np.ascontiguousarray(z.T)).to(dev)
-        Xt = torch.linalg.solve_triangular(L.T.contiguous(), Zt, upper=True)
-        x = Xt.T.contiguous().cpu().numpy()
-        del A, L, Zt, Xt
-        return x
+        try:
+            return _cholesky_torch(dense, z, n, p, device)
+        except RuntimeError:
+            pass   # device linear algebra unavailable: same factor and solve on the host
     import scipy.linalg as sla
     L = sla.cholesky(dense, lower=True)
     xt = sla.solve_triangular(L.T, z.T, lower=False)
     return np.ascontiguousarray(xt.T)
+
+
+def _cholesky_torch(dense, z, n, p, device):
+    if True:
+        import torch
+        dev = torch.device(device or "cpu")
+        A = torch.from_numpy(dense).to(dev)
+        L = torch.linalg.cholesky(A)
+        U = L.T.contiguous()
+        del A, L
+        # X = Z L^{-1}  <=>  X^T = L^{-T} Z^T, solved for blocks of right-hand sides
+        x = np.empty((n, p))
+        for c0 in range(0, n, 512):
+            c1 = min(n, c0 + 512)
+            Zt = torch.from_numpy(np.ascontiguousarray(z[c0:c1].T)).to(dev)
+            x[c0:c1] = torch.linalg.solve_triangular(U, Zt, upper=True).T.cpu().numpy()
+            del Zt
+        del U
+        return x
 
 
 def _bbt_factor(omega0: sp.csr_matrix) -> sp.csr_matrix:

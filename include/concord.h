@@ -234,6 +234,23 @@ int concord_batch_get_omega(concord_batch* b, int32_t instance, int32_t l1_index
 const char* concord_batch_last_error(const concord_batch* b);
 void concord_batch_destroy(concord_batch* b);
 
+/* Per-kernel-class timing (HIP events recorded on the handle's stream around
+   each launch group; read at the synchronisation points the solver already
+   has).  Classes: */
+#define CONCORD_PROF_DENSE 0   /* MFMA SYR2K (Obs gradient) / SYRK (Cov, once) */
+#define CONCORD_PROF_SPMM  1   /* product refresh at the accepted iterate + objective sums */
+#define CONCORD_PROF_CAND  2   /* gradient + candidate set */
+#define CONCORD_PROF_TRIAL 3   /* step-size trials + test sums + decision */
+#define CONCORD_PROF_EMIT  4   /* CSR emission of the accepted iterate */
+#define CONCORD_PROF_NCLASS 5
+typedef struct concord_profile {
+    double  ms[8];        /* accumulated milliseconds per class */
+    int64_t launches[8];  /* timed launch groups per class */
+} concord_profile;
+/* on != 0 starts timing and clears the counters; on = 0 stops it. */
+int concord_set_profiling(concord_ctx* ctx, int32_t on);
+int concord_get_profile(const concord_ctx* ctx, concord_profile* host_out);
+
 /* Description of the last error on this handle ("" if none). Never NULL. */
 const char* concord_last_error(const concord_ctx* ctx);
 

@@ -54,6 +54,13 @@ class concord_step_info(ctypes.Structure):
                 ("rhs", ctypes.c_double)]
 
 
+class concord_profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8)]
+
+
+PROF_CLASSES = ("dense", "spmm", "cand", "trial", "emit")
+
+
 class concord_solve_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("f", ctypes.c_double), ("F", ctypes.c_double),
                 ("nnz", ctypes.c_int64), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
@@ -84,6 +91,8 @@ _SIGS = {
     "concord_batch_get_omega": (_I32, [_P, _I32, _I32, ctypes.POINTER(_I64), _P, _P, _P]),
     "concord_batch_last_error": (ctypes.c_char_p, [_P]),
     "concord_batch_destroy": (None, [_P]),
+    "concord_set_profiling": (_I32, [_P, _I32]),
+    "concord_get_profile": (_I32, [_P, ctypes.c_void_p]),
     "concord_last_error": (ctypes.c_char_p, [_P]),
     "concord_destroy": (None, [_P]),
     "concord_version": (ctypes.c_char_p, []),
@@ -214,6 +223,16 @@ def concord_get_omega(h, rowptr: int = 0, col: int = 0, val: int = 0, dtype: int
     return nnz.value
 
 
+def concord_set_profiling(h, on: bool) -> int:
+    return _check(load().concord_set_profiling(h, 1 if on else 0), h)
+
+
+def concord_get_profile(h) -> dict:
+    pr = concord_profile()
+    _check(load().concord_get_profile(h, ctypes.byref(pr)), h)
+    return {name: (pr.ms[i], pr.launches[i]) for i, name in enumerate(PROF_CLASSES)}
+
+
 def concord_iterations(h) -> int:
     return load().concord_iterations(h)
 
@@ -320,6 +339,13 @@ class Solver:
 
     def objective(self, lam1: float, lam2: float) -> Tuple[float, float]:
         return concord_objective(self._h, lam1, lam2)
+
+    def set_profiling(self, on: bool = True) -> None:
+        concord_set_profiling(self._h, on)
+
+    def profile(self) -> dict:
+        """{class: (milliseconds, launch groups)} since profiling was switched on."""
+        return concord_get_profile(self._h)
 
     @property
     def iterations(self) -> int:

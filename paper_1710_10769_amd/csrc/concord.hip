@@ -112,6 +112,15 @@ struct concord_ctx {
     double obj[5] = {0, 0, 0, 0, 0};
 
     std::vector<void*> allocs;
+
+    // profiling
+    bool prof = false;
+    hipEvent_t ev[16][2] = {};
+    int ev_cls[16] = {};
+    int nrec = 0;
+    int open_slot = -1;
+    double prof_ms[8] = {};
+    int64_t prof_cnt[8] = {};
 };
 
 namespace {
@@ -209,9 +218,37 @@ int ensure_cand_cap(concord_ctx* c, int64_t cap) {
     return CONCORD_OK;
 }
 
+void prof_begin(concord_ctx* c, int cls) {
+    if (!c->prof || c->nrec >= 16) return;
+    const int s = c->nrec++;
+    c->ev_cls[s] = cls;
+    hipEventRecord(c->ev[s][0], c->stream);
+    c->open_slot = s;
+}
+
+void prof_end(concord_ctx* c) {
+    if (!c->prof || c->open_slot < 0) return;
+    hipEventRecord(c->ev[c->open_slot][1], c->stream);
+    c->open_slot = -1;
+}
+
+// after a stream synchronisation: fold the recorded intervals into the totals
+void prof_collect(concord_ctx* c) {
+    if (!c->prof) return;
+    for (int s = 0; s < c->nrec; ++s) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ev[s][0], c->ev[s][1]) == hipSuccess) {
+            c->prof_ms[c->ev_cls[s]] += ms;
+            c->prof_cnt[c->ev_cls[s]] += 1;
+        }
+    }
+    c->nrec = 0;
+}
+
 int sync_state(concord_ctx* c) {
     HIPCK(c, hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
     HIPCK(c, hipStreamSynchronize(c->stream));
+    prof_collect(c);
     return CONCORD_OK;
 }
 
@@ -234,6 +271,7 @@ int products_at(concord_ctx* c, int which, const int* gate) {
     const Csr& O = c->om[which];
     const int64_t p = c->p;
     int nysq = 0;
+    prof_begin(c, CONCORD_PROF_SPMM);
     if (c->variant == CONCORD_OBS) {
         const bool split = c->precision == CONCORD_BF16X3;
         const int nch = spmm_nchunks(c->dstore, c->ldk);
@@ -255,6 +293,7 @@ int products_at(concord_ctx* c, int which, const int* gate) {
     hipLaunchKernelGGL(obj_finish_kernel, dim3(1), dim3(64), 0, c->stream, c->objsums, nysq, c->st,
                        gate);
     HIPCK(c, hipGetLastError());
+    prof_end(c);
     return CONCORD_OK;
 }
 
@@ -307,8 +346,10 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
         const void* P1 = split ? (const void*)c->Y_lo : nullptr;
         const void* Q0 = split ? (const void*)c->Xt_hi : c->Xt;
         const void* Q1 = split ? (const void*)c->Xt_lo : nullptr;
+        prof_begin(c, CONCORD_PROF_DENSE);
         HIPCK(c, launch_gemm_sym(c->gkind, true, P0, P1, Q0, Q1, c->ldk, p,
                                  0.5 / (double)c->n, c->M, c->dstore, c->ldp, c->stream));
+        prof_end(c);
     }
     const int nxt = c->cur ^ 1;
     const double inv_n = c->variant == CONCORD_OBS ? 1.0 / (double)c->n : 1.0;
@@ -319,11 +360,13 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
     for (int attempt = 0; attempt < 8; ++attempt) {
         hipLaunchKernelGGL(state_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->st);
         // candidate set
+        prof_begin(c, CONCORD_PROF_CAND);
         HIPCK(c, launch_cand_count(c->M, c->dstore, c->ldp, c->om[c->cur], p, lam1, c->bitmap,
                                    c->nwords, c->cnt, c->stream));
         HIPCK(c, launch_scan(c->cnt, p, c->A.rowptr, c->a_cap, &c->st->overflow, c->stream));
         HIPCK(c, launch_cand_fill(c->M, c->dstore, c->ldp, c->om[c->cur], p, lam2, c->bitmap,
                                   c->nwords, c->A, c->a_cap, &c->st->overflow, c->stream));
+        prof_end(c);
         if ((rc = ensure_csr_cap(c, nxt, c->a_cap))) return rc;
 
         const int total = c->max_bt + 1;   // step sizes 1 .. 2^-max_bt
@@ -334,16 +377,20 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
         while (q_base < total) {
             const int m = forced_q >= 0 ? 1 : std::min(c->tb, total - q_base);
             const double tau0 = std::ldexp(1.0, -q_base);
+            prof_begin(c, CONCORD_PROF_TRIAL);
             HIPCK(c, launch_trial(c->A, p, tau0, m, lam1, c->variant, TB, tbstore, tld,
                                   c->variant == CONCORD_OBS ? c->ldk : 0, c->part, c->st,
                                   c->stream));
             HIPCK(c, launch_colsum(c->part, p, 4 * m, c->sums, c->stream));
             HIPCK(c, launch_decide(c->sums, m, tau0, q_base, lam2, c->variant, inv_n, forced_q,
                                    c->st, c->stream));
+            prof_end(c);
             // emission and products at Omega+ (all gated on the decision)
+            prof_begin(c, CONCORD_PROF_EMIT);
             HIPCK(c, launch_emit_count(c->A, p, lam1, c->st, c->cnt, c->stream));
             HIPCK(c, launch_scan(c->cnt, p, c->om[nxt].rowptr, c->om_cap[nxt], nullptr, c->stream));
             HIPCK(c, launch_emit_fill(c->A, p, lam1, c->st, c->om[nxt], c->stream));
+            prof_end(c);
             if ((rc = products_at(c, nxt, &c->st->accepted))) return rc;
             HIPCK(c, hipMemcpyAsync(c->h_stage, c->om[nxt].rowptr + p, sizeof(int64_t),
                                     hipMemcpyDeviceToHost, c->stream));
@@ -411,11 +458,35 @@ const char* concord_last_error(const concord_ctx* ctx) {
     return ctx->err.c_str();
 }
 
+int concord_set_profiling(concord_ctx* c, int32_t on) {
+    if (!c) return CONCORD_EINVAL;
+    DeviceGuard g(c->device);
+    if (on && !c->ev[0][0]) {
+        for (int s = 0; s < 16; ++s)
+            for (int t = 0; t < 2; ++t) HIPCK(c, hipEventCreate(&c->ev[s][t]));
+    }
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    c->nrec = 0;
+    c->open_slot = -1;
+    for (int i = 0; i < 8; ++i) { c->prof_ms[i] = 0.0; c->prof_cnt[i] = 0; }
+    c->prof = on != 0;
+    return CONCORD_OK;
+}
+
+int concord_get_profile(const concord_ctx* c, concord_profile* out) {
+    if (!c || !out) return CONCORD_EINVAL;
+    for (int i = 0; i < 8; ++i) { out->ms[i] = c->prof_ms[i]; out->launches[i] = c->prof_cnt[i]; }
+    return CONCORD_OK;
+}
+
 void concord_destroy(concord_ctx* ctx) {
     if (!ctx) return;
     {
         DeviceGuard g(ctx->device);
         hipStreamSynchronize(ctx->stream);
+        for (int s = 0; s < 16; ++s)
+            for (int t = 0; t < 2; ++t)
+                if (ctx->ev[s][t]) hipEventDestroy(ctx->ev[s][t]);
         for (void* a : ctx->allocs)
             if (a) hipFree(a);
         if (ctx->st_host) hipHostFree(ctx->st_host);
@@ -546,8 +617,10 @@ int concord_set_data(concord_ctx* c, int32_t kind, const void* dev_data, int32_t
         if (c->variant == CONCORD_COV) {
             const void* P0 = split ? (const void*)c->Xt_hi : c->Xt;
             const void* P1 = split ? (const void*)c->Xt_lo : nullptr;
+            prof_begin(c, CONCORD_PROF_DENSE);
             HIPCK(c, launch_gemm_sym(c->gkind, false, P0, P1, nullptr, nullptr, c->ldk, c->p,
                                      1.0 / (double)c->n, c->S, c->sstore, c->ldp, c->stream));
+            prof_end(c);
         }
     } else {
         HIPCK(c, launch_copy_square(dev_data, is64, c->p, ld, c->S, c->sstore, c->ldp, c->stream));
@@ -556,6 +629,7 @@ int concord_set_data(concord_ctx* c, int32_t kind, const void* dev_data, int32_t
     int rc = set_identity(c);
     if (rc) return rc;
     HIPCK(c, hipStreamSynchronize(c->stream));
+    prof_collect(c);
     return CONCORD_OK;
 }
 
