@@ -334,3 +334,16 @@ def env_threads() -> int:
         return len(os.sched_getaffinity(0))
     except AttributeError:  # pragma: no cover
         return os.cpu_count() or 1
+
+
+def perturb_symmetric(omega: sp.spmatrix, rng: np.random.Generator, scale: float = 0.1):
+    """Omega with every stored value scaled by (1 + scale*U(-1, 1)), the same factor
+    for (i, j) and (j, i), so the result stays symmetric with the same pattern."""
+    om = sp.csr_matrix(omega, dtype=np.float64).copy()
+    coo = sp.triu(om).tocoo()
+    fac = 1.0 + scale * rng.uniform(-1.0, 1.0, size=coo.nnz)
+    up = sp.csr_matrix((coo.data * fac, (coo.row, coo.col)), shape=om.shape)
+    low = sp.triu(up, k=1).T
+    out = (up + low).tocsr()
+    out.sort_indices()
+    return out

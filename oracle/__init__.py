@@ -24,5 +24,5 @@ other than these properties, since the paper prints no worked example.
 from .concord import (  # noqa: F401
     soft_threshold, prox_step, sample_covariance, smooth_objective, gradient,
     penalty, test_difference_terms, solve, SolveResult, IterRecord,
-    smooth_value_and_grads,
+    smooth_value_and_grads, smooth_value_and_sampled_grads,
 )

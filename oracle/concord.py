@@ -302,3 +302,37 @@ def smooth_value_and_grads(omega: sp.spmatrix, X: np.ndarray, lam2: float):
     G = gradient(W, omega, lam2)
     dX = np.asarray(omega @ Y).T / n
     return f, G, dX
+
+
+def smooth_value_and_sampled_grads(omega: sp.spmatrix, X: np.ndarray, lam2: float,
+                                   entries, x_cols):
+    """As smooth_value_and_grads, for large p: f, G at the listed (i, j) entries and
+    the listed columns of dX, each computed one by one from Y = Omega X^T.
+
+    G_ij = (Y_i . X^T_j + Y_j . X^T_i) / (2n) + lam2 omega_ij - [i == j] / omega_ii
+    (half the sum of (Omega S)_ij and (Omega S)_ji, written with S = X^T X / n);
+    dX[:, j] = (sum_k omega_jk Y_k) / n.
+    """
+    omega = sp.csr_matrix(omega, dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64)
+    n = X.shape[0]
+    Xt = X.T
+    Y = np.asarray(omega @ Xt)
+    d = _diag(omega)
+    f = -float(np.sum(np.log(d))) + float(np.sum(Y * Y)) / (2 * n) \
+        + 0.5 * lam2 * float(np.sum(omega.data ** 2))
+    G = []
+    for (i, j) in entries:
+        w = omega[i, j]
+        g = (float(Y[i] @ Xt[j]) + float(Y[j] @ Xt[i])) / (2 * n) + lam2 * w
+        if i == j:
+            g -= 1.0 / w
+        G.append(g)
+    dX = []
+    for j in x_cols:
+        row = omega.getrow(j)
+        acc = np.zeros(n)
+        for k, v in zip(row.indices, row.data):
+            acc += v * Y[k]
+        dX.append(acc / n)
+    return f, np.array(G), np.array(dX).T

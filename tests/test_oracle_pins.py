@@ -269,3 +269,16 @@ def test_s1_cov_obs_rule_golden():
         r_obs, t, pct = float(r_obs), float(t), float(pct)
         thr = r_obs / (1 - r_obs) / t * 100
         assert abs(thr - pct) < 0.05 + 1e-12, (r_obs, thr, pct)
+
+
+def test_sampled_grads_match_dense():
+    rng = _rng(81)
+    p, n = 30, 12
+    X = rng.standard_normal((n, p))
+    om = datagen.random_omega0(p, 4, rng)
+    f, G, dX = oc.smooth_value_and_grads(om, X, 0.1)
+    ent = [(0, 0), (3, 7), (7, 3), (29, 29), (5, 11)]
+    f2, g2, dx2 = oc.smooth_value_and_sampled_grads(om, X, 0.1, ent, [0, 4, 29])
+    assert abs(f - f2) < 1e-12
+    assert np.allclose(g2, [G[i, j] for i, j in ent], atol=1e-12)
+    assert np.allclose(dx2, dX[:, [0, 4, 29]], atol=1e-12)
