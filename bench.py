@@ -102,6 +102,44 @@ def cpu_baseline(X64, lam1, lam2):
             "seconds": sec}
 
 
+def bench_c4(args, torch, np, datagen):
+    """Batched lambda path: 48 Cov instances (p in {1k, 2k, 4k, 8k}, n = p/2), each
+    solved at lambda1 in {0.2, 0.3, 0.5} from Omega = I (FP32 products, FP64
+    reductions, stop at relative F change < 1e-5 or 200 iterations).  A step is
+    one whole path (all 144 solves); value = solves per second."""
+    from paper_1710_10769_amd import Batch
+    l1s, lam2 = datagen.lambda_path_c4()
+    log("generating 48 instances")
+    inst = datagen.c4_instances(backend="torch", device="cuda")
+    Xs = [torch.from_numpy(X.astype(np.float32)).cuda() for _, X, _ in inst]
+    torch.cuda.synchronize()
+    times = []
+    iters = None
+    for rep in range(args.warmup + args.steps):
+        b = Batch(Xs, l1s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters, Fs, rc = b.solve(lam2, 1e-5, 200)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        b.close()
+        if rep >= args.warmup:
+            times.append(t1 - t0)
+        log(f"path {rep}: {t1 - t0:.3f} s, mean iterations {np.mean(iters):.1f}")
+    sec = float(np.mean(times))
+    nsolve = len(inst) * len(l1s)
+    line = {
+        "metric": "batched lambda-path solves/sec (48 Cov instances x 3 lambda1)",
+        "value": nsolve / sec, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": "cov_batched_lambda_path_48x3", "instances": len(inst),
+                   "p": [p for p, _, _ in inst], "lambda1": list(l1s), "lam2": lam2},
+        "mean_iterations": float(np.mean(iters)), "total_iterations": int(np.sum(iters)),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +149,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--p", type=int, default=20000)
     ap.add_argument("--n", type=int, default=5000)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4"],
+                    help="c2: the Obs p=20k headline; c4: the batched lambda path")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -125,6 +165,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "c4":
+        return bench_c4(args, torch, np, datagen)
     p, n = args.p, args.n
     if args.copy_probe_mib:
         src = torch.ones(args.copy_probe_mib * 262144, dtype=torch.float32, device="cuda")

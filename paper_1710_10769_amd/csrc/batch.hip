@@ -1,29 +1,45 @@
 // Batched lambda path over independent Cov problems (see include/concord.h).
 //
-// Each instance keeps its own handle (its S formed once on the GPU from X);
-// every lambda1 of the path is solved from Omega = I with the single-problem
-// solver, and the estimate is kept in batch-owned CSR buffers.
+// Execution: a pool of worker threads, each with its own HIP stream (default
+// priority) on the batch's device, pulls instances from a shared queue ordered
+// by decreasing p (largest first, so the tail of the batch is short).  A worker
+// forms S = X^T X / n once per instance (MFMA), then solves every lambda1 of
+// the path from Omega = I with the single-problem solver on its stream, and
+// copies each estimate into batch-owned CSR buffers.  Independent instances
+// thus overlap on the GPU instead of serialising on launch latency and on the
+// host synchronisation of each step.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
+#include <cstdlib>
+#include <mutex>
+#include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/concord.h"
 
 struct BatchResult {
     int64_t nnz = 0;
+    int64_t cap = 0;
     int64_t* rowptr = nullptr;
     int32_t* col = nullptr;
     double* val = nullptr;
+    int64_t iters = 0;
+    double F = 0.0;
 };
 
 struct concord_batch {
     int count = 0, n_l1 = 0;
-    std::vector<concord_ctx*> ctx;
+    int device = 0;
+    std::vector<int64_t> p, n, ld;
+    std::vector<const void*> X;
     std::vector<double> lambda1;
-    std::vector<int64_t> p;
     std::vector<BatchResult> res;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;   // caller's stream (result copies)
+    int workers = 8;
     std::string err;
 };
 
@@ -33,10 +49,60 @@ int bfail(concord_batch* b, int code, const std::string& m) {
     return code;
 }
 void free_result(BatchResult& r) {
-    if (r.rowptr) hipFree(r.rowptr);
-    if (r.col) hipFree(r.col);
-    if (r.val) hipFree(r.val);
+    if (r.rowptr) (void)hipFree(r.rowptr);
+    if (r.col) (void)hipFree(r.col);
+    if (r.val) (void)hipFree(r.val);
     r = BatchResult();
+}
+
+// One instance, every lambda1, on `stream`.  Returns a status and a message.
+int solve_instance(concord_batch* b, int i, hipStream_t stream, double lam2, double tol,
+                   int64_t max_iter, std::string* msg) {
+    concord_config cfg;
+    concord_config_init(&cfg);
+    cfg.p = b->p[i];
+    cfg.n = b->n[i];
+    cfg.variant = CONCORD_COV;
+    cfg.precision = CONCORD_FP32;
+    cfg.stream = stream;
+    cfg.device = b->device;
+    concord_ctx* c = nullptr;
+    int rc = concord_create(&cfg, &c);
+    if (rc) {
+        *msg = "concord_create failed for instance " + std::to_string(i);
+        return rc;
+    }
+    rc = concord_set_data(c, CONCORD_DATA_X, b->X[i], CONCORD_F32, b->n[i], b->p[i], b->ld[i]);
+    int worst = CONCORD_OK;
+    for (int l = 0; rc >= 0 && l < b->n_l1; ++l) {
+        if ((rc = concord_reset(c))) break;
+        concord_solve_info si;
+        rc = concord_solve(c, b->lambda1[l], lam2, tol, max_iter, &si);
+        if (rc < 0) break;
+        worst = std::max(worst, rc);
+        BatchResult& r = b->res[(size_t)i * b->n_l1 + l];
+        int64_t nnz = 0;
+        concord_get_omega(c, &nnz, nullptr, nullptr, nullptr, CONCORD_F64);
+        if (!r.rowptr || nnz > r.cap) {
+            free_result(r);
+            if (hipMalloc((void**)&r.rowptr, (b->p[i] + 1) * sizeof(int64_t)) != hipSuccess ||
+                hipMalloc((void**)&r.col, std::max<int64_t>(nnz, 1) * sizeof(int32_t)) != hipSuccess ||
+                hipMalloc((void**)&r.val, std::max<int64_t>(nnz, 1) * sizeof(double)) != hipSuccess) {
+                rc = CONCORD_ENOMEM;
+                break;
+            }
+            r.cap = nnz;
+        }
+        rc = concord_get_omega(c, &nnz, r.rowptr, r.col, r.val, CONCORD_F64);
+        if (rc) break;
+        r.nnz = nnz;
+        r.iters = si.iters;
+        r.F = si.F;
+        rc = CONCORD_OK;
+    }
+    if (rc < 0) *msg = std::string("instance ") + std::to_string(i) + ": " + concord_last_error(c);
+    concord_destroy(c);
+    return rc < 0 ? rc : worst;
 }
 }  // namespace
 
@@ -44,9 +110,12 @@ extern "C" {
 
 void concord_batch_destroy(concord_batch* b) {
     if (!b) return;
-    if (b->stream) hipStreamSynchronize(b->stream);
-    for (auto* c : b->ctx) concord_destroy(c);
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(b->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
     for (auto& r : b->res) free_result(r);
+    if (prev >= 0) (void)hipSetDevice(prev);
     delete b;
 }
 
@@ -63,34 +132,28 @@ int concord_batch_create(int32_t count, const int64_t* host_p, const int64_t* ho
         return CONCORD_EINVAL;
     for (int l = 0; l < n_l1; ++l)
         if (!(host_lambda1[l] >= 0.0)) return CONCORD_EINVAL;
+    for (int i = 0; i < count; ++i)
+        if (host_p[i] < 1 || host_n[i] < 1 || host_ld[i] < host_p[i] || !host_dev_X[i])
+            return CONCORD_EINVAL;
     concord_batch* b = new concord_batch();
+    if (hipGetDevice(&b->device) != hipSuccess) {
+        delete b;
+        return CONCORD_EHIP;
+    }
     b->count = count;
     b->n_l1 = n_l1;
     b->stream = (hipStream_t)stream;
+    b->p.assign(host_p, host_p + count);
+    b->n.assign(host_n, host_n + count);
+    b->ld.assign(host_ld, host_ld + count);
+    b->X.assign(host_dev_X, host_dev_X + count);
     b->lambda1.assign(host_lambda1, host_lambda1 + n_l1);
     b->res.resize((size_t)count * n_l1);
-    for (int i = 0; i < count; ++i) {
-        concord_config cfg;
-        concord_config_init(&cfg);
-        cfg.p = host_p[i];
-        cfg.n = host_n[i];
-        cfg.variant = CONCORD_COV;
-        cfg.precision = CONCORD_FP32;
-        cfg.stream = stream;
-        concord_ctx* c = nullptr;
-        int rc = concord_create(&cfg, &c);
-        if (rc) {
-            concord_batch_destroy(b);
-            return rc;
-        }
-        b->ctx.push_back(c);
-        b->p.push_back(host_p[i]);
-        rc = concord_set_data(c, CONCORD_DATA_X, host_dev_X[i], CONCORD_F32, host_n[i], host_p[i],
-                              host_ld[i]);
-        if (rc) {
-            concord_batch_destroy(b);
-            return rc;
-        }
+    if (const char* w = std::getenv("CONCORD_BATCH_WORKERS")) b->workers = std::max(1, atoi(w));
+    // the inputs were produced on the caller's stream: make them visible to the workers' streams
+    if (hipStreamSynchronize(b->stream) != hipSuccess) {
+        delete b;
+        return CONCORD_EHIP;
     }
     *out = b;
     return CONCORD_OK;
@@ -101,34 +164,49 @@ int concord_batch_solve(concord_batch* b, double lambda2, double tol, int64_t ma
     if (!b) return CONCORD_EINVAL;
     if (!(lambda2 >= 0.0) || !(tol >= 0.0) || max_iter < 0)
         return bfail(b, CONCORD_EINVAL, "lambda2, tol must be >= 0");
-    int worst = CONCORD_OK;
-    for (int i = 0; i < b->count; ++i) {
-        concord_ctx* c = b->ctx[i];
-        for (int l = 0; l < b->n_l1; ++l) {
-            int rc = concord_reset(c);
-            if (rc) return bfail(b, rc, concord_last_error(c));
-            concord_solve_info si;
-            rc = concord_solve(c, b->lambda1[l], lambda2, tol, max_iter, &si);
-            if (rc < 0) return bfail(b, rc, concord_last_error(c));
-            if (rc > worst) worst = rc;
-            BatchResult& r = b->res[(size_t)i * b->n_l1 + l];
-            int64_t nnz = 0;
-            concord_get_omega(c, &nnz, nullptr, nullptr, nullptr, CONCORD_F64);
-            if (nnz > r.nnz || !r.rowptr) {
-                free_result(r);
-                if (hipMalloc((void**)&r.rowptr, (b->p[i] + 1) * sizeof(int64_t)) != hipSuccess ||
-                    hipMalloc((void**)&r.col, nnz * sizeof(int32_t)) != hipSuccess ||
-                    hipMalloc((void**)&r.val, nnz * sizeof(double)) != hipSuccess)
-                    return bfail(b, CONCORD_ENOMEM, "result allocation failed");
-            }
-            rc = concord_get_omega(c, &nnz, r.rowptr, r.col, r.val, CONCORD_F64);
-            if (rc) return bfail(b, rc, concord_last_error(c));
-            r.nnz = nnz;
-            if (host_iters) host_iters[(size_t)i * b->n_l1 + l] = si.iters;
-            if (host_F) host_F[(size_t)i * b->n_l1 + l] = si.F;
+    std::vector<int> order(b->count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return b->p[a] > b->p[c]; });
+    std::atomic<int> next(0);
+    std::mutex mu;
+    int status = CONCORD_OK;
+    std::string first_err;
+    auto worker = [&]() {
+        (void)hipSetDevice(b->device);
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+            std::lock_guard<std::mutex> g(mu);
+            if (status >= 0) { status = CONCORD_EHIP; first_err = "stream creation failed"; }
+            return;
         }
-    }
-    return worst;
+        for (;;) {
+            {
+                std::lock_guard<std::mutex> g(mu);
+                if (status < 0) break;
+            }
+            const int k = next.fetch_add(1);
+            if (k >= b->count) break;
+            std::string msg;
+            const int rc = solve_instance(b, order[k], s, lambda2, tol, max_iter, &msg);
+            std::lock_guard<std::mutex> g(mu);
+            if (rc < 0 && status >= 0) { status = rc; first_err = msg; }
+            else if (rc > status && status >= 0) status = rc;
+        }
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+    };
+    const int nw = std::min(b->workers, b->count);
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nw; ++t) pool.emplace_back(worker);
+    for (auto& t : pool) t.join();
+    if (status < 0) return bfail(b, status, first_err);
+    for (int i = 0; i < b->count; ++i)
+        for (int l = 0; l < b->n_l1; ++l) {
+            const BatchResult& r = b->res[(size_t)i * b->n_l1 + l];
+            if (host_iters) host_iters[(size_t)i * b->n_l1 + l] = r.iters;
+            if (host_F) host_F[(size_t)i * b->n_l1 + l] = r.F;
+        }
+    return status;
 }
 
 int concord_batch_get_omega(concord_batch* b, int32_t instance, int32_t l1_index,
@@ -141,11 +219,15 @@ int concord_batch_get_omega(concord_batch* b, int32_t instance, int32_t l1_index
     *host_nnz = r.nnz;
     if (!dev_row_ptr) return CONCORD_OK;
     if (!r.rowptr) return bfail(b, CONCORD_ENODATA, "not solved yet");
-    hipMemcpyAsync(dev_row_ptr, r.rowptr, (b->p[instance] + 1) * sizeof(int64_t),
-                   hipMemcpyDeviceToDevice, b->stream);
-    hipMemcpyAsync(dev_col, r.col, r.nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, b->stream);
-    hipMemcpyAsync(dev_val, r.val, r.nnz * sizeof(double), hipMemcpyDeviceToDevice, b->stream);
-    if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, CONCORD_EHIP, "copy failed");
+    if (!dev_col || !dev_val) return bfail(b, CONCORD_EINVAL, "col/val must be given with row_ptr");
+    if (hipMemcpyAsync(dev_row_ptr, r.rowptr, (b->p[instance] + 1) * sizeof(int64_t),
+                       hipMemcpyDeviceToDevice, b->stream) != hipSuccess ||
+        hipMemcpyAsync(dev_col, r.col, r.nnz * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                       b->stream) != hipSuccess ||
+        hipMemcpyAsync(dev_val, r.val, r.nnz * sizeof(double), hipMemcpyDeviceToDevice,
+                       b->stream) != hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess)
+        return bfail(b, CONCORD_EHIP, "copy failed");
     return CONCORD_OK;
 }
 

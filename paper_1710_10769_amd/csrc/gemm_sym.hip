@@ -23,6 +23,8 @@
 //   GK_F64    v_mfma_f64_16x16x4f64
 //   GK_BF16X3 v_mfma_f32_32x32x16_bf16 three times: hi*hi + hi*lo + lo*hi,
 //             where x = hi + lo, hi = bf16(x), lo = bf16(x - hi)
+#include <mutex>
+
 #include "internal.h"
 
 namespace concord {
@@ -382,12 +384,11 @@ hipError_t launch_kind(bool syr2k, const void* P0, const void* P1, const void* Q
     const int T = (int)((p + BT - 1) / BT);
     const int ntiles = T * (T + 1) / 2;
     const size_t lds = 2 * (2 * F::NPLANE * BT * ROWB);
-    static bool attr_set = false;
-    if (!attr_set) {
+    static std::once_flag attr_once;   // handles on several host threads may launch concurrently
+    std::call_once(attr_once, [&] {
         (void)hipFuncSetAttribute((const void*)gemm_sym_kernel<KIND>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        attr_set = true;
-    }
+    });
     if (ntiles == 0 || nk == 0) return hipSuccess;
     hipLaunchKernelGGL(gemm_sym_kernel<KIND>, dim3(ntiles), dim3(NT), lds, stream,
                        (const char*)P0, (const char*)P1, (const char*)(syr2k ? Q0 : P0),
