@@ -23,6 +23,9 @@
 //   GK_F64    v_mfma_f64_16x16x4f64
 //   GK_BF16X3 v_mfma_f32_32x32x16_bf16 three times: hi*hi + hi*lo + lo*hi,
 //             where x = hi + lo, hi = bf16(x), lo = bf16(x - hi)
+#include <cstdio>
+#include <cstdlib>
+#include <map>
 #include <mutex>
 
 #include "internal.h"
@@ -223,20 +226,14 @@ __device__ inline void store_val(void* C, int store, int64_t idx, double v) {
     }
 }
 
-// Tile configuration: BT x BT output tile, WM x WN waves.
-template <int KIND> struct Cfg;
-template <> struct Cfg<GK_BF16X3> { static constexpr int BT = 256, WM = 4, WN = 2; };
-template <> struct Cfg<GK_F32> { static constexpr int BT = 256, WM = 4, WN = 2; };
-template <> struct Cfg<GK_F64> { static constexpr int BT = 128, WM = 2, WN = 2; };
-
-template <int KIND>
-__global__ void __launch_bounds__(Cfg<KIND>::WM * Cfg<KIND>::WN * 64)
+template <int KIND, int BT_, int WM_, int WN_>
+__global__ void __launch_bounds__(WM_ * WN_ * 64)
 gemm_sym_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
                 const char* __restrict__ Q0, const char* __restrict__ Q1, int64_t ldk_bytes,
                 int nk, int syr2k, int p, int T, int ntiles, double alpha, void* __restrict__ C,
                 int out_store, int64_t ldc) {
     typedef Form<KIND> F;
-    constexpr int BT = Cfg<KIND>::BT, WM = Cfg<KIND>::WM, WN = Cfg<KIND>::WN;
+    constexpr int BT = BT_, WM = WM_, WN = WN_;   // BT x BT output tile, WM x WN waves
     constexpr int NT = WM * WN * 64;
     constexpr int NP = F::NPLANE;
     constexpr int PLANE = BT * ROWB;          // bytes of one plane of one side
@@ -371,13 +368,218 @@ gemm_sym_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
             }
 }
 
-template <int KIND>
+// ---- BF16-split contraction with a direct-to-LDS load ring ---------------------
+//
+// 256 x 256 tile, 8 waves (4 x 2, 64 x 128 each), K stages of 16 bf16 (32 bytes per
+// row per plane).  Stage data goes from global memory straight into LDS
+// (global_load_lds_dwordx4, no staging registers, no LDS store instructions) in a
+// ring of 4 stage slots, issued 3 stages ahead.  A wave waits only for its own
+// loads of the stage about to be read (s_waitcnt vmcnt with the later stages
+// still in flight), then one s_barrier publishes the stage and frees the slot
+// that the next load overwrites.  Rows of 32 bytes hold two 16-byte chunks,
+// swapped on every other group of four rows, so eight consecutive rows read at
+// the same logical chunk fall in eight distinct 16-byte bank groups.
+namespace dma {
+constexpr int BT = 256, NT = 512, WM = 4, WN = 2;
+constexpr int ROW = 32;                 // bytes per row, stage, plane
+constexpr int PS = BT * ROW;            // 8 KB per plane-side
+constexpr int SLOT = 4 * PS;            // A hi, A lo, B hi, B lo
+constexpr int MB = 2, NB = 4;           // 32 x 32 blocks per wave
+typedef __attribute__((address_space(3))) void lds_t;
+typedef __attribute__((address_space(1))) void gbl_t;
+
+__device__ inline int off(int row, int chunk) { return row * ROW + ((chunk ^ ((row >> 2) & 1)) << 4); }
+
+// compiler-only ordering point around the raw barrier (emits no instruction)
+__device__ inline void order() { asm volatile("" ::: "memory"); }
+
+// wait until at most n of this wave's ring loads are outstanding
+__device__ inline void wait_vm(int n) {
+    if (n >= 8) __builtin_amdgcn_s_waitcnt(0x0f78);
+    else if (n >= 4) __builtin_amdgcn_s_waitcnt(0x0f74);
+    else __builtin_amdgcn_s_waitcnt(0x0f70);
+}
+}  // namespace dma
+
+__global__ void __launch_bounds__(dma::NT)
+gemm_bf16x3_dma_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
+                       const char* __restrict__ Q0, const char* __restrict__ Q1,
+                       int64_t ldk_bytes, int nk, int syr2k, int p, int T, int ntiles,
+                       double alpha, void* __restrict__ C, int out_store, int64_t ldc) {
+    using namespace dma;
+    __shared__ __attribute__((aligned(16))) char r0[SLOT];
+    __shared__ __attribute__((aligned(16))) char r1[SLOT];
+    __shared__ __attribute__((aligned(16))) char r2[SLOT];
+    __shared__ __attribute__((aligned(16))) char r3[SLOT];
+
+    int I, J;
+    tile_of(blockIdx.x, ntiles, T, I, J);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave / WN, wn = wave % WN;
+    const int64_t rowI0 = (int64_t)I * BT, rowJ0 = (int64_t)J * BT;
+    const int nkt = syr2k ? 2 * nk : nk;
+
+    // this wave's 4 load instructions per stage: plane-side ps, 32-row block rb
+    auto issue = [&](int kt, char* slot) {
+        const bool second = kt >= nk;
+        const int64_t kb = (int64_t)(second ? kt - nk : kt) * ROW;
+        const char* a0 = second ? Q0 : P0;
+        const char* a1 = second ? Q1 : P1;
+        const char* b0 = syr2k ? (second ? P0 : Q0) : P0;
+        const char* b1 = syr2k ? (second ? P1 : Q1) : P1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int m = wave * 4 + q;
+            const int ps = m >> 3, rb = m & 7;
+            const int row = rb * 32 + (lane >> 1);
+            const int c = (lane & 1) ^ ((row >> 2) & 1);
+            const char* base = ps == 0 ? a0 : (ps == 1 ? a1 : (ps == 2 ? b0 : b1));
+            const int64_t grow = (ps < 2 ? rowI0 : rowJ0) + row;
+            const char* g = base + grow * ldk_bytes + kb + c * 16;
+            __builtin_amdgcn_global_load_lds((gbl_t*)g, (lds_t*)(slot + ps * PS + rb * 1024), 16, 0, 0);
+        }
+    };
+
+    f32x16_t acc[MB][NB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    const int r32 = lane & 31, hk = lane >> 5;
+    auto compute = [&](const char* slot) {
+        bf16x8_t ah[MB], al[MB], bh[NB], bl[NB];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            const int o = off(wm * 64 + i * 32 + r32, hk);
+            ah[i] = *(const bf16x8_t*)(slot + o);
+            al[i] = *(const bf16x8_t*)(slot + PS + o);
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int o = off(wn * 128 + j * 32 + r32, hk);
+            bh[j] = *(const bf16x8_t*)(slot + 2 * PS + o);
+            bl[j] = *(const bf16x8_t*)(slot + 3 * PS + o);
+        }
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+    };
+    // one ring step: consume stage k from `cur`, refill `nxt` with stage k + 3
+    auto step = [&](int k, const char* cur, char* nxt) {
+        if (k >= nkt) return;
+        const int ahead = nkt - 1 - k < 2 ? nkt - 1 - k : 2;
+        wait_vm(4 * ahead);
+        order();
+        __builtin_amdgcn_s_barrier();
+        order();
+        if (k + 3 < nkt) issue(k + 3, nxt);
+        compute(cur);
+    };
+
+    issue(0, r0);
+    if (1 < nkt) issue(1, r1);
+    if (2 < nkt) issue(2, r2);
+    for (int kt = 0; kt < nkt; kt += 4) {
+        step(kt + 0, r0, r3);
+        step(kt + 1, r1, r0);
+        step(kt + 2, r2, r1);
+        step(kt + 3, r3, r2);
+    }
+    wait_vm(0);
+
+    // epilogue: symmetric store (same element layout as Form<GK_BF16X3>)
+    typedef Form<GK_BF16X3> F;
+    const int64_t gr0 = rowI0 + wm * 64, gc0 = rowJ0 + wn * 128;
+    if (I != J && out_store != ST_F64) {
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int64_t gj = gc0 + j * 32 + (lane & 31);
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int64_t gi0 = gr0 + i * 32 + 8 * g + 4 * (lane >> 5);
+                    uint32_t w[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const float x = (float)(alpha * (double)acc[i][j][4 * g + t]);
+                        if (out_store == ST_F32) {
+                            w[t] = __float_as_uint(x);
+                        } else {
+                            const uint16_t h = f2bf_rne(x);
+                            const uint16_t l = f2bf_rne(x - __uint_as_float(((uint32_t)h) << 16));
+                            w[t] = (uint32_t)h | ((uint32_t)l << 16);
+                        }
+                        if (gj < p && gi0 + t < p) ((uint32_t*)C)[(gi0 + t) * ldc + gj] = w[t];
+                    }
+                    if (gj < p) {
+                        if (gi0 + 3 < p) {
+                            *(u32x4_t*)((uint32_t*)C + gj * ldc + gi0) = u32x4_t{w[0], w[1], w[2], w[3]};
+                        } else {
+#pragma unroll
+                            for (int t = 0; t < 4; ++t)
+                                if (gi0 + t < p) ((uint32_t*)C)[gj * ldc + gi0 + t] = w[t];
+                        }
+                    }
+                }
+            }
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                int rr, cc;
+                F::coord(r, lane, rr, cc);
+                const int64_t gi = gr0 + i * 32 + rr, gj = gc0 + j * 32 + cc;
+                if (gi >= p || gj >= p) continue;
+                if (I == J && gi > gj) continue;
+                const double v = alpha * (double)acc[i][j][r];
+                store_val(C, out_store, gi * ldc + gj, v);
+                if (gi != gj) store_val(C, out_store, gj * ldc + gi, v);
+            }
+}
+
+hipError_t launch_bf16x3_dma(bool syr2k, const void* P0, const void* P1, const void* Q0,
+                             const void* Q1, int64_t ldk, int64_t p, double alpha, void* C,
+                             int out_store, int64_t ldc, hipStream_t stream) {
+    const int64_t ldk_bytes = ldk * 2;
+    if (ldk_bytes % dma::ROW) return hipErrorInvalidValue;
+    const int nk = (int)(ldk_bytes / dma::ROW);
+    const int T = (int)((p + dma::BT - 1) / dma::BT);
+    const int ntiles = T * (T + 1) / 2;
+    if (ntiles == 0 || nk == 0) return hipSuccess;
+    hipLaunchKernelGGL(gemm_bf16x3_dma_kernel, dim3(ntiles), dim3(dma::NT), 0, stream,
+                       (const char*)P0, (const char*)P1, (const char*)(syr2k ? Q0 : P0),
+                       (const char*)(syr2k ? Q1 : P1), ldk_bytes, nk, syr2k ? 1 : 0, (int)p, T,
+                       ntiles, alpha, C, out_store, ldc);
+    return hipGetLastError();
+}
+
+template <int KIND, int BT, int WM, int WN>
 hipError_t launch_kind(bool syr2k, const void* P0, const void* P1, const void* Q0,
                        const void* Q1, int64_t ldk, int64_t p, double alpha, void* C,
                        int out_store, int64_t ldc, hipStream_t stream) {
     typedef Form<KIND> F;
-    constexpr int BT = Cfg<KIND>::BT;
-    constexpr int NT = Cfg<KIND>::WM * Cfg<KIND>::WN * 64;
+    constexpr int NT = WM * WN * 64;
     const int64_t ldk_bytes = ldk * F::ELEM;
     if (ldk_bytes % ROWB) return hipErrorInvalidValue;
     const int nk = (int)(ldk_bytes / ROWB);
@@ -386,15 +588,95 @@ hipError_t launch_kind(bool syr2k, const void* P0, const void* P1, const void* Q
     const size_t lds = 2 * (2 * F::NPLANE * BT * ROWB);
     static std::once_flag attr_once;   // handles on several host threads may launch concurrently
     std::call_once(attr_once, [&] {
-        (void)hipFuncSetAttribute((const void*)gemm_sym_kernel<KIND>,
+        (void)hipFuncSetAttribute((const void*)gemm_sym_kernel<KIND, BT, WM, WN>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     });
     if (ntiles == 0 || nk == 0) return hipSuccess;
-    hipLaunchKernelGGL(gemm_sym_kernel<KIND>, dim3(ntiles), dim3(NT), lds, stream,
+    hipLaunchKernelGGL((gemm_sym_kernel<KIND, BT, WM, WN>), dim3(ntiles), dim3(NT), lds, stream,
                        (const char*)P0, (const char*)P1, (const char*)(syr2k ? Q0 : P0),
                        (const char*)(syr2k ? Q1 : P1), ldk_bytes, nk, syr2k ? 1 : 0, (int)p, T,
                        ntiles, alpha, C, out_store, ldc);
     return hipGetLastError();
+}
+
+// ---- variants and the autotuner ------------------------------------------------
+//
+// Variants per form: 256-wide tiles (8 waves, register-staged), 128-wide tiles (4
+// waves, register-staged) and, for the BF16 split, the 256-wide direct-to-LDS
+// ring.  All variants of a form produce bitwise-identical results (same
+// per-accumulator order of the K steps and of the three split products), so the
+// choice only affects speed.  The first contraction of a new shape key
+// (form, syr2k, p rounded up to 256, K) times every variant (after one warm-up
+// launch, best of two runs) with HIP events on the caller's stream and keeps the
+// fastest for the rest of the process.
+// CONCORD_GEMM_VARIANT=<index> forces a variant; CONCORD_TUNE_CACHE=<file> loads
+// and stores the choices as "form syr2k p256 ldk variant" lines.
+typedef hipError_t (*LaunchFn)(bool, const void*, const void*, const void*, const void*, int64_t,
+                               int64_t, double, void*, int, int64_t, hipStream_t);
+
+struct Variant {
+    const char* name;
+    LaunchFn fn;
+};
+
+const Variant* variants(int kind, int* count) {
+    static const Variant bf[] = {
+        {"bf16x3_256x256_w8", launch_kind<GK_BF16X3, 256, 4, 2>},
+        {"bf16x3_128x128_w4", launch_kind<GK_BF16X3, 128, 2, 2>},
+        {"bf16x3_256x256_w8_ldsring", launch_bf16x3_dma},
+    };
+    static const Variant f32[] = {
+        {"f32_256x256_w8", launch_kind<GK_F32, 256, 4, 2>},
+        {"f32_128x128_w4", launch_kind<GK_F32, 128, 2, 2>},
+    };
+    static const Variant f64[] = {
+        {"f64_128x128_w4", launch_kind<GK_F64, 128, 2, 2>},
+    };
+    switch (kind) {
+        case GK_BF16X3: *count = 3; return bf;
+        case GK_F32: *count = 2; return f32;
+        default: *count = 1; return f64;
+    }
+}
+
+struct TuneKey {
+    int kind, syr2k;
+    int64_t p256, ldk;
+    bool operator<(const TuneKey& o) const {
+        if (kind != o.kind) return kind < o.kind;
+        if (syr2k != o.syr2k) return syr2k < o.syr2k;
+        if (p256 != o.p256) return p256 < o.p256;
+        return ldk < o.ldk;
+    }
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+bool g_tune_loaded = false;
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("CONCORD_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    int kind, syr2k, v;
+    long long p256, ldk;
+    while (std::fscanf(f, "%d %d %lld %lld %d", &kind, &syr2k, &p256, &ldk, &v) == 5)
+        g_tune[TuneKey{kind, syr2k, (int64_t)p256, (int64_t)ldk}] = v;
+    std::fclose(f);
+}
+
+void tune_store_locked() {
+    const char* path = std::getenv("CONCORD_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "w");
+    if (!f) return;
+    for (const auto& kv : g_tune)
+        std::fprintf(f, "%d %d %lld %lld %d\n", kv.first.kind, kv.first.syr2k,
+                     (long long)kv.first.p256, (long long)kv.first.ldk, kv.second);
+    std::fclose(f);
 }
 
 }  // namespace
@@ -403,15 +685,66 @@ hipError_t launch_gemm_sym(int kind, bool syr2k, const void* P0, const void* P1,
                            const void* Q0, const void* Q1, int64_t ldk, int64_t p,
                            double alpha, void* C, int out_store, int64_t ldc,
                            hipStream_t stream) {
-    switch (kind) {
-        case GK_F64:
-            return launch_kind<GK_F64>(syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc, stream);
-        case GK_F32:
-            return launch_kind<GK_F32>(syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc, stream);
-        case GK_BF16X3:
-            return launch_kind<GK_BF16X3>(syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc, stream);
+    int nv = 0;
+    const Variant* V = variants(kind, &nv);
+    if (const char* e = std::getenv("CONCORD_GEMM_VARIANT")) {
+        const int v = std::atoi(e);
+        if (v >= 0 && v < nv)
+            return V[v].fn(syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc, stream);
     }
-    return hipErrorInvalidValue;
+    if (nv == 1) return V[0].fn(syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc, stream);
+    const TuneKey key{kind, syr2k ? 1 : 0, round_up(p, 256), ldk};
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end() && it->second >= 0 && it->second < nv)
+            return V[it->second].fn(syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc, stream);
+    }
+    // not tuned yet: time each variant once (each run writes the same result)
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
+        return V[0].fn(syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc, stream);
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return hipErrorOutOfMemory;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return hipErrorOutOfMemory;
+    }
+    int best = 0;
+    float best_ms = 1e30f;
+    // one untimed launch warms clocks and caches, then the best of two runs per variant
+    hipError_t err = V[0].fn(syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc, stream);
+    for (int v = 0; v < nv && err == hipSuccess; ++v) {
+        for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
+            (void)hipEventRecord(a, stream);
+            err = V[v].fn(syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc, stream);
+            (void)hipEventRecord(b, stream);
+            if (err == hipSuccess) err = hipEventSynchronize(b);
+            float ms = 0.f;
+            if (err == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess && ms < best_ms) {
+                best_ms = ms;
+                best = v;
+            }
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (err != hipSuccess) return err;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[key] = best;
+    tune_store_locked();
+    return hipSuccess;
+}
+
+int gemm_sym_choice(int kind, bool syr2k, int64_t p, int64_t ldk, const char** name) {
+    int nv = 0;
+    const Variant* V = variants(kind, &nv);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(TuneKey{kind, syr2k ? 1 : 0, round_up(p, 256), ldk});
+    const int v = it == g_tune.end() ? -1 : it->second;
+    if (name) *name = v >= 0 && v < nv ? V[v].name : "untuned";
+    return v;
 }
 
 }  // namespace concord

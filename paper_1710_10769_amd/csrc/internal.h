@@ -21,7 +21,6 @@ enum GemmKind : int {
     GK_BF16X3 = 2, // BF16 MFMA 32x32x16, hi*hi + hi*lo + lo*hi
 };
 
-constexpr int GEMM_BM = 128;   // output tile edge
 constexpr int ROW_PAD = 256;   // dense operands are allocated with rows padded to this
 constexpr int K_PAD = 64;      // and their K (column) dimension padded to this
 
@@ -32,7 +31,7 @@ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 // C = alpha * (P Q^T + Q P^T)  (syr2k)  or  alpha * P P^T  (syrk, Q ignored),
 // over the upper-triangle tiles only, written symmetrically (both triangles,
 // bitwise symmetric).  P and Q are prow x ldk row-major planes (prow a
-// multiple of 128, zero rows beyond p; ldk a multiple of 64, zero columns
+// multiple of 256, zero rows beyond p; ldk a multiple of 64, zero columns
 // beyond the true K).  For GK_BF16X3, P0/P1 and Q0/Q1 are the hi/lo planes
 // (uint16 bf16 bits); otherwise P0/Q0 hold float (GK_F32) or double (GK_F64).
 // out_store: ST_F32, ST_F64 or ST_B16P.
@@ -40,6 +39,9 @@ hipError_t launch_gemm_sym(int kind, bool syr2k, const void* P0, const void* P1,
                            const void* Q0, const void* Q1, int64_t ldk, int64_t p,
                            double alpha, void* C, int out_store, int64_t ldc,
                            hipStream_t stream);
+
+// Tuned variant index for a shape (-1 if not tuned yet) and its name.
+int gemm_sym_choice(int kind, bool syr2k, int64_t p, int64_t ldk, const char** name);
 
 // X (rows x cols, ld, F64 or F32) -> Xt (cols x ldo) in `store` (F64/F32);
 // optionally bf16 hi/lo planes (hi, lo may be null).  Scale applied on copy.

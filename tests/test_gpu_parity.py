@@ -250,3 +250,26 @@ def test_lambda1_max_closed_form_gpu():
     want = checks.diagonal_solution(S, w.lam2)
     assert np.abs(om.diagonal() - want).max() < 1e-5
     s.close()
+
+
+@pytest.mark.parametrize("variant,precision,nvar", [("obs", "bf16x3", 3), ("obs", "fp32", 2),
+                                                    ("cov", "bf16x3", 3), ("cov", "fp32", 2)])
+def test_contraction_variants_bitwise_equal(variant, precision, nvar, monkeypatch):
+    """Every tile variant the autotuner may pick gives bitwise the same iterates."""
+    torch = _torch()
+    p, n = 600, 260
+    w = datagen.make_workload("c2_obs_p20000", p=p, n=n)
+    X = _rounded(w.X, precision)
+    outs = []
+    for v in range(nvar):
+        monkeypatch.setenv("CONCORD_GEMM_VARIANT", str(v))
+        _say(f"variant {v} {variant} {precision} p={p} n={n}")
+        s = _solver(p, n, variant, precision)
+        s.set_data(_to_dev(X, torch.float32))
+        for _ in range(3):
+            s.step(0.12, w.lam2)
+        outs.append(s.get_omega_scipy())
+        s.close()
+    for o in outs[1:]:
+        d = o - outs[0]
+        assert d.nnz == 0 or np.abs(d.data).max() == 0.0
