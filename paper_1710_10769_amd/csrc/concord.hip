@@ -101,7 +101,8 @@ struct concord_ctx {
     double* part = nullptr;
     int64_t part_elems = 0;
     double* sums = nullptr;      // 64
-    double* objsums = nullptr;   // 64
+    double* objsums = nullptr;   // 64 + chunks
+    double* colsum_ws = nullptr; // (max columns) * COLSUM_MAXSEG segment sums
     DevState* st = nullptr;
     DevState* st_host = nullptr; // pinned
     int64_t* h_stage = nullptr;  // pinned, 4 int64
@@ -282,13 +283,13 @@ int products_at(concord_ctx* c, int which, const int* gate) {
                              split ? c->Y_lo : nullptr, sq, gate, c->stream));
         nysq = nch;
         HIPCK(c, launch_obj_parts(O, p, nullptr, c->dstore, 0, c->part, gate, c->stream));
-        HIPCK(c, launch_colsum(c->part, p, 4 + nch, c->objsums, c->stream));
+        HIPCK(c, launch_colsum(c->part, p, 4 + nch, c->objsums, c->colsum_ws, c->stream));
     } else {
         HIPCK(c, launch_spmm(O, p, c->S, c->sstore, c->ldp, c->ldp, c->M, c->dstore, c->ldp,
                              nullptr, nullptr, nullptr, gate, c->stream));
         HIPCK(c, launch_symmetrize(c->M, c->dstore, p, c->ldp, gate, c->stream));
         HIPCK(c, launch_obj_parts(O, p, c->M, c->dstore, c->ldp, c->part, gate, c->stream));
-        HIPCK(c, launch_colsum(c->part, p, 4, c->objsums, c->stream));
+        HIPCK(c, launch_colsum(c->part, p, 4, c->objsums, c->colsum_ws, c->stream));
     }
     hipLaunchKernelGGL(obj_finish_kernel, dim3(1), dim3(64), 0, c->stream, c->objsums, nysq, c->st,
                        gate);
@@ -381,7 +382,8 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
             HIPCK(c, launch_trial(c->A, p, tau0, m, lam1, c->variant, TB, tbstore, tld,
                                   c->variant == CONCORD_OBS ? c->ldk : 0, c->part, c->st,
                                   c->stream));
-            HIPCK(c, launch_colsum(c->part, p, 4 * m, c->sums, c->stream));
+            const int S = trial_splits(c->variant, tbstore, c->variant == CONCORD_OBS ? c->ldk : 0);
+            HIPCK(c, launch_colsum(c->part, (int64_t)S * p, 4 * m, c->sums, c->colsum_ws, c->stream));
             HIPCK(c, launch_decide(c->sums, m, tau0, q_base, lam2, c->variant, inv_n, forced_q,
                                    c->st, c->stream));
             prof_end(c);
@@ -567,10 +569,12 @@ int concord_create(const concord_config* cfg, concord_ctx** out) {
     if ((rc = ensure_cand_cap(c, cap0))) return bail(rc);
     if ((rc = dalloc_t(c, &c->cnt, p + 1, true))) return bail(rc);
     const int nch = c->variant == CONCORD_OBS ? spmm_nchunks(c->dstore, c->ldk) : 0;
-    c->part_elems = (int64_t)std::max(4 * MAXQ, 4 + nch) * p;
+    c->part_elems = (int64_t)std::max(4 * MAXQ * 8, 4 + nch) * p;   // trials: up to 8 column splits
     if ((rc = dalloc_t(c, &c->part, c->part_elems, true))) return bail(rc);
     if ((rc = dalloc_t(c, &c->sums, 64, true))) return bail(rc);
     if ((rc = dalloc_t(c, &c->objsums, 64 + nch, true))) return bail(rc);
+    if ((rc = dalloc_t(c, &c->colsum_ws, (size_t)std::max(4 * MAXQ, 4 + nch) * COLSUM_MAXSEG, true)))
+        return bail(rc);
     if ((rc = dalloc_t(c, &c->st, 1, true))) return bail(rc);
     if ((rc = dalloc_t(c, &c->d_one, 1, false))) return bail(rc);
     if ((rc = dalloc_t(c, &c->d_flags, 8, true))) return bail(rc);

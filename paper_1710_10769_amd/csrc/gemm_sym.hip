@@ -48,9 +48,11 @@ __device__ inline uint16_t f2bf_rne(float f) {
 }
 
 // LDS rows are 64 bytes; the four 16-byte chunks of a row are XOR-swizzled by
-// bits 1..2 of the row so that 8 consecutive rows read at the same logical
-// chunk hit 8 distinct 16-byte bank groups (conflict-free ds_read_b128).
-__device__ inline int swz(int row, int chunk) { return row * ROWB + ((chunk ^ ((row >> 1) & 3)) << 4); }
+// bits 2..3 of the row.  A 128-bit LDS read is serviced 16 lanes at a time over
+// 64 banks (a 256-byte period = four 64-byte rows): rows r..r+15 read at the same
+// logical chunk then hit 16 distinct 16-byte slots (row mod 4 picks the 64-byte
+// segment, the swizzled chunk the slot inside it), i.e. no bank conflict.
+__device__ inline int swz(int row, int chunk) { return row * ROWB + ((chunk ^ ((row >> 2) & 3)) << 4); }
 
 __device__ inline void tile_of(int w, int ntiles, int T, int& I, int& J) {
     // XCD-aware remap: hardware places workgroup w on XCD w % 8.  Give XCD x
@@ -226,7 +228,7 @@ __device__ inline void store_val(void* C, int store, int64_t idx, double v) {
     }
 }
 
-template <int KIND, int BT_, int WM_, int WN_>
+template <int KIND, int BT_, int WM_, int WN_, bool PERSIST>
 __global__ void __launch_bounds__(WM_ * WN_ * 64)
 gemm_sym_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
                 const char* __restrict__ Q0, const char* __restrict__ Q1, int64_t ldk_bytes,
@@ -243,8 +245,13 @@ gemm_sym_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
     constexpr int MB = WR / F::BS, NB = WC / F::BS;
     extern __shared__ __attribute__((aligned(16))) char smem[];
 
+    // PERSIST: one workgroup per CU walks tiles w, w + grid, w + 2 grid, ... Workgroup
+    // b runs on XCD b % 8 and the grid is a multiple of 8, so each XCD's workgroups
+    // advance through that XCD's contiguous run of the tile order in lockstep rounds
+    // (one round = one 8-row band x 4 columns), sharing their slabs in L2.
+    for (int w = blockIdx.x; w < ntiles; w += PERSIST ? (int)gridDim.x : ntiles) {
     int I, J;
-    tile_of(blockIdx.x, ntiles, T, I, J);
+    tile_of(w, ntiles, T, I, J);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WN, wn = wave % WN;
     const int64_t rowI0 = (int64_t)I * BT, rowJ0 = (int64_t)J * BT;
@@ -349,7 +356,7 @@ gemm_sym_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
                     }
                 }
             }
-        return;
+        continue;
     }
 #pragma unroll
     for (int i = 0; i < MB; ++i)
@@ -366,6 +373,7 @@ gemm_sym_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
                 store_val(C, out_store, gi * ldc + gj, v);
                 if (gi != gj) store_val(C, out_store, gj * ldc + gi, v);
             }
+    }  // tiles
 }
 
 // ---- BF16-split contraction with a direct-to-LDS load ring ---------------------
@@ -377,8 +385,8 @@ gemm_sym_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
 // loads of the stage about to be read (s_waitcnt vmcnt with the later stages
 // still in flight), then one s_barrier publishes the stage and frees the slot
 // that the next load overwrites.  Rows of 32 bytes hold two 16-byte chunks,
-// swapped on every other group of four rows, so eight consecutive rows read at
-// the same logical chunk fall in eight distinct 16-byte bank groups.
+// swapped on every other group of eight rows, so sixteen consecutive rows read at
+// the same logical chunk fall in sixteen distinct 16-byte bank groups.
 namespace dma {
 constexpr int BT = 256, NT = 512, WM = 4, WN = 2;
 constexpr int ROW = 32;                 // bytes per row, stage, plane
@@ -388,7 +396,8 @@ constexpr int MB = 2, NB = 4;           // 32 x 32 blocks per wave
 typedef __attribute__((address_space(3))) void lds_t;
 typedef __attribute__((address_space(1))) void gbl_t;
 
-__device__ inline int off(int row, int chunk) { return row * ROW + ((chunk ^ ((row >> 2) & 1)) << 4); }
+// 32-byte rows: eight rows per 256-byte bank period, so the chunk flips on bit 3
+__device__ inline int off(int row, int chunk) { return row * ROW + ((chunk ^ ((row >> 3) & 1)) << 4); }
 
 // compiler-only ordering point around the raw barrier (emits no instruction)
 __device__ inline void order() { asm volatile("" ::: "memory"); }
@@ -433,7 +442,7 @@ gemm_bf16x3_dma_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
             const int m = wave * 4 + q;
             const int ps = m >> 3, rb = m & 7;
             const int row = rb * 32 + (lane >> 1);
-            const int c = (lane & 1) ^ ((row >> 2) & 1);
+            const int c = (lane & 1) ^ ((row >> 3) & 1);
             const char* base = ps == 0 ? a0 : (ps == 1 ? a1 : (ps == 2 ? b0 : b1));
             const int64_t grow = (ps < 2 ? rowI0 : rowJ0) + row;
             const char* g = base + grow * ldk_bytes + kb + c * 16;
@@ -574,7 +583,18 @@ hipError_t launch_bf16x3_dma(bool syr2k, const void* P0, const void* P1, const v
     return hipGetLastError();
 }
 
-template <int KIND, int BT, int WM, int WN>
+int device_cus() {
+    static int cus = [] {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 8)
+            n = 256;
+        return n;
+    }();
+    return cus;
+}
+
+template <int KIND, int BT, int WM, int WN, bool PERSIST = false>
 hipError_t launch_kind(bool syr2k, const void* P0, const void* P1, const void* Q0,
                        const void* Q1, int64_t ldk, int64_t p, double alpha, void* C,
                        int out_store, int64_t ldc, hipStream_t stream) {
@@ -588,11 +608,18 @@ hipError_t launch_kind(bool syr2k, const void* P0, const void* P1, const void* Q
     const size_t lds = 2 * (2 * F::NPLANE * BT * ROWB);
     static std::once_flag attr_once;   // handles on several host threads may launch concurrently
     std::call_once(attr_once, [&] {
-        (void)hipFuncSetAttribute((const void*)gemm_sym_kernel<KIND, BT, WM, WN>,
+        (void)hipFuncSetAttribute((const void*)gemm_sym_kernel<KIND, BT, WM, WN, PERSIST>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     });
     if (ntiles == 0 || nk == 0) return hipSuccess;
-    hipLaunchKernelGGL((gemm_sym_kernel<KIND, BT, WM, WN>), dim3(ntiles), dim3(NT), lds, stream,
+    // persistent grid: one workgroup per CU (the 256-wide tiles hold 64-128 KB of LDS),
+    // rounded down to whole rounds of 8 XCDs
+    int grid = ntiles;
+    if (PERSIST) {
+        const int cus = device_cus() / 8 * 8;
+        grid = ntiles < cus ? ntiles : cus;
+    }
+    hipLaunchKernelGGL((gemm_sym_kernel<KIND, BT, WM, WN, PERSIST>), dim3(grid), dim3(NT), lds, stream,
                        (const char*)P0, (const char*)P1, (const char*)(syr2k ? Q0 : P0),
                        (const char*)(syr2k ? Q1 : P1), ldk_bytes, nk, syr2k ? 1 : 0, (int)p, T,
                        ntiles, alpha, C, out_store, ldc);
@@ -602,8 +629,8 @@ hipError_t launch_kind(bool syr2k, const void* P0, const void* P1, const void* Q
 // ---- variants and the autotuner ------------------------------------------------
 //
 // Variants per form: 256-wide tiles (8 waves, register-staged), 128-wide tiles (4
-// waves, register-staged) and, for the BF16 split, the 256-wide direct-to-LDS
-// ring.  All variants of a form produce bitwise-identical results (same
+// waves, register-staged), the 256-wide kernel as a persistent grid of one
+// workgroup per CU, and, for the BF16 split, the 256-wide direct-to-LDS ring.  All variants of a form produce bitwise-identical results (same
 // per-accumulator order of the K steps and of the three split products), so the
 // choice only affects speed.  The first contraction of a new shape key
 // (form, syr2k, p rounded up to 256, K) times every variant (after one warm-up
@@ -624,17 +651,19 @@ const Variant* variants(int kind, int* count) {
         {"bf16x3_256x256_w8", launch_kind<GK_BF16X3, 256, 4, 2>},
         {"bf16x3_128x128_w4", launch_kind<GK_BF16X3, 128, 2, 2>},
         {"bf16x3_256x256_w8_ldsring", launch_bf16x3_dma},
+        {"bf16x3_256x256_w8_persistent", launch_kind<GK_BF16X3, 256, 4, 2, true>},
     };
     static const Variant f32[] = {
         {"f32_256x256_w8", launch_kind<GK_F32, 256, 4, 2>},
         {"f32_128x128_w4", launch_kind<GK_F32, 128, 2, 2>},
+        {"f32_256x256_w8_persistent", launch_kind<GK_F32, 256, 4, 2, true>},
     };
     static const Variant f64[] = {
         {"f64_128x128_w4", launch_kind<GK_F64, 128, 2, 2>},
     };
     switch (kind) {
-        case GK_BF16X3: *count = 3; return bf;
-        case GK_F32: *count = 2; return f32;
+        case GK_BF16X3: *count = 4; return bf;
+        case GK_F32: *count = 3; return f32;
         default: *count = 1; return f64;
     }
 }

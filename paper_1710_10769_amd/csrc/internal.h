@@ -102,8 +102,11 @@ hipError_t launch_scan(const int64_t* cnt, int64_t p, int64_t* out, int64_t cap,
                        hipStream_t stream);
 
 struct DevState;
+// Column splits of the Obs quadratic term in launch_trial (1 for Cov).
+int trial_splits(int variant, int bstore, int64_t ncols);
 // Trial evaluation for `m` step sizes tau_q = tau0 * 2^-q (q < m) at once.
-// Per row partials part[(q*4 + t) * p + row], t = 0: sum x - log1p x over the
+// Per row partials part[((q*4 + t) * S + s) * p + row] for column split s < S =
+// trial_splits(...), t = 0: sum x - log1p x over the
 // diagonal, 1: ||Delta_i||^2, 2: quadratic term of row i, 3: 1 if the
 // diagonal entry is <= 0.  Obs quadratic: ||Delta_i X^T||^2 (B = Xt, ncols = n);
 // Cov quadratic: sum_{j,k in A_i} Delta_ij S_jk Delta_ik (B = S).
@@ -111,8 +114,10 @@ hipError_t launch_trial(const Cand& A, int64_t p, double tau0, int m, double lam
                         const void* B, int bstore, int64_t ldb, int64_t ncols, double* part,
                         const struct DevState* st, hipStream_t stream);
 
-// Deterministic FP64 column sums: in[c * rows + r] -> out[c], c < ncol.
-hipError_t launch_colsum(const double* in, int64_t rows, int ncol, double* out,
+// Deterministic FP64 column sums: in[c * rows + r] -> out[c], c < ncol.  ws holds
+// at least ncol * COLSUM_MAXSEG doubles (segment sums).
+constexpr int COLSUM_MAXSEG = 256;
+hipError_t launch_colsum(const double* in, int64_t rows, int ncol, double* out, double* ws,
                          hipStream_t stream);
 
 // Decision: given per-q sums (sum[q*4 + t]), picks the first passing q

@@ -369,12 +369,15 @@ trial_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
     const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
     if (row >= p) return;
     const int64_t s = arow[row], e = arow[row + 1];
+    // blockIdx.y = column split of the Obs quadratic term; split 0 also does the
+    // elementwise terms.  Partials land in part[((q*4 + t) * nsplit + split) * p + row].
+    const int split = blockIdx.y, nsplit = gridDim.y;
     double slog[MAXQ], sdd[MAXQ], squad[MAXQ], snp[MAXQ];
 #pragma unroll
     for (int q = 0; q < MAXQ; ++q) { slog[q] = 0; sdd[q] = 0; squad[q] = 0; snp[q] = 0; }
 
     // elementwise terms (lanes over entries)
-    for (int64_t k = s + lane; k < e; k += 64) {
+    for (int64_t k = s + lane; split == 0 && k < e; k += 64) {
         const int64_t j = acol[k];
         const double om = aom[k], g = agr[k];
         const bool diag = j == row;
@@ -399,7 +402,7 @@ trial_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
     // quadratic term
     if (OBS) {
         // ||Delta_i X^T||^2 over n columns: lanes over columns, loop over entries
-        for (int64_t c0 = 0; c0 < ncols; c0 += 64 * V) {
+        for (int64_t c0 = (int64_t)split * 64 * V; c0 < ncols; c0 += (int64_t)nsplit * 64 * V) {
             const int64_t c = c0 + lane * V;
             const bool act = c < ncols;
             T acc[MAXQ][V];
@@ -476,30 +479,44 @@ trial_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
             const double c2 = wave_sum(squad[q]);
             const double d2 = wave_sum(snp[q]);
             if (lane == 0) {
-                part[(int64_t)(q * 4 + 0) * p + row] = a;
-                part[(int64_t)(q * 4 + 1) * p + row] = b2;
-                part[(int64_t)(q * 4 + 2) * p + row] = c2;
-                part[(int64_t)(q * 4 + 3) * p + row] = d2;
+                part[((int64_t)(q * 4 + 0) * nsplit + split) * p + row] = a;
+                part[((int64_t)(q * 4 + 1) * nsplit + split) * p + row] = b2;
+                part[((int64_t)(q * 4 + 2) * nsplit + split) * p + row] = c2;
+                part[((int64_t)(q * 4 + 3) * nsplit + split) * p + row] = d2;
             }
         }
     }
 }
 
 // ---- column sums -----------------------------------------------------------------
+// Two fixed-order stages: block (c, b) sums segment b of column c (thread-strided,
+// then an LDS tree) into ws[c * nseg + b]; then one block per column adds its
+// nseg segment sums in order.  The association depends only on (rows, nseg), so
+// results are bitwise reproducible.
 __global__ void __launch_bounds__(NT)
-colsum_kernel(const double* __restrict__ in, int64_t rows, double* __restrict__ out) {
+colsum_seg_kernel(const double* __restrict__ in, int64_t rows, int64_t seg, double* __restrict__ ws) {
     __shared__ double red[NT];
-    const int c = blockIdx.x, t = threadIdx.x;
+    const int c = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
     const double* a = in + (int64_t)c * rows;
+    const int64_t lo = (int64_t)b * seg, hi = lo + seg < rows ? lo + seg : rows;
     double s = 0.0;
-    for (int64_t i = t; i < rows; i += NT) s += a[i];
+    for (int64_t i = lo + t; i < hi; i += NT) s += a[i];
     red[t] = s;
     __syncthreads();
     for (int o = NT / 2; o >= 1; o >>= 1) {
         if (t < o) red[t] += red[t + o];
         __syncthreads();
     }
-    if (t == 0) out[c] = red[0];
+    if (t == 0) ws[(int64_t)c * gridDim.y + b] = red[0];
+}
+
+__global__ void __launch_bounds__(64)
+colsum_fin_kernel(const double* __restrict__ ws, int nseg, double* __restrict__ out) {
+    if (threadIdx.x != 0) return;
+    const int c = blockIdx.x;
+    double s = 0.0;
+    for (int b = 0; b < nseg; ++b) s += ws[(int64_t)c * nseg + b];
+    out[c] = s;
 }
 
 // ---- decision ----------------------------------------------------------------
@@ -901,12 +918,21 @@ hipError_t launch_scan(const int64_t* cnt, int64_t p, int64_t* out, int64_t cap,
     return hipGetLastError();
 }
 
+// Splitting the Obs column loop over blocks was measured slower than one wave per
+// row at the benchmark shape (many tiny waves), so one split is used.
+int trial_splits(int variant, int bstore, int64_t ncols) {
+    (void)variant;
+    (void)bstore;
+    (void)ncols;
+    return 1;
+}
+
 hipError_t launch_trial(const Cand& A, int64_t p, double tau0, int m, double lam1, int variant,
                         const void* B, int bstore, int64_t ldb, int64_t ncols, double* part,
                         const DevState* st, hipStream_t stream) {
     if (p == 0) return hipSuccess;
     if (m < 1 || m > MAXQ) return hipErrorInvalidValue;
-    dim3 grid(blocks_for(p, WPB));
+    dim3 grid(blocks_for(p, WPB), trial_splits(variant, bstore, ncols));
 #define TRIAL(BS, OBS)                                                                       \
     hipLaunchKernelGGL((trial_kernel<BS, OBS>), grid, dim3(NT), 0, stream, A.rowptr, A.col,   \
                        A.omega, A.grad, p, tau0, m, lam1, B, ldb, ncols, part, st)
@@ -918,9 +944,19 @@ hipError_t launch_trial(const Cand& A, int64_t p, double tau0, int m, double lam
     return hipGetLastError();
 }
 
-hipError_t launch_colsum(const double* in, int64_t rows, int ncol, double* out,
+hipError_t launch_colsum(const double* in, int64_t rows, int ncol, double* out, double* ws,
                          hipStream_t stream) {
-    hipLaunchKernelGGL(colsum_kernel, dim3(ncol), dim3(NT), 0, stream, in, rows, out);
+    if (ncol <= 0) return hipSuccess;
+    const int64_t seg0 = 8192;
+    int nseg = (int)((rows + seg0 - 1) / seg0);
+    if (nseg < 1) nseg = 1;
+    if (nseg > COLSUM_MAXSEG) nseg = COLSUM_MAXSEG;
+    const int64_t seg = (rows + nseg - 1) / nseg;
+    // a single segment writes the column sums directly
+    hipLaunchKernelGGL(colsum_seg_kernel, dim3(ncol, nseg), dim3(NT), 0, stream, in, rows,
+                       seg < 1 ? 1 : seg, nseg == 1 ? out : ws);
+    if (nseg > 1)
+        hipLaunchKernelGGL(colsum_fin_kernel, dim3(ncol), dim3(64), 0, stream, ws, nseg, out);
     return hipGetLastError();
 }
 
