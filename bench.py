@@ -102,6 +102,44 @@ def cpu_baseline(X64, lam1, lam2):
             "seconds": sec}
 
 
+def bench_c1(args, torch, np, datagen):
+    """Small Cov FP64 solve (p = 200, n = 100, chain graph; lambda1 0.3, lambda2 0.1,
+    tol 1e-5 / 200 iterations): launch-latency bound, so it is reported with and
+    without graph replay.  A step is one whole solve; value = iterations/s with
+    graph replay."""
+    from paper_1710_10769_amd import Solver
+    w = datagen.make_workload("c1_cov_fp64_p200")
+    X = torch.from_numpy(w.X).cuda()
+    out = {}
+    for g in (False, True):
+        s = Solver(w.p, w.n, variant="cov", precision="fp64", use_graph=g)
+        s.set_data(X)
+        times, iters = [], 0
+        for rep in range(args.warmup + args.steps):
+            s.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            si = s.solve(w.lam1, w.lam2, w.tol, w.max_iter)
+            torch.cuda.synchronize()
+            if rep >= args.warmup:
+                times.append(time.perf_counter() - t0)
+                iters = si.iters
+        s.close()
+        out[g] = (iters, float(np.median(times)))
+        log(f"graph={g}: {iters} iterations in {out[g][1] * 1e3:.3f} ms")
+    it, sec = out[True]
+    line = {
+        "metric": "prox-grad iters/sec, Cov FP64 p=200 (launch-latency bound)",
+        "value": it / sec, "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "cov_chain_p200_n100", "p": w.p, "n": w.n, "lam1": w.lam1,
+                   "lam2": w.lam2, "iterations": it},
+        "without_graph": {"value": out[False][0] / out[False][1], "ms_per_solve": out[False][1] * 1e3},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def bench_c4(args, torch, np, datagen):
     """Batched lambda path: 48 Cov instances (p in {1k, 2k, 4k, 8k}, n = p/2), each
     solved at lambda1 in {0.2, 0.3, 0.5} from Omega = I (FP32 products, FP64
@@ -149,8 +187,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--p", type=int, default=20000)
     ap.add_argument("--n", type=int, default=5000)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4"],
-                    help="c2: the Obs p=20k headline; c4: the batched lambda path")
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4"],
+                    help="c2: the Obs p=20k headline; c1: the small Cov FP64 solve; "
+                         "c4: the batched lambda path")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -167,6 +206,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "c4":
         return bench_c4(args, torch, np, datagen)
+    if args.workload == "c1":
+        return bench_c1(args, torch, np, datagen)
     p, n = args.p, args.n
     if args.copy_probe_mib:
         src = torch.ones(args.copy_probe_mib * 262144, dtype=torch.float32, device="cuda")

@@ -89,7 +89,10 @@ typedef struct concord_config {
     int32_t device;         /* HIP device ordinal; -1 = the current device */
     int32_t max_backtracks; /* step-size halvings allowed per iteration (default 60) */
     int32_t trial_batch;    /* step sizes evaluated together per launch, 1..8 (default 8) */
-    int32_t reserved;
+    int32_t use_graph;      /* 1: the handle works on a stream of its own (ordered after
+                               `stream` at every call) and replays each iteration's common
+                               path (contraction, candidates, first trial batch, accept) as
+                               one captured HIP graph; 0 (default): direct launches */
 } concord_config;
 
 /* Per-iteration record (Algorithm 1, one pass of the outer loop). */
@@ -116,7 +119,7 @@ typedef struct concord_solve_info {
 } concord_solve_info;
 
 /* Fill *cfg with defaults: variant COV, precision FP64, stream NULL,
-   device -1, max_backtracks 60, trial_batch 8, p = n = 0. */
+   device -1, max_backtracks 60, trial_batch 8, use_graph 0, p = n = 0. */
 void concord_config_init(concord_config* cfg);
 
 /* Create a handle for problems of size p (and n).  Allocates the workspace

@@ -114,6 +114,17 @@ struct concord_ctx {
 
     std::vector<void*> allocs;
 
+    // graph replay of the common step path
+    bool use_graph = false;
+    hipStream_t user_stream = nullptr;   // caller's stream when the handle runs on its own
+    hipEvent_t enter_ev = nullptr;
+    int64_t gen = 0;                     // bumped whenever a captured buffer is reallocated
+    struct StepGraph {
+        hipGraphExec_t exec = nullptr;
+        double lam1 = -1, lam2 = -1;
+        int64_t gen = -1;
+    } graphs[2];
+
     // profiling
     bool prof = false;
     hipEvent_t ev[16][2] = {};
@@ -203,6 +214,7 @@ int ensure_csr_cap(concord_ctx* c, int which, int64_t cap) {
     if ((rc = dalloc_t(c, &o.col, cap))) return rc;
     if ((rc = dalloc_t(c, &o.val, cap))) return rc;
     c->om_cap[which] = cap;
+    c->gen += 1;
     return CONCORD_OK;
 }
 
@@ -216,6 +228,7 @@ int ensure_cand_cap(concord_ctx* c, int64_t cap) {
     if ((rc = dalloc_t(c, &c->A.omega, cap))) return rc;
     if ((rc = dalloc_t(c, &c->A.grad, cap))) return rc;
     c->a_cap = cap;
+    c->gen += 1;
     return CONCORD_OK;
 }
 
@@ -244,6 +257,14 @@ void prof_collect(concord_ctx* c) {
         }
     }
     c->nrec = 0;
+}
+
+// When the handle runs on its own stream, make it wait for the caller's stream.
+int enter(concord_ctx* c) {
+    if (!c->use_graph) return CONCORD_OK;
+    HIPCK(c, hipEventRecord(c->enter_ev, c->user_stream));
+    HIPCK(c, hipStreamWaitEvent(c->stream, c->enter_ev, 0));
+    return CONCORD_OK;
 }
 
 int sync_state(concord_ctx* c) {
@@ -335,32 +356,37 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
     if (forced_trials > c->max_bt + 1)
         return fail(c, CONCORD_EINVAL, "forced trial count exceeds max_backtracks + 1");
     DeviceGuard g(c->device);
+    if (int rc0 = enter(c)) return rc0;
     int rc = ensure_dense(c);
     if (rc) return rc;
     if ((rc = ensure_products(c))) return rc;
     const int64_t p = c->p;
 
-    // gradient-side dense product
-    if (c->variant == CONCORD_OBS) {
+    const int nxt = c->cur ^ 1;
+    const double inv_n = c->variant == CONCORD_OBS ? 1.0 / (double)c->n : 1.0;
+    const void* TB = c->variant == CONCORD_OBS ? c->Xt : c->S;
+    const int tbstore = c->variant == CONCORD_OBS ? c->dstore : c->sstore;
+    const int64_t tld = c->variant == CONCORD_OBS ? c->ldk : c->ldp;
+    const int forced_q = forced_trials >= 1 ? forced_trials - 1 : -1;
+    const int total = c->max_bt + 1;   // step sizes 1 .. 2^-max_bt
+
+    // gradient-side dense product (Obs): M = (Y X + (Y X)^T) / (2n)
+    auto enqueue_gemm = [&]() -> int {
+        if (c->variant != CONCORD_OBS) return CONCORD_OK;
         const bool split = c->precision == CONCORD_BF16X3;
         const void* P0 = split ? (const void*)c->Y_hi : c->Y;
         const void* P1 = split ? (const void*)c->Y_lo : nullptr;
         const void* Q0 = split ? (const void*)c->Xt_hi : c->Xt;
         const void* Q1 = split ? (const void*)c->Xt_lo : nullptr;
         prof_begin(c, CONCORD_PROF_DENSE);
-        HIPCK(c, launch_gemm_sym(c->gkind, true, P0, P1, Q0, Q1, c->ldk, p,
-                                 0.5 / (double)c->n, c->M, c->dstore, c->ldp, c->stream));
+        HIPCK(c, launch_gemm_sym(c->gkind, true, P0, P1, Q0, Q1, c->ldk, p, 0.5 / (double)c->n,
+                                 c->M, c->dstore, c->ldp, c->stream));
         prof_end(c);
-    }
-    const int nxt = c->cur ^ 1;
-    const double inv_n = c->variant == CONCORD_OBS ? 1.0 / (double)c->n : 1.0;
-    const void* TB = c->variant == CONCORD_OBS ? c->Xt : c->S;
-    const int tbstore = c->variant == CONCORD_OBS ? c->dstore : c->sstore;
-    const int64_t tld = c->variant == CONCORD_OBS ? c->ldk : c->ldp;
-
-    for (int attempt = 0; attempt < 8; ++attempt) {
+        return CONCORD_OK;
+    };
+    // candidate set A of this iteration
+    auto enqueue_cands = [&]() -> int {
         hipLaunchKernelGGL(state_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->st);
-        // candidate set
         prof_begin(c, CONCORD_PROF_CAND);
         HIPCK(c, launch_cand_count(c->M, c->dstore, c->ldp, c->om[c->cur], p, lam1, c->bitmap,
                                    c->nwords, c->cnt, c->stream));
@@ -368,37 +394,92 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
         HIPCK(c, launch_cand_fill(c->M, c->dstore, c->ldp, c->om[c->cur], p, lam2, c->bitmap,
                                   c->nwords, c->A, c->a_cap, &c->st->overflow, c->stream));
         prof_end(c);
-        if ((rc = ensure_csr_cap(c, nxt, c->a_cap))) return rc;
+        return CONCORD_OK;
+    };
+    // one batch of step sizes tau0 * 2^-q, q < m, then emission, products and
+    // objective at Omega+ (gated on the device-side decision) and the read-back
+    auto enqueue_batch = [&](int q_base, int m) -> int {
+        const double tau0 = std::ldexp(1.0, -q_base);
+        prof_begin(c, CONCORD_PROF_TRIAL);
+        HIPCK(c, launch_trial(c->A, p, tau0, m, lam1, c->variant, TB, tbstore, tld,
+                              c->variant == CONCORD_OBS ? c->ldk : 0, c->part, c->st, c->stream));
+        const int S = trial_splits(c->variant, tbstore, c->variant == CONCORD_OBS ? c->ldk : 0);
+        HIPCK(c, launch_colsum(c->part, (int64_t)S * p, 4 * m, c->sums, c->colsum_ws, c->stream));
+        HIPCK(c, launch_decide(c->sums, m, tau0, q_base, lam2, c->variant, inv_n, forced_q, c->st,
+                               c->stream));
+        prof_end(c);
+        prof_begin(c, CONCORD_PROF_EMIT);
+        HIPCK(c, launch_emit_count(c->A, p, lam1, c->st, c->cnt, c->stream));
+        HIPCK(c, launch_scan(c->cnt, p, c->om[nxt].rowptr, c->om_cap[nxt], nullptr, c->stream));
+        HIPCK(c, launch_emit_fill(c->A, p, lam1, c->st, c->om[nxt], c->stream));
+        prof_end(c);
+        int rc2 = products_at(c, nxt, &c->st->accepted);
+        if (rc2) return rc2;
+        HIPCK(c, hipMemcpyAsync(c->h_stage, c->om[nxt].rowptr + p, sizeof(int64_t),
+                                hipMemcpyDeviceToHost, c->stream));
+        HIPCK(c, hipMemcpyAsync(c->h_stage + 1, c->A.rowptr + p, sizeof(int64_t),
+                                hipMemcpyDeviceToHost, c->stream));
+        HIPCK(c, hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost,
+                                c->stream));
+        return CONCORD_OK;
+    };
 
-        const int total = c->max_bt + 1;   // step sizes 1 .. 2^-max_bt
-        int q_base = 0, batches = 0;
-        const int forced_q = forced_trials >= 1 ? forced_trials - 1 : -1;
-        if (forced_q >= 0) q_base = forced_q;
+    // Common path as one graph launch: contraction, candidates and the first batch.
+    // Used after the first iteration of a handle (the contraction's tile variant is
+    // chosen by timing on its first call, which cannot happen inside a capture).
+    const int m0 = std::min(c->tb, total);
+    bool first_done = false;
+    if (c->use_graph && !c->prof && forced_q < 0 && c->k > 0) {
+        if ((rc = ensure_csr_cap(c, nxt, c->a_cap))) return rc;
+        if ((rc = ensure_csr_cap(c, c->cur, c->a_cap))) return rc;
+        concord_ctx::StepGraph& sg = c->graphs[c->cur];
+        if (!sg.exec || sg.lam1 != lam1 || sg.lam2 != lam2 || sg.gen != c->gen) {
+            if (sg.exec) {
+                (void)hipGraphExecDestroy(sg.exec);
+                sg.exec = nullptr;
+            }
+            hipGraph_t g = nullptr;
+            HIPCK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            int rc1 = enqueue_gemm();
+            if (!rc1) rc1 = enqueue_cands();
+            if (!rc1) rc1 = enqueue_batch(0, m0);
+            hipError_t ec = hipStreamEndCapture(c->stream, &g);
+            if (rc1) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc1;
+            }
+            HIPCK(c, ec);
+            hipError_t ei = hipGraphInstantiate(&sg.exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIPCK(c, ei);
+            sg.lam1 = lam1;
+            sg.lam2 = lam2;
+            sg.gen = c->gen;
+        }
+        HIPCK(c, hipGraphLaunch(sg.exec, c->stream));
+        HIPCK(c, hipStreamSynchronize(c->stream));
+        prof_collect(c);
+        first_done = true;
+    } else {
+        if ((rc = enqueue_gemm())) return rc;
+    }
+
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        int q_base = forced_q >= 0 ? forced_q : 0, batches = 0;
         bool overflow = false, accepted = false;
+        if (!first_done) {
+            if ((rc = enqueue_cands())) return rc;
+            if ((rc = ensure_csr_cap(c, nxt, c->a_cap))) return rc;
+        }
         while (q_base < total) {
             const int m = forced_q >= 0 ? 1 : std::min(c->tb, total - q_base);
-            const double tau0 = std::ldexp(1.0, -q_base);
-            prof_begin(c, CONCORD_PROF_TRIAL);
-            HIPCK(c, launch_trial(c->A, p, tau0, m, lam1, c->variant, TB, tbstore, tld,
-                                  c->variant == CONCORD_OBS ? c->ldk : 0, c->part, c->st,
-                                  c->stream));
-            const int S = trial_splits(c->variant, tbstore, c->variant == CONCORD_OBS ? c->ldk : 0);
-            HIPCK(c, launch_colsum(c->part, (int64_t)S * p, 4 * m, c->sums, c->colsum_ws, c->stream));
-            HIPCK(c, launch_decide(c->sums, m, tau0, q_base, lam2, c->variant, inv_n, forced_q,
-                                   c->st, c->stream));
-            prof_end(c);
-            // emission and products at Omega+ (all gated on the decision)
-            prof_begin(c, CONCORD_PROF_EMIT);
-            HIPCK(c, launch_emit_count(c->A, p, lam1, c->st, c->cnt, c->stream));
-            HIPCK(c, launch_scan(c->cnt, p, c->om[nxt].rowptr, c->om_cap[nxt], nullptr, c->stream));
-            HIPCK(c, launch_emit_fill(c->A, p, lam1, c->st, c->om[nxt], c->stream));
-            prof_end(c);
-            if ((rc = products_at(c, nxt, &c->st->accepted))) return rc;
-            HIPCK(c, hipMemcpyAsync(c->h_stage, c->om[nxt].rowptr + p, sizeof(int64_t),
-                                    hipMemcpyDeviceToHost, c->stream));
-            HIPCK(c, hipMemcpyAsync(c->h_stage + 1, c->A.rowptr + p, sizeof(int64_t),
-                                    hipMemcpyDeviceToHost, c->stream));
-            if ((rc = sync_state(c))) return rc;
+            if (first_done) {
+                first_done = false;   // the graph ran candidates and this batch
+            } else {
+                if ((rc = enqueue_batch(q_base, m))) return rc;
+                HIPCK(c, hipStreamSynchronize(c->stream));
+                prof_collect(c);
+            }
             ++batches;
             if (c->st_host->overflow) { overflow = true; break; }
             if (c->st_host->accepted_q >= 0) { accepted = true; break; }
@@ -489,6 +570,13 @@ void concord_destroy(concord_ctx* ctx) {
         for (int s = 0; s < 16; ++s)
             for (int t = 0; t < 2; ++t)
                 if (ctx->ev[s][t]) hipEventDestroy(ctx->ev[s][t]);
+        for (auto& sg : ctx->graphs)
+            if (sg.exec) hipGraphExecDestroy(sg.exec);
+        if (ctx->use_graph) {
+            hipStreamSynchronize(ctx->stream);
+            hipStreamDestroy(ctx->stream);
+            if (ctx->enter_ev) hipEventDestroy(ctx->enter_ev);
+        }
         for (void* a : ctx->allocs)
             if (a) hipFree(a);
         if (ctx->st_host) hipHostFree(ctx->st_host);
@@ -525,7 +613,17 @@ int concord_create(const concord_config* cfg, concord_ctx** out) {
     c->device = dev;
     c->max_bt = cfg->max_backtracks;
     c->tb = cfg->trial_batch;
+    c->use_graph = cfg->use_graph != 0;
     DeviceGuard g(dev);
+    if (c->use_graph) {
+        // captures need a stream of our own (the caller's may be the null stream)
+        c->user_stream = c->stream;
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&c->enter_ev, hipEventDisableTiming) != hipSuccess) {
+            c->use_graph = false;
+            c->stream = c->user_stream;
+        }
+    }
 
     c->dstore = c->precision == CONCORD_FP64 ? ST_F64 : ST_F32;
     c->sstore = c->precision == CONCORD_FP64 ? ST_F64 : (c->precision == CONCORD_FP32 ? ST_F32 : ST_B16P);
@@ -596,6 +694,7 @@ int concord_set_data(concord_ctx* c, int32_t kind, const void* dev_data, int32_t
     if (dtype != CONCORD_F64 && dtype != CONCORD_F32) return fail(c, CONCORD_EINVAL, "dtype");
     if (ld < cols) return fail(c, CONCORD_EINVAL, "ld < cols");
     DeviceGuard g(c->device);
+    if (int rc0 = enter(c)) return rc0;
     const int is64 = dtype == CONCORD_F64;
     if (kind == CONCORD_DATA_X) {
         if (rows != c->n || cols != c->p)
@@ -644,6 +743,7 @@ int concord_set_omega(concord_ctx* c, int64_t nnz, const int64_t* dev_row_ptr,
         return fail(c, CONCORD_EINVAL, "bad CSR arguments");
     if (dtype != CONCORD_F64 && dtype != CONCORD_F32) return fail(c, CONCORD_EINVAL, "dtype");
     DeviceGuard g(c->device);
+    if (int rc0 = enter(c)) return rc0;
     hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, c->stream, c->d_flags, 0);
     hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, c->stream, c->d_flags + 1, 0);
     hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, c->stream, c->d_flags + 2, 0);
@@ -744,6 +844,7 @@ int concord_get_omega(concord_ctx* c, int64_t* host_nnz, int64_t* dev_row_ptr, i
     if (!dev_col || !dev_val) return fail(c, CONCORD_EINVAL, "col/val must be given with row_ptr");
     if (dtype != CONCORD_F64 && dtype != CONCORD_F32) return fail(c, CONCORD_EINVAL, "dtype");
     DeviceGuard g(c->device);
+    if (int rc0 = enter(c)) return rc0;
     const Csr& o = c->om[c->cur];
     HIPCK(c, hipMemcpyAsync(dev_row_ptr, o.rowptr, (c->p + 1) * sizeof(int64_t),
                             hipMemcpyDeviceToDevice, c->stream));
@@ -772,6 +873,7 @@ int concord_gradient(concord_ctx* c, double lam2, int32_t mode, void* dev_dOmega
         return fail(c, CONCORD_EINVAL, "mode");
     if (dtype != CONCORD_F64 && dtype != CONCORD_F32) return fail(c, CONCORD_EINVAL, "dtype");
     DeviceGuard g(c->device);
+    if (int rc0 = enter(c)) return rc0;
     int rc = ensure_products(c);   // Y at the current iterate (recomputed if stale)
     if (rc) return rc;
     const bool split = c->precision == CONCORD_BF16X3;

@@ -273,3 +273,27 @@ def test_contraction_variants_bitwise_equal(variant, precision, nvar, monkeypatc
     for o in outs[1:]:
         d = o - outs[0]
         assert d.nnz == 0 or np.abs(d.data).max() == 0.0
+
+
+@pytest.mark.parametrize("variant,precision,lam1,p,n", [
+    ("cov", "fp64", 0.3, 200, 100),      # the C1 shape
+    ("obs", "bf16x3", 0.12, 700, 300),
+    ("cov", "fp32", 0.01, 300, 120),     # dense candidate sets: capacity regrowth under graphs
+])
+def test_graph_replay_matches_direct_launches(variant, precision, lam1, p, n):
+    torch = _torch()
+    w = datagen.make_workload("c2_obs_p20000", p=p, n=n)
+    X = _rounded(w.X, precision)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    runs = []
+    for g in (False, True):
+        _say(f"graph={g} {variant} {precision} p={p} n={n} lam1={lam1}")
+        s = _solver(p, n, variant, precision, use_graph=g)
+        s.set_data(_to_dev(X, dt))
+        infos = [s.step(lam1, w.lam2) for _ in range(6)]
+        infos += [s.step(lam1 * 1.5, w.lam2) for _ in range(3)]   # new lambda -> new capture
+        runs.append(([(i.tau, i.F, i.nnz) for i in infos], s.get_omega_scipy()))
+        s.close()
+    assert runs[0][0] == runs[1][0]
+    d = runs[0][1] - runs[1][1]
+    assert d.nnz == 0 or np.abs(d.data).max() == 0.0
