@@ -140,6 +140,106 @@ def bench_c1(args, torch, np, datagen):
     print(json.dumps(line), flush=True)
 
 
+def bench_c3(args, torch, np, datagen):
+    """Cov precision forms at p = 16,384, n = 4,096 (random degree 8; lambda1 0.3,
+    lambda2 0.1, tol 1e-5 / 200): S formed once on MFMA, then the solve.  Each
+    form is timed; its final Omega is compared with the FP64 form's."""
+    from paper_1710_10769_amd import Solver
+    log("generating c3 workload")
+    w = datagen.make_workload("c3_cov_p16384", backend="torch", device="cuda")
+    X32 = torch.from_numpy(w.X.astype(np.float32)).cuda()
+    X64 = X32.double()
+    res, oms = {}, {}
+    for form in ("fp64", "fp32", "bf16x3"):
+        s = Solver(w.p, w.n, variant="cov", precision=form)
+        s.set_profiling(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.set_data(X64 if form == "fp64" else X32)
+        torch.cuda.synchronize()
+        t_s = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        si = s.solve(w.lam1, w.lam2, w.tol, w.max_iter)
+        torch.cuda.synchronize()
+        t_solve = time.perf_counter() - t0
+        prof = s.profile()
+        oms[form] = s.get_omega_scipy()
+        s.close()
+        spmm_ms = prof["spmm"][0] / max(prof["spmm"][1], 1)
+        eb = 8 if form == "fp64" else 4
+        # W = Omega S (read S, write W), symmetrise (read + write W): 4 p^2 elements
+        gbs = 4.0 * w.p * w.p * eb / (spmm_ms * 1e-3) / 1e9
+        res[form] = {"iters": si.iters, "iters_per_s": si.iters / t_solve, "solve_s": t_solve,
+                     "s_formation_s": t_s, "nnz": si.nnz, "F": si.F,
+                     "refresh_ms": spmm_ms, "refresh_GBps": gbs,
+                     "kernel_ms_per_iter": {k: v[0] / max(si.iters, 1) for k, v in prof.items()}}
+        log(f"{form}: {si.iters} iterations, {t_solve:.3f} s, S in {t_s:.3f} s")
+    ref = oms["fp64"]
+    scale = float(np.abs(ref.data).max())
+    for form in ("fp32", "bf16x3"):
+        d = oms[form] - ref
+        res[form]["max_abs_diff_vs_fp64_rel"] = (float(np.abs(d.data).max()) if d.nnz else 0.0) / scale
+        g, r = oms[form].copy(), ref.copy()
+        g.data[:] = 1; r.data[:] = 1
+        res[form]["support_mismatches_vs_fp64"] = int((abs(g - r)).nnz)
+    line = {
+        "metric": "Cov prox-grad iters/sec at p=16,384 per precision form",
+        "value": res["bf16x3"]["iters_per_s"], "unit": "iters/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": 1e3 / res["bf16x3"]["iters_per_s"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3",
+        "data": "synthetic",
+        "config": {"workload": "cov_random_deg8_p16384_n4096", "p": w.p, "n": w.n,
+                   "lam1": w.lam1, "lam2": w.lam2, "tol": w.tol},
+        "forms": res,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_c5(args, torch, np, datagen):
+    """Differentiation form at p = 200,000, n = 1,000 (random degree 20), FP32:
+    forward f(Omega; X) and backward (d f / d Omega on the stored entries, d f / d X)."""
+    import scipy.sparse as sp
+    from paper_1710_10769_amd import Solver
+    from paper_1710_10769_amd.autograd import concord_smooth
+    log("generating c5 workload (B B^T + CG)")
+    w = datagen.make_workload("c5_grad_p200000", backend="torch", device="cuda")
+    rng = np.random.Generator(np.random.PCG64(505))
+    om = sp.csr_matrix(datagen.perturb_symmetric(w.omega0, rng, 0.1))
+    rp = torch.from_numpy(om.indptr.astype(np.int64)).cuda()
+    cl = torch.from_numpy(om.indices.astype(np.int32)).cuda()
+    vals = torch.from_numpy(om.data.astype(np.float32)).cuda()
+    X = torch.from_numpy(w.X.astype(np.float32)).cuda()
+    s = Solver(w.p, w.n, variant="obs", precision="fp32")
+    fw, bw = [], []
+    for rep in range(args.warmup + args.steps):
+        v = vals.clone().requires_grad_(True)
+        x = X.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f = concord_smooth(v, x, rp, cl, w.lam2, s)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        f.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if rep >= args.warmup:
+            fw.append(t1 - t0)
+            bw.append(t2 - t1)
+    s.close()
+    tf, tb = float(np.median(fw)), float(np.median(bw))
+    line = {
+        "metric": "differentiation form forward+backward per second at p=200,000",
+        "value": 1.0 / (tf + tb), "unit": "fwd+bwd/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": (tf + tb) * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": "obs_grad_random_deg20_p200000_n1000", "p": w.p, "n": w.n,
+                   "nnz": int(om.nnz), "lam2": w.lam2},
+        "forward_ms": tf * 1e3, "backward_ms": tb * 1e3,
+        "note": "forward includes X ingest (transpose to variable-major) and the CSR copy-in",
+    }
+    print(json.dumps(line), flush=True)
+
+
 def bench_c4(args, torch, np, datagen):
     """Batched lambda path: 48 Cov instances (p in {1k, 2k, 4k, 8k}, n = p/2), each
     solved at lambda1 in {0.2, 0.3, 0.5} from Omega = I (FP32 products, FP64
@@ -187,7 +287,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--p", type=int, default=20000)
     ap.add_argument("--n", type=int, default=5000)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4"],
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
                     help="c2: the Obs p=20k headline; c1: the small Cov FP64 solve; "
                          "c4: the batched lambda path")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -208,6 +308,10 @@ def main():
         return bench_c4(args, torch, np, datagen)
     if args.workload == "c1":
         return bench_c1(args, torch, np, datagen)
+    if args.workload == "c3":
+        return bench_c3(args, torch, np, datagen)
+    if args.workload == "c5":
+        return bench_c5(args, torch, np, datagen)
     p, n = args.p, args.n
     if args.copy_probe_mib:
         src = torch.ones(args.copy_probe_mib * 262144, dtype=torch.float32, device="cuda")

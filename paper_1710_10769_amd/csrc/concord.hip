@@ -85,6 +85,7 @@ struct concord_ctx {
     uint16_t* Y_lo = nullptr;
     void* S = nullptr;
     void* M = nullptr;
+    void* dxt = nullptr;   // differentiation form: Omega Y before its transpose
 
     Csr om[2] = {};
     int64_t om_cap[2] = {0, 0};
@@ -893,17 +894,14 @@ int concord_gradient(concord_ctx* c, double lam2, int32_t mode, void* dev_dOmega
         }
     }
     if (dev_dX) {
-        // d f / d X^T = Omega Y / n, written transposed (n x p); the product
-        // goes through the Y buffer's twin (M is large enough: p x ldp >= p x ldk
-        // is not guaranteed, so use a temporary).
-        void* tmp = nullptr;
-        if ((rc = dalloc(c, &tmp, (size_t)c->prow * c->ldk * elem_bytes(c->dstore), true))) return rc;
-        HIPCK(c, launch_spmm(O, c->p, c->Y, c->dstore, c->ldk, c->ldk, tmp, c->dstore, c->ldk,
+        // d f / d X^T = Omega Y / n, formed in a handle-owned p x n buffer (kept for
+        // later calls) and written transposed (n x p).
+        if (!c->dxt && (rc = dalloc(c, &c->dxt, (size_t)c->prow * c->ldk * elem_bytes(c->dstore), true)))
+            return rc;
+        HIPCK(c, launch_spmm(O, c->p, c->Y, c->dstore, c->ldk, c->ldk, c->dxt, c->dstore, c->ldk,
                              nullptr, nullptr, nullptr, c->d_one, c->stream));
-        HIPCK(c, launch_transpose_out(tmp, c->dstore, c->p, c->n, c->ldk, 1.0 / (double)c->n,
+        HIPCK(c, launch_transpose_out(c->dxt, c->dstore, c->p, c->n, c->ldk, 1.0 / (double)c->n,
                                       dev_dX, out64, c->stream));
-        HIPCK(c, hipStreamSynchronize(c->stream));
-        dfree(c, tmp);
     }
     HIPCK(c, hipStreamSynchronize(c->stream));
     return CONCORD_OK;

@@ -729,8 +729,12 @@ __global__ void check_finite_kernel(const In* __restrict__ A, int64_t rows, int6
 }
 
 // ---- differentiation form ------------------------------------------------------
-// G_ij on the stored entries: ( <Y_i, Xt_j> + <Y_j, Xt_i> ) / (2n) + lam2 w_ij - [i==j]/w_ii
-template <int S>
+// G_ij on the stored entries: ( <Y_i, Xt_j> + <Y_j, Xt_i> ) / (2n) + lam2 w_ij - [i==j]/w_ii.
+// One wave per row i keeps Y_i and Xt_i in registers (up to RC chunks of 64*V
+// columns) and computes each unordered pair once: for j > i it writes G_ij to
+// entry (i,j) and, mirrored, to entry (j,i) (found by binary search of row j);
+// entries with j < i are written by row j's wave.
+template <int S, int RC>
 __global__ void __launch_bounds__(NT)
 sddmm_grad_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                   const double* __restrict__ val, int64_t p, const void* __restrict__ Y,
@@ -743,31 +747,70 @@ sddmm_grad_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict_
     const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
     if (row >= p) return;
     const int64_t s = rowptr[row], e = rowptr[row + 1];
-    double wii = 0.0;
+    const int nch = (int)((n + 64 * V - 1) / (64 * V));
+    T yi[RC][V], xi[RC][V];
+#pragma unroll
+    for (int q = 0; q < RC; ++q) {
+        const int64_t c = (int64_t)q * 64 * V + lane * V;
+        if (q < nch && c < n) {
+            Ch::load(Y, row * ld + c, yi[q]);
+            Ch::load(Xt, row * ld + c, xi[q]);
+        } else {
+#pragma unroll
+            for (int t = 0; t < V; ++t) { yi[q][t] = 0; xi[q][t] = 0; }
+        }
+    }
+    auto emit = [&](int64_t k, double g) {
+        if (out_f64) ((double*)out)[k] = g;
+        else ((float*)out)[k] = (float)g;
+    };
     for (int64_t k = s; k < e; ++k) {
         const int64_t j = col[k];
+        if (j < row) continue;
         double acc = 0.0;
-        for (int64_t c = lane * V; c < n; c += 64 * V) {
-            T yi[V], xj[V], yj[V], xi[V];
-            Ch::load(Y, row * ld + c, yi);
-            Ch::load(Xt, j * ld + c, xj);
-            Ch::load(Y, j * ld + c, yj);
-            Ch::load(Xt, row * ld + c, xi);
-            T a = 0;
+        if (nch <= RC) {
 #pragma unroll
-            for (int t = 0; t < V; ++t) a += yi[t] * xj[t] + yj[t] * xi[t];
-            acc += (double)a;
+            for (int q = 0; q < RC; ++q) {
+                const int64_t c = (int64_t)q * 64 * V + lane * V;
+                if (q < nch && c < n) {
+                    T xj[V], yj[V];
+                    Ch::load(Xt, j * ld + c, xj);
+                    Ch::load(Y, j * ld + c, yj);
+                    T a = 0;
+#pragma unroll
+                    for (int t = 0; t < V; ++t) a += yi[q][t] * xj[t] + yj[t] * xi[q][t];
+                    acc += (double)a;
+                }
+            }
+        } else {
+            for (int64_t c = lane * V; c < n; c += 64 * V) {
+                T a4[V], b4[V], c4[V], d4[V];
+                Ch::load(Y, row * ld + c, a4);
+                Ch::load(Xt, j * ld + c, b4);
+                Ch::load(Y, j * ld + c, c4);
+                Ch::load(Xt, row * ld + c, d4);
+                T a = 0;
+#pragma unroll
+                for (int t = 0; t < V; ++t) a += a4[t] * b4[t] + c4[t] * d4[t];
+                acc += (double)a;
+            }
         }
         acc = wave_sum(acc);
         const double v = val[k];
         double g = acc / (2.0 * (double)n) + lam2 * v;
-        if (j == row) { wii = v; g -= 1.0 / v; }
+        if (j == row) g -= 1.0 / v;
         if (lane == 0) {
-            if (out_f64) ((double*)out)[k] = g;
-            else ((float*)out)[k] = (float)g;
+            emit(k, g);
+            if (j != row) {
+                int64_t lo_ = rowptr[j], hi_ = rowptr[j + 1];
+                while (lo_ < hi_) {
+                    const int64_t mid = (lo_ + hi_) >> 1;
+                    if (col[mid] < row) lo_ = mid + 1; else hi_ = mid;
+                }
+                if (lo_ < rowptr[j + 1] && col[lo_] == row) emit(lo_, g);
+            }
         }
     }
-    (void)wii;
 }
 
 template <int S>
@@ -1070,12 +1113,13 @@ hipError_t launch_sddmm_grad(const Csr& om, int64_t p, const void* Y, const void
                              int out_f64, hipStream_t stream) {
     if (p == 0) return hipSuccess;
     dim3 grid(blocks_for(p, WPB));
+    // register cache of 8 column chunks: n <= 2048 (FP32) / 1024 (FP64) stay resident
     if (store == ST_F64)
-        hipLaunchKernelGGL(sddmm_grad_kernel<ST_F64>, grid, dim3(NT), 0, stream, om.rowptr, om.col,
-                           om.val, p, Y, Xt, ld, n, lam2, out, out_f64);
+        hipLaunchKernelGGL((sddmm_grad_kernel<ST_F64, 8>), grid, dim3(NT), 0, stream, om.rowptr,
+                           om.col, om.val, p, Y, Xt, ld, n, lam2, out, out_f64);
     else
-        hipLaunchKernelGGL(sddmm_grad_kernel<ST_F32>, grid, dim3(NT), 0, stream, om.rowptr, om.col,
-                           om.val, p, Y, Xt, ld, n, lam2, out, out_f64);
+        hipLaunchKernelGGL((sddmm_grad_kernel<ST_F32, 8>), grid, dim3(NT), 0, stream, om.rowptr,
+                           om.col, om.val, p, Y, Xt, ld, n, lam2, out, out_f64);
     return hipGetLastError();
 }
 
