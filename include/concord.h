@@ -254,6 +254,29 @@ typedef struct concord_profile {
 int concord_set_profiling(concord_ctx* ctx, int32_t on);
 int concord_get_profile(const concord_ctx* ctx, concord_profile* host_out);
 
+/* ---- choice of the product form (Section 3, Lemma 3.1; Section S.1) ----
+   Lemma 3.1 counts F_Cov = 2np^2 + 2dp^2(st+1) and F_Obs = 2np^2 s + 2dnp(st+1)
+   flops for s iterations with t step sizes tried per iteration and d nonzeros
+   per row of Omega on average; paper_choice is the form with fewer flops.
+   choice is the form with the shorter modelled time on this library's kernels:
+     Cov: S once (symmetric, n p^2 flops at dense_tflops) + per iteration the
+          streaming passes of W = Omega S, its symmetrisation and the candidate
+          scan, 5 p^2 elements at hbm_gbps;
+     Obs: per iteration the symmetric rank-2n contraction (2 n p^2 flops at
+          dense_tflops) + the candidate scan and the Y refresh, p^2 + 3 p n
+          elements at hbm_gbps.
+   dense_tflops / hbm_gbps <= 0 select rates measured on MI355X for `precision`
+   (BF16 split 330, FP32 125, FP64 60 TFLOP/s useful; 3200 GB/s).  Host-only:
+   no GPU is touched.  Errors: EINVAL (p, n < 1; d, t, s < 0; precision). */
+typedef struct concord_variant_estimate {
+    int32_t paper_choice;   /* CONCORD_COV or CONCORD_OBS by flop count */
+    int32_t choice;         /* CONCORD_COV or CONCORD_OBS by modelled time */
+    double  cov_flops, obs_flops;
+    double  cov_seconds, obs_seconds;
+} concord_variant_estimate;
+int concord_suggest_variant(int64_t p, int64_t n, double d, double t, double s, int32_t precision,
+                            double dense_tflops, double hbm_gbps, concord_variant_estimate* out);
+
 /* Description of the last error on this handle ("" if none). Never NULL. */
 const char* concord_last_error(const concord_ctx* ctx);
 

@@ -6,7 +6,7 @@ The iteration runs in hand-written HIP kernels behind the C-ABI of
 """
 from ._lib import (  # noqa: F401
     Solver, Batch, ConcordError, StepInfo, SolveInfo, load, EXPORTED, LIB_PATH,
-    concord_version,
+    concord_version, concord_suggest_variant,
 )
 
 __all__ = ["Solver", "Batch", "ConcordError", "StepInfo", "SolveInfo", "load"]

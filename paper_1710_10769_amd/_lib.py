@@ -61,6 +61,12 @@ class concord_profile(ctypes.Structure):
 PROF_CLASSES = ("dense", "spmm", "cand", "trial", "emit")
 
 
+class concord_variant_estimate(ctypes.Structure):
+    _fields_ = [("paper_choice", ctypes.c_int32), ("choice", ctypes.c_int32),
+                ("cov_flops", ctypes.c_double), ("obs_flops", ctypes.c_double),
+                ("cov_seconds", ctypes.c_double), ("obs_seconds", ctypes.c_double)]
+
+
 class concord_solve_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("f", ctypes.c_double), ("F", ctypes.c_double),
                 ("nnz", ctypes.c_int64), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
@@ -91,6 +97,7 @@ _SIGS = {
     "concord_batch_get_omega": (_I32, [_P, _I32, _I32, ctypes.POINTER(_I64), _P, _P, _P]),
     "concord_batch_last_error": (ctypes.c_char_p, [_P]),
     "concord_batch_destroy": (None, [_P]),
+    "concord_suggest_variant": (_I32, [_I64, _I64, _D, _D, _D, _I32, _D, _D, ctypes.c_void_p]),
     "concord_set_profiling": (_I32, [_P, _I32]),
     "concord_get_profile": (_I32, [_P, ctypes.c_void_p]),
     "concord_last_error": (ctypes.c_char_p, [_P]),
@@ -221,6 +228,19 @@ def concord_get_omega(h, rowptr: int = 0, col: int = 0, val: int = 0, dtype: int
     _check(load().concord_get_omega(h, ctypes.byref(nnz), rowptr or None, col or None,
                                     val or None, dtype), h)
     return nnz.value
+
+
+def concord_suggest_variant(p: int, n: int, d: float, t: float, s: float,
+                            precision: str = "bf16x3", dense_tflops: float = 0.0,
+                            hbm_gbps: float = 0.0) -> dict:
+    """Product form for a problem (Lemma 3.1 flop rule and the library's time model)."""
+    est = concord_variant_estimate()
+    _check(load().concord_suggest_variant(p, n, d, t, s, _PRECISIONS[precision], dense_tflops,
+                                          hbm_gbps, ctypes.byref(est)))
+    names = {COV: "cov", OBS: "obs"}
+    return {"paper_choice": names[est.paper_choice], "choice": names[est.choice],
+            "cov_flops": est.cov_flops, "obs_flops": est.obs_flops,
+            "cov_seconds": est.cov_seconds, "obs_seconds": est.obs_seconds}
 
 
 def concord_set_profiling(h, on: bool) -> int:

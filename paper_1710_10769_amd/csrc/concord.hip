@@ -858,6 +858,27 @@ int concord_get_omega(concord_ctx* c, int64_t* host_nnz, int64_t* dev_row_ptr, i
 
 int64_t concord_iterations(const concord_ctx* c) { return c ? c->k : -1; }
 
+int concord_suggest_variant(int64_t p, int64_t n, double d, double t, double s, int32_t precision,
+                            double dense_tflops, double hbm_gbps, concord_variant_estimate* out) {
+    if (!out || p < 1 || n < 1 || !(d >= 0.0) || !(t >= 0.0) || !(s >= 0.0)) return CONCORD_EINVAL;
+    if (precision < CONCORD_FP64 || precision > CONCORD_BF16X3) return CONCORD_EINVAL;
+    const double P = (double)p, N = (double)n;
+    // Lemma 3.1
+    out->cov_flops = 2.0 * N * P * P + 2.0 * d * P * P * (s * t + 1.0);
+    out->obs_flops = 2.0 * N * P * P * s + 2.0 * d * N * P * (s * t + 1.0);
+    out->paper_choice = out->cov_flops < out->obs_flops ? CONCORD_COV : CONCORD_OBS;
+    // time model of this library's pipeline
+    const double rate = (dense_tflops > 0.0 ? dense_tflops
+                         : precision == CONCORD_BF16X3 ? 330.0
+                         : precision == CONCORD_FP32 ? 125.0 : 60.0) * 1e12;
+    const double bw = (hbm_gbps > 0.0 ? hbm_gbps : 3200.0) * 1e9;
+    const double b = precision == CONCORD_FP64 ? 8.0 : 4.0;
+    out->cov_seconds = N * P * P / rate + s * 5.0 * P * P * b / bw;
+    out->obs_seconds = s * (2.0 * N * P * P / rate + (P * P + 3.0 * P * N) * b / bw);
+    out->choice = out->cov_seconds < out->obs_seconds ? CONCORD_COV : CONCORD_OBS;
+    return CONCORD_OK;
+}
+
 int concord_smooth_value(concord_ctx* c, double lam2, double* host_f) {
     if (!c) return CONCORD_EINVAL;
     if (c->variant != CONCORD_OBS) return fail(c, CONCORD_EINVAL, "differentiation form needs Obs");

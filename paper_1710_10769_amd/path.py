@@ -1,0 +1,83 @@
+"""Tuning lambda1 to a target sparsity and scoring support recovery.
+
+Section 4 chooses the tuning parameters so that estimates reach a given
+average degree (the degree of the true graph, or the sparsity of a competing
+estimate), and scores the recovered sparsity pattern against the true
+precision matrix by positive predictive value and false discovery rate
+(Table 1).  The solves run on the GPU through ``Solver``; the search and the
+scoring are host logic.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def average_degree(omega: sp.spmatrix) -> float:
+    """Off-diagonal stored entries per row (both triangles counted once per row)."""
+    om = sp.csr_matrix(omega)
+    off = om.nnz - int(np.count_nonzero(om.diagonal()))
+    return off / om.shape[0]
+
+
+def support_recovery(estimate: sp.spmatrix, truth: sp.spmatrix) -> dict:
+    """PPV and FDR of the estimated off-diagonal support against the true one.
+
+    An edge is an unordered pair i < j with a nonzero entry.  PPV = TP / (TP + FP),
+    FDR = FP / (TP + FP) = 1 - PPV (both 0 when nothing is estimated); recall is
+    TP / (TP + FN).
+    """
+    def edges(m):
+        u = sp.triu(sp.csr_matrix(m), k=1).tocoo()
+        keep = u.data != 0
+        return set(zip(u.row[keep].tolist(), u.col[keep].tolist()))
+    e, t = edges(estimate), edges(truth)
+    tp = len(e & t)
+    fp = len(e - t)
+    fn = len(t - e)
+    est = tp + fp
+    return {"tp": tp, "fp": fp, "fn": fn,
+            "ppv": tp / est if est else 0.0,
+            "fdr": fp / est if est else 0.0,
+            "recall": tp / (tp + fn) if tp + fn else 0.0}
+
+
+@dataclasses.dataclass
+class SearchResult:
+    lam1: float
+    degree: float
+    iters: int
+    omega: sp.csr_matrix
+    history: List[tuple]
+
+
+def lambda1_for_degree(solver, target_degree: float, lam2: float, lo: float = 0.0,
+                       hi: float = 1.0, tol: float = 1e-5, max_iter: int = 200,
+                       steps: int = 14, rel_tol: float = 0.02) -> SearchResult:
+    """Bisection on lambda1 (the estimated degree falls as lambda1 grows) until the
+    average degree is within ``rel_tol`` of the target or ``steps`` solves are done.
+    Every solve starts from Omega = I.  ``solver`` already holds the data."""
+    history = []
+    best: Optional[SearchResult] = None
+    a, b = lo, hi
+    for _ in range(steps):
+        lam1 = 0.5 * (a + b)
+        solver.reset()
+        info = solver.solve(lam1, lam2, tol, max_iter)
+        om = solver.get_omega_scipy()
+        deg = average_degree(om)
+        history.append((lam1, deg, info.iters))
+        cand = SearchResult(lam1, deg, info.iters, om, history)
+        if best is None or abs(deg - target_degree) < abs(best.degree - target_degree):
+            best = cand
+        if abs(deg - target_degree) <= rel_tol * max(target_degree, 1e-12):
+            break
+        if deg > target_degree:
+            a = lam1
+        else:
+            b = lam1
+    best.history = history
+    return best

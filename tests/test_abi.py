@@ -97,3 +97,34 @@ def test_missing_library_fails_loudly(tmp_path):
             _lib.load(str(tmp_path / "nope.so"))
     finally:
         _lib._lib = saved
+
+
+def test_suggest_variant_lemma_3_1_rule(lib):
+    """The flop rule reproduces Section S.1's printed thresholds: with t = 10 and
+    many iterations, Cov has fewer flops while r_nnz < r_obs / (1 - r_obs) / t."""
+    from paper_1710_10769_amd import _lib
+    p, t, s = 20000, 10.0, 1e6
+    for r_obs, pct in ((0.01, 0.1), (0.10, 1.1), (0.25, 3.3)):
+        n = int(r_obs * p)
+        thr = r_obs / (1 - r_obs) / t          # relaxed form (S.2)
+        below = _lib.concord_suggest_variant(p, n, 0.9 * thr * p, t, s)
+        above = _lib.concord_suggest_variant(p, n, 1.1 * thr * p, t, s)
+        assert below["paper_choice"] == "cov" and above["paper_choice"] == "obs", (r_obs, below, above)
+        assert abs(thr * 100 - pct) < 0.05
+
+
+def test_suggest_variant_time_model(lib):
+    from paper_1710_10769_amd import _lib
+    # the benchmark workload (p 20k, n 5k, nearly diagonal): Cov's streaming passes win
+    e = _lib.concord_suggest_variant(20000, 5000, 1.0, 3.0, 100, "bf16x3")
+    assert e["choice"] == "cov" and e["cov_seconds"] < e["obs_seconds"] / 3
+    # very wide p, few samples, dense iterates: Obs
+    e = _lib.concord_suggest_variant(200000, 100, 50.0, 3.0, 50, "bf16x3")
+    assert e["choice"] == "obs"
+    # flop counts are Lemma 3.1's
+    p, n, d, t, s = 1000, 200, 5.0, 4.0, 30.0
+    e = _lib.concord_suggest_variant(p, n, d, t, s, "fp32")
+    assert e["cov_flops"] == 2 * n * p * p + 2 * d * p * p * (s * t + 1)
+    assert e["obs_flops"] == 2 * n * p * p * s + 2 * d * n * p * (s * t + 1)
+    with pytest.raises(_lib.ConcordError):
+        _lib.concord_suggest_variant(0, 10, 1.0, 1.0, 1.0)
