@@ -73,6 +73,35 @@ def run_form(torch, X32, p, n, lam1, lam2, form, steps, warmup):
     return res, om
 
 
+def run_cov_context(torch, X32, p, n, lam1, lam2, steps, warmup):
+    """The Cov form on the same data: S = X^T X / n formed once (timed apart), then
+    the same outer iterations from Omega = I.  Context for the choice between the two
+    forms (Lemma 3.1); not the headline."""
+    from paper_1710_10769_amd import Solver
+    s = Solver(p, n, variant="cov", precision="bf16x3")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.set_data(X32)
+    torch.cuda.synchronize()
+    form_s = time.perf_counter() - t0
+    for _ in range(warmup):
+        s.step(lam1, lam2)
+    s.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [s.step(lam1, lam2) for _ in range(steps)]
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    prof = s.profile()
+    om = s.get_omega_scipy()
+    s.close()
+    log(f"cov context: {steps} steps in {sec:.3f} s, S formed in {form_s * 1e3:.1f} ms")
+    return {"variant": "cov", "precision": "bf16x3", "value": steps / sec, "unit": "iters/s",
+            "ms_per_step": sec / steps * 1e3, "s_formation_ms": form_s * 1e3,
+            "kernel_ms_per_step": {k: v[0] / steps for k, v in prof.items()},
+            "final_F": infos[-1].F, "final_nnz": infos[-1].nnz}, om
+
+
 def stored_traffic(form):
     """HBM bytes per launch of the contraction from the committed counter record, or None
     when the record is for another form or the kernel source changed since it was taken."""
@@ -285,6 +314,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--forms", default="bf16x3,fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cov-context", action="store_true",
+                    help="skip timing the Cov form on the same problem")
     ap.add_argument("--p", type=int, default=20000)
     ap.add_argument("--n", type=int, default=5000)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
@@ -361,6 +392,13 @@ def main():
     line["dense_kernel_avg_ms"] = out[head]["dense_kernel_avg_ms"]
     line["trials_per_step"] = out[head]["trials_per_step"]
     line["final_nnz"] = out[head]["final_nnz"]
+    if not args.no_cov_context:
+        ctx, om_cov = run_cov_context(torch, X32, p, n, w.lam1, w.lam2, args.steps, args.warmup)
+        d = om_cov - oms[head]
+        ctx[f"final_omega_maxdiff_rel_vs_obs_{head}"] = (
+            (float(np.abs(d.data).max()) if d.nnz else 0.0) / float(np.abs(oms[head].data).max()))
+        ctx["cov_over_obs"] = ctx["value"] / out[head]["value"]
+        line["cov_form_same_problem"] = ctx
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, 1 iteration)")
         X64 = w.X.astype(np.float32).astype(np.float64)

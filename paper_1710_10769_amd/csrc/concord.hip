@@ -302,13 +302,14 @@ int products_at(concord_ctx* c, int which, const int* gate) {
         double* sq = c->part + 4 * p;
         HIPCK(c, launch_spmm(O, p, c->Xt, c->dstore, c->ldk, c->ldk, split ? nullptr : c->Y,
                              c->dstore, c->ldk, split ? c->Y_hi : nullptr,
-                             split ? c->Y_lo : nullptr, sq, gate, c->stream));
+                             split ? c->Y_lo : nullptr, kblk_stride(c->prow), sq, gate,
+                             c->stream));
         nysq = nch;
         HIPCK(c, launch_obj_parts(O, p, nullptr, c->dstore, 0, c->part, gate, c->stream));
         HIPCK(c, launch_colsum(c->part, p, 4 + nch, c->objsums, c->colsum_ws, c->stream));
     } else {
         HIPCK(c, launch_spmm(O, p, c->S, c->sstore, c->ldp, c->ldp, c->M, c->dstore, c->ldp,
-                             nullptr, nullptr, nullptr, gate, c->stream));
+                             nullptr, nullptr, 0, nullptr, gate, c->stream));
         HIPCK(c, launch_symmetrize(c->M, c->dstore, p, c->ldp, gate, c->stream));
         HIPCK(c, launch_obj_parts(O, p, c->M, c->dstore, c->ldp, c->part, gate, c->stream));
         HIPCK(c, launch_colsum(c->part, p, 4, c->objsums, c->colsum_ws, c->stream));
@@ -717,7 +718,7 @@ int concord_set_data(concord_ctx* c, int32_t kind, const void* dev_data, int32_t
         const bool split = c->precision == CONCORD_BF16X3;
         HIPCK(c, launch_transpose_in(dev_data, is64, rows, cols, ld, c->Xt, c->dstore, c->ldk,
                                      split ? c->Xt_hi : nullptr, split ? c->Xt_lo : nullptr,
-                                     c->stream));
+                                     kblk_stride(c->prow), c->stream));
         if (c->variant == CONCORD_COV) {
             const void* P0 = split ? (const void*)c->Xt_hi : c->Xt;
             const void* P1 = split ? (const void*)c->Xt_lo : nullptr;
@@ -920,7 +921,7 @@ int concord_gradient(concord_ctx* c, double lam2, int32_t mode, void* dev_dOmega
         if (!c->dxt && (rc = dalloc(c, &c->dxt, (size_t)c->prow * c->ldk * elem_bytes(c->dstore), true)))
             return rc;
         HIPCK(c, launch_spmm(O, c->p, c->Y, c->dstore, c->ldk, c->ldk, c->dxt, c->dstore, c->ldk,
-                             nullptr, nullptr, nullptr, c->d_one, c->stream));
+                             nullptr, nullptr, 0, nullptr, c->d_one, c->stream));
         HIPCK(c, launch_transpose_out(c->dxt, c->dstore, c->p, c->n, c->ldk, 1.0 / (double)c->n,
                                       dev_dX, out64, c->stream));
     }

@@ -4,8 +4,12 @@
 //   syr2k:  C = alpha * (P Q^T + Q P^T)    (Z + Z^T with Z = Y X / n,
 //                                           Algorithm 3, gradient step)
 //
-// Operands are "K-major": P and Q are row-major p x K planes (variable-major
-// X^T and Y = Omega X^T), so every product row reads contiguous K.  Only the
+// Operands are "K-major": P and Q are p x K (variable-major X^T and
+// Y = Omega X^T), so every product row reads contiguous K.  FP32/FP64 operands
+// are row-major; the BF16 hi/lo planes are K-blocked (32-byte blocks of K with
+// all rows of a block back to back), so the K stage of a tile is one contiguous
+// run per plane and the loads use whole cache lines instead of a short piece of
+// each of 256 rows.  Only the
 // upper-triangle output tiles (I <= J) are computed; each tile writes its
 // values to (I, J) and, mirrored, to (J, I), so the result is bitwise
 // symmetric and Z^T is never formed separately (the paper's explicit
@@ -232,8 +236,8 @@ template <int KIND, int BT_, int WM_, int WN_, bool PERSIST>
 __global__ void __launch_bounds__(WM_ * WN_ * 64)
 gemm_sym_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
                 const char* __restrict__ Q0, const char* __restrict__ Q1, int64_t ldk_bytes,
-                int nk, int syr2k, int p, int T, int ntiles, double alpha, void* __restrict__ C,
-                int out_store, int64_t ldc) {
+                int64_t kbs, int nk, int syr2k, int p, int T, int ntiles, double alpha,
+                void* __restrict__ C, int out_store, int64_t ldc) {
     typedef Form<KIND> F;
     constexpr int BT = BT_, WM = WM_, WN = WN_;   // BT x BT output tile, WM x WN waves
     constexpr int NT = WM * WN * 64;
@@ -261,7 +265,7 @@ gemm_sym_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
 
     auto gload = [&](int kt) {
         const bool second = kt >= nk;
-        const int64_t kb = (int64_t)(second ? kt - nk : kt) * ROWB;
+        const int64_t ks = second ? kt - nk : kt;
         // phase 1: A = P rows I, B = Q rows J; phase 2: A = Q rows I, B = P rows J
         const char* a0 = second ? Q0 : P0;
         const char* a1 = second ? Q1 : P1;
@@ -271,8 +275,16 @@ gemm_sym_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
         for (int h = 0; h < CPT; ++h) {
             const int ci = tid + h * NT;
             const int row = ci >> 2, ch = ci & 3;
-            const int64_t oa = (rowI0 + row) * ldk_bytes + kb + ch * 16;
-            const int64_t ob = (rowJ0 + row) * ldk_bytes + kb + ch * 16;
+            int64_t oa, ob;
+            if (KIND == GK_BF16X3) {
+                // K-blocked planes: a 64-byte stage is two 32-byte K blocks
+                const int64_t kb = (ks * 2 + (ch >> 1)) * kbs + (ch & 1) * 16;
+                oa = kb + (rowI0 + row) * 32;
+                ob = kb + (rowJ0 + row) * 32;
+            } else {
+                oa = (rowI0 + row) * ldk_bytes + ks * ROWB + ch * 16;
+                ob = (rowJ0 + row) * ldk_bytes + ks * ROWB + ch * 16;
+            }
             ra[0][h] = *(const u32x4_t*)(a0 + oa);
             rb[0][h] = *(const u32x4_t*)(b0 + ob);
             if (NP == 2) {
@@ -408,12 +420,34 @@ __device__ inline void wait_vm(int n) {
     else if (n >= 4) __builtin_amdgcn_s_waitcnt(0x0f74);
     else __builtin_amdgcn_s_waitcnt(0x0f70);
 }
+// 12 fragment reads of one stage: A hi/lo at a (+1024 per 32-row block, +PS for lo),
+// B hi/lo at b (four 32-row blocks)
+__device__ inline void read_frags(uint32_t a, uint32_t b, u32x4_t (&f)[12]) {
+    asm volatile(
+        "ds_read_b128 %0, %12\n\t"
+        "ds_read_b128 %1, %12 offset:1024\n\t"
+        "ds_read_b128 %2, %12 offset:8192\n\t"
+        "ds_read_b128 %3, %12 offset:9216\n\t"
+        "ds_read_b128 %4, %13\n\t"
+        "ds_read_b128 %5, %13 offset:1024\n\t"
+        "ds_read_b128 %6, %13 offset:2048\n\t"
+        "ds_read_b128 %7, %13 offset:3072\n\t"
+        "ds_read_b128 %8, %13 offset:8192\n\t"
+        "ds_read_b128 %9, %13 offset:9216\n\t"
+        "ds_read_b128 %10, %13 offset:10240\n\t"
+        "ds_read_b128 %11, %13 offset:11264\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(f[0]), "=&v"(f[1]), "=&v"(f[2]), "=&v"(f[3]), "=&v"(f[4]), "=&v"(f[5]),
+          "=&v"(f[6]), "=&v"(f[7]), "=&v"(f[8]), "=&v"(f[9]), "=&v"(f[10]), "=&v"(f[11])
+        : "v"(a), "v"(b)
+        : "memory");
+}
 }  // namespace dma
 
 __global__ void __launch_bounds__(dma::NT)
 gemm_bf16x3_dma_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
                        const char* __restrict__ Q0, const char* __restrict__ Q1,
-                       int64_t ldk_bytes, int nk, int syr2k, int p, int T, int ntiles,
+                       int64_t kbs, int nk, int syr2k, int p, int T, int ntiles,
                        double alpha, void* __restrict__ C, int out_store, int64_t ldc) {
     using namespace dma;
     __shared__ __attribute__((aligned(16))) char r0[SLOT];
@@ -432,7 +466,7 @@ gemm_bf16x3_dma_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
     // this wave's 4 load instructions per stage: plane-side ps, 32-row block rb
     auto issue = [&](int kt, char* slot) {
         const bool second = kt >= nk;
-        const int64_t kb = (int64_t)(second ? kt - nk : kt) * ROW;
+        const int64_t kb = (int64_t)(second ? kt - nk : kt) * kbs;   // one 32-byte K block per stage
         const char* a0 = second ? Q0 : P0;
         const char* a1 = second ? Q1 : P1;
         const char* b0 = syr2k ? (second ? P0 : Q0) : P0;
@@ -445,7 +479,7 @@ gemm_bf16x3_dma_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
             const int c = (lane & 1) ^ ((row >> 3) & 1);
             const char* base = ps == 0 ? a0 : (ps == 1 ? a1 : (ps == 2 ? b0 : b1));
             const int64_t grow = (ps < 2 ? rowI0 : rowJ0) + row;
-            const char* g = base + grow * ldk_bytes + kb + c * 16;
+            const char* g = base + kb + grow * ROW + c * 16;
             __builtin_amdgcn_global_load_lds((gbl_t*)g, (lds_t*)(slot + ps * PS + rb * 1024), 16, 0, 0);
         }
     };
@@ -459,19 +493,21 @@ gemm_bf16x3_dma_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
     const int r32 = lane & 31, hk = lane >> 5;
+    const uint32_t lds_a = off(wm * 64 + r32, hk), lds_b = 2 * PS + off(wn * 128 + r32, hk);
     auto compute = [&](const char* slot) {
+        const uint32_t s = (uint32_t)(uintptr_t)(lds_t*)slot;
+        u32x4_t f[12];
+        read_frags(s + lds_a, s + lds_b, f);
         bf16x8_t ah[MB], al[MB], bh[NB], bl[NB];
 #pragma unroll
         for (int i = 0; i < MB; ++i) {
-            const int o = off(wm * 64 + i * 32 + r32, hk);
-            ah[i] = *(const bf16x8_t*)(slot + o);
-            al[i] = *(const bf16x8_t*)(slot + PS + o);
+            ah[i] = __builtin_bit_cast(bf16x8_t, f[i]);
+            al[i] = __builtin_bit_cast(bf16x8_t, f[2 + i]);
         }
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
-            const int o = off(wn * 128 + j * 32 + r32, hk);
-            bh[j] = *(const bf16x8_t*)(slot + 2 * PS + o);
-            bl[j] = *(const bf16x8_t*)(slot + 3 * PS + o);
+            bh[j] = __builtin_bit_cast(bf16x8_t, f[4 + j]);
+            bl[j] = __builtin_bit_cast(bf16x8_t, f[8 + j]);
         }
 #pragma unroll
         for (int i = 0; i < MB; ++i)
@@ -567,6 +603,195 @@ gemm_bf16x3_dma_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
             }
 }
 
+// ---- BF16-split contraction, ping-pong schedule ---------------------------------
+//
+// Same tile, LDS ring and direct-to-LDS loads as above, with the eight waves in two
+// groups of four (waves 0-3 and 4-7; wave w runs on SIMD w % 4, so every SIMD holds
+// one wave of each group).  Each wave alternates a memory phase (issue the global
+// loads of stage k + 3 into the ring, read its fragments of stage k from LDS) and a
+// compute phase (the 24 MFMAs of stage k on those registers), with a workgroup
+// barrier between phases.  Group 1 starts one phase late, so on every SIMD one
+// wave issues MFMAs while the other does its memory work.  Fragment reads are one
+// asm block that waits for its own results before it ends: written as ordinary
+// loads, the compiler would wait for every ring load in flight (it cannot tell
+// which slot a direct-to-LDS load writes) and drain the ring at each stage.
+namespace pp {
+__device__ inline void phase_barrier() {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+}
+}  // namespace pp
+
+__global__ void __launch_bounds__(dma::NT)
+gemm_bf16x3_pp_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
+                      const char* __restrict__ Q0, const char* __restrict__ Q1,
+                      int64_t kbs, int nk, int syr2k, int p, int T, int ntiles,
+                      double alpha, void* __restrict__ C, int out_store, int64_t ldc) {
+    using namespace dma;
+    __shared__ __attribute__((aligned(16))) char ring[4 * SLOT];
+
+    int I, J;
+    tile_of(blockIdx.x, ntiles, T, I, J);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave / WN, wn = wave % WN, grp = wave >> 2;
+    const int64_t rowI0 = (int64_t)I * BT, rowJ0 = (int64_t)J * BT;
+    const int nkt = syr2k ? 2 * nk : nk;
+
+    auto issue = [&](int kt) {
+        char* slot = ring + (kt & 3) * SLOT;
+        const bool second = kt >= nk;
+        const int64_t kb = (int64_t)(second ? kt - nk : kt) * kbs;   // one 32-byte K block per stage
+        const char* a0 = second ? Q0 : P0;
+        const char* a1 = second ? Q1 : P1;
+        const char* b0 = syr2k ? (second ? P0 : Q0) : P0;
+        const char* b1 = syr2k ? (second ? P1 : Q1) : P1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int m = wave * 4 + q;
+            const int ps = m >> 3, rb = m & 7;
+            const int row = rb * 32 + (lane >> 1);
+            const int c = (lane & 1) ^ ((row >> 3) & 1);
+            const char* base = ps == 0 ? a0 : (ps == 1 ? a1 : (ps == 2 ? b0 : b1));
+            const int64_t grow = (ps < 2 ? rowI0 : rowJ0) + row;
+            const char* g = base + kb + grow * ROW + c * 16;
+            __builtin_amdgcn_global_load_lds((gbl_t*)g, (lds_t*)(slot + ps * PS + rb * 1024), 16, 0, 0);
+        }
+    };
+
+    f32x16_t acc[MB][NB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    const int r32 = lane & 31, hk = lane >> 5;
+    const uint32_t lds0 = (uint32_t)(uintptr_t)(lds_t*)ring;
+    const uint32_t aoff = lds0 + off(wm * 64 + r32, hk);
+    const uint32_t boff = lds0 + 2 * PS + off(wn * 128 + r32, hk);
+
+    issue(0);
+    if (1 < nkt) issue(1);
+    if (2 < nkt) issue(2);
+    wait_vm(4 * (nkt - 1 < 2 ? nkt - 1 : 2));
+    pp::phase_barrier();
+    if (grp) pp::phase_barrier();
+    for (int k = 0; k < nkt; ++k) {
+        // memory phase
+        if (k + 3 < nkt) issue(k + 3);
+        u32x4_t f[12];
+        read_frags(aoff + (k & 3) * SLOT, boff + (k & 3) * SLOT, f);
+        if (k + 1 < nkt) {
+            // this wave's share of stage k + 1 has landed (stages k + 2, k + 3 may be in flight)
+            const int ahead = nkt - 2 - k < 2 ? nkt - 2 - k : 2;
+            wait_vm(4 * ahead);
+        }
+        pp::phase_barrier();
+        // compute phase
+        bf16x8_t ah[MB], al[MB], bh[NB], bl[NB];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            ah[i] = __builtin_bit_cast(bf16x8_t, f[i]);
+            al[i] = __builtin_bit_cast(bf16x8_t, f[2 + i]);
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            bh[j] = __builtin_bit_cast(bf16x8_t, f[4 + j]);
+            bl[j] = __builtin_bit_cast(bf16x8_t, f[8 + j]);
+        }
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        pp::phase_barrier();
+    }
+    if (!grp) pp::phase_barrier();   // both groups pass the same number of barriers
+    wait_vm(0);
+
+    typedef Form<GK_BF16X3> F;
+    const int64_t gr0 = rowI0 + wm * 64, gc0 = rowJ0 + wn * 128;
+    if (I != J && out_store != ST_F64) {
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int64_t gj = gc0 + j * 32 + (lane & 31);
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int64_t gi0 = gr0 + i * 32 + 8 * g + 4 * (lane >> 5);
+                    uint32_t w[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const float x = (float)(alpha * (double)acc[i][j][4 * g + t]);
+                        if (out_store == ST_F32) {
+                            w[t] = __float_as_uint(x);
+                        } else {
+                            const uint16_t h = f2bf_rne(x);
+                            const uint16_t l = f2bf_rne(x - __uint_as_float(((uint32_t)h) << 16));
+                            w[t] = (uint32_t)h | ((uint32_t)l << 16);
+                        }
+                        if (gj < p && gi0 + t < p) ((uint32_t*)C)[(gi0 + t) * ldc + gj] = w[t];
+                    }
+                    if (gj < p) {
+                        if (gi0 + 3 < p) {
+                            *(u32x4_t*)((uint32_t*)C + gj * ldc + gi0) = u32x4_t{w[0], w[1], w[2], w[3]};
+                        } else {
+#pragma unroll
+                            for (int t = 0; t < 4; ++t)
+                                if (gi0 + t < p) ((uint32_t*)C)[gj * ldc + gi0 + t] = w[t];
+                        }
+                    }
+                }
+            }
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                int rr, cc;
+                F::coord(r, lane, rr, cc);
+                const int64_t gi = gr0 + i * 32 + rr, gj = gc0 + j * 32 + cc;
+                if (gi >= p || gj >= p) continue;
+                if (I == J && gi > gj) continue;
+                const double v = alpha * (double)acc[i][j][r];
+                store_val(C, out_store, gi * ldc + gj, v);
+                if (gi != gj) store_val(C, out_store, gj * ldc + gi, v);
+            }
+}
+
+hipError_t launch_bf16x3_pp(bool syr2k, const void* P0, const void* P1, const void* Q0,
+                            const void* Q1, int64_t ldk, int64_t p, double alpha, void* C,
+                            int out_store, int64_t ldc, hipStream_t stream) {
+    const int64_t ldk_bytes = ldk * 2;
+    if (ldk_bytes % dma::ROW) return hipErrorInvalidValue;
+    const int nk = (int)(ldk_bytes / dma::ROW);
+    const int T = (int)((p + dma::BT - 1) / dma::BT);
+    const int ntiles = T * (T + 1) / 2;
+    if (ntiles == 0 || nk == 0) return hipSuccess;
+    hipLaunchKernelGGL(gemm_bf16x3_pp_kernel, dim3(ntiles), dim3(dma::NT), 0, stream,
+                       (const char*)P0, (const char*)P1, (const char*)(syr2k ? Q0 : P0),
+                       (const char*)(syr2k ? Q1 : P1), round_up(p, ROW_PAD) * dma::ROW, nk,
+                       syr2k ? 1 : 0, (int)p, T, ntiles, alpha, C, out_store, ldc);
+    return hipGetLastError();
+}
+
 hipError_t launch_bf16x3_dma(bool syr2k, const void* P0, const void* P1, const void* Q0,
                              const void* Q1, int64_t ldk, int64_t p, double alpha, void* C,
                              int out_store, int64_t ldc, hipStream_t stream) {
@@ -578,8 +803,8 @@ hipError_t launch_bf16x3_dma(bool syr2k, const void* P0, const void* P1, const v
     if (ntiles == 0 || nk == 0) return hipSuccess;
     hipLaunchKernelGGL(gemm_bf16x3_dma_kernel, dim3(ntiles), dim3(dma::NT), 0, stream,
                        (const char*)P0, (const char*)P1, (const char*)(syr2k ? Q0 : P0),
-                       (const char*)(syr2k ? Q1 : P1), ldk_bytes, nk, syr2k ? 1 : 0, (int)p, T,
-                       ntiles, alpha, C, out_store, ldc);
+                       (const char*)(syr2k ? Q1 : P1), round_up(p, ROW_PAD) * dma::ROW, nk,
+                       syr2k ? 1 : 0, (int)p, T, ntiles, alpha, C, out_store, ldc);
     return hipGetLastError();
 }
 
@@ -605,6 +830,7 @@ hipError_t launch_kind(bool syr2k, const void* P0, const void* P1, const void* Q
     const int nk = (int)(ldk_bytes / ROWB);
     const int T = (int)((p + BT - 1) / BT);
     const int ntiles = T * (T + 1) / 2;
+    const int64_t kbs = round_up(p, ROW_PAD) * (KBLK * 2);   // bytes per K block of a BF16 plane
     const size_t lds = 2 * (2 * F::NPLANE * BT * ROWB);
     static std::once_flag attr_once;   // handles on several host threads may launch concurrently
     std::call_once(attr_once, [&] {
@@ -621,8 +847,8 @@ hipError_t launch_kind(bool syr2k, const void* P0, const void* P1, const void* Q
     }
     hipLaunchKernelGGL((gemm_sym_kernel<KIND, BT, WM, WN, PERSIST>), dim3(grid), dim3(NT), lds, stream,
                        (const char*)P0, (const char*)P1, (const char*)(syr2k ? Q0 : P0),
-                       (const char*)(syr2k ? Q1 : P1), ldk_bytes, nk, syr2k ? 1 : 0, (int)p, T,
-                       ntiles, alpha, C, out_store, ldc);
+                       (const char*)(syr2k ? Q1 : P1), ldk_bytes, kbs, nk, syr2k ? 1 : 0, (int)p,
+                       T, ntiles, alpha, C, out_store, ldc);
     return hipGetLastError();
 }
 
@@ -652,6 +878,7 @@ const Variant* variants(int kind, int* count) {
         {"bf16x3_128x128_w4", launch_kind<GK_BF16X3, 128, 2, 2>},
         {"bf16x3_256x256_w8_ldsring", launch_bf16x3_dma},
         {"bf16x3_256x256_w8_persistent", launch_kind<GK_BF16X3, 256, 4, 2, true>},
+        {"bf16x3_256x256_w8_pingpong", launch_bf16x3_pp},
     };
     static const Variant f32[] = {
         {"f32_256x256_w8", launch_kind<GK_F32, 256, 4, 2>},
@@ -662,7 +889,7 @@ const Variant* variants(int kind, int* count) {
         {"f64_128x128_w4", launch_kind<GK_F64, 128, 2, 2>},
     };
     switch (kind) {
-        case GK_BF16X3: *count = 4; return bf;
+        case GK_BF16X3: *count = 5; return bf;
         case GK_F32: *count = 3; return f32;
         default: *count = 1; return f64;
     }

@@ -26,14 +26,26 @@ constexpr int K_PAD = 64;      // and their K (column) dimension padded to this
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
+// BF16 hi/lo operand planes are K-blocked: blocks of KBLK elements (32 bytes) of K,
+// and within a block all rows back to back, so element (row, k) sits at
+//   (k / KBLK) * kblk_stride(prow) + row * KBLK + k % KBLK
+// with prow = round_up(rows, ROW_PAD).  One K stage of a 256-row tile is then one
+// contiguous 8 KB run per plane, and the contraction's loads use whole cache lines.
+constexpr int KBLK = 16;
+__host__ __device__ inline int64_t kblk_stride(int64_t prow) { return prow * KBLK; }
+__host__ __device__ inline int64_t kblk_index(int64_t row, int64_t k, int64_t stride) {
+    return (k / KBLK) * stride + row * KBLK + k % KBLK;
+}
+
 // ---- launchers (all asynchronous on `stream`) ----
 
 // C = alpha * (P Q^T + Q P^T)  (syr2k)  or  alpha * P P^T  (syrk, Q ignored),
 // over the upper-triangle tiles only, written symmetrically (both triangles,
-// bitwise symmetric).  P and Q are prow x ldk row-major planes (prow a
-// multiple of 256, zero rows beyond p; ldk a multiple of 64, zero columns
-// beyond the true K).  For GK_BF16X3, P0/P1 and Q0/Q1 are the hi/lo planes
-// (uint16 bf16 bits); otherwise P0/Q0 hold float (GK_F32) or double (GK_F64).
+// bitwise symmetric).  P and Q hold prow x ldk operands (prow = round_up(p,
+// ROW_PAD), zero rows beyond p; ldk a multiple of K_PAD, zero columns beyond the
+// true K).  For GK_BF16X3, P0/P1 and Q0/Q1 are the hi/lo planes (uint16 bf16 bits)
+// in the K-blocked layout above; otherwise P0/Q0 are row-major float (GK_F32) or
+// double (GK_F64) with row stride ldk.
 // out_store: ST_F32, ST_F64 or ST_B16P.
 hipError_t launch_gemm_sym(int kind, bool syr2k, const void* P0, const void* P1,
                            const void* Q0, const void* Q1, int64_t ldk, int64_t p,
@@ -44,10 +56,11 @@ hipError_t launch_gemm_sym(int kind, bool syr2k, const void* P0, const void* P1,
 int gemm_sym_choice(int kind, bool syr2k, int64_t p, int64_t ldk, const char** name);
 
 // X (rows x cols, ld, F64 or F32) -> Xt (cols x ldo) in `store` (F64/F32);
-// optionally bf16 hi/lo planes (hi, lo may be null).  Scale applied on copy.
+// optionally bf16 hi/lo planes (hi, lo may be null), K-blocked with block stride
+// kbs elements.
 hipError_t launch_transpose_in(const void* X, int x_is_f64, int64_t rows, int64_t cols,
                                int64_t ld, void* Xt, int store, int64_t ldo, uint16_t* hi,
-                               uint16_t* lo, hipStream_t stream);
+                               uint16_t* lo, int64_t kbs, hipStream_t stream);
 
 // Copy a square p x p (ld) F64/F32 matrix into `store` layout with ldo.
 hipError_t launch_copy_square(const void* S, int s_is_f64, int64_t p, int64_t ld, void* out,
@@ -67,13 +80,15 @@ struct Csr {
 };
 
 // Y = Omega B (B: K x N dense, ldb, store), rows < p written to C (ldc) in
-// `cstore` (F64/F32) unless C is null; hi/lo planes written if non-null.
+// `cstore` (F64/F32) unless C is null; hi/lo planes written if non-null, K-blocked
+// with block stride kbs elements.
 // sq_part (if non-null) receives sum_j Y_ij^2 per (row, column-chunk) in FP64
 // as sq_part[chunk * p + row]; nchunks returned through *nchunks_out.
 // `gate` (device int, may be null): kernel does nothing unless *gate != 0.
 hipError_t launch_spmm(const Csr& A, int64_t p, const void* B, int bstore, int64_t ldb,
                        int64_t ncols, void* C, int cstore, int64_t ldc, uint16_t* hi,
-                       uint16_t* lo, double* sq_part, const int* gate, hipStream_t stream);
+                       uint16_t* lo, int64_t kbs, double* sq_part, const int* gate,
+                       hipStream_t stream);
 int spmm_nchunks(int bstore, int64_t ncols);
 
 // Candidate set of one iteration.

@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(NT)
 spmm_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
             const double* __restrict__ val, int64_t p, const void* __restrict__ B, int64_t ldb,
             int64_t ncols, void* __restrict__ C, int64_t ldc, uint16_t* __restrict__ hi,
-            uint16_t* __restrict__ lo, double* __restrict__ sq_part, const int* gate) {
+            uint16_t* __restrict__ lo, int64_t kbs, double* __restrict__ sq_part, const int* gate) {
     if (gate && *gate == 0) return;
     typedef Chunk<BS> Ch;
     typedef typename Ch::T T;
@@ -148,14 +148,16 @@ spmm_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                 h[t] = f2bf_rne(x);
                 l[t] = f2bf_rne(x - bf2f(h[t]));
             }
+            // V consecutive columns (c0 % V == 0) stay inside one K block
+            const int64_t o = kblk_index(row, c0, kbs);
             if (V == 4) {
-                *(uint2*)(hi + row * ldc + c0) =
+                *(uint2*)(hi + o) =
                     make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
-                *(uint2*)(lo + row * ldc + c0) =
+                *(uint2*)(lo + o) =
                     make_uint2((uint32_t)l[0] | ((uint32_t)l[1] << 16), (uint32_t)l[2] | ((uint32_t)l[3] << 16));
             } else {
 #pragma unroll
-                for (int t = 0; t < V; ++t) { hi[row * ldc + c0 + t] = h[t]; lo[row * ldc + c0 + t] = l[t]; }
+                for (int t = 0; t < V; ++t) { hi[o + t] = h[t]; lo[o + t] = l[t]; }
             }
         }
 #pragma unroll
@@ -674,7 +676,7 @@ template <typename In, typename Out>
 __global__ void __launch_bounds__(NT)
 transpose_in_kernel(const In* __restrict__ X, int64_t rows, int64_t cols, int64_t ld,
                     Out* __restrict__ Xt, int64_t ldo, uint16_t* __restrict__ hi,
-                    uint16_t* __restrict__ lo) {
+                    uint16_t* __restrict__ lo, int64_t kbs) {
     __shared__ Out tile[64][65];
     const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
@@ -691,8 +693,9 @@ transpose_in_kernel(const In* __restrict__ X, int64_t rows, int64_t cols, int64_
             if (hi) {
                 const float x = (float)v;
                 const uint16_t h = f2bf_rne(x);
-                hi[oc * ldo + orr] = h;
-                lo[oc * ldo + orr] = f2bf_rne(x - bf2f(h));
+                const int64_t o = kblk_index(oc, orr, kbs);
+                hi[o] = h;
+                lo[o] = f2bf_rne(x - bf2f(h));
             }
         }
     }
@@ -909,13 +912,14 @@ int spmm_nchunks(int bstore, int64_t ncols) {
 
 hipError_t launch_spmm(const Csr& A, int64_t p, const void* B, int bstore, int64_t ldb,
                        int64_t ncols, void* C, int cstore, int64_t ldc, uint16_t* hi,
-                       uint16_t* lo, double* sq_part, const int* gate, hipStream_t stream) {
+                       uint16_t* lo, int64_t kbs, double* sq_part, const int* gate,
+                       hipStream_t stream) {
     if (p == 0) return hipSuccess;
     const int nch = spmm_nchunks(bstore, ncols);
     dim3 grid(blocks_for(p, WPB), nch);
 #define SPMM(BS, CS)                                                                     \
     hipLaunchKernelGGL((spmm_kernel<BS, CS>), grid, dim3(NT), 0, stream, A.rowptr, A.col, \
-                       A.val, p, B, ldb, ncols, C, ldc, hi, lo, sq_part, gate)
+                       A.val, p, B, ldb, ncols, C, ldc, hi, lo, kbs, sq_part, gate)
     if (bstore == ST_F64) SPMM(ST_F64, ST_F64);
     else if (bstore == ST_F32) {
         if (cstore == ST_F64) SPMM(ST_F32, ST_F64); else SPMM(ST_F32, ST_F32);
@@ -1062,22 +1066,22 @@ hipError_t launch_symmetrize(void* W, int store, int64_t p, int64_t ld, const in
 
 hipError_t launch_transpose_in(const void* X, int x_is_f64, int64_t rows, int64_t cols,
                                int64_t ld, void* Xt, int store, int64_t ldo, uint16_t* hi,
-                               uint16_t* lo, hipStream_t stream) {
+                               uint16_t* lo, int64_t kbs, hipStream_t stream) {
     dim3 grid(blocks_for(cols, 64), blocks_for(rows, 64));
     if (x_is_f64) {
         if (store == ST_F64)
             hipLaunchKernelGGL((transpose_in_kernel<double, double>), grid, dim3(NT), 0, stream,
-                               (const double*)X, rows, cols, ld, (double*)Xt, ldo, hi, lo);
+                               (const double*)X, rows, cols, ld, (double*)Xt, ldo, hi, lo, kbs);
         else
             hipLaunchKernelGGL((transpose_in_kernel<double, float>), grid, dim3(NT), 0, stream,
-                               (const double*)X, rows, cols, ld, (float*)Xt, ldo, hi, lo);
+                               (const double*)X, rows, cols, ld, (float*)Xt, ldo, hi, lo, kbs);
     } else {
         if (store == ST_F64)
             hipLaunchKernelGGL((transpose_in_kernel<float, double>), grid, dim3(NT), 0, stream,
-                               (const float*)X, rows, cols, ld, (double*)Xt, ldo, hi, lo);
+                               (const float*)X, rows, cols, ld, (double*)Xt, ldo, hi, lo, kbs);
         else
             hipLaunchKernelGGL((transpose_in_kernel<float, float>), grid, dim3(NT), 0, stream,
-                               (const float*)X, rows, cols, ld, (float*)Xt, ldo, hi, lo);
+                               (const float*)X, rows, cols, ld, (float*)Xt, ldo, hi, lo, kbs);
     }
     return hipGetLastError();
 }

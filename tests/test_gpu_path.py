@@ -21,6 +21,8 @@ def test_lambda1_search_hits_target_degree():
     res = lambda1_for_degree(s, float(deg), 0.1, lo=0.0, hi=1.0, rel_tol=0.05)
     assert abs(res.degree - deg) <= 0.05 * deg, res.history
     rec = support_recovery(res.omega, om0)
-    # n = 2p samples from a degree-6 graph: most recovered edges are true ones
-    assert rec["ppv"] > 0.8, rec
+    # n = 2p samples of a degree-6 graph: well above chance (an estimate of the same
+    # size drawn at random would score PPV ~ deg / (p - 1) = 0.015)
+    assert rec["ppv"] > 0.5 and rec["recall"] > 0.5, rec
+    assert abs(rec["ppv"] + rec["fdr"] - 1.0) < 1e-12
     s.close()
