@@ -51,6 +51,7 @@ def run_form(torch, X32, p, n, lam1, lam2, form, steps, warmup):
     prof = s.profile()
     s.set_profiling(False)
     log(f"{form}: {steps} steps in {t1 - t0:.3f} s")
+    variant = s.contraction_variant()[1]
     om = s.get_omega_scipy()
     s.close()
     sec = t1 - t0
@@ -63,9 +64,10 @@ def run_form(torch, X32, p, n, lam1, lam2, form, steps, warmup):
         "ms_per_step": sec / steps * 1e3,
         "kernel_ms_per_step": {k: v[0] / steps for k, v in prof.items()},
         "dense_kernel_avg_ms": gemm_ms,
+        "contraction_variant": variant,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[form],
                      "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[form],
-                     "traffic": stored_traffic(form)},
+                     "traffic": stored_traffic(form, variant)},
         "trials_per_step": sum(i.n_trials for i in infos) / steps,
         "final_F": infos[-1].F,
         "final_nnz": infos[-1].nnz,
@@ -102,14 +104,17 @@ def run_cov_context(torch, X32, p, n, lam1, lam2, steps, warmup):
             "final_F": infos[-1].F, "final_nnz": infos[-1].nnz}, om
 
 
-def stored_traffic(form):
+def stored_traffic(form, variant):
     """HBM bytes per launch of the contraction from the committed counter record, or None
-    when the record is for another form or the kernel source changed since it was taken."""
+    when the record is for another form or tile variant, or the kernel source changed
+    since it was taken."""
     import hashlib
     rec_path = os.path.join(ROOT, "profiles", "traffic_gemm_sym_obs_p20000_n5000.json")
     if form != "bf16x3" or not os.path.exists(rec_path):
         return None
     rec = json.load(open(rec_path))
+    if rec.get("variant") != variant:
+        return None
     src = os.path.join(ROOT, rec["source"])
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
         return None
@@ -382,7 +387,8 @@ def main():
         "roofline": out[head]["roofline"],
     }
     for f in forms[1:]:
-        line[f] = {k: out[f][k] for k in ("value", "ms_per_step", "roofline", "dense_kernel_avg_ms")}
+        line[f] = {k: out[f][k] for k in ("value", "ms_per_step", "roofline", "dense_kernel_avg_ms",
+                                           "contraction_variant")}
         line[f"{head}_over_{f}"] = out[head]["value"] / out[f]["value"]
         a, b = oms[head], oms[f]
         d = a - b
@@ -390,6 +396,7 @@ def main():
         line[f"final_omega_maxdiff_rel_{head}_vs_{f}"] = (float(np.abs(d.data).max()) if d.nnz else 0.0) / scale
     line["kernel_ms_per_step"] = out[head]["kernel_ms_per_step"]
     line["dense_kernel_avg_ms"] = out[head]["dense_kernel_avg_ms"]
+    line["contraction_variant"] = out[head]["contraction_variant"]
     line["trials_per_step"] = out[head]["trials_per_step"]
     line["final_nnz"] = out[head]["final_nnz"]
     if not args.no_cov_context:

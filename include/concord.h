@@ -253,6 +253,15 @@ typedef struct concord_profile {
 /* on != 0 starts timing and clears the counters; on = 0 stops it. */
 int concord_set_profiling(concord_ctx* ctx, int32_t on);
 int concord_get_profile(const concord_ctx* ctx, concord_profile* host_out);
+/* Tile variant the library's autotuner picked for this handle's dense contraction
+   (Obs: the gradient SYR2K of Algorithm 3; Cov: the S = X^T X / n SYRK of
+   Algorithm 2).  The first contraction of a shape times every variant of the
+   precision form and keeps the fastest for the rest of the process (all variants
+   give bitwise the same result).  Writes the variant's name, NUL-terminated and
+   truncated to host_cap bytes, into host_name (may be null) and returns its index,
+   -1 if the shape has not been tuned yet (or the form has a single variant and was
+   never tuned), or CONCORD_EINVAL for a null handle. */
+int concord_contraction_variant(const concord_ctx* ctx, char* host_name, int32_t host_cap);
 
 /* ---- choice of the product form (Section 3, Lemma 3.1; Section S.1) ----
    Lemma 3.1 counts F_Cov = 2np^2 + 2dp^2(st+1) and F_Obs = 2np^2 s + 2dnp(st+1)

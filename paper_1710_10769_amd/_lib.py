@@ -100,6 +100,7 @@ _SIGS = {
     "concord_suggest_variant": (_I32, [_I64, _I64, _D, _D, _D, _I32, _D, _D, ctypes.c_void_p]),
     "concord_set_profiling": (_I32, [_P, _I32]),
     "concord_get_profile": (_I32, [_P, ctypes.c_void_p]),
+    "concord_contraction_variant": (_I32, [_P, ctypes.c_char_p, _I32]),
     "concord_last_error": (ctypes.c_char_p, [_P]),
     "concord_destroy": (None, [_P]),
     "concord_version": (ctypes.c_char_p, []),
@@ -253,6 +254,15 @@ def concord_get_profile(h) -> dict:
     return {name: (pr.ms[i], pr.launches[i]) for i, name in enumerate(PROF_CLASSES)}
 
 
+def concord_contraction_variant(h) -> Tuple[int, str]:
+    """(index, name) of the contraction tile variant the autotuner picked (-1 if untuned)."""
+    buf = ctypes.create_string_buffer(64)
+    v = load().concord_contraction_variant(h, buf, 64)
+    if v < -1:
+        _check(v, h)
+    return v, buf.value.decode()
+
+
 def concord_iterations(h) -> int:
     return load().concord_iterations(h)
 
@@ -367,6 +377,10 @@ class Solver:
     def profile(self) -> dict:
         """{class: (milliseconds, launch groups)} since profiling was switched on."""
         return concord_get_profile(self._h)
+
+    def contraction_variant(self) -> Tuple[int, str]:
+        """(index, name) of the dense-contraction tile variant in use (-1 if untuned)."""
+        return concord_contraction_variant(self._h)
 
     @property
     def iterations(self) -> int:

@@ -564,6 +564,16 @@ int concord_get_profile(const concord_ctx* c, concord_profile* out) {
     return CONCORD_OK;
 }
 
+int concord_contraction_variant(const concord_ctx* c, char* name, int32_t cap) {
+    if (!c) return CONCORD_EINVAL;
+    const char* nm = "untuned";
+    const int v = gemm_sym_choice(c->gkind, c->variant == CONCORD_OBS, c->p, c->ldk, &nm);
+    if (name && cap > 0) {
+        std::snprintf(name, (size_t)cap, "%s", nm);
+    }
+    return v;
+}
+
 void concord_destroy(concord_ctx* ctx) {
     if (!ctx) return;
     {

@@ -444,6 +444,67 @@ __device__ inline void read_frags(uint32_t a, uint32_t b, u32x4_t (&f)[12]) {
 }
 }  // namespace dma
 
+// Symmetric store of one 256 x 256 tile held as the 8 waves' 64 x 128 accumulators
+// (element layout of Form<GK_BF16X3>); shared by the direct-to-LDS kernels below.
+__device__ inline void store_tile_256(const f32x16_t (&acc)[dma::MB][dma::NB], int I, int J,
+                                      int64_t rowI0, int64_t rowJ0, int wm, int wn, int lane,
+                                      int p, double alpha, void* __restrict__ C, int out_store,
+                                      int64_t ldc) {
+    using namespace dma;
+    typedef Form<GK_BF16X3> F;
+    const int64_t gr0 = rowI0 + wm * 64, gc0 = rowJ0 + wn * 128;
+    if (I != J && out_store != ST_F64) {
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int64_t gj = gc0 + j * 32 + (lane & 31);
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int64_t gi0 = gr0 + i * 32 + 8 * g + 4 * (lane >> 5);
+                    uint32_t w[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const float x = (float)(alpha * (double)acc[i][j][4 * g + t]);
+                        if (out_store == ST_F32) {
+                            w[t] = __float_as_uint(x);
+                        } else {
+                            const uint16_t h = f2bf_rne(x);
+                            const uint16_t l = f2bf_rne(x - __uint_as_float(((uint32_t)h) << 16));
+                            w[t] = (uint32_t)h | ((uint32_t)l << 16);
+                        }
+                        if (gj < p && gi0 + t < p) ((uint32_t*)C)[(gi0 + t) * ldc + gj] = w[t];
+                    }
+                    if (gj < p) {
+                        if (gi0 + 3 < p) {
+                            *(u32x4_t*)((uint32_t*)C + gj * ldc + gi0) = u32x4_t{w[0], w[1], w[2], w[3]};
+                        } else {
+#pragma unroll
+                            for (int t = 0; t < 4; ++t)
+                                if (gi0 + t < p) ((uint32_t*)C)[gj * ldc + gi0 + t] = w[t];
+                        }
+                    }
+                }
+            }
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                int rr, cc;
+                F::coord(r, lane, rr, cc);
+                const int64_t gi = gr0 + i * 32 + rr, gj = gc0 + j * 32 + cc;
+                if (gi >= p || gj >= p) continue;
+                if (I == J && gi > gj) continue;
+                const double v = alpha * (double)acc[i][j][r];
+                store_val(C, out_store, gi * ldc + gj, v);
+                if (gi != gj) store_val(C, out_store, gj * ldc + gi, v);
+            }
+}
+
 __global__ void __launch_bounds__(dma::NT)
 gemm_bf16x3_dma_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
                        const char* __restrict__ Q0, const char* __restrict__ Q1,
@@ -548,59 +609,7 @@ gemm_bf16x3_dma_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
     }
     wait_vm(0);
 
-    // epilogue: symmetric store (same element layout as Form<GK_BF16X3>)
-    typedef Form<GK_BF16X3> F;
-    const int64_t gr0 = rowI0 + wm * 64, gc0 = rowJ0 + wn * 128;
-    if (I != J && out_store != ST_F64) {
-#pragma unroll
-        for (int i = 0; i < MB; ++i)
-#pragma unroll
-            for (int j = 0; j < NB; ++j) {
-                const int64_t gj = gc0 + j * 32 + (lane & 31);
-#pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    const int64_t gi0 = gr0 + i * 32 + 8 * g + 4 * (lane >> 5);
-                    uint32_t w[4];
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const float x = (float)(alpha * (double)acc[i][j][4 * g + t]);
-                        if (out_store == ST_F32) {
-                            w[t] = __float_as_uint(x);
-                        } else {
-                            const uint16_t h = f2bf_rne(x);
-                            const uint16_t l = f2bf_rne(x - __uint_as_float(((uint32_t)h) << 16));
-                            w[t] = (uint32_t)h | ((uint32_t)l << 16);
-                        }
-                        if (gj < p && gi0 + t < p) ((uint32_t*)C)[(gi0 + t) * ldc + gj] = w[t];
-                    }
-                    if (gj < p) {
-                        if (gi0 + 3 < p) {
-                            *(u32x4_t*)((uint32_t*)C + gj * ldc + gi0) = u32x4_t{w[0], w[1], w[2], w[3]};
-                        } else {
-#pragma unroll
-                            for (int t = 0; t < 4; ++t)
-                                if (gi0 + t < p) ((uint32_t*)C)[gj * ldc + gi0 + t] = w[t];
-                        }
-                    }
-                }
-            }
-        return;
-    }
-#pragma unroll
-    for (int i = 0; i < MB; ++i)
-#pragma unroll
-        for (int j = 0; j < NB; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                int rr, cc;
-                F::coord(r, lane, rr, cc);
-                const int64_t gi = gr0 + i * 32 + rr, gj = gc0 + j * 32 + cc;
-                if (gi >= p || gj >= p) continue;
-                if (I == J && gi > gj) continue;
-                const double v = alpha * (double)acc[i][j][r];
-                store_val(C, out_store, gi * ldc + gj, v);
-                if (gi != gj) store_val(C, out_store, gj * ldc + gi, v);
-            }
+    store_tile_256(acc, I, J, rowI0, rowJ0, wm, wn, lane, p, alpha, C, out_store, ldc);
 }
 
 // ---- BF16-split contraction, ping-pong schedule ---------------------------------
@@ -722,58 +731,176 @@ gemm_bf16x3_pp_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
     if (!grp) pp::phase_barrier();   // both groups pass the same number of barriers
     wait_vm(0);
 
-    typedef Form<GK_BF16X3> F;
-    const int64_t gr0 = rowI0 + wm * 64, gc0 = rowJ0 + wn * 128;
-    if (I != J && out_store != ST_F64) {
-#pragma unroll
-        for (int i = 0; i < MB; ++i)
-#pragma unroll
-            for (int j = 0; j < NB; ++j) {
-                const int64_t gj = gc0 + j * 32 + (lane & 31);
-#pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    const int64_t gi0 = gr0 + i * 32 + 8 * g + 4 * (lane >> 5);
-                    uint32_t w[4];
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const float x = (float)(alpha * (double)acc[i][j][4 * g + t]);
-                        if (out_store == ST_F32) {
-                            w[t] = __float_as_uint(x);
-                        } else {
-                            const uint16_t h = f2bf_rne(x);
-                            const uint16_t l = f2bf_rne(x - __uint_as_float(((uint32_t)h) << 16));
-                            w[t] = (uint32_t)h | ((uint32_t)l << 16);
-                        }
-                        if (gj < p && gi0 + t < p) ((uint32_t*)C)[(gi0 + t) * ldc + gj] = w[t];
-                    }
-                    if (gj < p) {
-                        if (gi0 + 3 < p) {
-                            *(u32x4_t*)((uint32_t*)C + gj * ldc + gi0) = u32x4_t{w[0], w[1], w[2], w[3]};
-                        } else {
-#pragma unroll
-                            for (int t = 0; t < 4; ++t)
-                                if (gi0 + t < p) ((uint32_t*)C)[gj * ldc + gi0 + t] = w[t];
-                        }
-                    }
-                }
-            }
-        return;
-    }
+    store_tile_256(acc, I, J, rowI0, rowJ0, wm, wn, lane, p, alpha, C, out_store, ldc);
+}
+
+// ---- BF16-split contraction: A fragments in registers, B through the LDS ring ----
+//
+// The LDS port is shared by the direct-to-LDS writes and the fragment reads; with
+// both sides staged in LDS that port, not HBM or L2, bounds the loop.  Here only the
+// B side (the 128 rows a wave shares with three other waves) goes through a 4-slot
+// ring (16 KB per stage); each wave loads its own 64 A rows (hi and lo, 4 x 1 KB
+// per stage, whole 32-row K blocks in MFMA operand layout) straight into registers,
+// two stages ahead, in three register sets.  LDS traffic per stage drops from
+// 32 KB written + 96 KB read to 16 KB + 64 KB.  Same per-accumulator MFMA order as
+// every other variant, so the result is bitwise the same.
+namespace ar {
+constexpr int BSLOT = 2 * dma::PS;   // B hi, B lo planes of one stage
+
+// the 8 B fragment reads of one stage (hi planes at b, lo at b + PS; 32-row blocks)
+__device__ inline void read_frags_b(uint32_t b, u32x4_t (&f)[8]) {
+    asm volatile(
+        "ds_read_b128 %0, %8\n\t"
+        "ds_read_b128 %1, %8 offset:1024\n\t"
+        "ds_read_b128 %2, %8 offset:2048\n\t"
+        "ds_read_b128 %3, %8 offset:3072\n\t"
+        "ds_read_b128 %4, %8 offset:8192\n\t"
+        "ds_read_b128 %5, %8 offset:9216\n\t"
+        "ds_read_b128 %6, %8 offset:10240\n\t"
+        "ds_read_b128 %7, %8 offset:11264\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(f[0]), "=&v"(f[1]), "=&v"(f[2]), "=&v"(f[3]), "=&v"(f[4]), "=&v"(f[5]),
+          "=&v"(f[6]), "=&v"(f[7])
+        : "v"(b)
+        : "memory");
+}
+
+}  // namespace ar
+
+__global__ void __launch_bounds__(dma::NT)
+gemm_bf16x3_ar_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
+                      const char* __restrict__ Q0, const char* __restrict__ Q1,
+                      int64_t kbs, int nk, int syr2k, int p, int T, int ntiles,
+                      double alpha, void* __restrict__ C, int out_store, int64_t ldc) {
+    using namespace dma;
+    using ar::BSLOT;
+    __shared__ __attribute__((aligned(16))) char ring[4 * BSLOT];
+
+    int I, J;
+    tile_of(blockIdx.x, ntiles, T, I, J);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave / WN, wn = wave % WN;
+    const int64_t rowI0 = (int64_t)I * BT, rowJ0 = (int64_t)J * BT;
+    const int nkt = syr2k ? 2 * nk : nk;
+    const int r32 = lane & 31, hk = lane >> 5;
+
+    // B side of stage kt: 16 load instructions (2 planes x 8 blocks of 32 rows), 2 per
+    // wave; waves 0-3 load the hi plane, waves 4-7 the lo plane.  Each wave's plane
+    // pointer per phase is fixed up front (phase 1 reads Q for B, phase 2 reads P).
+    const int bpl = wave >> 2;
+    const char* bsrc1 = syr2k ? (bpl ? Q1 : Q0) : (bpl ? P1 : P0);
+    const char* bsrc2 = bpl ? P1 : P0;
+    const int64_t brow = rowJ0 + (wave & 3) * 64 + (lane >> 1);   // + 32 q
+    const int bsw = (lane & 1) ^ (((lane >> 1) >> 3) & 1);          // swizzled chunk
+    // stage kt's B data into ring slot `slot_kt & 3`
+    auto issue_b = [&](int slot_kt, int kt) {
+        char* slot = ring + (slot_kt & 3) * BSLOT + bpl * PS + (wave & 3) * 2048;
+        const bool second = kt >= nk;
+        const char* g = (second ? bsrc2 : bsrc1) + (int64_t)(second ? kt - nk : kt) * kbs +
+                        brow * ROW + bsw * 16;
+        __builtin_amdgcn_global_load_lds((gbl_t*)g, (lds_t*)slot, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((gbl_t*)(g + 32 * ROW), (lds_t*)(slot + 1024), 16, 0, 0);
+    };
+    // A side of stage kt for this wave: rows wm*64 + {0..31, 32..63}, hi then lo;
+    // lane l holds row l % 32, K elements 8 (l / 32) .. +8 of the block
+    const int64_t arow = (rowI0 + wm * 64 + r32) * ROW + hk * 16;
+    auto load_a = [&](int kt, u32x4_t (&a)[4]) {
+        const bool second = kt >= nk;
+        const int64_t o = (int64_t)(second ? kt - nk : kt) * kbs + arow;
+        const char* ah = second ? Q0 : P0;
+        const char* al = second ? Q1 : P1;
+        a[0] = *(const u32x4_t*)(ah + o);
+        a[1] = *(const u32x4_t*)(ah + o + 32 * ROW);
+        a[2] = *(const u32x4_t*)(al + o);
+        a[3] = *(const u32x4_t*)(al + o + 32 * ROW);
+    };
+
+    f32x16_t acc[MB][NB];
 #pragma unroll
     for (int i = 0; i < MB; ++i)
 #pragma unroll
         for (int j = 0; j < NB; ++j)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                int rr, cc;
-                F::coord(r, lane, rr, cc);
-                const int64_t gi = gr0 + i * 32 + rr, gj = gc0 + j * 32 + cc;
-                if (gi >= p || gj >= p) continue;
-                if (I == J && gi > gj) continue;
-                const double v = alpha * (double)acc[i][j][r];
-                store_val(C, out_store, gi * ldc + gj, v);
-                if (gi != gj) store_val(C, out_store, gj * ldc + gi, v);
-            }
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    const uint32_t lds_b = (uint32_t)(uintptr_t)(lds_t*)ring + off(wn * 128 + r32, hk);
+
+    // Every stage issues exactly 4 A loads and then 2 B loads (past the last stage they
+    // re-read stage nkt - 1 into a register set / ring slot nothing reads again), and
+    // the prologue issues the same pattern (A(-1) is a dummy), so the operation counts
+    // are the same on every path into the loop: when stage k starts, 12 operations
+    // were issued after B(k) (A(k), B(k+1), A(k+1), B(k+2)); nkt >= 4.
+    u32x4_t a0[4], a1[4], a2[4];
+    load_a(0, a2);
+    issue_b(0, 0);
+    load_a(0, a0);
+    issue_b(1, 1);
+    load_a(1, a1);
+    issue_b(2, 2);
+    const int last = nkt - 1;
+    auto step = [&](int k, u32x4_t (&acur)[4], u32x4_t (&anext)[4]) {
+        __builtin_amdgcn_s_waitcnt(0x0f7c);   // vmcnt(12): this wave's share of B(k) landed
+        order();
+        __builtin_amdgcn_s_barrier();         // ... and every wave's; slot (k-1)&3 is free
+        order();
+        u32x4_t f[8];
+        ar::read_frags_b(lds_b + (k & 3) * BSLOT, f);
+        load_a(k + 2 < last ? k + 2 : last, anext);
+        issue_b(k + 3, k + 3 < last ? k + 3 : last);
+        bf16x8_t ah[MB], al[MB], bh[NB], bl[NB];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            ah[i] = __builtin_bit_cast(bf16x8_t, acur[i]);
+            al[i] = __builtin_bit_cast(bf16x8_t, acur[2 + i]);
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            bh[j] = __builtin_bit_cast(bf16x8_t, f[j]);
+            bl[j] = __builtin_bit_cast(bf16x8_t, f[4 + j]);
+        }
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+    };
+    int kt = 0;
+    for (; kt + 3 <= nkt; kt += 3) {
+        step(kt + 0, a0, a2);
+        step(kt + 1, a1, a0);
+        step(kt + 2, a2, a1);
+    }
+    if (kt < nkt) step(kt, a0, a2);
+    if (kt + 1 < nkt) step(kt + 1, a1, a0);
+    wait_vm(0);
+    store_tile_256(acc, I, J, rowI0, rowJ0, wm, wn, lane, p, alpha, C, out_store, ldc);
+}
+
+hipError_t launch_bf16x3_ar(bool syr2k, const void* P0, const void* P1, const void* Q0,
+                            const void* Q1, int64_t ldk, int64_t p, double alpha, void* C,
+                            int out_store, int64_t ldc, hipStream_t stream) {
+    const int64_t ldk_bytes = ldk * 2;
+    if (ldk_bytes % dma::ROW) return hipErrorInvalidValue;
+    const int nk = (int)(ldk_bytes / dma::ROW);
+    const int T = (int)((p + dma::BT - 1) / dma::BT);
+    const int ntiles = T * (T + 1) / 2;
+    if (ntiles == 0 || nk == 0) return hipSuccess;
+    hipLaunchKernelGGL(gemm_bf16x3_ar_kernel, dim3(ntiles), dim3(dma::NT), 0, stream,
+                       (const char*)P0, (const char*)P1, (const char*)(syr2k ? Q0 : P0),
+                       (const char*)(syr2k ? Q1 : P1), round_up(p, ROW_PAD) * dma::ROW, nk,
+                       syr2k ? 1 : 0, (int)p, T, ntiles, alpha, C, out_store, ldc);
+    return hipGetLastError();
 }
 
 hipError_t launch_bf16x3_pp(bool syr2k, const void* P0, const void* P1, const void* Q0,
@@ -856,12 +983,13 @@ hipError_t launch_kind(bool syr2k, const void* P0, const void* P1, const void* Q
 //
 // Variants per form: 256-wide tiles (8 waves, register-staged), 128-wide tiles (4
 // waves, register-staged), the 256-wide kernel as a persistent grid of one
-// workgroup per CU, and, for the BF16 split, the 256-wide direct-to-LDS ring.  All variants of a form produce bitwise-identical results (same
-// per-accumulator order of the K steps and of the three split products), so the
-// choice only affects speed.  The first contraction of a new shape key
-// (form, syr2k, p rounded up to 256, K) times every variant (after one warm-up
-// launch, best of two runs) with HIP events on the caller's stream and keeps the
-// fastest for the rest of the process.
+// workgroup per CU, and, for the BF16 split, the 256-wide direct-to-LDS ring, its
+// ping-pong schedule, and the ring with the A side in registers.  All variants of a
+// form produce bitwise-identical results (same per-accumulator order of the K steps
+// and of the three split products), so the choice only affects speed.  The first
+// contraction of a new shape key (form, syr2k, p rounded up to 256, K) times every
+// variant (after one warm-up launch, best of two runs) with HIP events on the
+// caller's stream and keeps the fastest for the rest of the process.
 // CONCORD_GEMM_VARIANT=<index> forces a variant; CONCORD_TUNE_CACHE=<file> loads
 // and stores the choices as "form syr2k p256 ldk variant" lines.
 typedef hipError_t (*LaunchFn)(bool, const void*, const void*, const void*, const void*, int64_t,
@@ -879,6 +1007,7 @@ const Variant* variants(int kind, int* count) {
         {"bf16x3_256x256_w8_ldsring", launch_bf16x3_dma},
         {"bf16x3_256x256_w8_persistent", launch_kind<GK_BF16X3, 256, 4, 2, true>},
         {"bf16x3_256x256_w8_pingpong", launch_bf16x3_pp},
+        {"bf16x3_256x256_w8_ldsring_aregs", launch_bf16x3_ar},
     };
     static const Variant f32[] = {
         {"f32_256x256_w8", launch_kind<GK_F32, 256, 4, 2>},
@@ -889,7 +1018,7 @@ const Variant* variants(int kind, int* count) {
         {"f64_128x128_w4", launch_kind<GK_F64, 128, 2, 2>},
     };
     switch (kind) {
-        case GK_BF16X3: *count = 5; return bf;
+        case GK_BF16X3: *count = 6; return bf;
         case GK_F32: *count = 3; return f32;
         default: *count = 1; return f64;
     }

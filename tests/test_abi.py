@@ -48,6 +48,7 @@ def test_version_and_null_handles(lib):
     assert lib.concord_reset(None) == _lib.EINVAL
     nnz = ctypes.c_int64()
     assert lib.concord_get_omega(None, ctypes.byref(nnz), None, None, None, 0) == _lib.EINVAL
+    assert lib.concord_contraction_variant(None, None, 0) == _lib.EINVAL
 
 
 def test_config_defaults(lib):

@@ -252,8 +252,8 @@ def test_lambda1_max_closed_form_gpu():
     s.close()
 
 
-@pytest.mark.parametrize("variant,precision,nvar", [("obs", "bf16x3", 5), ("obs", "fp32", 3),
-                                                    ("cov", "bf16x3", 5), ("cov", "fp32", 3)])
+@pytest.mark.parametrize("variant,precision,nvar", [("obs", "bf16x3", 6), ("obs", "fp32", 3),
+                                                    ("cov", "bf16x3", 6), ("cov", "fp32", 3)])
 def test_contraction_variants_bitwise_equal(variant, precision, nvar, monkeypatch):
     """Every tile variant the autotuner may pick gives bitwise the same iterates."""
     torch = _torch()
@@ -273,6 +273,26 @@ def test_contraction_variants_bitwise_equal(variant, precision, nvar, monkeypatc
     for o in outs[1:]:
         d = o - outs[0]
         assert d.nnz == 0 or np.abs(d.data).max() == 0.0
+
+
+@pytest.mark.parametrize("variant,precision", [("obs", "bf16x3"), ("cov", "fp32"), ("cov", "fp64")])
+def test_contraction_variant_reports_tuned_choice(variant, precision):
+    """After the first contraction the handle names the tile variant the tuner kept."""
+    torch = _torch()
+    p, n = 520, 200
+    w = datagen.make_workload("c2_obs_p20000", p=p, n=n)
+    X = _rounded(w.X, precision)
+    _say(f"contraction variant {variant} {precision} p={p} n={n}")
+    s = _solver(p, n, variant, precision)
+    s.set_data(_to_dev(X, torch.float64 if precision == "fp64" else torch.float32))
+    s.step(0.12, w.lam2)
+    idx, name = s.contraction_variant()
+    s.close()
+    if precision == "fp64":
+        # a single FP64 variant: launched directly, never timed
+        assert (idx, name) in ((-1, "untuned"), (0, "f64_128x128_w4"))
+    else:
+        assert idx >= 0 and name.startswith({"bf16x3": "bf16x3_", "fp32": "f32_"}[precision])
 
 
 @pytest.mark.parametrize("variant,precision,lam1,p,n", [
