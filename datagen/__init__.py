@@ -38,6 +38,10 @@ __all__ = [
     "make_workload",
     "WORKLOADS",
     "c4_instances",
+    "spatial_omega0",
+    "FMRI_BLOCKS",
+    "FMRI_LAMBDA1",
+    "FMRI_LAMBDA2",
 ]
 
 
@@ -222,6 +226,74 @@ def sample_bbt_cg(omega0: sp.spmatrix, n: int, rng: np.random.Generator,
     return out
 
 
+# fMRI-shaped stand-in (Section 5; Section S.3.1): p = 91,282 coordinates, the left
+# hemisphere's 29,696 given by the paper, the right hemisphere taken of the same size
+# and the remaining 31,890 as a third (volume) block; the estimates the paper shows are
+# block diagonal by hemisphere with spatially nearest coordinates linked.
+FMRI_BLOCKS = (("sphere", 29696), ("sphere", 29696), ("ball", 31890))
+FMRI_LAMBDA1 = (0.48, 0.5, 0.52, 0.54, 0.57, 0.59, 0.61, 0.64, 0.67, 0.69, 0.72)
+FMRI_LAMBDA2 = (0.10, 0.13, 0.16, 0.2, 0.25, 0.31, 0.39, 0.49)
+
+
+def _sphere_points(m: int) -> np.ndarray:
+    """m nearly evenly spaced points on the unit sphere (golden-angle spiral)."""
+    t = np.arange(m) + 0.5
+    polar = np.arccos(1.0 - 2.0 * t / m)
+    azim = np.pi * (1.0 + 5.0 ** 0.5) * t
+    return np.c_[np.cos(azim) * np.sin(polar), np.sin(azim) * np.sin(polar), np.cos(polar)]
+
+
+def _ball_points(m: int, rng: np.random.Generator) -> np.ndarray:
+    """m points uniform in the unit ball (radius by inverse CDF, direction Gaussian)."""
+    g = rng.standard_normal((m, 3))
+    g /= np.linalg.norm(g, axis=1, keepdims=True)
+    return g * rng.random(m)[:, None] ** (1.0 / 3.0)
+
+
+def _knn_pairs(pts: np.ndarray, k: int) -> tuple[np.ndarray, np.ndarray]:
+    """Unordered pairs i<j with j among the k nearest points of i or i among those of j."""
+    from scipy.spatial import cKDTree
+    m = len(pts)
+    _, idx = cKDTree(pts).query(pts, k + 1)
+    r = np.repeat(np.arange(m, dtype=np.int64), k)
+    c = idx[:, 1:].ravel().astype(np.int64)
+    keep = r != c
+    r, c = r[keep], c[keep]
+    codes = np.unique(np.minimum(r, c) * m + np.maximum(r, c))
+    return codes // m, codes % m
+
+
+def spatial_omega0(blocks, k: int, rng: np.random.Generator, lo: float = 0.1, hi: float = 0.3,
+                   delta: float = 0.1) -> sp.csr_matrix:
+    """Block-diagonal Omega0 with k-nearest-neighbour graphs on points in space.
+
+    Each block is ("sphere", m) (points on a sphere) or ("ball", m) (points in a ball);
+    blocks are independent.  Every edge gets -U[lo, hi] (a positive partial correlation
+    between neighbours, like a spatially smooth signal); diagonal = row abs-sum + delta.
+    """
+    rows, cols, vals = [], [], []
+    base = 0
+    for kind, m in blocks:
+        pts = _sphere_points(m) if kind == "sphere" else _ball_points(m, rng)
+        i, j = _knn_pairs(pts, k)
+        v = -rng.uniform(lo, hi, size=i.size)
+        rows += [i + base, j + base]
+        cols += [j + base, i + base]
+        vals += [v, v]
+        base += m
+    off = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                        shape=(base, base))
+    d = np.asarray(abs(off).sum(axis=1)).ravel() + delta
+    om = (off + sp.diags(d)).tocsr()
+    om.sort_indices()
+    return om
+
+
+def fmri_blocks(scale: float = 1.0):
+    """FMRI_BLOCKS with every block size multiplied by ``scale`` (at least 16 each)."""
+    return tuple((kind, max(16, int(round(m * scale)))) for kind, m in FMRI_BLOCKS)
+
+
 def standardize_columns(X: np.ndarray) -> np.ndarray:
     """Centre each column and divide by its population standard deviation (1/n)."""
     mu = X.mean(axis=0, keepdims=True)
@@ -269,6 +341,11 @@ WORKLOADS = {
     # Differentiation form, Obs, p=200,000, n=1,000, random degree 20, B B^T + CG sampler.
     "c5_grad_p200000": dict(p=200000, n=1000, graph="random", deg=20, seed=5, lam1=0.0,
                             lam2=0.1, variant="obs", tol=0.0, max_iter=0, sampler="cg"),
+    # fMRI-shaped Cov stand-in (Section 5): three spatial kNN blocks (k = 6), n = 5,142,
+    # B B^T + CG sampler, standardised columns; lambda grid FMRI_LAMBDA1 x FMRI_LAMBDA2.
+    "c6_fmri_cov_p91282": dict(p=91282, n=5142, graph="spatial", knn=6, seed=6,
+                               lam1=0.48, lam2=0.10, variant="cov", tol=1e-5, max_iter=200,
+                               sampler="cg", cg_chunk=512, standardize=True),
     # Finite-difference size of the differentiation form.
     "c5_fd_p500": dict(p=500, n=250, graph="random", deg=20, seed=55, lam1=0.0, lam2=0.1,
                        variant="obs", tol=0.0, max_iter=0),
@@ -287,11 +364,15 @@ def make_workload(name: str, p: Optional[int] = None, n: Optional[int] = None,
     rng = _rng(r["seed"])
     if r["graph"] == "chain":
         om = chain_omega0(r["p"])
+    elif r["graph"] == "spatial":
+        # p overrides scale the three blocks proportionally
+        om = spatial_omega0(fmri_blocks(r["p"] / 91282.0), r["knn"], rng)
     else:
         om = random_omega0(r["p"], r["deg"], rng)
     sampler = r.get("sampler", "cholesky")
     if sampler == "cg":
-        X = sample_bbt_cg(om, r["n"], rng, backend=backend, device=device)
+        X = sample_bbt_cg(om, r["n"], rng, backend=backend, device=device,
+                          chunk=r.get("cg_chunk", 64))
     else:
         X = sample_cholesky(om, r["n"], rng, backend=backend, device=device)
     if r.get("standardize"):

@@ -81,3 +81,21 @@ def lambda1_for_degree(solver, target_degree: float, lam2: float, lo: float = 0.
             b = lam1
     best.history = history
     return best
+
+
+def scale_for_lambda_grid(max_offdiag_s: float, lam1_top: float, lam2: float) -> float:
+    """Factor c for data whose sample covariance S has unit diagonal, such that the
+    estimate from c^2 S turns diagonal exactly at lambda1 = lam1_top for this lambda2.
+
+    With unit diagonal, Omega = D (d_i = 1 / sqrt(c^2 + lambda2)) is optimal iff every
+    |G_ij(D)| = c^2 |s_ij| d <= lambda1 (the KKT conditions at a diagonal point), so the
+    threshold is c^2 m / sqrt(c^2 + lambda2) with m = max_{i != j} |s_ij|; solving
+    c^2 m / sqrt(c^2 + lambda2) = lam1_top for u = c^2 gives
+    m^2 u^2 - lam1_top^2 u - lam1_top^2 lambda2 = 0.  By the scaling identity of the
+    objective, c only selects which part of the lambda path a fixed grid samples.
+    """
+    m, a, b = float(max_offdiag_s), float(lam1_top), float(lam2)
+    if not (m > 0 and a > 0 and b >= 0):
+        raise ValueError("need max_offdiag_s > 0, lam1_top > 0, lam2 >= 0")
+    u = (a * a + (a ** 4 + 4.0 * m * m * a * a * b) ** 0.5) / (2.0 * m * m)
+    return u ** 0.5

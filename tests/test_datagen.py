@@ -62,3 +62,37 @@ def test_cg_sampler_solves_exactly():
     b = B @ z.T
     r = om @ X.T - b
     assert np.abs(r).max() < 1e-10 * np.abs(b).max()
+
+
+def test_spatial_omega0_blocks_and_dominance():
+    blocks = (("sphere", 300), ("sphere", 300), ("ball", 320))
+    om = datagen.spatial_omega0(blocks, 6, datagen._rng(6))
+    p = 920
+    assert om.shape == (p, p)
+    assert abs(om - om.T).max() == 0
+    A = om.toarray()
+    off = A - np.diag(np.diag(A))
+    # strictly diagonally dominant with margin 0.1, every coupling negative in [-0.3, -0.1]
+    assert np.allclose(np.diag(A), np.abs(off).sum(1) + 0.1)
+    nz = off[off != 0]
+    assert (nz <= -0.1).all() and (nz >= -0.3).all()
+    # no edge between blocks; every vertex has at least its k nearest neighbours
+    bounds = np.cumsum([0, 300, 300, 320])
+    for b in range(3):
+        for c in range(3):
+            if b != c:
+                assert not off[bounds[b]:bounds[b + 1], bounds[c]:bounds[c + 1]].any()
+    assert ((off != 0).sum(1) >= 6).all()
+
+
+def test_spatial_omega0_is_seeded():
+    blocks = (("sphere", 100), ("ball", 120))
+    a = datagen.spatial_omega0(blocks, 4, datagen._rng(9))
+    b = datagen.spatial_omega0(blocks, 4, datagen._rng(9))
+    assert (a != b).nnz == 0
+
+
+def test_fmri_shape_matches_the_paper():
+    assert sum(m for _, m in datagen.FMRI_BLOCKS) == 91282
+    assert datagen.FMRI_BLOCKS[0][1] == 29696
+    assert len(datagen.FMRI_LAMBDA1) == 11 and len(datagen.FMRI_LAMBDA2) == 8

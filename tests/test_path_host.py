@@ -19,3 +19,25 @@ def test_support_recovery_counts():
 def test_average_degree():
     m = sp.csr_matrix(np.array([[1, 1, 0], [1, 1, 1], [0, 1, 1]], float))
     assert average_degree(m) == 4 / 3
+
+
+def test_scale_for_lambda_grid_hits_the_threshold():
+    from paper_1710_10769_amd.path import scale_for_lambda_grid
+    for m, a, b in [(0.6, 0.8, 0.1), (0.3, 0.72, 0.49), (0.9, 0.5, 0.0)]:
+        c = scale_for_lambda_grid(m, a, b)
+        # threshold of the scaled problem: c^2 m / sqrt(c^2 + lambda2)
+        assert abs(c * c * m / (c * c + b) ** 0.5 - a) < 1e-12
+
+
+def test_scale_for_lambda_grid_matches_the_diagonal_optimum():
+    """At the computed scale the oracle's lambda1_max closed form equals the target."""
+    import numpy as np
+    from oracle import checks
+    from paper_1710_10769_amd.path import scale_for_lambda_grid
+    rng = np.random.Generator(np.random.PCG64(3))
+    X = rng.standard_normal((50, 6))
+    X = (X - X.mean(0)) / X.std(0)
+    S = X.T @ X / 50
+    m = np.abs(S - np.diag(np.diag(S))).max()
+    c = scale_for_lambda_grid(m, 0.8, 0.1)
+    assert abs(checks.lambda1_max(c * c * S, 0.1) - 0.8) < 1e-12
