@@ -274,7 +274,7 @@ def bench_c6(args, torch, np, datagen):
     lam2 = b
     points = []
     t_all = 0.0
-    est_last = None
+    est_first = None
     for lam1 in datagen.FMRI_LAMBDA1:
         s.reset()
         s.set_profiling(True)
@@ -291,13 +291,14 @@ def bench_c6(args, torch, np, datagen):
                        "avg_degree": deg,
                        "ms_per_iter": {k: v[0] / max(si.iters, 1) for k, v in prof.items()}})
         log(f"lambda1 {lam1}: {si.iters} iterations, {dt:.2f} s, degree {deg:.2f}")
-        if deg > 0:
-            est_last = est
-    # support recovery at the densest point, and edges between blocks
-    rec = support_recovery(est_last, om0) if est_last is not None else None
+        if lam1 == min(datagen.FMRI_LAMBDA1):
+            est_first = est
+    # support recovery at the densest point of the column (smallest lambda1), and edges
+    # between blocks there
+    rec = support_recovery(est_first, om0)
     blocks = datagen.fmri_blocks(args.scale)
     bounds = np.cumsum([0] + [mm for _, mm in blocks])
-    e = sp_triu_coo(s.get_omega_scipy() if est_last is None else est_last)
+    e = sp_triu_coo(est_first)
     blk_r = np.searchsorted(bounds, e[0], side="right")
     blk_c = np.searchsorted(bounds, e[1], side="right")
     s.close()
