@@ -201,8 +201,9 @@ def bench_c3(args, torch, np, datagen):
         s.close()
         spmm_ms = prof["spmm"][0] / max(prof["spmm"][1], 1)
         eb = 8 if form == "fp64" else 4
-        # W = Omega S (read S, write W), symmetrise (read + write W): 4 p^2 elements
-        gbs = 4.0 * w.p * w.p * eb / (spmm_ms * 1e-3) / 1e9
+        # one-pass refresh M = (Omega S + S Omega) / 2: read S once, write M once (2 p^2
+        # elements; S rows re-read per nonzero of Omega come from L2/MALL)
+        gbs = 2.0 * w.p * w.p * eb / (spmm_ms * 1e-3) / 1e9
         res[form] = {"iters": si.iters, "iters_per_s": si.iters / t_solve, "solve_s": t_solve,
                      "s_formation_s": t_s, "nnz": si.nnz, "F": si.F,
                      "refresh_ms": spmm_ms, "refresh_GBps": gbs,

@@ -308,9 +308,8 @@ int products_at(concord_ctx* c, int which, const int* gate) {
         HIPCK(c, launch_obj_parts(O, p, nullptr, c->dstore, 0, c->part, gate, c->stream));
         HIPCK(c, launch_colsum(c->part, p, 4 + nch, c->objsums, c->colsum_ws, c->stream));
     } else {
-        HIPCK(c, launch_spmm(O, p, c->S, c->sstore, c->ldp, c->ldp, c->M, c->dstore, c->ldp,
-                             nullptr, nullptr, 0, nullptr, gate, c->stream));
-        HIPCK(c, launch_symmetrize(c->M, c->dstore, p, c->ldp, gate, c->stream));
+        HIPCK(c, launch_cov_refresh(O, p, c->S, c->sstore, c->ldp, c->M, c->dstore, c->ldp, gate,
+                                    c->stream));
         HIPCK(c, launch_obj_parts(O, p, c->M, c->dstore, c->ldp, c->part, gate, c->stream));
         HIPCK(c, launch_colsum(c->part, p, 4, c->objsums, c->colsum_ws, c->stream));
     }

@@ -156,9 +156,12 @@ hipError_t launch_obj_parts(const Csr& om, int64_t p, const void* W, int wstore,
 // Identity CSR (omega = I) into `om`.
 hipError_t launch_identity(const Csr& om, int64_t p, hipStream_t stream);
 
-// Symmetrise a dense square matrix in place: M = (W + W^T)/2.
-hipError_t launch_symmetrize(void* W, int store, int64_t p, int64_t ld, const int* gate,
-                             hipStream_t stream);
+// Cov refresh at the accepted iterate: M = (W + W^T) / 2 with W = Omega S (S: p x p,
+// row stride lds, `sstore`; M: row stride ldm, `mstore`: F64 with F64 S, F32
+// otherwise), in one pass over upper-triangle tile pairs.  Gated like launch_spmm.
+hipError_t launch_cov_refresh(const Csr& A, int64_t p, const void* S, int sstore, int64_t lds,
+                              void* M, int mstore, int64_t ldm, const int* gate,
+                              hipStream_t stream);
 
 // Differentiation form.
 hipError_t launch_sddmm_grad(const Csr& om, int64_t p, const void* Yt, const void* Xt,

@@ -14,6 +14,8 @@
 // Every FP64 reduction is done in a fixed order (lane-local sequential sums,
 // then a fixed xor-butterfly, then fixed-order column sums), so results are
 // bitwise reproducible run to run.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace concord {
@@ -642,32 +644,114 @@ __global__ void identity_kernel(int64_t* rowptr, int32_t* col, double* val, int6
     if (i == p) rowptr[p] = p;
 }
 
-// ---- symmetrise (Cov): M = (W + W^T) / 2, tile pairs through LDS ----------------
-template <int S>
+// ---- Cov refresh: M = (W + W^T) / 2 with W = Omega S, one pass -------------------
+// One workgroup per upper-triangle pair of 64 x 64 tiles (I <= J).  It forms
+// W_JI = Omega_J S_:,I into LDS and W_IJ = Omega_I S_:,J in registers, then writes
+// M_IJ = (W_IJ + W_JI^T) / 2 and its mirror M_JI, so W never goes to memory: S is
+// read once from HBM (its rows are re-read from L2/MALL once per nonzero of Omega)
+// and M written once, instead of W written, read back and M written.  Each wave
+// owns 16 rows and walks their nonzeros together (16 independent row loads in
+// flight); every element accumulates over its row's nonzeros in CSR order, as the
+// row-wise product does, so the result is the same bit for bit.
+template <int BS, int CS>
 __global__ void __launch_bounds__(NT)
-symmetrize_kernel(void* W, int64_t p, int64_t ld, int T, const int* gate) {
+cov_refresh_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                   const double* __restrict__ val, int64_t p, const void* __restrict__ S,
+                   int64_t lds, void* __restrict__ Mout, int64_t ldm, int T, const int* gate) {
     if (gate && *gate == 0) return;
-    typedef typename Chunk<S>::T E;
-    __shared__ E a[64][65], b[64][65];
-    // tile pair from linear upper-triangle index
+    typedef typename Chunk<BS>::T A;                          // accumulation type
+    typedef typename std::conditional<CS == ST_F64, double, float>::type E;
+    __shared__ E wt[64][65];   // W_JI (or W_II), then M_IJ for the mirrored store
     int t = blockIdx.x;
     int I = 0;
     while (t >= T - I) { t -= T - I; ++I; }
     const int J = I + t;
-    E* M = (E*)W;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int r = ty; r < 64; r += 4) {
-        const int64_t gi = (int64_t)I * 64 + r, gj = (int64_t)J * 64 + tx;
-        a[r][tx] = (gi < p && gj < p) ? M[gi * ld + gj] : (E)0;
-        const int64_t hi_ = (int64_t)J * 64 + r, hj = (int64_t)I * 64 + tx;
-        b[r][tx] = (hi_ < p && hj < p) ? M[hi_ * ld + hj] : (E)0;
+    const int lane = lane_id();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t i0 = (int64_t)I * 64, j0 = (int64_t)J * 64;
+
+    // rows r0 .. r0+15 of the tile starting at row `rb`, against columns `cb` + lane.
+    // Lane q < 16 fetches row q's CSR entry of each step (one vector load for all 16
+    // rows), broadcast by readlane; then all 16 S loads are issued before any is used.
+    // Rows past their last nonzero (or past p, where they start at entry 0) re-read a
+    // valid entry and keep their sum.
+    auto rows16 = [&](int64_t rb, int64_t cb, A (&acc)[16]) {
+        const int64_t myrow = rb + wave * 16 + (lane & 15);
+        int64_t my_s0 = 0;
+        int my_cnt = 0;
+        if (myrow < p) {
+            my_s0 = rowptr[myrow];
+            my_cnt = (int)(rowptr[myrow + 1] - my_s0);
+        }
+        int maxc = my_cnt;
+#pragma unroll
+        for (int o = 8; o >= 1; o >>= 1) {
+            const int other = __shfl_xor(maxc, o, 64);
+            maxc = other > maxc ? other : maxc;
+        }
+        maxc = __builtin_amdgcn_readfirstlane(maxc);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] = (A)0;
+        const int64_t c = cb + lane;
+        for (int m = 0; m < maxc; ++m) {
+            const int64_t k = my_s0 + (m < my_cnt ? m : 0);
+            const int cl = col[k];
+            const int64_t vb = __double_as_longlong(val[k]);
+            A x[16], v[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int cq = __builtin_amdgcn_readlane(cl, q);
+                const int64_t bq =
+                    ((int64_t)(uint32_t)__builtin_amdgcn_readlane((int)(vb >> 32), q) << 32) |
+                    (uint32_t)__builtin_amdgcn_readlane((int)vb, q);
+                v[q] = (A)__longlong_as_double(bq);
+                x[q] = (A)load_one_d<BS>(S, (int64_t)cq * lds + c);
+            }
+            __builtin_amdgcn_sched_barrier(0);   // keep the 16 loads ahead of their uses
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const A f = fma(v[q], x[q], acc[q]);
+                const int cnt_q = __builtin_amdgcn_readlane(my_cnt, q);
+                acc[q] = m < cnt_q ? f : acc[q];
+            }
+        }
+    };
+
+    A w[16];
+    if (I != J) {
+        rows16(j0, i0, w);   // W_JI rows j, columns i
+#pragma unroll
+        for (int q = 0; q < 16; ++q) wt[wave * 16 + q][lane] = (E)w[q];
+    }
+    rows16(i0, j0, w);       // W_IJ rows i, columns j
+    if (I == J) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) wt[wave * 16 + q][lane] = (E)w[q];
     }
     __syncthreads();
-    for (int r = ty; r < 64; r += 4) {
-        const int64_t gi = (int64_t)I * 64 + r, gj = (int64_t)J * 64 + tx;
-        if (gi < p && gj < p) M[gi * ld + gj] = (E)0.5 * (a[r][tx] + b[tx][r]);
-        const int64_t hi_ = (int64_t)J * 64 + r, hj = (int64_t)I * 64 + tx;
-        if (I != J && hi_ < p && hj < p) M[hi_ * ld + hj] = (E)0.5 * (b[r][tx] + a[tx][r]);
+    E mrow[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int r = wave * 16 + q;
+        mrow[q] = (E)0.5 * ((E)w[q] + wt[lane][r]);
+    }
+    __syncthreads();
+    E* M = (E*)Mout;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int r = wave * 16 + q;
+        const int64_t gi = i0 + r, gj = j0 + lane;
+        if (gi < p && gj < p) M[gi * ldm + gj] = mrow[q];
+        wt[r][lane] = mrow[q];
+    }
+    if (I == J) return;
+    __syncthreads();
+    // mirrored tile: M_JI[r][c] = M_IJ[c][r]
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int r = wave * 16 + q;
+        const int64_t gi = j0 + r, gj = i0 + lane;
+        if (gi < p && gj < p) M[gi * ldm + gj] = wt[lane][r];
     }
 }
 
@@ -1052,15 +1136,26 @@ hipError_t launch_identity(const Csr& om, int64_t p, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_symmetrize(void* W, int store, int64_t p, int64_t ld, const int* gate,
-                             hipStream_t stream) {
+hipError_t launch_cov_refresh(const Csr& A, int64_t p, const void* S, int sstore, int64_t lds,
+                              void* M, int mstore, int64_t ldm, const int* gate,
+                              hipStream_t stream) {
     const int T = (int)((p + 63) / 64);
     const int nt = T * (T + 1) / 2;
     if (nt == 0) return hipSuccess;
-    if (store == ST_F64)
-        hipLaunchKernelGGL(symmetrize_kernel<ST_F64>, dim3(nt), dim3(NT), 0, stream, W, p, ld, T, gate);
-    else
-        hipLaunchKernelGGL(symmetrize_kernel<ST_F32>, dim3(nt), dim3(NT), 0, stream, W, p, ld, T, gate);
+#define REFRESH(BS, CS)                                                                   \
+    hipLaunchKernelGGL((cov_refresh_kernel<BS, CS>), dim3(nt), dim3(NT), 0, stream, A.rowptr, \
+                       A.col, A.val, p, S, lds, M, ldm, T, gate)
+    if (sstore == ST_F64) {
+        if (mstore != ST_F64) return hipErrorInvalidValue;
+        REFRESH(ST_F64, ST_F64);
+    } else if (mstore != ST_F32) {
+        return hipErrorInvalidValue;
+    } else if (sstore == ST_F32) {
+        REFRESH(ST_F32, ST_F32);
+    } else {
+        REFRESH(ST_B16P, ST_F32);
+    }
+#undef REFRESH
     return hipGetLastError();
 }
 
