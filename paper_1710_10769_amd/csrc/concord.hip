@@ -112,6 +112,10 @@ struct concord_ctx {
 
     bool prod_valid = false;     // products and objective sums valid for om[cur]
     double obj[5] = {0, 0, 0, 0, 0};
+    // Cov: the candidate bitmap holds, for om[cur], at least the threshold words for
+    // lambda1 = bits_lam1 (written by the refresh at acceptance, or by a full pass)
+    bool bits_valid = false;
+    double bits_lam1 = -1.0;
 
     std::vector<void*> allocs;
 
@@ -124,6 +128,7 @@ struct concord_ctx {
         hipGraphExec_t exec = nullptr;
         double lam1 = -1, lam2 = -1;
         int64_t gen = -1;
+        bool merge = false;   // candidate pass captured: merge of threshold words or full
     } graphs[2];
 
     // profiling
@@ -285,8 +290,9 @@ int ensure_dense(concord_ctx* c) {
     return CONCORD_OK;
 }
 
-// Products and objective sums at om[which], gated on `gate` (device int).
-int products_at(concord_ctx* c, int which, const int* gate) {
+// Products and objective sums at om[which], gated on `gate` (device int).  With
+// bits_lam1 >= 0 the Cov refresh also writes the candidate threshold words for it.
+int products_at(concord_ctx* c, int which, const int* gate, double bits_lam1 = -1.0) {
     if (c->variant == CONCORD_COV) {
         int rc = ensure_dense(c);
         if (rc) return rc;
@@ -308,8 +314,9 @@ int products_at(concord_ctx* c, int which, const int* gate) {
         HIPCK(c, launch_obj_parts(O, p, nullptr, c->dstore, 0, c->part, gate, c->stream));
         HIPCK(c, launch_colsum(c->part, p, 4 + nch, c->objsums, c->colsum_ws, c->stream));
     } else {
-        HIPCK(c, launch_cov_refresh(O, p, c->S, c->sstore, c->ldp, c->M, c->dstore, c->ldp, gate,
-                                    c->stream));
+        HIPCK(c, launch_cov_refresh(O, p, c->S, c->sstore, c->ldp, c->M, c->dstore, c->ldp,
+                                    bits_lam1, bits_lam1 >= 0.0 ? c->bitmap : nullptr, c->nwords,
+                                    gate, c->stream));
         HIPCK(c, launch_obj_parts(O, p, c->M, c->dstore, c->ldp, c->part, gate, c->stream));
         HIPCK(c, launch_colsum(c->part, p, 4, c->objsums, c->colsum_ws, c->stream));
     }
@@ -346,6 +353,7 @@ int set_identity(concord_ctx* c) {
     c->nnz = c->p;
     c->k = 0;
     c->prod_valid = false;
+    c->bits_valid = false;
     return CONCORD_OK;
 }
 
@@ -385,12 +393,17 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
         prof_end(c);
         return CONCORD_OK;
     };
-    // candidate set A of this iteration
+    // candidate set A of this iteration.  Cov: when the accepted step's refresh already
+    // wrote the threshold words for this lambda1, only the support is merged in.
+    const bool merge = c->variant == CONCORD_COV && c->bits_valid && c->bits_lam1 == lam1;
     auto enqueue_cands = [&]() -> int {
         hipLaunchKernelGGL(state_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->st);
         prof_begin(c, CONCORD_PROF_CAND);
-        HIPCK(c, launch_cand_count(c->M, c->dstore, c->ldp, c->om[c->cur], p, lam1, c->bitmap,
-                                   c->nwords, c->cnt, c->stream));
+        if (merge)
+            HIPCK(c, launch_cand_merge(c->om[c->cur], p, c->bitmap, c->nwords, c->cnt, c->stream));
+        else
+            HIPCK(c, launch_cand_count(c->M, c->dstore, c->ldp, c->om[c->cur], p, lam1,
+                                       c->bitmap, c->nwords, c->cnt, c->stream));
         HIPCK(c, launch_scan(c->cnt, p, c->A.rowptr, c->a_cap, &c->st->overflow, c->stream));
         HIPCK(c, launch_cand_fill(c->M, c->dstore, c->ldp, c->om[c->cur], p, lam2, c->bitmap,
                                   c->nwords, c->A, c->a_cap, &c->st->overflow, c->stream));
@@ -414,7 +427,8 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
         HIPCK(c, launch_scan(c->cnt, p, c->om[nxt].rowptr, c->om_cap[nxt], nullptr, c->stream));
         HIPCK(c, launch_emit_fill(c->A, p, lam1, c->st, c->om[nxt], c->stream));
         prof_end(c);
-        int rc2 = products_at(c, nxt, &c->st->accepted);
+        int rc2 = products_at(c, nxt, &c->st->accepted,
+                              c->variant == CONCORD_COV ? lam1 : -1.0);
         if (rc2) return rc2;
         HIPCK(c, hipMemcpyAsync(c->h_stage, c->om[nxt].rowptr + p, sizeof(int64_t),
                                 hipMemcpyDeviceToHost, c->stream));
@@ -434,7 +448,8 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
         if ((rc = ensure_csr_cap(c, nxt, c->a_cap))) return rc;
         if ((rc = ensure_csr_cap(c, c->cur, c->a_cap))) return rc;
         concord_ctx::StepGraph& sg = c->graphs[c->cur];
-        if (!sg.exec || sg.lam1 != lam1 || sg.lam2 != lam2 || sg.gen != c->gen) {
+        if (!sg.exec || sg.lam1 != lam1 || sg.lam2 != lam2 || sg.gen != c->gen ||
+            sg.merge != merge) {
             if (sg.exec) {
                 (void)hipGraphExecDestroy(sg.exec);
                 sg.exec = nullptr;
@@ -456,6 +471,7 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
             sg.lam1 = lam1;
             sg.lam2 = lam2;
             sg.gen = c->gen;
+            sg.merge = merge;
         }
         HIPCK(c, hipGraphLaunch(sg.exec, c->stream));
         HIPCK(c, hipStreamSynchronize(c->stream));
@@ -491,6 +507,12 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
             const int64_t need = c->h_stage[1];
             if ((rc = ensure_cand_cap(c, need + need / 2 + 1024))) return rc;
             continue;
+        }
+        // the candidate pass ran for (om[cur], lam1); an accepted step's refresh rewrote
+        // the threshold words for (om[nxt], lam1)
+        if (c->variant == CONCORD_COV) {
+            c->bits_valid = true;
+            c->bits_lam1 = lam1;
         }
         if (c->st_host->nonpos)
             return fail(c, CONCORD_ENOTPD, "replayed step leaves a diagonal entry <= 0");
@@ -777,6 +799,7 @@ int concord_set_omega(concord_ctx* c, int64_t nnz, const int64_t* dev_row_ptr,
     c->nnz = nnz;
     c->k = 0;
     c->prod_valid = false;
+    c->bits_valid = false;
     return CONCORD_OK;
 }
 

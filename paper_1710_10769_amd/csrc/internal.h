@@ -99,6 +99,12 @@ struct Cand {
     double* grad;     // cap: G_ij
 };
 
+// Candidate bitmap and counts from threshold words written by launch_cov_refresh for
+// the same iterate and lambda1: ORs supp(Omega_i) into row i's words (in place) and
+// writes cnt[i] = |A_i|; the result equals launch_cand_count's.
+hipError_t launch_cand_merge(const Csr& om, int64_t p, uint64_t* bitmap, int64_t nwords,
+                             int64_t* cnt, hipStream_t stream);
+
 // Count pass: for every row, A_i = {j != i : |M_ij| > lam1} U supp(Omega_i) U {i}.
 // Writes the candidate bitmap (p x nwords64 uint64, row-major, word w bit b
 // covers column 64*w+b) and cnt[i] = |A_i|.
@@ -159,9 +165,11 @@ hipError_t launch_identity(const Csr& om, int64_t p, hipStream_t stream);
 // Cov refresh at the accepted iterate: M = (W + W^T) / 2 with W = Omega S (S: p x p,
 // row stride lds, `sstore`; M: row stride ldm, `mstore`: F64 with F64 S, F32
 // otherwise), in one pass over upper-triangle tile pairs.  Gated like launch_spmm.
+// If tbits is non-null (p x nwords, nwords = ceil(p/64)), it also writes the
+// threshold words {j : j == i or |M_ij| > lam1} of every row (see launch_cand_merge).
 hipError_t launch_cov_refresh(const Csr& A, int64_t p, const void* S, int sstore, int64_t lds,
-                              void* M, int mstore, int64_t ldm, const int* gate,
-                              hipStream_t stream);
+                              void* M, int mstore, int64_t ldm, double lam1, uint64_t* tbits,
+                              int64_t nwords, const int* gate, hipStream_t stream);
 
 // Differentiation form.
 hipError_t launch_sddmm_grad(const Csr& om, int64_t p, const void* Yt, const void* Xt,

@@ -657,7 +657,8 @@ template <int BS, int CS>
 __global__ void __launch_bounds__(NT)
 cov_refresh_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                    const double* __restrict__ val, int64_t p, const void* __restrict__ S,
-                   int64_t lds, void* __restrict__ Mout, int64_t ldm, int T, const int* gate) {
+                   int64_t lds, void* __restrict__ Mout, int64_t ldm, int T, double lam1,
+                   uint64_t* __restrict__ tbits, int64_t nwords, const int* gate) {
     if (gate && *gate == 0) return;
     typedef typename Chunk<BS>::T A;                          // accumulation type
     typedef typename std::conditional<CS == ST_F64, double, float>::type E;
@@ -737,12 +738,20 @@ cov_refresh_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict
     }
     __syncthreads();
     E* M = (E*)Mout;
+    // threshold bits of the next candidate set (optional): word J of row i holds
+    // j == i or |M_ij| > lam1 for the 64 columns of tile J, the same test (in FP64 on
+    // the stored value) as the full candidate pass
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int r = wave * 16 + q;
         const int64_t gi = i0 + r, gj = j0 + lane;
         if (gi < p && gj < p) M[gi * ldm + gj] = mrow[q];
         wt[r][lane] = mrow[q];
+        if (tbits) {
+            const bool b = gj < p && (gj == gi || fabs((double)mrow[q]) > lam1);
+            const uint64_t word = __ballot(b);
+            if (lane == 0 && gi < p) tbits[gi * nwords + J] = word;
+        }
     }
     if (I == J) return;
     __syncthreads();
@@ -751,8 +760,40 @@ cov_refresh_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict
     for (int q = 0; q < 16; ++q) {
         const int r = wave * 16 + q;
         const int64_t gi = j0 + r, gj = i0 + lane;
-        if (gi < p && gj < p) M[gi * ldm + gj] = wt[lane][r];
+        const E v = wt[lane][r];
+        if (gi < p && gj < p) M[gi * ldm + gj] = v;
+        if (tbits) {
+            const bool b = gj < p && (gj == gi || fabs((double)v) > lam1);
+            const uint64_t word = __ballot(b);
+            if (lane == 0 && gi < p) tbits[gi * nwords + I] = word;
+        }
     }
+}
+
+// ---- candidate set from the refresh's threshold bits -------------------------------
+// Row i's words already hold {j : j == i or |M_ij| > lam1}; OR in supp(Omega_i) and
+// count: the same bitmap and counts as cand_count_kernel, reading p/8 bytes per row
+// instead of the row of M.
+__global__ void __launch_bounds__(NT)
+cand_merge_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col, int64_t p,
+                  uint64_t* __restrict__ bitmap, int64_t nwords, int64_t* __restrict__ cnt) {
+    extern __shared__ uint32_t sbits[];
+    const int64_t nw32 = nwords * 2;
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
+    if (row >= p) return;
+    uint32_t* bits = sbits + wave * nw32;
+    build_supp_bits(bits, nw32, col, rowptr[row], rowptr[row + 1]);
+    int64_t total = 0;
+    for (int64_t w = lane; w < nwords; w += 64) {
+        const uint64_t supp = (uint64_t)bits[2 * w] | ((uint64_t)bits[2 * w + 1] << 32);
+        const uint64_t word = bitmap[row * nwords + w] | supp;
+        bitmap[row * nwords + w] = word;
+        total += __popcll(word);
+    }
+    double tt = (double)total;
+    tt = wave_sum(tt);
+    if (lane == 0) cnt[row] = (int64_t)tt;
 }
 
 // ---- ingest ----------------------------------------------------------------------
@@ -1026,6 +1067,15 @@ hipError_t launch_cand_count(const void* M, int mstore, int64_t ldm, const Csr& 
     return hipGetLastError();
 }
 
+hipError_t launch_cand_merge(const Csr& om, int64_t p, uint64_t* bitmap, int64_t nwords,
+                             int64_t* cnt, hipStream_t stream) {
+    if (p == 0) return hipSuccess;
+    const size_t lds = (size_t)WPB * nwords * 8;
+    hipLaunchKernelGGL(cand_merge_kernel, dim3(blocks_for(p, WPB)), dim3(NT), lds, stream,
+                       om.rowptr, om.col, p, bitmap, nwords, cnt);
+    return hipGetLastError();
+}
+
 hipError_t launch_cand_fill(const void* M, int mstore, int64_t ldm, const Csr& om, int64_t p,
                             double lam2, const uint64_t* bitmap, int64_t nwords,
                             const Cand& A, int64_t cap, const int* overflow,
@@ -1137,14 +1187,15 @@ hipError_t launch_identity(const Csr& om, int64_t p, hipStream_t stream) {
 }
 
 hipError_t launch_cov_refresh(const Csr& A, int64_t p, const void* S, int sstore, int64_t lds,
-                              void* M, int mstore, int64_t ldm, const int* gate,
-                              hipStream_t stream) {
+                              void* M, int mstore, int64_t ldm, double lam1, uint64_t* tbits,
+                              int64_t nwords, const int* gate, hipStream_t stream) {
+    if (tbits && nwords != (p + 63) / 64) return hipErrorInvalidValue;
     const int T = (int)((p + 63) / 64);
     const int nt = T * (T + 1) / 2;
     if (nt == 0) return hipSuccess;
 #define REFRESH(BS, CS)                                                                   \
     hipLaunchKernelGGL((cov_refresh_kernel<BS, CS>), dim3(nt), dim3(NT), 0, stream, A.rowptr, \
-                       A.col, A.val, p, S, lds, M, ldm, T, gate)
+                       A.col, A.val, p, S, lds, M, ldm, T, lam1, tbits, nwords, gate)
     if (sstore == ST_F64) {
         if (mstore != ST_F64) return hipErrorInvalidValue;
         REFRESH(ST_F64, ST_F64);

@@ -317,3 +317,30 @@ def test_graph_replay_matches_direct_launches(variant, precision, lam1, p, n):
     assert runs[0][0] == runs[1][0]
     d = runs[0][1] - runs[1][1]
     assert d.nnz == 0 or np.abs(d.data).max() == 0.0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_cov_steps_with_changing_lambda1(precision):
+    """Cov steps whose lambda1 changes between calls (the candidate pass then starts over
+    from M) and repeats (it reuses the threshold words of the last refresh) follow the
+    oracle stepped the same way."""
+    torch = _torch()
+    p, n, lam2 = 500, 220, 0.1
+    w = datagen.make_workload("c2_obs_p20000", p=p, n=n)
+    X = _rounded(w.X, precision)
+    seq = [0.12, 0.12, 0.2, 0.2, 0.12, 0.3, 0.12, 0.12]
+    _say(f"changing lambda1 cov {precision} p={p} n={n}")
+    s = _solver(p, n, "cov", precision)
+    s.set_data(_to_dev(X, torch.float64 if precision == "fp64" else torch.float32))
+    om = None
+    for it, lam1 in enumerate(seq):
+        ref = oc.solve(lam1, lam2, "cov", X=X, fixed_iters=1, omega_init=om,
+                       record_iterates=True, check_literal=False)
+        info = s.step_replay(lam1, lam2, ref.log[0].trials)
+        got, want = s.get_omega_scipy(), ref.iterates[1]
+        tol = 1e-6 if precision == "fp64" else 1e-4 * np.abs(want.data).max()
+        assert max_abs_diff(got, want) <= tol, (it, lam1)
+        assert len(support_mismatch(got, want)) <= (0 if precision == "fp64" else 2), (it, lam1)
+        assert info.n_candidates >= want.nnz
+        om = want
+    s.close()
