@@ -388,14 +388,20 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
         const void* Q0 = split ? (const void*)c->Xt_hi : c->Xt;
         const void* Q1 = split ? (const void*)c->Xt_lo : nullptr;
         prof_begin(c, CONCORD_PROF_DENSE);
+        // the epilogue also writes this iteration's candidate threshold words
+        ThreshOut th;
+        th.lam1 = lam1;
+        th.bits = c->bitmap;
+        th.nwords = c->nwords;
         HIPCK(c, launch_gemm_sym(c->gkind, true, P0, P1, Q0, Q1, c->ldk, p, 0.5 / (double)c->n,
-                                 c->M, c->dstore, c->ldp, c->stream));
+                                 c->M, c->dstore, c->ldp, c->stream, th));
         prof_end(c);
         return CONCORD_OK;
     };
-    // candidate set A of this iteration.  Cov: when the accepted step's refresh already
-    // wrote the threshold words for this lambda1, only the support is merged in.
-    const bool merge = c->variant == CONCORD_COV && c->bits_valid && c->bits_lam1 == lam1;
+    // candidate set A of this iteration: the support is merged into threshold words
+    // already written for this lambda1 by the Obs contraction's epilogue (every step) or
+    // by the Cov refresh of the accepted step; otherwise a full pass over M.
+    const bool merge = c->variant == CONCORD_OBS || (c->bits_valid && c->bits_lam1 == lam1);
     auto enqueue_cands = [&]() -> int {
         hipLaunchKernelGGL(state_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->st);
         prof_begin(c, CONCORD_PROF_CAND);

@@ -31,6 +31,7 @@
 #include <cstdlib>
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -232,6 +233,84 @@ __device__ inline void store_val(void* C, int store, int64_t idx, double v) {
     }
 }
 
+// Threshold words of the next candidate set, from the accumulators of one tile (the
+// 32 x 32 MFMA result layout of the FP32 and BF16-split forms): bit j of row i is set
+// iff i == j or |M_ij| > lam1 for the value stored in M (rounded to the stored type,
+// compared in FP64).  The bitmap is written as 32-bit half-words, each by exactly one
+// lane: for a 32 x 32 block, one ballot per accumulator register gives two rows'
+// half-words (lanes 0-31 hold one row, 32-63 the row four below), and the 16 rows a
+// lane holds, joined with its partner lane's 16, give the mirrored row's half-word.
+// In a diagonal tile only blocks on or above the diagonal write (their values are the
+// stored ones), and a block on the diagonal joins its upper part with the mirror of it.
+// Threshold words of the next candidate set from the accumulators of one 256 x 256
+// tile of the direct-to-LDS kernels (8 waves of 64 x 128, 32 x 32 MFMA blocks): bit j
+// of row i is set iff i == j or |M_ij| > lam1 for the value stored in M (rounded to
+// the stored type, compared in FP64).  The bitmap is written as 32-bit half-words,
+// each by exactly one lane: for a 32 x 32 block, one ballot per accumulator register
+// gives two rows' half-words (lanes 0-31 hold one row, 32-63 the row four below),
+// and the 16 rows a lane holds, joined with its partner lane's 16, give the mirrored
+// row's half-word.  In a diagonal tile only blocks on or above the diagonal write
+// (their values are the stored ones); a block on the diagonal joins its upper part
+// with the mirror of it.
+template <int N, int K = 0, typename Fn>
+__device__ __forceinline__ void static_for(Fn&& f) {
+    if constexpr (K < N) {
+        f(std::integral_constant<int, K>{});
+        static_for<N, K + 1>(f);
+    }
+}
+
+template <int MB, int NB>
+__device__ __forceinline__ void write_thresh_bits(const f32x16_t (&acc)[MB][NB], bool diag_tile,
+                                                  int64_t rowI0, int64_t rowJ0, int wr0, int wc0,
+                                                  int lane, int p, double alpha, int out_store,
+                                                  const ThreshOut& th) {
+    uint32_t* hw = (uint32_t*)th.bits;
+    const int64_t nh = 2 * th.nwords;   // half-words per row
+    const int l32 = lane & 31, hi = lane >> 5;
+    static_for<MB>([&](auto ic) __attribute__((always_inline)) {
+        constexpr int i = decltype(ic)::value;
+        static_for<NB>([&](auto jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(jc)::value;
+            const int bi = (wr0 >> 5) + i, bj = (wc0 >> 5) + j;   // 32-blocks in the tile
+            if (diag_tile && bj < bi) return;
+            const bool dblk = diag_tile && bi == bj;
+            const int64_t row0 = rowI0 + bi * 32, col0 = rowJ0 + bj * 32;
+            const bool colok = col0 + l32 < p;
+            uint32_t direct = 0, mirror = 0;
+            static_for<16>([&](auto rc) __attribute__((always_inline)) {
+                constexpr int r = decltype(rc)::value;
+                constexpr int r_lo = 8 * (r >> 2) + (r & 3);   // row of lanes 0-31 (+4: 32-63)
+                const int rr = r_lo + 4 * hi;                   // this lane's row in the block
+                const double v = alpha * (double)acc[i][j][r];
+                const double sv = out_store == ST_F32 ? (double)(float)v : v;
+                const bool ok = colok && row0 + rr < p;
+                // upper element (rr < l32) in a diagonal block, any element elsewhere
+                const bool hit = ok && (!dblk || l32 > rr) && fabs(sv) > th.lam1;
+                const uint64_t bal = __ballot(hit);
+                direct = l32 == r_lo ? (uint32_t)bal : direct;
+                direct = l32 == r_lo + 4 ? (uint32_t)(bal >> 32) : direct;
+                mirror |= (uint32_t)hit << rr;
+            });
+            mirror |= __shfl_xor(mirror, 32, 64);
+            if (hi) return;
+            // half-words exist for columns < 64 * nwords only (blocks past them hold
+            // padding columns and write nothing)
+            if (dblk) {
+                // row row0 + l32: upper part from the ballots, the diagonal, and the part
+                // below the diagonal from the mirror of the upper part
+                const int64_t row = row0 + l32;
+                const uint32_t below = l32 ? (mirror & ((1u << l32) - 1u)) : 0u;
+                if (row < p) hw[row * nh + (col0 >> 5)] = direct | (1u << l32) | below;
+            } else {
+                const int64_t row = row0 + l32, mrow = col0 + l32;
+                if (row < p && (col0 >> 5) < nh) hw[row * nh + (col0 >> 5)] = direct;
+                if (mrow < p && (row0 >> 5) < nh) hw[mrow * nh + (row0 >> 5)] = mirror;
+            }
+        });
+    });
+}
+
 template <int KIND, int BT_, int WM_, int WN_, bool PERSIST>
 __global__ void __launch_bounds__(WM_ * WN_ * 64)
 gemm_sym_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
@@ -329,6 +408,7 @@ gemm_sym_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
 
     // epilogue: symmetric store
     const int64_t r0 = rowI0 + wm * WR, c0 = rowJ0 + wn * WC;
+
     if (F::BS == 32 && I != J && out_store != ST_F64) {
         // Off-diagonal tile, 4-byte elements.  Direct store: consecutive lanes
         // hold consecutive columns.  Mirrored store: registers 4g..4g+3 of a
@@ -446,13 +526,17 @@ __device__ inline void read_frags(uint32_t a, uint32_t b, u32x4_t (&f)[12]) {
 
 // Symmetric store of one 256 x 256 tile held as the 8 waves' 64 x 128 accumulators
 // (element layout of Form<GK_BF16X3>); shared by the direct-to-LDS kernels below.
-__device__ inline void store_tile_256(const f32x16_t (&acc)[dma::MB][dma::NB], int I, int J,
+__device__ __forceinline__ void store_tile_256(const f32x16_t (&acc)[dma::MB][dma::NB], int I, int J,
                                       int64_t rowI0, int64_t rowJ0, int wm, int wn, int lane,
                                       int p, double alpha, void* __restrict__ C, int out_store,
-                                      int64_t ldc) {
+                                      int64_t ldc, const ThreshOut& th) {
     using namespace dma;
     typedef Form<GK_BF16X3> F;
     const int64_t gr0 = rowI0 + wm * 64, gc0 = rowJ0 + wn * 128;
+    if (th.bits)
+        write_thresh_bits<MB, NB>(acc, I == J, rowI0, rowJ0, wm * 64, wn * 128, lane, p, alpha,
+                                  out_store, th);
+
     if (I != J && out_store != ST_F64) {
 #pragma unroll
         for (int i = 0; i < MB; ++i)
@@ -509,7 +593,8 @@ __global__ void __launch_bounds__(dma::NT)
 gemm_bf16x3_dma_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
                        const char* __restrict__ Q0, const char* __restrict__ Q1,
                        int64_t kbs, int nk, int syr2k, int p, int T, int ntiles,
-                       double alpha, void* __restrict__ C, int out_store, int64_t ldc) {
+                       double alpha, void* __restrict__ C, int out_store, int64_t ldc,
+                       ThreshOut th) {
     using namespace dma;
     __shared__ __attribute__((aligned(16))) char r0[SLOT];
     __shared__ __attribute__((aligned(16))) char r1[SLOT];
@@ -609,7 +694,7 @@ gemm_bf16x3_dma_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
     }
     wait_vm(0);
 
-    store_tile_256(acc, I, J, rowI0, rowJ0, wm, wn, lane, p, alpha, C, out_store, ldc);
+    store_tile_256(acc, I, J, rowI0, rowJ0, wm, wn, lane, p, alpha, C, out_store, ldc, th);
 }
 
 // ---- BF16-split contraction, ping-pong schedule ---------------------------------
@@ -636,7 +721,8 @@ __global__ void __launch_bounds__(dma::NT)
 gemm_bf16x3_pp_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
                       const char* __restrict__ Q0, const char* __restrict__ Q1,
                       int64_t kbs, int nk, int syr2k, int p, int T, int ntiles,
-                      double alpha, void* __restrict__ C, int out_store, int64_t ldc) {
+                      double alpha, void* __restrict__ C, int out_store, int64_t ldc,
+                       ThreshOut th) {
     using namespace dma;
     __shared__ __attribute__((aligned(16))) char ring[4 * SLOT];
 
@@ -731,7 +817,7 @@ gemm_bf16x3_pp_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
     if (!grp) pp::phase_barrier();   // both groups pass the same number of barriers
     wait_vm(0);
 
-    store_tile_256(acc, I, J, rowI0, rowJ0, wm, wn, lane, p, alpha, C, out_store, ldc);
+    store_tile_256(acc, I, J, rowI0, rowJ0, wm, wn, lane, p, alpha, C, out_store, ldc, th);
 }
 
 // ---- BF16-split contraction: A fragments in registers, B through the LDS ring ----
@@ -771,7 +857,8 @@ __global__ void __launch_bounds__(dma::NT)
 gemm_bf16x3_ar_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
                       const char* __restrict__ Q0, const char* __restrict__ Q1,
                       int64_t kbs, int nk, int syr2k, int p, int T, int ntiles,
-                      double alpha, void* __restrict__ C, int out_store, int64_t ldc) {
+                      double alpha, void* __restrict__ C, int out_store, int64_t ldc,
+                       ThreshOut th) {
     using namespace dma;
     using ar::BSLOT;
     __shared__ __attribute__((aligned(16))) char ring[4 * BSLOT];
@@ -884,12 +971,12 @@ gemm_bf16x3_ar_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
     if (kt < nkt) step(kt, a0, a2);
     if (kt + 1 < nkt) step(kt + 1, a1, a0);
     wait_vm(0);
-    store_tile_256(acc, I, J, rowI0, rowJ0, wm, wn, lane, p, alpha, C, out_store, ldc);
+    store_tile_256(acc, I, J, rowI0, rowJ0, wm, wn, lane, p, alpha, C, out_store, ldc, th);
 }
 
 hipError_t launch_bf16x3_ar(bool syr2k, const void* P0, const void* P1, const void* Q0,
                             const void* Q1, int64_t ldk, int64_t p, double alpha, void* C,
-                            int out_store, int64_t ldc, hipStream_t stream) {
+                            int out_store, int64_t ldc, hipStream_t stream, ThreshOut th) {
     const int64_t ldk_bytes = ldk * 2;
     if (ldk_bytes % dma::ROW) return hipErrorInvalidValue;
     const int nk = (int)(ldk_bytes / dma::ROW);
@@ -899,13 +986,13 @@ hipError_t launch_bf16x3_ar(bool syr2k, const void* P0, const void* P1, const vo
     hipLaunchKernelGGL(gemm_bf16x3_ar_kernel, dim3(ntiles), dim3(dma::NT), 0, stream,
                        (const char*)P0, (const char*)P1, (const char*)(syr2k ? Q0 : P0),
                        (const char*)(syr2k ? Q1 : P1), round_up(p, ROW_PAD) * dma::ROW, nk,
-                       syr2k ? 1 : 0, (int)p, T, ntiles, alpha, C, out_store, ldc);
+                       syr2k ? 1 : 0, (int)p, T, ntiles, alpha, C, out_store, ldc, th);
     return hipGetLastError();
 }
 
 hipError_t launch_bf16x3_pp(bool syr2k, const void* P0, const void* P1, const void* Q0,
                             const void* Q1, int64_t ldk, int64_t p, double alpha, void* C,
-                            int out_store, int64_t ldc, hipStream_t stream) {
+                            int out_store, int64_t ldc, hipStream_t stream, ThreshOut th) {
     const int64_t ldk_bytes = ldk * 2;
     if (ldk_bytes % dma::ROW) return hipErrorInvalidValue;
     const int nk = (int)(ldk_bytes / dma::ROW);
@@ -915,13 +1002,13 @@ hipError_t launch_bf16x3_pp(bool syr2k, const void* P0, const void* P1, const vo
     hipLaunchKernelGGL(gemm_bf16x3_pp_kernel, dim3(ntiles), dim3(dma::NT), 0, stream,
                        (const char*)P0, (const char*)P1, (const char*)(syr2k ? Q0 : P0),
                        (const char*)(syr2k ? Q1 : P1), round_up(p, ROW_PAD) * dma::ROW, nk,
-                       syr2k ? 1 : 0, (int)p, T, ntiles, alpha, C, out_store, ldc);
+                       syr2k ? 1 : 0, (int)p, T, ntiles, alpha, C, out_store, ldc, th);
     return hipGetLastError();
 }
 
 hipError_t launch_bf16x3_dma(bool syr2k, const void* P0, const void* P1, const void* Q0,
                              const void* Q1, int64_t ldk, int64_t p, double alpha, void* C,
-                             int out_store, int64_t ldc, hipStream_t stream) {
+                             int out_store, int64_t ldc, hipStream_t stream, ThreshOut th) {
     const int64_t ldk_bytes = ldk * 2;
     if (ldk_bytes % dma::ROW) return hipErrorInvalidValue;
     const int nk = (int)(ldk_bytes / dma::ROW);
@@ -931,7 +1018,7 @@ hipError_t launch_bf16x3_dma(bool syr2k, const void* P0, const void* P1, const v
     hipLaunchKernelGGL(gemm_bf16x3_dma_kernel, dim3(ntiles), dim3(dma::NT), 0, stream,
                        (const char*)P0, (const char*)P1, (const char*)(syr2k ? Q0 : P0),
                        (const char*)(syr2k ? Q1 : P1), round_up(p, ROW_PAD) * dma::ROW, nk,
-                       syr2k ? 1 : 0, (int)p, T, ntiles, alpha, C, out_store, ldc);
+                       syr2k ? 1 : 0, (int)p, T, ntiles, alpha, C, out_store, ldc, th);
     return hipGetLastError();
 }
 
@@ -949,7 +1036,7 @@ int device_cus() {
 template <int KIND, int BT, int WM, int WN, bool PERSIST = false>
 hipError_t launch_kind(bool syr2k, const void* P0, const void* P1, const void* Q0,
                        const void* Q1, int64_t ldk, int64_t p, double alpha, void* C,
-                       int out_store, int64_t ldc, hipStream_t stream) {
+                       int out_store, int64_t ldc, hipStream_t stream, ThreshOut th) {
     typedef Form<KIND> F;
     constexpr int NT = WM * WN * 64;
     const int64_t ldk_bytes = ldk * F::ELEM;
@@ -972,10 +1059,43 @@ hipError_t launch_kind(bool syr2k, const void* P0, const void* P1, const void* Q
         const int cus = device_cus() / 8 * 8;
         grid = ntiles < cus ? ntiles : cus;
     }
+    (void)th;   // no threshold output: launch_gemm_sym adds a separate pass
     hipLaunchKernelGGL((gemm_sym_kernel<KIND, BT, WM, WN, PERSIST>), dim3(grid), dim3(NT), lds, stream,
                        (const char*)P0, (const char*)P1, (const char*)(syr2k ? Q0 : P0),
                        (const char*)(syr2k ? Q1 : P1), ldk_bytes, kbs, nk, syr2k ? 1 : 0, (int)p,
                        T, ntiles, alpha, C, out_store, ldc);
+    return hipGetLastError();
+}
+
+// Threshold words from the stored M, for variants without the fused output: one wave
+// per (row, 64-column word), a ballot of j == i or |M_ij| > lam1 over the word's columns.
+template <typename E>
+__global__ void __launch_bounds__(256)
+thresh_words_kernel(const E* __restrict__ M, int64_t ldm, int64_t p, double lam1,
+                    uint64_t* __restrict__ bits, int64_t nwords) {
+    const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (wid >= p * nwords) return;
+    const int64_t row = wid / nwords, j = (wid % nwords) * 64 + lane;
+    bool b = false;
+    if (j < p) b = j == row || fabs((double)M[row * ldm + j]) > lam1;
+    const uint64_t word = __ballot(b);
+    if (lane == 0) bits[wid] = word;
+}
+
+hipError_t launch_thresh_words(const void* C, int out_store, int64_t ldc, int64_t p,
+                               const ThreshOut& th, hipStream_t stream) {
+    const int64_t waves = p * th.nwords;
+    if (waves == 0) return hipSuccess;
+    const dim3 grid((unsigned)((waves + 3) / 4));
+    if (out_store == ST_F64)
+        hipLaunchKernelGGL(thresh_words_kernel<double>, grid, dim3(256), 0, stream,
+                           (const double*)C, ldc, p, th.lam1, th.bits, th.nwords);
+    else if (out_store == ST_F32)
+        hipLaunchKernelGGL(thresh_words_kernel<float>, grid, dim3(256), 0, stream,
+                           (const float*)C, ldc, p, th.lam1, th.bits, th.nwords);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -993,29 +1113,30 @@ hipError_t launch_kind(bool syr2k, const void* P0, const void* P1, const void* Q
 // CONCORD_GEMM_VARIANT=<index> forces a variant; CONCORD_TUNE_CACHE=<file> loads
 // and stores the choices as "form syr2k p256 ldk variant" lines.
 typedef hipError_t (*LaunchFn)(bool, const void*, const void*, const void*, const void*, int64_t,
-                               int64_t, double, void*, int, int64_t, hipStream_t);
+                               int64_t, double, void*, int, int64_t, hipStream_t, ThreshOut);
 
 struct Variant {
     const char* name;
     LaunchFn fn;
+    bool bits;   // writes the threshold words itself (else a separate pass follows)
 };
 
 const Variant* variants(int kind, int* count) {
     static const Variant bf[] = {
-        {"bf16x3_256x256_w8", launch_kind<GK_BF16X3, 256, 4, 2>},
-        {"bf16x3_128x128_w4", launch_kind<GK_BF16X3, 128, 2, 2>},
-        {"bf16x3_256x256_w8_ldsring", launch_bf16x3_dma},
-        {"bf16x3_256x256_w8_persistent", launch_kind<GK_BF16X3, 256, 4, 2, true>},
-        {"bf16x3_256x256_w8_pingpong", launch_bf16x3_pp},
-        {"bf16x3_256x256_w8_ldsring_aregs", launch_bf16x3_ar},
+        {"bf16x3_256x256_w8", launch_kind<GK_BF16X3, 256, 4, 2>, false},
+        {"bf16x3_128x128_w4", launch_kind<GK_BF16X3, 128, 2, 2>, false},
+        {"bf16x3_256x256_w8_ldsring", launch_bf16x3_dma, true},
+        {"bf16x3_256x256_w8_persistent", launch_kind<GK_BF16X3, 256, 4, 2, true>, false},
+        {"bf16x3_256x256_w8_pingpong", launch_bf16x3_pp, true},
+        {"bf16x3_256x256_w8_ldsring_aregs", launch_bf16x3_ar, true},
     };
     static const Variant f32[] = {
-        {"f32_256x256_w8", launch_kind<GK_F32, 256, 4, 2>},
-        {"f32_128x128_w4", launch_kind<GK_F32, 128, 2, 2>},
-        {"f32_256x256_w8_persistent", launch_kind<GK_F32, 256, 4, 2, true>},
+        {"f32_256x256_w8", launch_kind<GK_F32, 256, 4, 2>, false},
+        {"f32_128x128_w4", launch_kind<GK_F32, 128, 2, 2>, false},
+        {"f32_256x256_w8_persistent", launch_kind<GK_F32, 256, 4, 2, true>, false},
     };
     static const Variant f64[] = {
-        {"f64_128x128_w4", launch_kind<GK_F64, 128, 2, 2>},
+        {"f64_128x128_w4", launch_kind<GK_F64, 128, 2, 2>, false},
     };
     switch (kind) {
         case GK_BF16X3: *count = 6; return bf;
@@ -1069,27 +1190,35 @@ void tune_store_locked() {
 hipError_t launch_gemm_sym(int kind, bool syr2k, const void* P0, const void* P1,
                            const void* Q0, const void* Q1, int64_t ldk, int64_t p,
                            double alpha, void* C, int out_store, int64_t ldc,
-                           hipStream_t stream) {
+                           hipStream_t stream, ThreshOut th) {
     int nv = 0;
     const Variant* V = variants(kind, &nv);
+    if (th.bits && out_store == ST_B16P) return hipErrorInvalidValue;
+    // a variant, plus the threshold pass when it does not write the words itself
+    auto run = [&](int v) -> hipError_t {
+        hipError_t e = V[v].fn(syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc, stream, th);
+        if (e == hipSuccess && th.bits && !V[v].bits)
+            e = launch_thresh_words(C, out_store, ldc, p, th, stream);
+        return e;
+    };
     if (const char* e = std::getenv("CONCORD_GEMM_VARIANT")) {
         const int v = std::atoi(e);
         if (v >= 0 && v < nv)
-            return V[v].fn(syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc, stream);
+            return run(v);
     }
-    if (nv == 1) return V[0].fn(syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc, stream);
+    if (nv == 1) return run(0);
     const TuneKey key{kind, syr2k ? 1 : 0, round_up(p, 256), ldk};
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
         tune_load_locked();
         auto it = g_tune.find(key);
         if (it != g_tune.end() && it->second >= 0 && it->second < nv)
-            return V[it->second].fn(syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc, stream);
+            return run(it->second);
     }
     // not tuned yet: time each variant once (each run writes the same result)
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(stream, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
-        return V[0].fn(syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc, stream);
+        return run(0);
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess) return hipErrorOutOfMemory;
     if (hipEventCreate(&b) != hipSuccess) {
@@ -1099,11 +1228,11 @@ hipError_t launch_gemm_sym(int kind, bool syr2k, const void* P0, const void* P1,
     int best = 0;
     float best_ms = 1e30f;
     // one untimed launch warms clocks and caches, then the best of two runs per variant
-    hipError_t err = V[0].fn(syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc, stream);
+    hipError_t err = run(0);
     for (int v = 0; v < nv && err == hipSuccess; ++v) {
         for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
             (void)hipEventRecord(a, stream);
-            err = V[v].fn(syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc, stream);
+            err = run(v);
             (void)hipEventRecord(b, stream);
             if (err == hipSuccess) err = hipEventSynchronize(b);
             float ms = 0.f;

@@ -47,10 +47,19 @@ __host__ __device__ inline int64_t kblk_index(int64_t row, int64_t k, int64_t st
 // in the K-blocked layout above; otherwise P0/Q0 are row-major float (GK_F32) or
 // double (GK_F64) with row stride ldk.
 // out_store: ST_F32, ST_F64 or ST_B16P.
+// Optional second output of the contraction: threshold words of the next candidate
+// set (p x nwords uint64, nwords = ceil(p/64)); bit j of word w of row i is set iff
+// i == j or |C_ij| > lam1 for the stored value.  bits == nullptr: not written.  The
+// FP32 and BF16-split forms write it (ST_F32 output); the FP64 form ignores it.
+struct ThreshOut {
+    double lam1 = 0.0;
+    uint64_t* bits = nullptr;
+    int64_t nwords = 0;
+};
 hipError_t launch_gemm_sym(int kind, bool syr2k, const void* P0, const void* P1,
                            const void* Q0, const void* Q1, int64_t ldk, int64_t p,
                            double alpha, void* C, int out_store, int64_t ldc,
-                           hipStream_t stream);
+                           hipStream_t stream, ThreshOut th = ThreshOut());
 
 // Tuned variant index for a shape (-1 if not tuned yet) and its name.
 int gemm_sym_choice(int kind, bool syr2k, int64_t p, int64_t ldk, const char** name);

@@ -260,19 +260,21 @@ def test_contraction_variants_bitwise_equal(variant, precision, nvar, monkeypatc
     p, n = 600, 260
     w = datagen.make_workload("c2_obs_p20000", p=p, n=n)
     X = _rounded(w.X, precision)
-    outs = []
+    outs, cands = [], []
     for v in range(nvar):
         monkeypatch.setenv("CONCORD_GEMM_VARIANT", str(v))
         _say(f"variant {v} {variant} {precision} p={p} n={n}")
         s = _solver(p, n, variant, precision)
         s.set_data(_to_dev(X, torch.float32))
-        for _ in range(3):
-            s.step(0.12, w.lam2)
+        # candidate-set sizes: the Obs variants that write the candidate threshold words
+        # in their epilogue must match the separate threshold pass of the others
+        cands.append([s.step(0.12, w.lam2).n_candidates for _ in range(3)])
         outs.append(s.get_omega_scipy())
         s.close()
-    for o in outs[1:]:
+    for o, c in zip(outs[1:], cands[1:]):
         d = o - outs[0]
         assert d.nnz == 0 or np.abs(d.data).max() == 0.0
+        assert c == cands[0]
 
 
 @pytest.mark.parametrize("variant,precision", [("obs", "bf16x3"), ("cov", "fp32"), ("cov", "fp64")])
