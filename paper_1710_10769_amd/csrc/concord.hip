@@ -379,6 +379,7 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
     const int forced_q = forced_trials >= 1 ? forced_trials - 1 : -1;
     const int total = c->max_bt + 1;   // step sizes 1 .. 2^-max_bt
 
+    int obs_bits = 0;   // the Obs contraction wrote the candidate threshold words
     // gradient-side dense product (Obs): M = (Y X + (Y X)^T) / (2n)
     auto enqueue_gemm = [&]() -> int {
         if (c->variant != CONCORD_OBS) return CONCORD_OK;
@@ -388,21 +389,26 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
         const void* Q0 = split ? (const void*)c->Xt_hi : c->Xt;
         const void* Q1 = split ? (const void*)c->Xt_lo : nullptr;
         prof_begin(c, CONCORD_PROF_DENSE);
-        // the epilogue also writes this iteration's candidate threshold words
+        // the epilogue of the tuned variant may also write this iteration's candidate
+        // threshold words (obs_bits says whether it did)
         ThreshOut th;
         th.lam1 = lam1;
         th.bits = c->bitmap;
         th.nwords = c->nwords;
+        th.wrote = &obs_bits;
         HIPCK(c, launch_gemm_sym(c->gkind, true, P0, P1, Q0, Q1, c->ldk, p, 0.5 / (double)c->n,
                                  c->M, c->dstore, c->ldp, c->stream, th));
         prof_end(c);
         return CONCORD_OK;
     };
     // candidate set A of this iteration: the support is merged into threshold words
-    // already written for this lambda1 by the Obs contraction's epilogue (every step) or
+    // already written for this lambda1 by the Obs contraction's epilogue (this step) or
     // by the Cov refresh of the accepted step; otherwise a full pass over M.
-    const bool merge = c->variant == CONCORD_OBS || (c->bits_valid && c->bits_lam1 == lam1);
+    auto merge_now = [&]() {
+        return c->variant == CONCORD_OBS ? obs_bits != 0 : (c->bits_valid && c->bits_lam1 == lam1);
+    };
     auto enqueue_cands = [&]() -> int {
+        const bool merge = merge_now();
         hipLaunchKernelGGL(state_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->st);
         prof_begin(c, CONCORD_PROF_CAND);
         if (merge)
@@ -454,6 +460,8 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
         if ((rc = ensure_csr_cap(c, nxt, c->a_cap))) return rc;
         if ((rc = ensure_csr_cap(c, c->cur, c->a_cap))) return rc;
         concord_ctx::StepGraph& sg = c->graphs[c->cur];
+        // Obs: the tuned variant (fixed after the first step) decides; Cov: the state
+        const bool merge = c->variant == CONCORD_OBS ? sg.merge : merge_now();
         if (!sg.exec || sg.lam1 != lam1 || sg.lam2 != lam2 || sg.gen != c->gen ||
             sg.merge != merge) {
             if (sg.exec) {
@@ -477,7 +485,7 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
             sg.lam1 = lam1;
             sg.lam2 = lam2;
             sg.gen = c->gen;
-            sg.merge = merge;
+            sg.merge = c->variant == CONCORD_OBS ? obs_bits != 0 : merge;
         }
         HIPCK(c, hipGraphLaunch(sg.exec, c->stream));
         HIPCK(c, hipStreamSynchronize(c->stream));

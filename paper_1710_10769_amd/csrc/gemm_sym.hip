@@ -1059,43 +1059,11 @@ hipError_t launch_kind(bool syr2k, const void* P0, const void* P1, const void* Q
         const int cus = device_cus() / 8 * 8;
         grid = ntiles < cus ? ntiles : cus;
     }
-    (void)th;   // no threshold output: launch_gemm_sym adds a separate pass
+    (void)th;   // no threshold output
     hipLaunchKernelGGL((gemm_sym_kernel<KIND, BT, WM, WN, PERSIST>), dim3(grid), dim3(NT), lds, stream,
                        (const char*)P0, (const char*)P1, (const char*)(syr2k ? Q0 : P0),
                        (const char*)(syr2k ? Q1 : P1), ldk_bytes, kbs, nk, syr2k ? 1 : 0, (int)p,
                        T, ntiles, alpha, C, out_store, ldc);
-    return hipGetLastError();
-}
-
-// Threshold words from the stored M, for variants without the fused output: one wave
-// per (row, 64-column word), a ballot of j == i or |M_ij| > lam1 over the word's columns.
-template <typename E>
-__global__ void __launch_bounds__(256)
-thresh_words_kernel(const E* __restrict__ M, int64_t ldm, int64_t p, double lam1,
-                    uint64_t* __restrict__ bits, int64_t nwords) {
-    const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (wid >= p * nwords) return;
-    const int64_t row = wid / nwords, j = (wid % nwords) * 64 + lane;
-    bool b = false;
-    if (j < p) b = j == row || fabs((double)M[row * ldm + j]) > lam1;
-    const uint64_t word = __ballot(b);
-    if (lane == 0) bits[wid] = word;
-}
-
-hipError_t launch_thresh_words(const void* C, int out_store, int64_t ldc, int64_t p,
-                               const ThreshOut& th, hipStream_t stream) {
-    const int64_t waves = p * th.nwords;
-    if (waves == 0) return hipSuccess;
-    const dim3 grid((unsigned)((waves + 3) / 4));
-    if (out_store == ST_F64)
-        hipLaunchKernelGGL(thresh_words_kernel<double>, grid, dim3(256), 0, stream,
-                           (const double*)C, ldc, p, th.lam1, th.bits, th.nwords);
-    else if (out_store == ST_F32)
-        hipLaunchKernelGGL(thresh_words_kernel<float>, grid, dim3(256), 0, stream,
-                           (const float*)C, ldc, p, th.lam1, th.bits, th.nwords);
-    else
-        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -1118,7 +1086,7 @@ typedef hipError_t (*LaunchFn)(bool, const void*, const void*, const void*, cons
 struct Variant {
     const char* name;
     LaunchFn fn;
-    bool bits;   // writes the threshold words itself (else a separate pass follows)
+    bool bits;   // writes the threshold words (ThreshOut) when asked
 };
 
 const Variant* variants(int kind, int* count) {
@@ -1194,12 +1162,10 @@ hipError_t launch_gemm_sym(int kind, bool syr2k, const void* P0, const void* P1,
     int nv = 0;
     const Variant* V = variants(kind, &nv);
     if (th.bits && out_store == ST_B16P) return hipErrorInvalidValue;
-    // a variant, plus the threshold pass when it does not write the words itself
+    // a variant; reports whether it wrote the threshold words
     auto run = [&](int v) -> hipError_t {
-        hipError_t e = V[v].fn(syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc, stream, th);
-        if (e == hipSuccess && th.bits && !V[v].bits)
-            e = launch_thresh_words(C, out_store, ldc, p, th, stream);
-        return e;
+        if (th.wrote) *th.wrote = th.bits && V[v].bits ? 1 : 0;
+        return V[v].fn(syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc, stream, th);
     };
     if (const char* e = std::getenv("CONCORD_GEMM_VARIANT")) {
         const int v = std::atoi(e);
@@ -1245,10 +1211,13 @@ hipError_t launch_gemm_sym(int kind, bool syr2k, const void* P0, const void* P1,
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     if (err != hipSuccess) return err;
-    std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune[key] = best;
-    tune_store_locked();
-    return hipSuccess;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune[key] = best;
+        tune_store_locked();
+    }
+    // the outputs (and the threshold-words report) are those of the variant kept
+    return run(best);
 }
 
 int gemm_sym_choice(int kind, bool syr2k, int64_t p, int64_t ldk, const char** name) {

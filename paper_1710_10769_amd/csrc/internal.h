@@ -49,12 +49,14 @@ __host__ __device__ inline int64_t kblk_index(int64_t row, int64_t k, int64_t st
 // out_store: ST_F32, ST_F64 or ST_B16P.
 // Optional second output of the contraction: threshold words of the next candidate
 // set (p x nwords uint64, nwords = ceil(p/64)); bit j of word w of row i is set iff
-// i == j or |C_ij| > lam1 for the stored value.  bits == nullptr: not written.  The
-// FP32 and BF16-split forms write it (ST_F32 output); the FP64 form ignores it.
+// i == j or |C_ij| > lam1 for the stored value.  bits == nullptr: not requested.
+// Only the direct-to-LDS BF16-split variants write it; *wrote (host, optional) tells
+// whether the variant that ran did (else the caller runs the full candidate pass).
 struct ThreshOut {
     double lam1 = 0.0;
     uint64_t* bits = nullptr;
     int64_t nwords = 0;
+    int* wrote = nullptr;
 };
 hipError_t launch_gemm_sym(int kind, bool syr2k, const void* P0, const void* P1,
                            const void* Q0, const void* Q1, int64_t ldk, int64_t p,
