@@ -35,6 +35,25 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def stream_copy_gbps(torch, mib=2048, reps=5):
+    """Device-to-device copy rate (bytes read + written per second) of torch's copy kernel
+    on two buffers of `mib` MiB: the achievable HBM rate that HBM-bound kernels are
+    also compared with (alongside the 8 TB/s peak)."""
+    src = torch.empty(mib * 262144, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * mib * 1048576 / (ms * 1e-3) / 1e9
+
+
 def run_form(torch, X32, p, n, lam1, lam2, form, steps, warmup):
     from paper_1710_10769_amd import Solver
     s = Solver(p, n, variant="obs", precision=form)
@@ -104,16 +123,17 @@ def run_cov_context(torch, X32, p, n, lam1, lam2, steps, warmup):
             "final_F": infos[-1].F, "final_nnz": infos[-1].nnz}, om
 
 
-def stored_traffic(form, variant):
-    """HBM bytes per launch of the contraction from the committed counter record, or None
-    when the record is for another form or tile variant, or the kernel source changed
-    since it was taken."""
+def stored_traffic(form, variant, record="traffic_gemm_sym_obs_p20000_n5000.json",
+                   want_form="bf16x3"):
+    """HBM bytes per launch of a kernel from a committed counter record under profiles/, or
+    None when the record is for another form or tile variant, or the kernel's source
+    changed since the counters were taken."""
     import hashlib
-    rec_path = os.path.join(ROOT, "profiles", "traffic_gemm_sym_obs_p20000_n5000.json")
-    if form != "bf16x3" or not os.path.exists(rec_path):
+    rec_path = os.path.join(ROOT, "profiles", record)
+    if form != want_form or not os.path.exists(rec_path):
         return None
     rec = json.load(open(rec_path))
-    if rec.get("variant") != variant:
+    if rec.get("variant", variant) != variant:
         return None
     src = os.path.join(ROOT, rec["source"])
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
@@ -217,6 +237,8 @@ def bench_c3(args, torch, np, datagen):
         g, r = oms[form].copy(), ref.copy()
         g.data[:] = 1; r.data[:] = 1
         res[form]["support_mismatches_vs_fp64"] = int((abs(g - r)).nnz)
+    copy_gbps = stream_copy_gbps(torch)
+    ref_gbps = res["bf16x3"]["refresh_GBps"]
     line = {
         "metric": "Cov prox-grad iters/sec at p=16,384 per precision form",
         "value": res["bf16x3"]["iters_per_s"], "unit": "iters/s", "n_gpus": 1,
@@ -226,6 +248,14 @@ def bench_c3(args, torch, np, datagen):
         "config": {"workload": "cov_random_deg8_p16384_n4096", "p": w.p, "n": w.n,
                    "lam1": w.lam1, "lam2": w.lam2, "tol": w.tol},
         "forms": res,
+        # the Cov refresh M = (Omega S + S Omega) / 2 of the BF16x3 form: S (packed hi|lo,
+        # 4 bytes an entry) read once and M (FP32) written once per iteration
+        "roofline": {"bound": "hbm", "kernel": "cov_refresh_kernel", "achieved": ref_gbps,
+                     "peak": 8000.0, "unit": "GB/s", "frac": ref_gbps / 8000.0,
+                     "traffic": stored_traffic("bf16x3", None,
+                                               record="traffic_cov_refresh_c3_p16384.json"),
+                     "stream_copy_GBps": copy_gbps,
+                     "frac_of_stream_copy": ref_gbps / copy_gbps},
     }
     print(json.dumps(line), flush=True)
 
@@ -446,6 +476,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe_mib:
+        src = torch.ones(args.copy_probe_mib * 262144, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
+        del src, dst
     if args.workload == "c4":
         return bench_c4(args, torch, np, datagen)
     if args.workload == "c1":
@@ -457,13 +494,6 @@ def main():
     if args.workload == "c6":
         return bench_c6(args, torch, np, datagen)
     p, n = args.p, args.n
-    if args.copy_probe_mib:
-        src = torch.ones(args.copy_probe_mib * 262144, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
-        del src, dst
     log(f"generating workload p={p} n={n}")
     t0 = time.perf_counter()
     w = datagen.make_workload("c2_obs_p20000", p=p, n=n, backend="torch", device="cuda")
@@ -502,6 +532,7 @@ def main():
         d = a - b
         scale = float(np.abs(b.data).max())
         line[f"final_omega_maxdiff_rel_{head}_vs_{f}"] = (float(np.abs(d.data).max()) if d.nnz else 0.0) / scale
+    line["stream_copy_GBps"] = stream_copy_gbps(torch)
     line["kernel_ms_per_step"] = out[head]["kernel_ms_per_step"]
     line["dense_kernel_avg_ms"] = out[head]["dense_kernel_avg_ms"]
     line["contraction_variant"] = out[head]["contraction_variant"]
