@@ -645,14 +645,40 @@ __global__ void identity_kernel(int64_t* rowptr, int32_t* col, double* val, int6
 }
 
 // ---- Cov refresh: M = (W + W^T) / 2 with W = Omega S, one pass -------------------
-// One workgroup per upper-triangle pair of 64 x 64 tiles (I <= J).  It forms
-// W_JI = Omega_J S_:,I into LDS and W_IJ = Omega_I S_:,J in registers, then writes
-// M_IJ = (W_IJ + W_JI^T) / 2 and its mirror M_JI, so W never goes to memory: S is
-// read once from HBM (its rows are re-read from L2/MALL once per nonzero of Omega)
-// and M written once, instead of W written, read back and M written.  Each wave
-// owns 16 rows and walks their nonzeros together (16 independent row loads in
-// flight); every element accumulates over its row's nonzeros in CSR order, as the
-// row-wise product does, so the result is the same bit for bit.
+// Tile-pair order: bands of RG = 8 tile-rows, each walked column block by column block,
+// so the 8 tiles of one column block share the S rows of their band's supports.
+// Workgroup w runs on XCD w % 8 (one L2 per XCD); in every run of 64 workgroups, XCD x
+// is given the 8 tiles of column block 8a + x, so one XCD's L2 serves a column block
+// while the 8 XCDs work on 8 neighbouring blocks of the same band (sharing the MALL).
+constexpr int RG = 8;
+__device__ inline void refresh_tile(int w, int T, int ntiles, int& I, int& J) {
+    int t = w;
+    if (w < ntiles / 64 * 64) {
+        const int a = w >> 6, b = (w >> 3) & 7, x = w & 7;
+        t = 64 * a + 8 * x + b;
+    }
+    int i0 = 0;
+    for (;;) {
+        const int h = T - i0 < RG ? T - i0 : RG;
+        const int cnt = h * (h + 1) / 2 + h * (T - i0 - h);
+        if (t < cnt || i0 + h >= T) break;
+        t -= cnt;
+        i0 += RG;
+    }
+    const int h = T - i0 < RG ? T - i0 : RG;
+    const int tri = h * (h + 1) / 2;
+    if (t < tri) {
+        int jj = 0;
+        while (t >= jj + 1) { t -= jj + 1; ++jj; }
+        I = i0 + t;
+        J = i0 + jj;
+    } else {
+        t -= tri;
+        J = i0 + h + t / h;
+        I = i0 + t % h;
+    }
+}
+
 template <int BS, int CS>
 __global__ void __launch_bounds__(NT)
 cov_refresh_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
@@ -663,10 +689,8 @@ cov_refresh_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict
     typedef typename Chunk<BS>::T A;                          // accumulation type
     typedef typename std::conditional<CS == ST_F64, double, float>::type E;
     __shared__ E wt[64][65];   // W_JI (or W_II), then M_IJ for the mirrored store
-    int t = blockIdx.x;
-    int I = 0;
-    while (t >= T - I) { t -= T - I; ++I; }
-    const int J = I + t;
+    int I, J;
+    refresh_tile(blockIdx.x, T, (int)gridDim.x, I, J);
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t i0 = (int64_t)I * 64, j0 = (int64_t)J * 64;
