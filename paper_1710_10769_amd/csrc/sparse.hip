@@ -263,64 +263,47 @@ cand_fill_kernel(const void* __restrict__ M, int64_t ldm, const int64_t* __restr
                  const int64_t* __restrict__ arow, int32_t* __restrict__ acol,
                  double* __restrict__ aom, double* __restrict__ agr, const int* overflow) {
     if (*overflow) return;
-    typedef Chunk<MS> Ch;
-    constexpr int V = Ch::V;
-    constexpr int LPW = 64 / V;
+    typedef typename Chunk<MS>::T E;
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
     if (row >= p) return;
     const int64_t s = rowptr[row], e = rowptr[row + 1];
     int64_t out = arow[row];
-    const int64_t base = row * ldm;
-    const int64_t step = 64 * V;
-    const int wpg = V;   // 64-bit words per group of 64*V columns
-    for (int64_t g = 0; g < p; g += step) {
-        const int64_t w0 = g / 64;
-        uint64_t words[V];
-        int before = 0;
+    const E* Mrow = (const E*)M + row * ldm;
+    // 64 bitmap words (4096 columns) per step, one per lane; an exclusive prefix of
+    // their popcounts places each lane's candidates, so the row stays sorted
+    for (int64_t w0 = 0; w0 < nwords; w0 += 64) {
+        const int64_t w = w0 + lane;
+        uint64_t word = w < nwords ? bitmap[row * nwords + w] : 0ull;
+        const int pc = __popcll(word);
+        int incl = pc;
 #pragma unroll
-        for (int q = 0; q < V; ++q) {
-            words[q] = (w0 + q < nwords) ? bitmap[row * nwords + w0 + q] : 0ull;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int up = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += up;
         }
-        const int myw = lane / LPW;
-        int grp_total = 0;
-#pragma unroll
-        for (int q = 0; q < V; ++q) {
-            const int pc = __popcll(words[q]);
-            if (q < myw) before += pc;
-            grp_total += pc;
-        }
-        (void)wpg;
-        const int sh = V * (lane % LPW);
-        const uint32_t nib = (uint32_t)(words[myw] >> sh) & ((1u << V) - 1u);
-        before += __popcll(words[myw] & ((sh == 0) ? 0ull : (~0ull >> (64 - sh))));
-        if (nib) {
-            const int64_t c = g + lane * V;
-            double m[V];
-            cand_load_group<MS>(M, base, c, p, m);
-            int k = 0;
-#pragma unroll
-            for (int t = 0; t < V; ++t) {
-                if (!((nib >> t) & 1u)) continue;
-                const int64_t j = c + t;
-                // omega_ij: binary search of the sorted CSR row
-                double om = 0.0;
-                int64_t lo_ = s, hi_ = e;
-                while (lo_ < hi_) {
-                    const int64_t mid = (lo_ + hi_) >> 1;
-                    if (col[mid] < j) lo_ = mid + 1; else hi_ = mid;
-                }
-                if (lo_ < e && col[lo_] == j) om = val[lo_];
-                double gval = m[t] + lam2 * om;
-                if (j == row) gval -= 1.0 / om;
-                const int64_t pos = out + before + k;
-                acol[pos] = (int32_t)j;
-                aom[pos] = om;
-                agr[pos] = gval;
-                ++k;
+        const int total = __shfl(incl, 63, 64);
+        int64_t pos = out + (incl - pc);
+        while (word) {
+            const int b = __builtin_ctzll(word);
+            word &= word - 1ull;
+            const int64_t j = w * 64 + b;
+            // omega_ij: binary search of the sorted CSR row
+            double om = 0.0;
+            int64_t lo_ = s, hi_ = e;
+            while (lo_ < hi_) {
+                const int64_t mid = (lo_ + hi_) >> 1;
+                if (col[mid] < j) lo_ = mid + 1; else hi_ = mid;
             }
+            if (lo_ < e && col[lo_] == j) om = val[lo_];
+            double gval = (double)Mrow[j] + lam2 * om;
+            if (j == row) gval -= 1.0 / om;
+            acol[pos] = (int32_t)j;
+            aom[pos] = om;
+            agr[pos] = gval;
+            ++pos;
         }
-        out += grp_total;
+        out += total;
     }
 }
 
