@@ -133,8 +133,11 @@ int concord_create(const concord_config* cfg, concord_ctx** out);
      X^T (p x n, variable-major) in the handle's precision (plus BF16 hi/lo
      planes for CONCORD_BF16X3).  For Cov, S = X^T X / n is then formed on
      the GPU (Algorithm 2, once).
-   kind = CONCORD_DATA_S (Cov only): rows = cols = p; S is copied as given
-     (it must be symmetric; it is not checked).
+   kind = CONCORD_DATA_S (Cov only): rows = cols = p; the library stores
+     (S + S^T) / 2, rounded once to its precision, so the stored S is exactly
+     symmetric (a symmetric S, e.g. one with rounding-level asymmetry from a
+     library GEMM, changes by at most one rounding; an exactly symmetric S is
+     stored unchanged).  The Cov products rely on that exact symmetry.
    dtype: CONCORD_F64 or CONCORD_F32.  Resets Omega to I and k to 0.
    Errors: EINVAL (shape/dtype/kind mismatch, S with Obs), ENONFINITE
    (NaN/Inf in the input), EHIP. */

@@ -280,18 +280,22 @@ int sync_state(concord_ctx* c) {
     return CONCORD_OK;
 }
 
-// Dense p x p work buffers (M and the candidate bitmap) are allocated on first
-// use, so handles used only for the differentiation form never hold them.
+// Dense p x p work buffers (M for Obs, the candidate bitmap) are allocated on first
+// use, so handles used only for the differentiation form never hold them.  The Cov
+// form never stores M (the refresh writes threshold words; the gradient is gathered
+// on the candidates).
 int ensure_dense(concord_ctx* c) {
     int rc;
-    if (!c->M && (rc = dalloc(c, &c->M, (size_t)c->p * c->ldp * elem_bytes(c->dstore), true)))
+    if (c->variant == CONCORD_OBS && !c->M &&
+        (rc = dalloc(c, &c->M, (size_t)c->p * c->ldp * elem_bytes(c->dstore), true)))
         return rc;
     if (!c->bitmap && (rc = dalloc_t(c, &c->bitmap, (size_t)c->p * c->nwords, true))) return rc;
     return CONCORD_OK;
 }
 
-// Products and objective sums at om[which], gated on `gate` (device int).  With
-// bits_lam1 >= 0 the Cov refresh also writes the candidate threshold words for it.
+// Products and objective sums at om[which], gated on `gate` (device int).  Cov: the
+// objective gathers M on the support; with bits_lam1 >= 0 the refresh writes the
+// candidate threshold words of om[which] for that lambda1.
 int products_at(concord_ctx* c, int which, const int* gate, double bits_lam1 = -1.0) {
     if (c->variant == CONCORD_COV) {
         int rc = ensure_dense(c);
@@ -314,10 +318,10 @@ int products_at(concord_ctx* c, int which, const int* gate, double bits_lam1 = -
         HIPCK(c, launch_obj_parts(O, p, nullptr, c->dstore, 0, c->part, gate, c->stream));
         HIPCK(c, launch_colsum(c->part, p, 4 + nch, c->objsums, c->colsum_ws, c->stream));
     } else {
-        HIPCK(c, launch_cov_refresh(O, p, c->S, c->sstore, c->ldp, c->M, c->dstore, c->ldp,
-                                    bits_lam1, bits_lam1 >= 0.0 ? c->bitmap : nullptr, c->nwords,
-                                    gate, c->stream));
-        HIPCK(c, launch_obj_parts(O, p, c->M, c->dstore, c->ldp, c->part, gate, c->stream));
+        if (bits_lam1 >= 0.0)
+            HIPCK(c, launch_cov_refresh(O, p, c->S, c->sstore, c->ldp, bits_lam1, c->bitmap,
+                                        c->nwords, gate, c->stream));
+        HIPCK(c, launch_obj_parts_cov(O, p, c->S, c->sstore, c->ldp, c->part, gate, c->stream));
         HIPCK(c, launch_colsum(c->part, p, 4, c->objsums, c->colsum_ws, c->stream));
     }
     hipLaunchKernelGGL(obj_finish_kernel, dim3(1), dim3(64), 0, c->stream, c->objsums, nysq, c->st,
@@ -327,11 +331,18 @@ int products_at(concord_ctx* c, int which, const int* gate, double bits_lam1 = -
     return CONCORD_OK;
 }
 
-int ensure_products(concord_ctx* c) {
+// bits_lam1 >= 0 (a step about to run with that lambda1): the Cov refresh also writes
+// the candidate threshold words for it.
+int ensure_products(concord_ctx* c, double bits_lam1 = -1.0) {
     if (c->prod_valid) return CONCORD_OK;
     hipLaunchKernelGGL(state_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->st);
-    int rc = products_at(c, c->cur, c->d_one);
+    const bool bits = c->variant == CONCORD_COV && bits_lam1 >= 0.0;
+    int rc = products_at(c, c->cur, c->d_one, bits ? bits_lam1 : -1.0);
     if (rc) return rc;
+    if (bits) {
+        c->bits_valid = true;
+        c->bits_lam1 = bits_lam1;
+    }
     if ((rc = sync_state(c))) return rc;
     for (int i = 0; i < 5; ++i) c->obj[i] = c->st_host->obj[i];
     c->prod_valid = true;
@@ -368,7 +379,7 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
     if (int rc0 = enter(c)) return rc0;
     int rc = ensure_dense(c);
     if (rc) return rc;
-    if ((rc = ensure_products(c))) return rc;
+    if ((rc = ensure_products(c, lam1))) return rc;
     const int64_t p = c->p;
 
     const int nxt = c->cur ^ 1;
@@ -403,7 +414,8 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
     };
     // candidate set A of this iteration: the support is merged into threshold words
     // already written for this lambda1 by the Obs contraction's epilogue (this step) or
-    // by the Cov refresh of the accepted step; otherwise a full pass over M.
+    // by the Cov refresh of the accepted step; otherwise a full pass over M (Obs) or a
+    // refresh of the words at the current iterate (Cov).
     auto merge_now = [&]() {
         return c->variant == CONCORD_OBS ? obs_bits != 0 : (c->bits_valid && c->bits_lam1 == lam1);
     };
@@ -411,14 +423,22 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
         const bool merge = merge_now();
         hipLaunchKernelGGL(state_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->st);
         prof_begin(c, CONCORD_PROF_CAND);
-        if (merge)
+        const bool cov = c->variant == CONCORD_COV;
+        if (cov && !merge)
+            HIPCK(c, launch_cov_refresh(c->om[c->cur], p, c->S, c->sstore, c->ldp, lam1,
+                                        c->bitmap, c->nwords, c->d_one, c->stream));
+        if (merge || cov)
             HIPCK(c, launch_cand_merge(c->om[c->cur], p, c->bitmap, c->nwords, c->cnt, c->stream));
         else
             HIPCK(c, launch_cand_count(c->M, c->dstore, c->ldp, c->om[c->cur], p, lam1,
                                        c->bitmap, c->nwords, c->cnt, c->stream));
         HIPCK(c, launch_scan(c->cnt, p, c->A.rowptr, c->a_cap, &c->st->overflow, c->stream));
-        HIPCK(c, launch_cand_fill(c->M, c->dstore, c->ldp, c->om[c->cur], p, lam2, c->bitmap,
-                                  c->nwords, c->A, c->a_cap, &c->st->overflow, c->stream));
+        HIPCK(c, launch_cand_fill(cov ? nullptr : c->M, c->dstore, c->ldp, c->om[c->cur], p, lam2,
+                                  c->bitmap, c->nwords, c->A, c->a_cap, &c->st->overflow,
+                                  c->stream));
+        if (cov)
+            HIPCK(c, launch_cand_grad_cov(c->om[c->cur], p, c->S, c->sstore, c->ldp, lam2, c->A,
+                                          &c->st->overflow, c->stream));
         prof_end(c);
         return CONCORD_OK;
     };
@@ -773,7 +793,7 @@ int concord_set_data(concord_ctx* c, int32_t kind, const void* dev_data, int32_t
             prof_end(c);
         }
     } else {
-        HIPCK(c, launch_copy_square(dev_data, is64, c->p, ld, c->S, c->sstore, c->ldp, c->stream));
+        HIPCK(c, launch_sym_copy(dev_data, is64, c->p, ld, c->S, c->sstore, c->ldp, c->stream));
     }
     c->has_data = true;
     int rc = set_identity(c);
@@ -843,7 +863,8 @@ int concord_solve(concord_ctx* c, double lam1, double lam2, double tol, int64_t 
     if (!(tol >= 0.0) || max_iter < 0) return fail(c, CONCORD_EINVAL, "tol must be >= 0, max_iter >= 0");
     if (!c->has_data) return fail(c, CONCORD_ENODATA, "no data: call concord_set_data first");
     DeviceGuard g(c->device);
-    int rc = ensure_products(c);
+    if (int rc0 = enter(c)) return rc0;
+    int rc = ensure_products(c, lam1);
     if (rc) return rc;
     double f, F_old;
     objective_from(c, c->obj, lam1, lam2, &f, &F_old);
@@ -875,6 +896,7 @@ int concord_objective(concord_ctx* c, double lam1, double lam2, double* host_f, 
     if (!(lam1 >= 0.0) || !(lam2 >= 0.0)) return fail(c, CONCORD_EINVAL, "lambda must be >= 0");
     if (!c->has_data) return fail(c, CONCORD_ENODATA, "no data: call concord_set_data first");
     DeviceGuard g(c->device);
+    if (int rc0 = enter(c)) return rc0;
     int rc = ensure_products(c);
     if (rc) return rc;
     double f, F;

@@ -73,9 +73,10 @@ hipError_t launch_transpose_in(const void* X, int x_is_f64, int64_t rows, int64_
                                int64_t ld, void* Xt, int store, int64_t ldo, uint16_t* hi,
                                uint16_t* lo, int64_t kbs, hipStream_t stream);
 
-// Copy a square p x p (ld) F64/F32 matrix into `store` layout with ldo.
-hipError_t launch_copy_square(const void* S, int s_is_f64, int64_t p, int64_t ld, void* out,
-                              int store, int64_t ldo, hipStream_t stream);
+// (S + S^T) / 2 of a square p x p (ld) F64/F32 matrix into `store` layout with ldo,
+// exactly symmetric in the stored type (a symmetric S is copied unchanged).
+hipError_t launch_sym_copy(const void* S, int s_is_f64, int64_t p, int64_t ld, void* out,
+                           int store, int64_t ldo, hipStream_t stream);
 
 // Non-finite detector: sets *flag (int) to 1 if any of the rows x cols (ld)
 // entries is NaN/Inf.
@@ -123,10 +124,18 @@ hipError_t launch_cand_count(const void* M, int mstore, int64_t ldm, const Csr& 
                              double lam1, uint64_t* bitmap, int64_t nwords, int64_t* cnt,
                              hipStream_t stream);
 // Fill pass: writes A (sorted columns) with omega and G = M + lam2*omega - [i==j]/omega_ii.
+// With M null (Cov form) it writes the columns and omega only; launch_cand_grad_cov then
+// writes G.
 hipError_t launch_cand_fill(const void* M, int mstore, int64_t ldm, const Csr& om, int64_t p,
                             double lam2, const uint64_t* bitmap, int64_t nwords,
                             const Cand& A, int64_t cap, const int* overflow,
                             hipStream_t stream);
+
+// Cov form: G on the candidates of A (filled for the same iterate), with M_ij gathered
+// from S and the CSR rows i and j of Omega; bitwise the value the Cov refresh tests.
+hipError_t launch_cand_grad_cov(const Csr& om, int64_t p, const void* S, int sstore, int64_t lds,
+                                double lam2, const Cand& A, const int* overflow,
+                                hipStream_t stream);
 
 // Exclusive scan of cnt[0..p) into out[0..p] (out[p] = total); sets
 // *overflow = 1 if total > cap.  Single workgroup, deterministic.
@@ -169,18 +178,22 @@ hipError_t launch_emit_fill(const Cand& A, int64_t p, double lam1, const DevStat
 // W_ij * omega_ij over the stored entries (only if W non-null).
 hipError_t launch_obj_parts(const Csr& om, int64_t p, const void* W, int wstore, int64_t ldw,
                             double* part, const int* gate, hipStream_t stream);
+// Cov form: the same partials, t = 3 as sum_j M_ij omega_ij with M gathered from S on
+// the support of Omega (no dense M).
+hipError_t launch_obj_parts_cov(const Csr& om, int64_t p, const void* S, int sstore, int64_t lds,
+                                double* part, const int* gate, hipStream_t stream);
 
 // Identity CSR (omega = I) into `om`.
 hipError_t launch_identity(const Csr& om, int64_t p, hipStream_t stream);
 
-// Cov refresh at the accepted iterate: M = (W + W^T) / 2 with W = Omega S (S: p x p,
-// row stride lds, `sstore`; M: row stride ldm, `mstore`: F64 with F64 S, F32
-// otherwise), in one pass over upper-triangle tile pairs.  Gated like launch_spmm.
-// If tbits is non-null (p x nwords, nwords = ceil(p/64)), it also writes the
-// threshold words {j : j == i or |M_ij| > lam1} of every row (see launch_cand_merge).
+// Cov refresh: forms M = (W + W^T) / 2 with W = Omega S (S: p x p, row stride
+// lds >= 64 * nwords, `sstore`; M in FP64 for an FP64 S, FP32 otherwise) tile pair by
+// tile pair over the upper triangle and writes the threshold words
+// {j : j == i or |M_ij| > lam1} of every row into tbits (p x nwords, nwords =
+// ceil(p/64); see launch_cand_merge).  M is not stored.  Gated like launch_spmm.
 hipError_t launch_cov_refresh(const Csr& A, int64_t p, const void* S, int sstore, int64_t lds,
-                              void* M, int mstore, int64_t ldm, double lam1, uint64_t* tbits,
-                              int64_t nwords, const int* gate, hipStream_t stream);
+                              double lam1, uint64_t* tbits, int64_t nwords, const int* gate,
+                              hipStream_t stream);
 
 // Differentiation form.
 hipError_t launch_sddmm_grad(const Csr& om, int64_t p, const void* Yt, const void* Xt,

@@ -81,6 +81,65 @@ template <int S> __device__ inline double load_one_d(const void* b, int64_t idx)
     return (double)Chunk<S>::one(b, idx);
 }
 
+// Element c of the row starting at element `row` (a wave-uniform offset): the row's
+// base address stays scalar and the lane offset is a 32-bit vector register.
+template <int BS> __device__ inline double load_row_d(const void* b, int64_t row, uint32_t c) {
+    typedef typename std::conditional<BS == ST_F64, double, uint32_t>::type U;
+    // the row's address goes through readfirstlane, so it is formed in scalar registers
+    // and the load takes the scalar-base + 32-bit vector-offset form
+    typedef const __attribute__((address_space(1))) char GC;   // global memory
+    GC* r = (GC*)uni((int64_t)((const U*)b + row));
+    const U x = *(const __attribute__((address_space(1))) U*)(r + (uint32_t)(c * (uint32_t)sizeof(U)));
+    if (BS == ST_F64) return (double)x;
+    if (BS == ST_F32) return (double)__uint_as_float((uint32_t)x);
+    return (double)Chunk<ST_B16P>::cv((uint32_t)x);
+}
+
+// Cov form: stored type of M = (W + W^T) / 2 for S stored as BS
+template <int BS> struct MType { typedef float T; };
+template <> struct MType<ST_F64> { typedef double T; };
+
+// One entry M_ij = (W_ij + W_ji) / 2 of the Cov gradient, W = Omega S, from the CSR
+// rows i and j of Omega.  With S exactly symmetric, W_ji = sum_{k in supp_j} omega_jk
+// S[i][k].  The arithmetic is that of cov_refresh_kernel (each half is a chain of FMAs
+// over its row's nonzeros in CSR order in the accumulation type, both halves are
+// rounded to M's type, then added and halved), so the value is bitwise the one the
+// refresh tests against lambda1.  Loads are issued four at a time ahead of their FMAs.
+// fma_chain: sum over entries k in [s, e) of val[k] * S[base + col[k] * stride].
+template <int BS>
+__device__ inline typename Chunk<BS>::T fma_chain(const int32_t* __restrict__ col,
+                                                  const double* __restrict__ val, int64_t s,
+                                                  int64_t e, const void* __restrict__ S,
+                                                  int64_t base, int64_t stride) {
+    typedef typename Chunk<BS>::T A;
+    A acc = (A)0;
+    int64_t k = s;
+    for (; k + 4 <= e; k += 4) {
+        const A x0 = (A)load_one_d<BS>(S, base + (int64_t)col[k] * stride);
+        const A x1 = (A)load_one_d<BS>(S, base + (int64_t)col[k + 1] * stride);
+        const A x2 = (A)load_one_d<BS>(S, base + (int64_t)col[k + 2] * stride);
+        const A x3 = (A)load_one_d<BS>(S, base + (int64_t)col[k + 3] * stride);
+        acc = fma((A)val[k], x0, acc);
+        acc = fma((A)val[k + 1], x1, acc);
+        acc = fma((A)val[k + 2], x2, acc);
+        acc = fma((A)val[k + 3], x3, acc);
+    }
+    for (; k < e; ++k)
+        acc = fma((A)val[k], (A)load_one_d<BS>(S, base + (int64_t)col[k] * stride), acc);
+    return acc;
+}
+
+template <int BS>
+__device__ inline double m_entry(const int64_t* __restrict__ rowptr,
+                                 const int32_t* __restrict__ col, const double* __restrict__ val,
+                                 const void* __restrict__ S, int64_t lds, int64_t i, int64_t j) {
+    typedef typename MType<BS>::T E;
+    // W_ij: S[k][j] over k in supp_i;  W_ji: S[i][k] over k in supp_j
+    const E wij = (E)fma_chain<BS>(col, val, rowptr[i], rowptr[i + 1], S, j, lds);
+    const E wji = (E)fma_chain<BS>(col, val, rowptr[j], rowptr[j + 1], S, i * lds, 1);
+    return (double)((E)0.5 * (wij + wji));
+}
+
 // ---- SpMM: C = Omega B ------------------------------------------------------
 // grid: x = ceil(p / 4) row blocks, y = column chunks of 64*V (chunk-major
 // dispatch keeps one column slab of B hot in L2/MALL across all rows).
@@ -269,7 +328,7 @@ cand_fill_kernel(const void* __restrict__ M, int64_t ldm, const int64_t* __restr
     if (row >= p) return;
     const int64_t s = rowptr[row], e = rowptr[row + 1];
     int64_t out = arow[row];
-    const E* Mrow = (const E*)M + row * ldm;
+    const E* Mrow = M ? (const E*)M + row * ldm : nullptr;
     // 64 bitmap words (4096 columns) per step, one per lane; an exclusive prefix of
     // their popcounts places each lane's candidates, so the row stays sorted
     for (int64_t w0 = 0; w0 < nwords; w0 += 64) {
@@ -296,14 +355,45 @@ cand_fill_kernel(const void* __restrict__ M, int64_t ldm, const int64_t* __restr
                 if (col[mid] < j) lo_ = mid + 1; else hi_ = mid;
             }
             if (lo_ < e && col[lo_] == j) om = val[lo_];
-            double gval = (double)Mrow[j] + lam2 * om;
-            if (j == row) gval -= 1.0 / om;
             acol[pos] = (int32_t)j;
             aom[pos] = om;
-            agr[pos] = gval;
+            if (M) {
+                double gval = (double)Mrow[j] + lam2 * om;
+                if (j == row) gval -= 1.0 / om;
+                agr[pos] = gval;
+            }
             ++pos;
         }
         out += total;
+    }
+}
+
+// Cov form: the gradient on the candidates, G_ij = M_ij + lam2 omega_ij - [i == j] / omega_ii,
+// with M_ij gathered from S by m_entry (no dense M).  Wave per row, lanes over the row's
+// candidates; the row-i half of every entry walks the same nonzeros in every lane.
+template <int BS>
+__global__ void __launch_bounds__(NT)
+cand_grad_cov_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                     const double* __restrict__ val, int64_t p, const void* __restrict__ S,
+                     int64_t lds, double lam2, const int64_t* __restrict__ arow,
+                     const int32_t* __restrict__ acol, const double* __restrict__ aom,
+                     double* __restrict__ agr, const int* overflow) {
+    if (*overflow) return;
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
+    if (row >= p) return;
+    const int64_t s = arow[row], e = arow[row + 1];
+    for (int64_t k0 = s; k0 < e; k0 += 64) {
+        const int64_t k = k0 + lane;
+        const bool act = k < e;
+        const int64_t j = act ? acol[k] : row;
+        const double m = m_entry<BS>(rowptr, col, val, S, lds, row, j);
+        if (act) {
+            const double om = aom[k];
+            double g = m + lam2 * om;
+            if (j == row) g -= 1.0 / om;
+            agr[k] = g;
+        }
     }
 }
 
@@ -621,6 +711,41 @@ obj_parts_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__
     }
 }
 
+// Cov form: the same four partials, the last as sum_j M_ij omega_ij with M_ij gathered
+// from S (m_entry) on the support.
+template <int BS>
+__global__ void __launch_bounds__(NT)
+obj_parts_cov_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                     const double* __restrict__ val, int64_t p, const void* __restrict__ S,
+                     int64_t lds, double* __restrict__ part, const int* gate) {
+    if (gate && *gate == 0) return;
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
+    if (row >= p) return;
+    const int64_t s = rowptr[row], e = rowptr[row + 1];
+    double lg = 0, sq = 0, l1 = 0, wv = 0;
+    for (int64_t k0 = s; k0 < e; k0 += 64) {
+        const int64_t k = k0 + lane;
+        const bool act = k < e;
+        const int64_t j = act ? col[k] : row;
+        const double m = m_entry<BS>(rowptr, col, val, S, lds, row, j);
+        if (act) {
+            const double v = val[k];
+            sq += v * v;
+            if (j == row) lg += log(v);
+            else l1 += fabs(v);
+            wv = fma(m, v, wv);
+        }
+    }
+    lg = wave_sum(lg); sq = wave_sum(sq); l1 = wave_sum(l1); wv = wave_sum(wv);
+    if (lane == 0) {
+        part[0 * p + row] = lg;
+        part[1 * p + row] = sq;
+        part[2 * p + row] = l1;
+        part[3 * p + row] = wv;
+    }
+}
+
 __global__ void identity_kernel(int64_t* rowptr, int32_t* col, double* val, int64_t p) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < p) { rowptr[i] = i; col[i] = (int32_t)i; val[i] = 1.0; }
@@ -633,109 +758,153 @@ __global__ void identity_kernel(int64_t* rowptr, int32_t* col, double* val, int6
 // Workgroup w runs on XCD w % 8 (one L2 per XCD); in every run of 64 workgroups, XCD x
 // is given the 8 tiles of column block 8a + x, so one XCD's L2 serves a column block
 // while the 8 XCDs work on 8 neighbouring blocks of the same band (sharing the MALL).
+// The mapping is closed-form (a square root per workgroup): a walk over the bands costs
+// T / RG scalar steps before the first load, which dominated the kernel at p ~ 10^5.
 constexpr int RG = 8;
-__device__ inline void refresh_tile(int w, int T, int ntiles, int& I, int& J) {
-    int t = w;
+__device__ inline int2 refresh_tile(int w, int T, int ntiles) {
+    int64_t t = w;
     if (w < ntiles / 64 * 64) {
         const int a = w >> 6, b = (w >> 3) & 7, x = w & 7;
         t = 64 * a + 8 * x + b;
     }
-    int i0 = 0;
-    for (;;) {
-        const int h = T - i0 < RG ? T - i0 : RG;
-        const int cnt = h * (h + 1) / 2 + h * (T - i0 - h);
-        if (t < cnt || i0 + h >= T) break;
-        t -= cnt;
-        i0 += RG;
-    }
-    const int h = T - i0 < RG ? T - i0 : RG;
-    const int tri = h * (h + 1) / 2;
+    // full bands b' < b hold P(b) = b (G(G+1)/2 + G(T-G)) - G^2 b(b-1)/2 tiles
+    constexpr int64_t G = RG;
+    const int64_t nfull = T / G, c1 = G * (G + 1) / 2 + G * (T - G);
+    auto P = [&](int64_t b) { return b * c1 - G * G * b * (b - 1) / 2; };
+    const double q = (double)c1 + 0.5 * G * G;
+    const double disc = q * q - 2.0 * G * G * (double)t;
+    int64_t b = (int64_t)((q - sqrt(disc > 0.0 ? disc : 0.0)) / (double)(G * G));
+    b = b < 0 ? 0 : (b > nfull ? nfull : b);
+    while (b > 0 && P(b) > t) --b;
+    while (b < nfull && P(b + 1) <= t) ++b;
+    t -= P(b);
+    const int64_t i0 = b * G, h = T - i0 < G ? T - i0 : G;
+    const int64_t tri = h * (h + 1) / 2;
     if (t < tri) {
-        int jj = 0;
-        while (t >= jj + 1) { t -= jj + 1; ++jj; }
-        I = i0 + t;
-        J = i0 + jj;
-    } else {
-        t -= tri;
-        J = i0 + h + t / h;
-        I = i0 + t % h;
+        // column jj of the band's triangle holds jj + 1 tiles
+        int64_t jj = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+        while (jj > 0 && jj * (jj + 1) / 2 > t) --jj;
+        while ((jj + 1) * (jj + 2) / 2 <= t) ++jj;
+        return make_int2((int)(i0 + t - jj * (jj + 1) / 2), (int)(i0 + jj));
     }
+    t -= tri;
+    return make_int2((int)(i0 + t % h), (int)(i0 + h + t / h));
 }
 
-template <int BS, int CS>
+template <int BS>
 __global__ void __launch_bounds__(NT)
 cov_refresh_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                    const double* __restrict__ val, int64_t p, const void* __restrict__ S,
-                   int64_t lds, void* __restrict__ Mout, int64_t ldm, int T, double lam1,
-                   uint64_t* __restrict__ tbits, int64_t nwords, const int* gate) {
+                   int64_t lds, int T, double lam1, uint64_t* __restrict__ tbits, int64_t nwords,
+                   const int* gate) {
     if (gate && *gate == 0) return;
     typedef typename Chunk<BS>::T A;                          // accumulation type
-    typedef typename std::conditional<CS == ST_F64, double, float>::type E;
-    __shared__ E wt[64][65];   // W_JI (or W_II), then M_IJ for the mirrored store
-    int I, J;
-    refresh_tile(blockIdx.x, T, (int)gridDim.x, I, J);
+    typedef typename MType<BS>::T E;                          // type of M
+    __shared__ E wt[64][65];   // W_JI, then M_IJ read transposed for the rows of J
+    const int2 ij = refresh_tile(blockIdx.x, T, (int)gridDim.x);
+    const int I = __builtin_amdgcn_readfirstlane(ij.x), J = __builtin_amdgcn_readfirstlane(ij.y);
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t i0 = (int64_t)I * 64, j0 = (int64_t)J * 64;
 
-    // rows r0 .. r0+15 of the tile starting at row `rb`, against columns `cb` + lane.
-    // Lane q < 16 fetches row q's CSR entry of each step (one vector load for all 16
-    // rows), broadcast by readlane; then all 16 S loads are issued before any is used.
-    // Rows past their last nonzero (or past p, where they start at entry 0) re-read a
-    // valid entry and keep their sum.
-    auto rows16 = [&](int64_t rb, int64_t cb, A (&acc)[16]) {
-        const int64_t myrow = rb + wave * 16 + (lane & 15);
-        int64_t my_s0 = 0;
-        int my_cnt = 0;
-        if (myrow < p) {
-            my_s0 = rowptr[myrow];
-            my_cnt = (int)(rowptr[myrow + 1] - my_s0);
-        }
-        int maxc = my_cnt;
+    // W_IJ[i][j] = sum_{k in supp_i} omega_ik S[k][j] for this wave's 16 rows of tile I and
+    // W_JI[j][i] = sum_{k in supp_j} omega_jk S[k][i] for the same 16 rows of tile J (on a
+    // diagonal pair the same rows twice); M_IJ = (W_IJ + W_JI^T) / 2.  Every row's nonzeros
+    // are uniform in the wave, so each load reads 64 consecutive columns of one S row.
+    // Lane h < 16 holds the CSR range of I-row h and lane 16 + h that of J-row h, fetched
+    // up front; each step fetches all 32 rows' next entries with one vector load and
+    // broadcasts them by readlane.  With 4-byte accumulators both halves' 32 S loads are
+    // issued before the first FMA; with 8-byte ones the halves run one after the other
+    // (register budget).  Rows past their last nonzero (or past p, where they start at
+    // entry 0) re-read a valid entry and keep their sum.
+    constexpr bool PAIR = sizeof(A) == 4;
+    const int hl = lane & 31;
+    const int64_t myrow = (hl < 16 ? i0 : j0) + wave * 16 + (hl & 15);
+    int64_t my_s0 = 0;
+    int my_cnt = 0;
+    if (myrow < p) {
+        my_s0 = rowptr[myrow];
+        my_cnt = (int)(rowptr[myrow + 1] - my_s0);
+    }
+    int mx = my_cnt;
 #pragma unroll
-        for (int o = 8; o >= 1; o >>= 1) {
-            const int other = __shfl_xor(maxc, o, 64);
-            maxc = other > maxc ? other : maxc;
-        }
-        maxc = __builtin_amdgcn_readfirstlane(maxc);
+    for (int o = 8; o >= 1; o >>= 1) {
+        const int other = __shfl_xor(mx, o, 64);
+        mx = other > mx ? other : mx;
+    }
+    const int maxI = __builtin_amdgcn_readlane(mx, 0), maxJ = __builtin_amdgcn_readlane(mx, 16);
+    const uint32_t ci = (uint32_t)(i0 + lane), cj = (uint32_t)(j0 + lane);
+    A w[16], wj[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = (A)0;
-        const int64_t c = cb + lane;
-        for (int m = 0; m < maxc; ++m) {
-            const int64_t k = my_s0 + (m < my_cnt ? m : 0);
-            const int cl = col[k];
-            const int64_t vb = __double_as_longlong(val[k]);
-            A x[16], v[16];
+    for (int q = 0; q < 16; ++q) { w[q] = (A)0; wj[q] = (A)0; }
+
+    // step m's entries of the 32 rows (value already converted to A)
+    auto fetch = [&](int m, int& cl, A& v) {
+        const int64_t k = my_s0 + (m < my_cnt ? m : 0);
+        cl = col[k];
+        v = (A)val[k];
+    };
+    auto bcast = [&](A x, int q) -> A {
+        if (sizeof(A) == 4)
+            return __int_as_float(__builtin_amdgcn_readlane(__float_as_int((float)x), q));
+        const int64_t b = __double_as_longlong((double)x);
+        return (A)__longlong_as_double(
+            ((int64_t)(uint32_t)__builtin_amdgcn_readlane((int)(b >> 32), q) << 32) |
+            (uint32_t)__builtin_amdgcn_readlane((int)b, q));
+    };
+    // the 16 rows at lanes base .. base + 15 against columns c0 + lane
+    auto issue = [&](int cl, int base, uint32_t c0, A (&x)[16]) {
+        uint32_t off = c0;
+        asm volatile("" : "+v"(off));   // a fresh 32-bit offset each step (scalar-base loads)
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int cq = __builtin_amdgcn_readlane(cl, q);
-                const int64_t bq =
-                    ((int64_t)(uint32_t)__builtin_amdgcn_readlane((int)(vb >> 32), q) << 32) |
-                    (uint32_t)__builtin_amdgcn_readlane((int)vb, q);
-                v[q] = (A)__longlong_as_double(bq);
-                x[q] = (A)load_one_d<BS>(S, (int64_t)cq * lds + c);
-            }
-            __builtin_amdgcn_sched_barrier(0);   // keep the 16 loads ahead of their uses
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const A f = fma(v[q], x[q], acc[q]);
-                const int cnt_q = __builtin_amdgcn_readlane(my_cnt, q);
-                acc[q] = m < cnt_q ? f : acc[q];
-            }
+        for (int q = 0; q < 16; ++q) {
+            const int64_t cq = __builtin_amdgcn_readlane(cl, base + q);
+            x[q] = (A)load_row_d<BS>(S, cq * lds, off);
         }
     };
-
-    A w[16];
-    if (I != J) {
-        rows16(j0, i0, w);   // W_JI rows j, columns i
+    auto accum = [&](int m, int base, A v, const A (&x)[16], A (&acc)[16]) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) wt[wave * 16 + q][lane] = (E)w[q];
+        for (int q = 0; q < 16; ++q) {
+            const A f = fma(bcast(v, base + q), x[q], acc[q]);
+            const int cnt_q = __builtin_amdgcn_readlane(my_cnt, base + q);
+            acc[q] = m < cnt_q ? f : acc[q];
+        }
+    };
+    if (PAIR) {
+        const int steps = maxI > maxJ ? maxI : maxJ;
+        for (int m = 0; m < steps; ++m) {
+            int cl;
+            A v;
+            fetch(m, cl, v);
+            A x[16], xj[16];
+            issue(cl, 0, cj, x);
+            issue(cl, 16, ci, xj);
+            __builtin_amdgcn_sched_barrier(0);   // keep the 32 loads ahead of their uses
+            accum(m, 0, v, x, w);
+            accum(m, 16, v, xj, wj);
+        }
+    } else {
+        for (int m = 0; m < maxJ; ++m) {
+            int cl;
+            A v;
+            fetch(m, cl, v);
+            A x[16];
+            issue(cl, 16, ci, x);
+            __builtin_amdgcn_sched_barrier(0);   // keep the 16 loads ahead of their uses
+            accum(m, 16, v, x, wj);
+        }
+        for (int m = 0; m < maxI; ++m) {
+            int cl;
+            A v;
+            fetch(m, cl, v);
+            A x[16];
+            issue(cl, 0, cj, x);
+            __builtin_amdgcn_sched_barrier(0);
+            accum(m, 0, v, x, w);
+        }
     }
-    rows16(i0, j0, w);       // W_IJ rows i, columns j
-    if (I == J) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) wt[wave * 16 + q][lane] = (E)w[q];
-    }
+    for (int q = 0; q < 16; ++q) wt[wave * 16 + q][lane] = (E)wj[q];   // W_JI (W_II if I == J)
     __syncthreads();
     E mrow[16];
 #pragma unroll
@@ -744,21 +913,18 @@ cov_refresh_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict
         mrow[q] = (E)0.5 * ((E)w[q] + wt[lane][r]);
     }
     __syncthreads();
-    E* M = (E*)Mout;
-    // threshold bits of the next candidate set (optional): word J of row i holds
-    // j == i or |M_ij| > lam1 for the 64 columns of tile J, the same test (in FP64 on
-    // the stored value) as the full candidate pass
+    // threshold words of the next candidate set: word J of row i holds j == i or
+    // |M_ij| > lam1 (in FP64 on M's value) for the 64 columns of tile J.  M itself is
+    // not stored: the gradient is needed only on the candidates, where m_entry
+    // recomputes it bitwise.
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int r = wave * 16 + q;
         const int64_t gi = i0 + r, gj = j0 + lane;
-        if (gi < p && gj < p) M[gi * ldm + gj] = mrow[q];
         wt[r][lane] = mrow[q];
-        if (tbits) {
-            const bool b = gj < p && (gj == gi || fabs((double)mrow[q]) > lam1);
-            const uint64_t word = __ballot(b);
-            if (lane == 0 && gi < p) tbits[gi * nwords + J] = word;
-        }
+        const bool b = gj < p && (gj == gi || fabs((double)mrow[q]) > lam1);
+        const uint64_t word = __ballot(b);
+        if (lane == 0 && gi < p) tbits[gi * nwords + J] = word;
     }
     if (I == J) return;
     __syncthreads();
@@ -768,12 +934,9 @@ cov_refresh_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict
         const int r = wave * 16 + q;
         const int64_t gi = j0 + r, gj = i0 + lane;
         const E v = wt[lane][r];
-        if (gi < p && gj < p) M[gi * ldm + gj] = v;
-        if (tbits) {
-            const bool b = gj < p && (gj == gi || fabs((double)v) > lam1);
-            const uint64_t word = __ballot(b);
-            if (lane == 0 && gi < p) tbits[gi * nwords + I] = word;
-        }
+        const bool b = gj < p && (gj == gi || fabs((double)v) > lam1);
+        const uint64_t word = __ballot(b);
+        if (lane == 0 && gi < p) tbits[gi * nwords + I] = word;
     }
 }
 
@@ -833,20 +996,35 @@ transpose_in_kernel(const In* __restrict__ X, int64_t rows, int64_t cols, int64_
     }
 }
 
+// (S + S^T) / 2 into `store` layout, one 64 x 64 tile per block: tile (bj, bi) is staged
+// transposed in LDS so both reads are row-wise.  out_ij and out_ji are the same FP64
+// expression 0.5 s_ij + 0.5 s_ji (the halvings are exact, the sum commutes) rounded
+// once to the store type, so the stored matrix is exactly symmetric; an S that already
+// is symmetric is copied unchanged.
 template <typename In>
-__global__ void copy_square_kernel(const In* __restrict__ S, int64_t p, int64_t ld, void* out,
-                                   int store, int64_t ldo) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= p * p) return;
-    const int64_t i = idx / p, j = idx % p;
-    const double v = (double)S[i * ld + j];
-    if (store == ST_F64) ((double*)out)[i * ldo + j] = v;
-    else if (store == ST_F32) ((float*)out)[i * ldo + j] = (float)v;
-    else {
-        const float x = (float)v;
-        const uint16_t h = f2bf_rne(x);
-        const uint16_t l = f2bf_rne(x - bf2f(h));
-        ((uint32_t*)out)[i * ldo + j] = (uint32_t)h | ((uint32_t)l << 16);
+__global__ void __launch_bounds__(NT)
+sym_copy_kernel(const In* __restrict__ S, int64_t p, int64_t ld, void* out, int store,
+                int64_t ldo) {
+    __shared__ double t[64][65];
+    const int64_t bi = (int64_t)blockIdx.y * 64, bj = (int64_t)blockIdx.x * 64;
+    const int c = threadIdx.x & 63;
+    for (int r = threadIdx.x >> 6; r < 64; r += NT / 64) {
+        const int64_t gi = bj + r, gj = bi + c;
+        t[c][r] = gi < p && gj < p ? (double)S[gi * ld + gj] : 0.0;   // S[bj + r][bi + c]
+    }
+    __syncthreads();
+    for (int r = threadIdx.x >> 6; r < 64; r += NT / 64) {
+        const int64_t gi = bi + r, gj = bj + c;
+        if (gi >= p || gj >= p) continue;
+        const double v = __dadd_rn(__dmul_rn(0.5, (double)S[gi * ld + gj]), __dmul_rn(0.5, t[r][c]));
+        if (store == ST_F64) ((double*)out)[gi * ldo + gj] = v;
+        else if (store == ST_F32) ((float*)out)[gi * ldo + gj] = (float)v;
+        else {
+            const float x = (float)v;
+            const uint16_t h = f2bf_rne(x);
+            const uint16_t l = f2bf_rne(x - bf2f(h));
+            ((uint32_t*)out)[gi * ldo + gj] = (uint32_t)h | ((uint32_t)l << 16);
+        }
     }
 }
 
@@ -1187,6 +1365,40 @@ hipError_t launch_obj_parts(const Csr& om, int64_t p, const void* W, int wstore,
     return hipGetLastError();
 }
 
+hipError_t launch_obj_parts_cov(const Csr& om, int64_t p, const void* S, int sstore, int64_t lds,
+                                double* part, const int* gate, hipStream_t stream) {
+    if (p == 0) return hipSuccess;
+    dim3 grid(blocks_for(p, WPB));
+    if (sstore == ST_F64)
+        hipLaunchKernelGGL(obj_parts_cov_kernel<ST_F64>, grid, dim3(NT), 0, stream, om.rowptr,
+                           om.col, om.val, p, S, lds, part, gate);
+    else if (sstore == ST_F32)
+        hipLaunchKernelGGL(obj_parts_cov_kernel<ST_F32>, grid, dim3(NT), 0, stream, om.rowptr,
+                           om.col, om.val, p, S, lds, part, gate);
+    else if (sstore == ST_B16P)
+        hipLaunchKernelGGL(obj_parts_cov_kernel<ST_B16P>, grid, dim3(NT), 0, stream, om.rowptr,
+                           om.col, om.val, p, S, lds, part, gate);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_cand_grad_cov(const Csr& om, int64_t p, const void* S, int sstore, int64_t lds,
+                                double lam2, const Cand& A, const int* overflow,
+                                hipStream_t stream) {
+    if (p == 0) return hipSuccess;
+    dim3 grid(blocks_for(p, WPB));
+#define CGRAD(BS)                                                                         \
+    hipLaunchKernelGGL(cand_grad_cov_kernel<BS>, grid, dim3(NT), 0, stream, om.rowptr, om.col, \
+                       om.val, p, S, lds, lam2, A.rowptr, A.col, A.omega, A.grad, overflow)
+    if (sstore == ST_F64) CGRAD(ST_F64);
+    else if (sstore == ST_F32) CGRAD(ST_F32);
+    else if (sstore == ST_B16P) CGRAD(ST_B16P);
+    else return hipErrorInvalidValue;
+#undef CGRAD
+    return hipGetLastError();
+}
+
 hipError_t launch_identity(const Csr& om, int64_t p, hipStream_t stream) {
     hipLaunchKernelGGL(identity_kernel, dim3(blocks_for(p + 1, NT)), dim3(NT), 0, stream,
                        om.rowptr, om.col, om.val, p);
@@ -1194,25 +1406,19 @@ hipError_t launch_identity(const Csr& om, int64_t p, hipStream_t stream) {
 }
 
 hipError_t launch_cov_refresh(const Csr& A, int64_t p, const void* S, int sstore, int64_t lds,
-                              void* M, int mstore, int64_t ldm, double lam1, uint64_t* tbits,
-                              int64_t nwords, const int* gate, hipStream_t stream) {
-    if (tbits && nwords != (p + 63) / 64) return hipErrorInvalidValue;
+                              double lam1, uint64_t* tbits, int64_t nwords, const int* gate,
+                              hipStream_t stream) {
+    if (!tbits || nwords != (p + 63) / 64 || lds < nwords * 64) return hipErrorInvalidValue;
     const int T = (int)((p + 63) / 64);
     const int nt = T * (T + 1) / 2;
     if (nt == 0) return hipSuccess;
-#define REFRESH(BS, CS)                                                                   \
-    hipLaunchKernelGGL((cov_refresh_kernel<BS, CS>), dim3(nt), dim3(NT), 0, stream, A.rowptr, \
-                       A.col, A.val, p, S, lds, M, ldm, T, lam1, tbits, nwords, gate)
-    if (sstore == ST_F64) {
-        if (mstore != ST_F64) return hipErrorInvalidValue;
-        REFRESH(ST_F64, ST_F64);
-    } else if (mstore != ST_F32) {
-        return hipErrorInvalidValue;
-    } else if (sstore == ST_F32) {
-        REFRESH(ST_F32, ST_F32);
-    } else {
-        REFRESH(ST_B16P, ST_F32);
-    }
+#define REFRESH(BS)                                                                     \
+    hipLaunchKernelGGL((cov_refresh_kernel<BS>), dim3(nt), dim3(NT), 0, stream, A.rowptr, \
+                       A.col, A.val, p, S, lds, T, lam1, tbits, nwords, gate)
+    if (sstore == ST_F64) REFRESH(ST_F64);
+    else if (sstore == ST_F32) REFRESH(ST_F32);
+    else if (sstore == ST_B16P) REFRESH(ST_B16P);
+    else return hipErrorInvalidValue;
 #undef REFRESH
     return hipGetLastError();
 }
@@ -1239,14 +1445,16 @@ hipError_t launch_transpose_in(const void* X, int x_is_f64, int64_t rows, int64_
     return hipGetLastError();
 }
 
-hipError_t launch_copy_square(const void* S, int s_is_f64, int64_t p, int64_t ld, void* out,
-                              int store, int64_t ldo, hipStream_t stream) {
-    const unsigned nb = blocks_for(p * p, NT);
+hipError_t launch_sym_copy(const void* S, int s_is_f64, int64_t p, int64_t ld, void* out,
+                           int store, int64_t ldo, hipStream_t stream) {
+    if (p == 0) return hipSuccess;
+    const unsigned T = (unsigned)((p + 63) / 64);
+    if (T > 65535u) return hipErrorInvalidValue;
     if (s_is_f64)
-        hipLaunchKernelGGL(copy_square_kernel<double>, dim3(nb), dim3(NT), 0, stream,
+        hipLaunchKernelGGL(sym_copy_kernel<double>, dim3(T, T), dim3(NT), 0, stream,
                            (const double*)S, p, ld, out, store, ldo);
     else
-        hipLaunchKernelGGL(copy_square_kernel<float>, dim3(nb), dim3(NT), 0, stream,
+        hipLaunchKernelGGL(sym_copy_kernel<float>, dim3(T, T), dim3(NT), 0, stream,
                            (const float*)S, p, ld, out, store, ldo);
     return hipGetLastError();
 }

@@ -85,3 +85,46 @@ def test_refresh_order_is_a_bijection_onto_upper_pairs(T):
     n = T * (T + 1) // 2
     got = sorted(refresh_order(w, T, n) for w in range(n))
     assert got == sorted((i, j) for i in range(T) for j in range(i, T))
+
+
+def refresh_order_closed(w, T, ntiles):
+    """The refresh's closed-form mapping (square roots instead of the band walk)."""
+    import math
+    t = w
+    if w < ntiles // 64 * 64:
+        a, b, x = w >> 6, (w >> 3) & 7, w & 7
+        t = 64 * a + 8 * x + b
+    G = 8
+    nfull, c1 = T // G, G * (G + 1) // 2 + G * (T - G)
+
+    def P(b):
+        return b * c1 - G * G * b * (b - 1) // 2
+    q = c1 + 0.5 * G * G
+    disc = q * q - 2.0 * G * G * t
+    b = int((q - math.sqrt(max(disc, 0.0))) / (G * G))
+    b = max(0, min(nfull, b))
+    while b > 0 and P(b) > t:
+        b -= 1
+    while b < nfull and P(b + 1) <= t:
+        b += 1
+    t -= P(b)
+    i0 = b * G
+    h = min(G, T - i0)
+    tri = h * (h + 1) // 2
+    if t < tri:
+        jj = int((math.sqrt(8.0 * t + 1.0) - 1.0) * 0.5)
+        while jj > 0 and jj * (jj + 1) // 2 > t:
+            jj -= 1
+        while (jj + 1) * (jj + 2) // 2 <= t:
+            jj += 1
+        return i0 + t - jj * (jj + 1) // 2, i0 + jj
+    t -= tri
+    return i0 + t % h, i0 + h + t // h
+
+
+@pytest.mark.parametrize("T", [1, 2, 7, 8, 9, 15, 16, 17, 33, 64, 65, 79, 100, 257, 1427])
+def test_refresh_closed_form_equals_band_walk(T):
+    n = T * (T + 1) // 2
+    step = max(1, n // 20000)
+    for w in list(range(0, n, step)) + [n - 1]:
+        assert refresh_order_closed(w, T, n) == refresh_order(w, T, n), (T, w)
