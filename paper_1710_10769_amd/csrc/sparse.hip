@@ -906,37 +906,38 @@ cov_refresh_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict
 #pragma unroll
     for (int q = 0; q < 16; ++q) wt[wave * 16 + q][lane] = (E)wj[q];   // W_JI (W_II if I == J)
     __syncthreads();
-    E mrow[16];
+    // Threshold words of the next candidate set: word J of row i holds j == i or
+    // |M_ij| > lam1 for the 64 columns of tile J, and by symmetry word I of row j the
+    // same tests with i and j exchanged.  M itself is not stored: the gradient is needed
+    // only on the candidates, where m_entry recomputes it bitwise.  The test is FP64's
+    // |M_ij| > lam1 taken in M's type: for FP32, |m| > lam1 holds exactly when
+    // |m| > lam1 rounded down to FP32.
+    E thr = (E)lam1;
+    if (sizeof(E) == 4 && (double)thr > lam1) thr = __int_as_float(__float_as_int((float)thr) - 1);
+    const int64_t gj = j0 + lane;
+    uint64_t wdir = 0;   // lane q < 16: the direct word of row i0 + 16 * wave + q
+    uint32_t cm = 0;     // bit q: the test at (row i0 + 16 * wave + q, column gj)
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int r = wave * 16 + q;
-        mrow[q] = (E)0.5 * ((E)w[q] + wt[lane][r]);
-    }
-    __syncthreads();
-    // threshold words of the next candidate set: word J of row i holds j == i or
-    // |M_ij| > lam1 (in FP64 on M's value) for the 64 columns of tile J.  M itself is
-    // not stored: the gradient is needed only on the candidates, where m_entry
-    // recomputes it bitwise.
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int r = wave * 16 + q;
-        const int64_t gi = i0 + r, gj = j0 + lane;
-        wt[r][lane] = mrow[q];
-        const bool b = gj < p && (gj == gi || fabs((double)mrow[q]) > lam1);
+        const int64_t gi = i0 + r;
+        const E m = (E)0.5 * ((E)w[q] + wt[lane][r]);
+        const bool b = gi < p && gj < p && (gj == gi || (m < (E)0 ? -m : m) > thr);
+        cm |= (uint32_t)b << q;
         const uint64_t word = __ballot(b);
-        if (lane == 0 && gi < p) tbits[gi * nwords + J] = word;
+        wdir = lane == q ? word : wdir;
     }
+    const int64_t mine = i0 + wave * 16 + lane;
+    if (lane < 16 && mine < p) tbits[mine * nwords + J] = wdir;
     if (I == J) return;
+    // mirrored words: row gj, bits over the 64 rows of tile I (16 from each wave)
+    __shared__ uint32_t cms[4][64];
+    cms[wave][lane] = cm;
     __syncthreads();
-    // mirrored tile: M_JI[r][c] = M_IJ[c][r]
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int r = wave * 16 + q;
-        const int64_t gi = j0 + r, gj = i0 + lane;
-        const E v = wt[lane][r];
-        const bool b = gj < p && (gj == gi || fabs((double)v) > lam1);
-        const uint64_t word = __ballot(b);
-        if (lane == 0 && gi < p) tbits[gi * nwords + I] = word;
+    if (wave == 0 && gj < p) {
+        const uint64_t word = (uint64_t)cms[0][lane] | ((uint64_t)cms[1][lane] << 16) |
+                              ((uint64_t)cms[2][lane] << 32) | ((uint64_t)cms[3][lane] << 48);
+        tbits[gj * nwords + I] = word;
     }
 }
 
