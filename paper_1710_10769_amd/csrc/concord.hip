@@ -84,6 +84,7 @@ struct concord_ctx {
     uint16_t* Y_hi = nullptr;
     uint16_t* Y_lo = nullptr;
     void* S = nullptr;
+    double* smax = nullptr;   // Cov: largest |S| of each 64 x 64 tile (T x T)
     void* M = nullptr;
     void* dxt = nullptr;   // differentiation form: Omega Y before its transpose
 
@@ -319,7 +320,7 @@ int products_at(concord_ctx* c, int which, const int* gate, double bits_lam1 = -
         HIPCK(c, launch_colsum(c->part, p, 4 + nch, c->objsums, c->colsum_ws, c->stream));
     } else {
         if (bits_lam1 >= 0.0)
-            HIPCK(c, launch_cov_refresh(O, p, c->S, c->sstore, c->ldp, bits_lam1, c->bitmap,
+            HIPCK(c, launch_cov_refresh(O, p, c->S, c->sstore, c->ldp, c->smax, bits_lam1, c->bitmap,
                                         c->nwords, gate, c->stream));
         HIPCK(c, launch_obj_parts_cov(O, p, c->S, c->sstore, c->ldp, c->part, gate, c->stream));
         HIPCK(c, launch_colsum(c->part, p, 4, c->objsums, c->colsum_ws, c->stream));
@@ -425,7 +426,7 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
         prof_begin(c, CONCORD_PROF_CAND);
         const bool cov = c->variant == CONCORD_COV;
         if (cov && !merge)
-            HIPCK(c, launch_cov_refresh(c->om[c->cur], p, c->S, c->sstore, c->ldp, lam1,
+            HIPCK(c, launch_cov_refresh(c->om[c->cur], p, c->S, c->sstore, c->ldp, c->smax, lam1,
                                         c->bitmap, c->nwords, c->d_one, c->stream));
         if (merge || cov)
             HIPCK(c, launch_cand_merge(c->om[c->cur], p, c->bitmap, c->nwords, c->cnt, c->stream));
@@ -725,6 +726,8 @@ int concord_create(const concord_config* cfg, concord_ctx** out) {
     } else {
         if ((rc = dalloc(c, &c->S, (size_t)p * c->ldp * (c->sstore == ST_F64 ? 8 : 4), true)))
             return bail(rc);
+        const int64_t T = (p + 63) / 64;
+        if ((rc = dalloc_t(c, &c->smax, (size_t)(T * T), true))) return bail(rc);
     }
     for (int w = 0; w < 2; ++w)
         if ((rc = dalloc_t(c, &c->om[w].rowptr, p + 1, true))) return bail(rc);
@@ -795,6 +798,8 @@ int concord_set_data(concord_ctx* c, int32_t kind, const void* dev_data, int32_t
     } else {
         HIPCK(c, launch_sym_copy(dev_data, is64, c->p, ld, c->S, c->sstore, c->ldp, c->stream));
     }
+    if (c->variant == CONCORD_COV)
+        HIPCK(c, launch_tile_max(c->S, c->sstore, c->p, c->ldp, c->smax, c->stream));
     c->has_data = true;
     int rc = set_identity(c);
     if (rc) return rc;

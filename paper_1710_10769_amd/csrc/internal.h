@@ -190,10 +190,15 @@ hipError_t launch_identity(const Csr& om, int64_t p, hipStream_t stream);
 // lds >= 64 * nwords, `sstore`; M in FP64 for an FP64 S, FP32 otherwise) tile pair by
 // tile pair over the upper triangle and writes the threshold words
 // {j : j == i or |M_ij| > lam1} of every row into tbits (p x nwords, nwords =
-// ceil(p/64); see launch_cand_merge).  M is not stored.  Gated like launch_spmm.
+// ceil(p/64); see launch_cand_merge).  M is not stored.  smax (T x T, T = nwords) holds
+// the largest |S| of each 64 x 64 tile (launch_tile_max); pairs whose bound on |M|
+// stays at or below lam1 skip their S loads.  Gated like launch_spmm.
 hipError_t launch_cov_refresh(const Csr& A, int64_t p, const void* S, int sstore, int64_t lds,
-                              double lam1, uint64_t* tbits, int64_t nwords, const int* gate,
-                              hipStream_t stream);
+                              const double* smax, double lam1, uint64_t* tbits, int64_t nwords,
+                              const int* gate, hipStream_t stream);
+// smax[I * T + J] = max |S| over tile (I, J), T = ceil(p / 64), as the refresh reads S.
+hipError_t launch_tile_max(const void* S, int sstore, int64_t p, int64_t lds, double* out,
+                           hipStream_t stream);
 
 // Differentiation form.
 hipError_t launch_sddmm_grad(const Csr& om, int64_t p, const void* Yt, const void* Xt,

@@ -795,8 +795,8 @@ template <int BS>
 __global__ void __launch_bounds__(NT)
 cov_refresh_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                    const double* __restrict__ val, int64_t p, const void* __restrict__ S,
-                   int64_t lds, int T, double lam1, uint64_t* __restrict__ tbits, int64_t nwords,
-                   const int* gate) {
+                   int64_t lds, const double* __restrict__ smax, int T, double lam1,
+                   uint64_t* __restrict__ tbits, int64_t nwords, const int* gate) {
     if (gate && *gate == 0) return;
     typedef typename Chunk<BS>::T A;                          // accumulation type
     typedef typename MType<BS>::T E;                          // type of M
@@ -826,13 +826,55 @@ cov_refresh_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict
         my_s0 = rowptr[myrow];
         my_cnt = (int)(rowptr[myrow + 1] - my_s0);
     }
+    // Exact screening of the pair: |W_ij| <= bw(i) = sum_{k in supp_i} |omega_ik| smax[k/64][J]
+    // with smax the largest |S| of each 64 x 64 tile, and likewise bv(j) for W_JI, so
+    // |M_ij| <= (max_i bw(i) + max_j bv(j)) / 2.  If that bound (widened by the FMA
+    // chains' rounding) is at most the threshold, no test in the pair passes and the
+    // S loads are skipped.  Diagonal pairs (which hold the j == i bits) always run.
+    double rbound = 0.0;
+    if (I != J) {
+        const int64_t other = hl < 16 ? J : I;
+        for (int m = 0; m < my_cnt; ++m)
+            rbound += fabs(val[my_s0 + m]) * smax[(int64_t)(col[my_s0 + m] >> 6) * T + other];
+    }
     int mx = my_cnt;
 #pragma unroll
     for (int o = 8; o >= 1; o >>= 1) {
         const int other = __shfl_xor(mx, o, 64);
         mx = other > mx ? other : mx;
+        const double ob = __shfl_xor(rbound, o, 64);
+        rbound = ob > rbound ? ob : rbound;
     }
     const int maxI = __builtin_amdgcn_readlane(mx, 0), maxJ = __builtin_amdgcn_readlane(mx, 16);
+    E thr = (E)lam1;
+    if (sizeof(E) == 4 && (double)thr > lam1) thr = __int_as_float(__float_as_int((float)thr) - 1);
+    const int64_t gj = j0 + lane;
+    __shared__ uint32_t cms[4][64];
+    if (I != J) {
+        __shared__ double bnd[4][2];
+        if (lane == 0) bnd[wave][0] = rbound;
+        if (lane == 16) bnd[wave][1] = rbound;
+        int cmax = maxI > maxJ ? maxI : maxJ;
+        if (lane == 0) cms[wave][0] = (uint32_t)cmax;
+        __syncthreads();
+        double bw = 0.0, bvv = 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            bw = bnd[v][0] > bw ? bnd[v][0] : bw;
+            bvv = bnd[v][1] > bvv ? bnd[v][1] : bvv;
+            cmax = (int)cms[v][0] > cmax ? (int)cms[v][0] : cmax;
+        }
+        // relative rounding of an FP32 chain of c FMAs (and of omega's conversion) is
+        // below (c + 2) 2^-24; 1% on top
+        const double widen = 1.01 + (double)(cmax + 2) * 0x1p-23;
+        if (0.5 * (bw + bvv) * widen <= (double)thr) {
+            const int64_t mine = i0 + wave * 16 + lane;
+            if (lane < 16 && mine < p) tbits[mine * nwords + J] = 0ull;
+            if (wave == 0 && gj < p) tbits[gj * nwords + I] = 0ull;
+            return;
+        }
+        __syncthreads();   // cms is reused below
+    }
     const uint32_t ci = (uint32_t)(i0 + lane), cj = (uint32_t)(j0 + lane);
     A w[16], wj[16];
 #pragma unroll
@@ -912,9 +954,6 @@ cov_refresh_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict
     // only on the candidates, where m_entry recomputes it bitwise.  The test is FP64's
     // |M_ij| > lam1 taken in M's type: for FP32, |m| > lam1 holds exactly when
     // |m| > lam1 rounded down to FP32.
-    E thr = (E)lam1;
-    if (sizeof(E) == 4 && (double)thr > lam1) thr = __int_as_float(__float_as_int((float)thr) - 1);
-    const int64_t gj = j0 + lane;
     uint64_t wdir = 0;   // lane q < 16: the direct word of row i0 + 16 * wave + q
     uint32_t cm = 0;     // bit q: the test at (row i0 + 16 * wave + q, column gj)
 #pragma unroll
@@ -931,13 +970,41 @@ cov_refresh_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict
     if (lane < 16 && mine < p) tbits[mine * nwords + J] = wdir;
     if (I == J) return;
     // mirrored words: row gj, bits over the 64 rows of tile I (16 from each wave)
-    __shared__ uint32_t cms[4][64];
     cms[wave][lane] = cm;
     __syncthreads();
     if (wave == 0 && gj < p) {
         const uint64_t word = (uint64_t)cms[0][lane] | ((uint64_t)cms[1][lane] << 16) |
                               ((uint64_t)cms[2][lane] << 32) | ((uint64_t)cms[3][lane] << 48);
         tbits[gj * nwords + I] = word;
+    }
+}
+
+// Largest |S| of every 64 x 64 tile (as the refresh reads S), for its screening.
+template <int BS>
+__global__ void __launch_bounds__(NT)
+tile_max_kernel(const void* __restrict__ S, int64_t p, int64_t lds, int T, double* __restrict__ out) {
+    __shared__ double red[WPB];
+    const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    double m = 0.0;
+    for (int r = wave; r < 64; r += WPB) {
+        const int64_t gi = i0 + r, gj = j0 + lane;
+        if (gi < p && gj < p) {
+            const double x = fabs(load_one_d<BS>(S, gi * lds + gj));
+            m = x > m ? x : m;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const double x = __shfl_xor(m, o, 64);
+        m = x > m ? x : m;
+    }
+    if (lane == 0) red[wave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = red[0];
+        for (int v = 1; v < WPB; ++v) t = red[v] > t ? red[v] : t;
+        out[(int64_t)blockIdx.y * T + blockIdx.x] = t;
     }
 }
 
@@ -1407,20 +1474,37 @@ hipError_t launch_identity(const Csr& om, int64_t p, hipStream_t stream) {
 }
 
 hipError_t launch_cov_refresh(const Csr& A, int64_t p, const void* S, int sstore, int64_t lds,
-                              double lam1, uint64_t* tbits, int64_t nwords, const int* gate,
-                              hipStream_t stream) {
-    if (!tbits || nwords != (p + 63) / 64 || lds < nwords * 64) return hipErrorInvalidValue;
+                              const double* smax, double lam1, uint64_t* tbits, int64_t nwords,
+                              const int* gate, hipStream_t stream) {
+    if (!tbits || !smax || nwords != (p + 63) / 64 || lds < nwords * 64) return hipErrorInvalidValue;
     const int T = (int)((p + 63) / 64);
     const int nt = T * (T + 1) / 2;
     if (nt == 0) return hipSuccess;
 #define REFRESH(BS)                                                                     \
     hipLaunchKernelGGL((cov_refresh_kernel<BS>), dim3(nt), dim3(NT), 0, stream, A.rowptr, \
-                       A.col, A.val, p, S, lds, T, lam1, tbits, nwords, gate)
+                       A.col, A.val, p, S, lds, smax, T, lam1, tbits, nwords, gate)
     if (sstore == ST_F64) REFRESH(ST_F64);
     else if (sstore == ST_F32) REFRESH(ST_F32);
     else if (sstore == ST_B16P) REFRESH(ST_B16P);
     else return hipErrorInvalidValue;
 #undef REFRESH
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_max(const void* S, int sstore, int64_t p, int64_t lds, double* out,
+                           hipStream_t stream) {
+    if (p == 0) return hipSuccess;
+    const unsigned T = (unsigned)((p + 63) / 64);
+    if (T > 65535u) return hipErrorInvalidValue;
+    dim3 grid(T, T);
+    if (sstore == ST_F64)
+        hipLaunchKernelGGL(tile_max_kernel<ST_F64>, grid, dim3(NT), 0, stream, S, p, lds, (int)T, out);
+    else if (sstore == ST_F32)
+        hipLaunchKernelGGL(tile_max_kernel<ST_F32>, grid, dim3(NT), 0, stream, S, p, lds, (int)T, out);
+    else if (sstore == ST_B16P)
+        hipLaunchKernelGGL(tile_max_kernel<ST_B16P>, grid, dim3(NT), 0, stream, S, p, lds, (int)T, out);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
