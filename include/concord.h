@@ -187,6 +187,20 @@ int concord_step_replay(concord_ctx* ctx, double lambda1, double lambda2, int32_
 int concord_solve(concord_ctx* ctx, double lambda1, double lambda2, double tol, int64_t max_iter,
                   concord_solve_info* info);
 
+/* Screening statistics of the Cov refresh (this library's exact screening; not part
+   of the paper's method, which forms every entry of W = Omega S).  The refresh bounds
+   |M_ij| over each pair of 64 x 64 tiles (I, J), I <= J, by
+     ( max_i sum_k |omega_ik| smax(k/64, J) + max_j sum_k |omega_jk| smax(k/64, I) ) / 2
+   with smax(K, L) the largest |S| of tile (K, L), and skips the pair's S loads when
+   the bound (widened by the FMA chains' rounding and 1%) is at most lambda1; the
+   skipped pairs' candidate words are provably empty, so results are unchanged.
+   This call runs the refresh once at the current iterate for lambda1 and writes the
+   number of tile pairs, T (T + 1) / 2 with T = ceil(p / 64), and the number that
+   loaded S (diagonal pairs always do).  Host pointers; either may be NULL.
+   Errors: EINVAL (null handle, Obs handle, lambda1 < 0), ENODATA, ENOMEM, EHIP. */
+int concord_refresh_screen_stats(concord_ctx* ctx, double lambda1, int64_t* host_pairs,
+                                 int64_t* host_active);
+
 /* f and F at the current iterate, FP64 (host pointers; either may be NULL).
    Errors: EINVAL, ENODATA, EHIP. */
 int concord_objective(concord_ctx* ctx, double lambda1, double lambda2, double* host_f,

@@ -101,6 +101,7 @@ _SIGS = {
     "concord_set_profiling": (_I32, [_P, _I32]),
     "concord_get_profile": (_I32, [_P, ctypes.c_void_p]),
     "concord_contraction_variant": (_I32, [_P, ctypes.c_char_p, _I32]),
+    "concord_refresh_screen_stats": (_I32, [_P, _D, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
     "concord_last_error": (ctypes.c_char_p, [_P]),
     "concord_destroy": (None, [_P]),
     "concord_version": (ctypes.c_char_p, []),
@@ -263,6 +264,13 @@ def concord_contraction_variant(h) -> Tuple[int, str]:
     return v, buf.value.decode()
 
 
+def concord_refresh_screen_stats(h, lam1: float) -> Tuple[int, int]:
+    """(tile pairs, pairs that loaded S) of one Cov refresh at the current iterate."""
+    pairs, active = _I64(0), _I64(0)
+    _check(load().concord_refresh_screen_stats(h, lam1, ctypes.byref(pairs), ctypes.byref(active)), h)
+    return int(pairs.value), int(active.value)
+
+
 def concord_iterations(h) -> int:
     return load().concord_iterations(h)
 
@@ -381,6 +389,11 @@ class Solver:
     def contraction_variant(self) -> Tuple[int, str]:
         """(index, name) of the dense-contraction tile variant in use (-1 if untuned)."""
         return concord_contraction_variant(self._h)
+
+    def refresh_screen_stats(self, lam1: float) -> Tuple[int, int]:
+        """(tile pairs, pairs that loaded S) of the Cov refresh at the current iterate
+        for lam1: the exact screening skips the others."""
+        return concord_refresh_screen_stats(self._h, lam1)
 
     @property
     def iterations(self) -> int:

@@ -51,6 +51,10 @@ __global__ void obj_finish_kernel(const double* sums, int nysq, DevState* st, co
     st->obj[4] = y;
 }
 
+__global__ void set_u64_kernel(unsigned long long* p, unsigned long long v) {
+    if (threadIdx.x == 0) *p = v;
+}
+
 __global__ void set_int_kernel(int* p, int v) {
     if (threadIdx.x == 0) *p = v;
 }
@@ -85,6 +89,7 @@ struct concord_ctx {
     uint16_t* Y_lo = nullptr;
     void* S = nullptr;
     double* smax = nullptr;   // Cov: largest |S| of each 64 x 64 tile (T x T)
+    unsigned long long* d_active = nullptr;   // screening statistics counter
     void* M = nullptr;
     void* dxt = nullptr;   // differentiation form: Omega Y before its transpose
 
@@ -105,6 +110,7 @@ struct concord_ctx {
     double* sums = nullptr;      // 64
     double* objsums = nullptr;   // 64 + chunks
     double* colsum_ws = nullptr; // (max columns) * COLSUM_MAXSEG segment sums
+    int64_t* scan_ws = nullptr;  // chunk sums of launch_scan
     DevState* st = nullptr;
     DevState* st_host = nullptr; // pinned
     int64_t* h_stage = nullptr;  // pinned, 4 int64
@@ -433,7 +439,8 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
         else
             HIPCK(c, launch_cand_count(c->M, c->dstore, c->ldp, c->om[c->cur], p, lam1,
                                        c->bitmap, c->nwords, c->cnt, c->stream));
-        HIPCK(c, launch_scan(c->cnt, p, c->A.rowptr, c->a_cap, &c->st->overflow, c->stream));
+        HIPCK(c, launch_scan(c->cnt, p, c->A.rowptr, c->a_cap, &c->st->overflow, c->scan_ws,
+                             c->stream));
         HIPCK(c, launch_cand_fill(cov ? nullptr : c->M, c->dstore, c->ldp, c->om[c->cur], p, lam2,
                                   c->bitmap, c->nwords, c->A, c->a_cap, &c->st->overflow,
                                   c->stream));
@@ -457,7 +464,8 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
         prof_end(c);
         prof_begin(c, CONCORD_PROF_EMIT);
         HIPCK(c, launch_emit_count(c->A, p, lam1, c->st, c->cnt, c->stream));
-        HIPCK(c, launch_scan(c->cnt, p, c->om[nxt].rowptr, c->om_cap[nxt], nullptr, c->stream));
+        HIPCK(c, launch_scan(c->cnt, p, c->om[nxt].rowptr, c->om_cap[nxt], nullptr, c->scan_ws,
+                             c->stream));
         HIPCK(c, launch_emit_fill(c->A, p, lam1, c->st, c->om[nxt], c->stream));
         prof_end(c);
         int rc2 = products_at(c, nxt, &c->st->accepted,
@@ -741,6 +749,7 @@ int concord_create(const concord_config* cfg, concord_ctx** out) {
     if ((rc = dalloc_t(c, &c->part, c->part_elems, true))) return bail(rc);
     if ((rc = dalloc_t(c, &c->sums, 64, true))) return bail(rc);
     if ((rc = dalloc_t(c, &c->objsums, 64 + nch, true))) return bail(rc);
+    if ((rc = dalloc_t(c, &c->scan_ws, (size_t)scan_ws_len(p), true))) return bail(rc);
     if ((rc = dalloc_t(c, &c->colsum_ws, (size_t)std::max(4 * MAXQ, 4 + nch) * COLSUM_MAXSEG, true)))
         return bail(rc);
     if ((rc = dalloc_t(c, &c->st, 1, true))) return bail(rc);
@@ -894,6 +903,32 @@ int concord_solve(concord_ctx* c, double lam1, double lam2, double tol, int64_t 
         info->status = status;
     }
     return status;
+}
+
+int concord_refresh_screen_stats(concord_ctx* c, double lam1, int64_t* host_pairs,
+                                 int64_t* host_active) {
+    if (!c) return CONCORD_EINVAL;
+    if (c->variant != CONCORD_COV) return fail(c, CONCORD_EINVAL, "screening is a Cov refresh");
+    if (!(lam1 >= 0.0) || !std::isfinite(lam1)) return fail(c, CONCORD_EINVAL, "lambda1 must be >= 0");
+    if (!c->has_data) return fail(c, CONCORD_ENODATA, "no data: call concord_set_data first");
+    DeviceGuard g(c->device);
+    if (int rc0 = enter(c)) return rc0;
+    int rc = ensure_dense(c);
+    if (rc) return rc;
+    if (!c->d_active && (rc = dalloc_t(c, &c->d_active, 1, false))) return rc;
+    hipLaunchKernelGGL(set_u64_kernel, dim3(1), dim3(64), 0, c->stream, c->d_active, 0ull);
+    HIPCK(c, launch_cov_refresh(c->om[c->cur], c->p, c->S, c->sstore, c->ldp, c->smax, lam1,
+                                c->bitmap, c->nwords, c->d_one, c->stream, c->d_active));
+    unsigned long long act = 0;
+    HIPCK(c, hipMemcpyAsync(&act, c->d_active, sizeof(act), hipMemcpyDeviceToHost, c->stream));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    // the words now belong to (current iterate, lam1)
+    c->bits_valid = true;
+    c->bits_lam1 = lam1;
+    const int64_t T = (c->p + 63) / 64;
+    if (host_pairs) *host_pairs = T * (T + 1) / 2;
+    if (host_active) *host_active = (int64_t)act;
+    return CONCORD_OK;
 }
 
 int concord_objective(concord_ctx* c, double lam1, double lam2, double* host_f, double* host_F) {

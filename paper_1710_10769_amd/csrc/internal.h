@@ -138,9 +138,12 @@ hipError_t launch_cand_grad_cov(const Csr& om, int64_t p, const void* S, int sst
                                 hipStream_t stream);
 
 // Exclusive scan of cnt[0..p) into out[0..p] (out[p] = total); sets
-// *overflow = 1 if total > cap.  Single workgroup, deterministic.
+// *overflow = 1 if total > cap (overflow may be null).  Two launches (chunk sums into
+// ws, scan_ws_len(p) int64, then per-chunk scans); integer, so deterministic.
 hipError_t launch_scan(const int64_t* cnt, int64_t p, int64_t* out, int64_t cap, int* overflow,
-                       hipStream_t stream);
+                       int64_t* ws, hipStream_t stream);
+// int64 workspace length launch_scan needs for p rows.
+int64_t scan_ws_len(int64_t p);
 
 struct DevState;
 // Column splits of the Obs quadratic term in launch_trial (1 for Cov).
@@ -192,10 +195,12 @@ hipError_t launch_identity(const Csr& om, int64_t p, hipStream_t stream);
 // {j : j == i or |M_ij| > lam1} of every row into tbits (p x nwords, nwords =
 // ceil(p/64); see launch_cand_merge).  M is not stored.  smax (T x T, T = nwords) holds
 // the largest |S| of each 64 x 64 tile (launch_tile_max); pairs whose bound on |M|
-// stays at or below lam1 skip their S loads.  Gated like launch_spmm.
+// stays at or below lam1 skip their S loads.  Gated like launch_spmm.  If `active` is
+// non-null, every pair that loads S adds one to it (a diagnostic: one atomic per pair).
 hipError_t launch_cov_refresh(const Csr& A, int64_t p, const void* S, int sstore, int64_t lds,
                               const double* smax, double lam1, uint64_t* tbits, int64_t nwords,
-                              const int* gate, hipStream_t stream);
+                              const int* gate, hipStream_t stream,
+                              unsigned long long* active = nullptr);
 // smax[I * T + J] = max |S| over tile (I, J), T = ceil(p / 64), as the refresh reads S.
 hipError_t launch_tile_max(const void* S, int sstore, int64_t p, int64_t lds, double* out,
                            hipStream_t stream);

@@ -423,6 +423,83 @@ scan_kernel(const int64_t* __restrict__ cnt, int64_t p, int64_t* __restrict__ ou
     }
 }
 
+// Two-kernel exclusive scan: chunk sums, then each chunk adds the sums before it and
+// scans itself.  Integer sums, so the result does not depend on the split.
+constexpr int SCAN_CHUNK = 2048;   // 8 per thread
+
+__device__ inline int64_t block_sum_i64(int64_t v, int64_t* red) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int wave = threadIdx.x >> 6;
+    if (lane_id() == 0) red[wave] = v;
+    __syncthreads();
+    int64_t t = 0;
+#pragma unroll
+    for (int w = 0; w < WPB; ++w) t += red[w];
+    return t;
+}
+
+__global__ void __launch_bounds__(NT)
+scan_part_kernel(const int64_t* __restrict__ cnt, int64_t p, int64_t* __restrict__ part) {
+    __shared__ int64_t red[WPB];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
+    int64_t s = 0;
+#pragma unroll
+    for (int e = 0; e < SCAN_CHUNK / NT; ++e) {
+        const int64_t i = base + e * NT + threadIdx.x;
+        if (i < p) s += cnt[i];
+    }
+    s = block_sum_i64(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(NT)
+scan_apply_kernel(const int64_t* __restrict__ cnt, int64_t p, const int64_t* __restrict__ part,
+                  int64_t* __restrict__ out, int64_t cap, int* overflow) {
+    __shared__ int64_t red[WPB];
+    __shared__ int64_t wtot[WPB];
+    const int64_t b = blockIdx.x;
+    int64_t o = 0;
+    for (int64_t k = threadIdx.x; k < b; k += NT) o += part[k];
+    const int64_t off = block_sum_i64(o, red);
+    constexpr int PER = SCAN_CHUNK / NT;
+    const int64_t i0 = b * SCAN_CHUNK + (int64_t)threadIdx.x * PER;
+    int64_t v[PER];
+    int64_t ts = 0;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        v[e] = i0 + e < p ? cnt[i0 + e] : 0;
+        ts += v[e];
+    }
+    // exclusive scan of the thread sums: within the wave, then over the waves
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    int64_t incl = ts;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t up = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += up;
+    }
+    if (lane == 63) wtot[wave] = incl;
+    __syncthreads();
+    int64_t before = 0, btotal = 0;
+#pragma unroll
+    for (int w = 0; w < WPB; ++w) {
+        before += w < wave ? wtot[w] : 0;
+        btotal += wtot[w];
+    }
+    int64_t run = off + before + incl - ts;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        if (i0 + e < p) out[i0 + e] = run;
+        run += v[e];
+    }
+    if (b == gridDim.x - 1 && threadIdx.x == 0) {
+        const int64_t total = off + btotal;
+        out[p] = total;
+        if (overflow) *overflow = total > cap ? 1 : 0;
+    }
+}
+
 // ---- trial evaluation ---------------------------------------------------------
 constexpr int MAXQ = 8;
 
@@ -796,7 +873,8 @@ __global__ void __launch_bounds__(NT)
 cov_refresh_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                    const double* __restrict__ val, int64_t p, const void* __restrict__ S,
                    int64_t lds, const double* __restrict__ smax, int T, double lam1,
-                   uint64_t* __restrict__ tbits, int64_t nwords, const int* gate) {
+                   uint64_t* __restrict__ tbits, int64_t nwords, const int* gate,
+                   unsigned long long* __restrict__ active) {
     if (gate && *gate == 0) return;
     typedef typename Chunk<BS>::T A;                          // accumulation type
     typedef typename MType<BS>::T E;                          // type of M
@@ -875,6 +953,7 @@ cov_refresh_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict
         }
         __syncthreads();   // cms is reused below
     }
+    if (active && threadIdx.x == 0) atomicAdd(active, 1ull);   // pairs that load S
     const uint32_t ci = (uint32_t)(i0 + lane), cj = (uint32_t)(j0 + lane);
     A w[16], wj[16];
 #pragma unroll
@@ -1347,10 +1426,19 @@ hipError_t launch_cand_fill(const void* M, int mstore, int64_t ldm, const Csr& o
 }
 
 hipError_t launch_scan(const int64_t* cnt, int64_t p, int64_t* out, int64_t cap, int* overflow,
-                       hipStream_t stream) {
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, stream, cnt, p, out, cap, overflow);
+                       int64_t* ws, hipStream_t stream) {
+    if (p == 0) {
+        hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, stream, cnt, p, out, cap, overflow);
+        return hipGetLastError();
+    }
+    const unsigned nb = (unsigned)((p + SCAN_CHUNK - 1) / SCAN_CHUNK);
+    hipLaunchKernelGGL(scan_part_kernel, dim3(nb), dim3(NT), 0, stream, cnt, p, ws);
+    hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(NT), 0, stream, cnt, p, ws, out, cap,
+                       overflow);
     return hipGetLastError();
 }
+
+int64_t scan_ws_len(int64_t p) { return (p + SCAN_CHUNK - 1) / SCAN_CHUNK + 1; }
 
 // Splitting the Obs column loop over blocks was measured slower than one wave per
 // row at the benchmark shape (many tiny waves), so one split is used.
@@ -1475,14 +1563,14 @@ hipError_t launch_identity(const Csr& om, int64_t p, hipStream_t stream) {
 
 hipError_t launch_cov_refresh(const Csr& A, int64_t p, const void* S, int sstore, int64_t lds,
                               const double* smax, double lam1, uint64_t* tbits, int64_t nwords,
-                              const int* gate, hipStream_t stream) {
+                              const int* gate, hipStream_t stream, unsigned long long* active) {
     if (!tbits || !smax || nwords != (p + 63) / 64 || lds < nwords * 64) return hipErrorInvalidValue;
     const int T = (int)((p + 63) / 64);
     const int nt = T * (T + 1) / 2;
     if (nt == 0) return hipSuccess;
 #define REFRESH(BS)                                                                     \
     hipLaunchKernelGGL((cov_refresh_kernel<BS>), dim3(nt), dim3(NT), 0, stream, A.rowptr, \
-                       A.col, A.val, p, S, lds, smax, T, lam1, tbits, nwords, gate)
+                       A.col, A.val, p, S, lds, smax, T, lam1, tbits, nwords, gate, active)
     if (sstore == ST_F64) REFRESH(ST_F64);
     else if (sstore == ST_F32) REFRESH(ST_F32);
     else if (sstore == ST_B16P) REFRESH(ST_B16P);

@@ -49,6 +49,7 @@ def test_version_and_null_handles(lib):
     nnz = ctypes.c_int64()
     assert lib.concord_get_omega(None, ctypes.byref(nnz), None, None, None, 0) == _lib.EINVAL
     assert lib.concord_contraction_variant(None, None, 0) == _lib.EINVAL
+    assert lib.concord_refresh_screen_stats(None, 0.1, None, None) == _lib.EINVAL
 
 
 def test_config_defaults(lib):

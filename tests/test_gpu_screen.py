@@ -1,0 +1,94 @@
+"""The Cov refresh's exact tile screening (GPU, through the C-ABI).
+
+The refresh skips the S loads of a pair of 64 x 64 tiles when a bound on |M_ij| over
+the pair is at most lambda1; the candidate words of a skipped pair are provably empty.
+These tests build a banded covariance (large entries near the diagonal, tiny ones
+elsewhere), so most pairs are skipped, and check
+  * the number of pairs that loaded S against the bound recomputed on the host, and
+  * the candidate count of a step from Omega = I against the dense count
+    |{(i, j) : i == j or |S_ij| > lambda1}| (at Omega = I, M = S), with lambda1 placed
+    away from every |S_ij| so the count does not depend on rounding.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _banded_cov(p, seed):
+    """Exactly symmetric S: rho^|i-j| within distance 3, +-1e-3 noise elsewhere."""
+    rng = np.random.default_rng(seed)
+    noise = rng.uniform(-1e-3, 1e-3, size=(p, p))
+    S = (noise + noise.T) * 0.5
+    i = np.arange(p)
+    d = np.abs(i[:, None] - i[None, :])
+    near = d <= 3
+    S[near] = (0.6 ** d)[near]
+    return S
+
+
+def _tile_max(S):
+    p = S.shape[0]
+    T = (p + 63) // 64
+    A = np.zeros((T * 64, T * 64))
+    A[:p, :p] = np.abs(S)
+    return A.reshape(T, 64, T, 64).max(axis=(1, 3))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("p", [700, 1000])
+def test_screen_stats_match_host_bound_at_identity(precision, p):
+    import torch
+    from paper_1710_10769_amd import Solver
+    _say(f"screen stats {precision} p={p} seed=11")
+    S = _banded_cov(p, 11)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    Sd = S if precision == "fp64" else S.astype(np.float32).astype(np.float64)
+    lam1 = 0.3
+    s = Solver(p, 1, variant="cov", precision=precision)
+    s.set_covariance(torch.from_numpy(np.ascontiguousarray(S)).to("cuda", dt))
+    pairs, active = s.refresh_screen_stats(lam1)
+    s.close()
+    T = (p + 63) // 64
+    assert pairs == T * (T + 1) // 2
+    # at Omega = I: bound(I, J) = (smax[I, J] + smax[J, I]) / 2 = smax[I, J]; the kernel
+    # widens by 1.01 + 3 * 2^-23 (one nonzero per row) and skips when <= threshold
+    sm = _tile_max(Sd)
+    widen = 1.01 + 3 * 2.0 ** -23
+    iu = np.triu_indices(T, 1)
+    b = sm[iu] * widen
+    thr = lam1 if precision == "fp64" else float(np.float32(lam1))
+    if precision == "fp32" and thr > lam1:
+        thr = float(np.nextafter(np.float32(lam1), np.float32(0)))
+    # rounding of the bound itself may move a pair sitting exactly at the threshold
+    lo = int((b > thr * (1 + 1e-9)).sum()) + T
+    hi = int((b > thr * (1 - 1e-9)).sum()) + T
+    assert lo <= active <= hi, (active, lo, hi)
+    assert active < pairs   # the banded S must actually be screened
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_screened_step_keeps_every_candidate(precision):
+    import torch
+    from paper_1710_10769_amd import Solver
+    p = 1000
+    _say(f"screened candidates {precision} p={p} seed=12")
+    S = _banded_cov(p, 12)
+    Sd = S if precision == "fp64" else S.astype(np.float32).astype(np.float64)
+    # lambda1 between 0.6^2 = 0.36 and 0.6 = 0.6: the |i - j| = 1 entries pass, the rest fail
+    lam1 = 0.45
+    a = np.abs(Sd)
+    assert np.min(np.abs(a - lam1)) > 1e-3
+    dense = int(((a > lam1) | np.eye(p, dtype=bool)).sum())
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    s = Solver(p, 1, variant="cov", precision=precision)
+    s.set_covariance(torch.from_numpy(np.ascontiguousarray(S)).to("cuda", dt))
+    info = s.step(lam1, 0.1)
+    pairs, active = s.refresh_screen_stats(lam1)
+    s.close()
+    assert info.n_candidates == dense
+    assert active < pairs
