@@ -90,6 +90,7 @@ struct concord_ctx {
     void* S = nullptr;
     double* smax = nullptr;   // Cov: largest |S| of each 64 x 64 tile (T x T)
     unsigned long long* d_active = nullptr;   // screening statistics counter
+    RefreshWs rws = {};                         // Cov refresh screening workspace
     void* M = nullptr;
     void* dxt = nullptr;   // differentiation form: Omega Y before its transpose
 
@@ -327,7 +328,7 @@ int products_at(concord_ctx* c, int which, const int* gate, double bits_lam1 = -
     } else {
         if (bits_lam1 >= 0.0)
             HIPCK(c, launch_cov_refresh(O, p, c->S, c->sstore, c->ldp, c->smax, bits_lam1, c->bitmap,
-                                        c->nwords, gate, c->stream));
+                                        c->nwords, c->rws, gate, c->stream));
         HIPCK(c, launch_obj_parts_cov(O, p, c->S, c->sstore, c->ldp, c->part, gate, c->stream));
         HIPCK(c, launch_colsum(c->part, p, 4, c->objsums, c->colsum_ws, c->stream));
     }
@@ -433,7 +434,7 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
         const bool cov = c->variant == CONCORD_COV;
         if (cov && !merge)
             HIPCK(c, launch_cov_refresh(c->om[c->cur], p, c->S, c->sstore, c->ldp, c->smax, lam1,
-                                        c->bitmap, c->nwords, c->d_one, c->stream));
+                                        c->bitmap, c->nwords, c->rws, c->d_one, c->stream));
         if (merge || cov)
             HIPCK(c, launch_cand_merge(c->om[c->cur], p, c->bitmap, c->nwords, c->cnt, c->stream));
         else
@@ -736,6 +737,12 @@ int concord_create(const concord_config* cfg, concord_ctx** out) {
             return bail(rc);
         const int64_t T = (p + 63) / 64;
         if ((rc = dalloc_t(c, &c->smax, (size_t)(T * T), true))) return bail(rc);
+        RefreshWs& r = c->rws;
+        if ((rc = dalloc_t(c, &r.lcnt, (size_t)T, true)) || (rc = dalloc_t(c, &r.lK, (size_t)T * 64, true)) ||
+            (rc = dalloc_t(c, &r.lW, (size_t)T * 64, true)) || (rc = dalloc_t(c, &r.lcmax, (size_t)T, true)) ||
+            (rc = dalloc_t(c, &r.plist, (size_t)(T * (T + 1) / 2), true)) ||
+            (rc = dalloc_t(c, &r.pcount, 1, true)))
+            return bail(rc);
     }
     for (int w = 0; w < 2; ++w)
         if ((rc = dalloc_t(c, &c->om[w].rowptr, p + 1, true))) return bail(rc);
@@ -918,7 +925,7 @@ int concord_refresh_screen_stats(concord_ctx* c, double lam1, int64_t* host_pair
     if (!c->d_active && (rc = dalloc_t(c, &c->d_active, 1, false))) return rc;
     hipLaunchKernelGGL(set_u64_kernel, dim3(1), dim3(64), 0, c->stream, c->d_active, 0ull);
     HIPCK(c, launch_cov_refresh(c->om[c->cur], c->p, c->S, c->sstore, c->ldp, c->smax, lam1,
-                                c->bitmap, c->nwords, c->d_one, c->stream, c->d_active));
+                                c->bitmap, c->nwords, c->rws, c->d_one, c->stream, c->d_active));
     unsigned long long act = 0;
     HIPCK(c, hipMemcpyAsync(&act, c->d_active, sizeof(act), hipMemcpyDeviceToHost, c->stream));
     HIPCK(c, hipStreamSynchronize(c->stream));

@@ -197,9 +197,19 @@ hipError_t launch_identity(const Csr& om, int64_t p, hipStream_t stream);
 // the largest |S| of each 64 x 64 tile (launch_tile_max); pairs whose bound on |M|
 // stays at or below lam1 skip their S loads.  Gated like launch_spmm.  If `active` is
 // non-null, every pair that loads S adds one to it (a diagnostic: one atomic per pair).
+// Workspace (see refresh_ws_sizes): per row tile the screened column-tile list, and the
+// list of kept pairs with its count.
+struct RefreshWs {
+    int* lcnt;      // T
+    int* lK;        // T * 64
+    double* lW;     // T * 64
+    int* lcmax;     // T
+    int* plist;     // T (T + 1) / 2
+    int* pcount;    // 1
+};
 hipError_t launch_cov_refresh(const Csr& A, int64_t p, const void* S, int sstore, int64_t lds,
                               const double* smax, double lam1, uint64_t* tbits, int64_t nwords,
-                              const int* gate, hipStream_t stream,
+                              const RefreshWs& ws, const int* gate, hipStream_t stream,
                               unsigned long long* active = nullptr);
 // smax[I * T + J] = max |S| over tile (I, J), T = ceil(p / 64), as the refresh reads S.
 hipError_t launch_tile_max(const void* S, int sstore, int64_t p, int64_t lds, double* out,

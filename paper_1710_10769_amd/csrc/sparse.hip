@@ -14,6 +14,8 @@
 // Every FP64 reduction is done in a fixed order (lane-local sequential sums,
 // then a fixed xor-butterfly, then fixed-order column sums), so results are
 // bitwise reproducible run to run.
+#include <algorithm>
+#include <cstdint>
 #include <type_traits>
 
 #include "internal.h"
@@ -868,19 +870,26 @@ __device__ inline int2 refresh_tile(int w, int T, int ntiles) {
     return make_int2((int)(i0 + t % h), (int)(i0 + h + t / h));
 }
 
+// FP32 test threshold: |m| > lam1 holds for an FP32 m exactly when |m| > lam1 rounded down.
+template <typename E> __device__ inline E test_threshold(double lam1) {
+    E thr = (E)lam1;
+    if (sizeof(E) == 4 && (double)thr > lam1) thr = __int_as_float(__float_as_int((float)thr) - 1);
+    return thr;
+}
+
+// One tile pair (I, J) of the refresh; every branch is uniform in the workgroup.
 template <int BS>
-__global__ void __launch_bounds__(NT)
-cov_refresh_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                   const double* __restrict__ val, int64_t p, const void* __restrict__ S,
-                   int64_t lds, const double* __restrict__ smax, int T, double lam1,
-                   uint64_t* __restrict__ tbits, int64_t nwords, const int* gate,
-                   unsigned long long* __restrict__ active) {
-    if (gate && *gate == 0) return;
+__device__ __forceinline__ void refresh_pair(const int I, const int J,
+                                             const int64_t* __restrict__ rowptr,
+                                             const int32_t* __restrict__ col,
+                                             const double* __restrict__ val, int64_t p,
+                                             const void* __restrict__ S, int64_t lds,
+                                             const double* __restrict__ smax, int T, double lam1,
+                                             uint64_t* __restrict__ tbits, int64_t nwords,
+                                             unsigned long long* __restrict__ active) {
     typedef typename Chunk<BS>::T A;                          // accumulation type
     typedef typename MType<BS>::T E;                          // type of M
     __shared__ E wt[64][65];   // W_JI, then M_IJ read transposed for the rows of J
-    const int2 ij = refresh_tile(blockIdx.x, T, (int)gridDim.x);
-    const int I = __builtin_amdgcn_readfirstlane(ij.x), J = __builtin_amdgcn_readfirstlane(ij.y);
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t i0 = (int64_t)I * 64, j0 = (int64_t)J * 64;
@@ -924,8 +933,7 @@ cov_refresh_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict
         rbound = ob > rbound ? ob : rbound;
     }
     const int maxI = __builtin_amdgcn_readlane(mx, 0), maxJ = __builtin_amdgcn_readlane(mx, 16);
-    E thr = (E)lam1;
-    if (sizeof(E) == 4 && (double)thr > lam1) thr = __int_as_float(__float_as_int((float)thr) - 1);
+    const E thr = test_threshold<E>(lam1);
     const int64_t gj = j0 + lane;
     __shared__ uint32_t cms[4][64];
     if (I != J) {
@@ -1056,6 +1064,141 @@ cov_refresh_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict
                               ((uint64_t)cms[2][lane] << 32) | ((uint64_t)cms[3][lane] << 48);
         tbits[gj * nwords + I] = word;
     }
+}
+
+// The refresh proper: workgroup w takes entry w of the list of tile pairs that passed
+// the pair screening (screen_pairs_kernel); the grid covers every pair and the
+// workgroups past the list's length exit at once.  (A persistent grid walking the list
+// needs 107 instead of 75 VGPRs for FP32: the loop around the pair costs occupancy.)
+template <int BS>
+__global__ void __launch_bounds__(NT)
+cov_refresh_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                   const double* __restrict__ val, int64_t p, const void* __restrict__ S,
+                   int64_t lds, const double* __restrict__ smax, int T, double lam1,
+                   uint64_t* __restrict__ tbits, int64_t nwords, const int* gate,
+                   unsigned long long* __restrict__ active, const int* __restrict__ plist,
+                   const int* __restrict__ pcount) {
+    if (gate && *gate == 0) return;
+    const int n = __builtin_amdgcn_readfirstlane(*pcount);
+    if ((int)blockIdx.x >= n) return;
+    const int2 ij = refresh_tile(plist[blockIdx.x], T, T * (T + 1) / 2);
+    const int I = __builtin_amdgcn_readfirstlane(ij.x);
+    const int J = __builtin_amdgcn_readfirstlane(ij.y);
+    refresh_pair<BS>(I, J, rowptr, col, val, p, S, lds, smax, T, lam1, tbits, nwords, active);
+}
+
+// Pair screening, first part: for every row tile I, the column tiles K its rows' nonzeros
+// fall in, with weight w(I, K) = max_{i in I} sum_{k in supp_i, k/64 = K} |omega_ik|, and
+// the largest row count.  More than SCREEN_L tiles marks I as unscreened (count > L).
+constexpr int SCREEN_L = 64;
+__global__ void __launch_bounds__(64)
+screen_rows_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                   const double* __restrict__ val, int64_t p, int T, int* __restrict__ lcnt,
+                   int* __restrict__ lK, double* __restrict__ lW, int* __restrict__ lcmax,
+                   const int* gate) {
+    if (gate && *gate == 0) return;
+    extern __shared__ unsigned long long wk[];   // T weights (bits of non-negative doubles)
+    const int I = blockIdx.x, lane = threadIdx.x;
+    for (int k = lane; k < T; k += 64) wk[k] = 0ull;
+    __syncthreads();
+    const int64_t row = (int64_t)I * 64 + lane;
+    int cnt = 0;
+    if (row < p) {
+        const int64_t s = rowptr[row], e = rowptr[row + 1];
+        cnt = (int)(e - s);
+        int cur = -1;
+        double acc = 0.0;
+        for (int64_t k = s; k < e; ++k) {
+            const int K = col[k] >> 6;
+            if (K != cur) {   // columns are sorted: one run per tile
+                if (cur >= 0) atomicMax(&wk[cur], (unsigned long long)__double_as_longlong(acc));
+                cur = K;
+                acc = 0.0;
+            }
+            acc += fabs(val[k]);
+        }
+        if (cur >= 0) atomicMax(&wk[cur], (unsigned long long)__double_as_longlong(acc));
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const int x = __shfl_xor(cnt, o, 64);
+        cnt = x > cnt ? x : cnt;
+    }
+    __syncthreads();
+    int base = 0;
+    for (int k0 = 0; k0 < T; k0 += 64) {
+        const int k = k0 + lane;
+        const unsigned long long v = k < T ? wk[k] : 0ull;
+        const uint64_t m = __ballot(v != 0ull);
+        const int pos = base + __popcll(m & lanemask_lt());
+        if (v != 0ull && pos < SCREEN_L) {
+            lK[(int64_t)I * SCREEN_L + pos] = k;
+            lW[(int64_t)I * SCREEN_L + pos] = __longlong_as_double((long long)v);
+        }
+        base += __popcll(m);
+    }
+    if (lane == 0) {
+        lcnt[I] = base;
+        lcmax[I] = cnt;
+    }
+}
+
+// Pair screening, second part: one thread per tile pair t (the refresh's order).  The
+// pair is kept if it is diagonal, if a tile is unscreened, or if
+//   (sum_K w(I, K) smax[K][J] + sum_K w(J, K) smax[K][I]) / 2,
+// a bound on |M_ij| over the pair no smaller than the refresh's own, exceeds the test
+// threshold after the same widening.  Kept pairs are appended to plist (one atomic per
+// block; the order of blocks is free, the refresh's result does not depend on it).
+template <typename E>
+__global__ void __launch_bounds__(NT)
+screen_pairs_kernel(int T, const int* __restrict__ lcnt, const int* __restrict__ lK,
+                    const double* __restrict__ lW, const int* __restrict__ lcmax,
+                    const double* __restrict__ smax, double lam1, int* __restrict__ plist,
+                    int* __restrict__ pcount, const int* gate) {
+    if (gate && *gate == 0) return;
+    __shared__ int wsum[WPB];
+    __shared__ int bbase;
+    const int nt = T * (T + 1) / 2;
+    const int t = blockIdx.x * NT + threadIdx.x;
+    bool keep = false;
+    if (t < nt) {
+        const int2 ij = refresh_tile(t, T, nt);
+        const int I = ij.x, J = ij.y;
+        const int cI = lcnt[I], cJ = lcnt[J];
+        if (I == J || cI > SCREEN_L || cJ > SCREEN_L) {
+            keep = true;
+        } else {
+            double bw = 0.0, bv = 0.0;
+            for (int q = 0; q < cI; ++q)
+                bw += lW[(int64_t)I * SCREEN_L + q] * smax[(int64_t)lK[(int64_t)I * SCREEN_L + q] * T + J];
+            for (int q = 0; q < cJ; ++q)
+                bv += lW[(int64_t)J * SCREEN_L + q] * smax[(int64_t)lK[(int64_t)J * SCREEN_L + q] * T + I];
+            const int cm = lcmax[I] > lcmax[J] ? lcmax[I] : lcmax[J];
+            const double widen = 1.01 + (double)(cm + 2) * 0x1p-23;
+            keep = 0.5 * (bw + bv) * widen > (double)test_threshold<E>(lam1);
+        }
+    }
+    const uint64_t m = __ballot(keep);
+    const int wave = threadIdx.x >> 6;
+    if (lane_id() == 0) wsum[wave] = __popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int v = 0; v < WPB; ++v) tot += wsum[v];
+        bbase = tot ? atomicAdd(pcount, tot) : 0;
+    }
+    __syncthreads();
+    int before = 0;
+    for (int v = 0; v < wave; ++v) before += wsum[v];
+    if (keep) plist[bbase + before + __popcll(m & lanemask_lt())] = t;
+}
+
+// Zero words (the screened-out pairs' words stay zero), gated like the refresh.
+__global__ void __launch_bounds__(NT)
+zero_words_kernel(uint64_t* __restrict__ w, int64_t n, const int* gate) {
+    if (gate && *gate == 0) return;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+        w[i] = 0ull;
 }
 
 // Largest |S| of every 64 x 64 tile (as the refresh reads S), for its screening.
@@ -1561,16 +1704,39 @@ hipError_t launch_identity(const Csr& om, int64_t p, hipStream_t stream) {
     return hipGetLastError();
 }
 
+__global__ void reset_count_kernel(int* c) {
+    if (threadIdx.x == 0) *c = 0;
+}
+
 hipError_t launch_cov_refresh(const Csr& A, int64_t p, const void* S, int sstore, int64_t lds,
                               const double* smax, double lam1, uint64_t* tbits, int64_t nwords,
-                              const int* gate, hipStream_t stream, unsigned long long* active) {
+                              const RefreshWs& ws, const int* gate, hipStream_t stream,
+                              unsigned long long* active) {
     if (!tbits || !smax || nwords != (p + 63) / 64 || lds < nwords * 64) return hipErrorInvalidValue;
+    if (!ws.lcnt || !ws.lK || !ws.lW || !ws.lcmax || !ws.plist || !ws.pcount)
+        return hipErrorInvalidValue;
     const int T = (int)((p + 63) / 64);
-    const int nt = T * (T + 1) / 2;
+    const int64_t nt = (int64_t)T * (T + 1) / 2;
     if (nt == 0) return hipSuccess;
-#define REFRESH(BS)                                                                     \
-    hipLaunchKernelGGL((cov_refresh_kernel<BS>), dim3(nt), dim3(NT), 0, stream, A.rowptr, \
-                       A.col, A.val, p, S, lds, smax, T, lam1, tbits, nwords, gate, active)
+    if (nt > INT32_MAX || (size_t)T * 8 > 64 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(reset_count_kernel, dim3(1), dim3(64), 0, stream, ws.pcount);
+    hipLaunchKernelGGL(screen_rows_kernel, dim3(T), dim3(64), (size_t)T * 8, stream, A.rowptr,
+                       A.col, A.val, p, T, ws.lcnt, ws.lK, ws.lW, ws.lcmax, gate);
+    const unsigned pb = (unsigned)((nt + NT - 1) / NT);
+    if (sstore == ST_F64)
+        hipLaunchKernelGGL(screen_pairs_kernel<double>, dim3(pb), dim3(NT), 0, stream, T, ws.lcnt,
+                           ws.lK, ws.lW, ws.lcmax, smax, lam1, ws.plist, ws.pcount, gate);
+    else
+        hipLaunchKernelGGL(screen_pairs_kernel<float>, dim3(pb), dim3(NT), 0, stream, T, ws.lcnt,
+                           ws.lK, ws.lW, ws.lcmax, smax, lam1, ws.plist, ws.pcount, gate);
+    const int64_t nw = p * nwords;
+    const unsigned zb = (unsigned)std::min<int64_t>((nw + NT - 1) / NT, 8192);
+    hipLaunchKernelGGL(zero_words_kernel, dim3(zb), dim3(NT), 0, stream, tbits, nw, gate);
+    const unsigned g = (unsigned)nt;
+#define REFRESH(BS)                                                                      \
+    hipLaunchKernelGGL((cov_refresh_kernel<BS>), dim3(g), dim3(NT), 0, stream, A.rowptr,   \
+                       A.col, A.val, p, S, lds, smax, T, lam1, tbits, nwords, gate, active, \
+                       ws.plist, ws.pcount)
     if (sstore == ST_F64) REFRESH(ST_F64);
     else if (sstore == ST_F32) REFRESH(ST_F32);
     else if (sstore == ST_B16P) REFRESH(ST_B16P);
