@@ -229,22 +229,22 @@ def bench_c3(args, torch, np, datagen):
             if k < si.iters:
                 s.step(w.lam1, w.lam2)
         s.close()
-        spmm_ms = prof["spmm"][0] / max(prof["spmm"][1], 1)
+        ref_ms = prof["refresh"][0] / max(prof["refresh"][1], 1)
         eb = 8 if form == "fp64" else 4
-        # the refresh forms M = (Omega S + S Omega) / 2 tile pair by tile pair and writes
-        # only the candidate threshold words; pairs whose bound on |M| stays at or below
-        # lambda1 skip their S loads.  Algorithmic bytes per refresh: the S tiles of the
-        # pairs that passed (two 64 x 64 tiles per off-diagonal pair, one per diagonal
-        # pair) plus p^2 / 8 bytes of words (S rows re-read per nonzero of Omega come from
-        # L2/MALL); the timed slot also holds the objective's gathers
+        # the refresh kernel forms M = (Omega S + S Omega) / 2 for the tile pairs kept by
+        # the screening and writes their candidate threshold words (the screening zeroes
+        # the rest).  Algorithmic bytes per launch: the S tiles of the kept pairs (two
+        # 64 x 64 tiles per off-diagonal pair, one per diagonal pair) plus their words
+        # (64 rows x 8 bytes per tile); S rows re-read per nonzero of Omega come from
+        # L2/MALL.  Timed alone (class "refresh").
         T = (w.p + 63) // 64
-        tile_b = 64 * 64 * eb
-        s_bytes = (2 * (act_total - nref * T) + nref * T) * tile_b / nref
-        words_b = w.p * T * 8.0
-        gbs = (s_bytes + words_b) / (spmm_ms * 1e-3) / 1e9
+        tiles = (2 * (act_total - nref * T) + nref * T) / nref
+        s_bytes = tiles * 64 * 64 * eb
+        words_b = tiles * 64 * 8.0
+        gbs = (s_bytes + words_b) / (ref_ms * 1e-3) / 1e9
         res[form] = {"iters": si.iters, "iters_per_s": si.iters / t_solve, "solve_s": t_solve,
                      "s_formation_s": t_s, "nnz": si.nnz, "F": si.F,
-                     "refresh_ms": spmm_ms, "refresh_GBps": gbs,
+                     "refresh_ms": ref_ms, "refresh_GBps": gbs,
                      "refresh_pairs_loading_S_frac": act_total / (nref * npairs),
                      "refresh_algorithmic_MB": (s_bytes + words_b) / 1e6,
                      "kernel_ms_per_iter": {k: v[0] / max(si.iters, 1) for k, v in prof.items()}}
@@ -268,9 +268,8 @@ def bench_c3(args, torch, np, datagen):
         "config": {"workload": "cov_random_deg8_p16384_n4096", "p": w.p, "n": w.n,
                    "lam1": w.lam1, "lam2": w.lam2, "tol": w.tol},
         "forms": res,
-        # the Cov refresh of the BF16x3 form: the S tiles (packed hi|lo, 4 bytes an entry) of
-        # the pairs that pass the screening, read once, and the p^2 / 8 bytes of threshold
-        # words written per iteration
+        # the Cov refresh kernel of the BF16x3 form: the S tiles (packed hi|lo, 4 bytes an
+        # entry) of the pairs kept by the screening, read once, and their threshold words
         "roofline": {"bound": "hbm", "kernel": "cov_refresh_kernel", "achieved": ref_gbps,
                      "peak": 8000.0, "unit": "GB/s", "frac": ref_gbps / 8000.0,
                      "traffic": stored_traffic("bf16x3", None,

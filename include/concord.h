@@ -262,7 +262,11 @@ void concord_batch_destroy(concord_batch* b);
 #define CONCORD_PROF_CAND  2   /* gradient + candidate set */
 #define CONCORD_PROF_TRIAL 3   /* step-size trials + test sums + decision */
 #define CONCORD_PROF_EMIT  4   /* CSR emission of the accepted iterate */
-#define CONCORD_PROF_NCLASS 5
+#define CONCORD_PROF_REFRESH 5 /* Cov: the refresh kernel alone (the tile pairs kept by the
+                                  screening) at the accepted iterate; its screening and the
+                                  objective sums stay in CONCORD_PROF_SPMM, which then times
+                                  two intervals per refresh */
+#define CONCORD_PROF_NCLASS 6
 typedef struct concord_profile {
     double  ms[8];        /* accumulated milliseconds per class */
     int64_t launches[8];  /* timed launch groups per class */

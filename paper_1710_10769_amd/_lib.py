@@ -58,7 +58,7 @@ class concord_profile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8)]
 
 
-PROF_CLASSES = ("dense", "spmm", "cand", "trial", "emit")
+PROF_CLASSES = ("dense", "spmm", "cand", "trial", "emit", "refresh")
 
 
 class concord_variant_estimate(ctypes.Structure):

@@ -326,9 +326,17 @@ int products_at(concord_ctx* c, int which, const int* gate, double bits_lam1 = -
         HIPCK(c, launch_obj_parts(O, p, nullptr, c->dstore, 0, c->part, gate, c->stream));
         HIPCK(c, launch_colsum(c->part, p, 4 + nch, c->objsums, c->colsum_ws, c->stream));
     } else {
-        if (bits_lam1 >= 0.0)
-            HIPCK(c, launch_cov_refresh(O, p, c->S, c->sstore, c->ldp, c->smax, bits_lam1, c->bitmap,
-                                        c->nwords, c->rws, gate, c->stream));
+        if (bits_lam1 >= 0.0) {
+            // the refresh kernel alone gets its own timing class
+            HIPCK(c, launch_cov_screen(O, p, c->sstore, c->smax, bits_lam1, c->bitmap, c->nwords,
+                                       c->rws, gate, c->stream));
+            prof_end(c);
+            prof_begin(c, CONCORD_PROF_REFRESH);
+            HIPCK(c, launch_cov_refresh_pairs(O, p, c->S, c->sstore, c->ldp, c->smax, bits_lam1,
+                                              c->bitmap, c->nwords, c->rws, gate, c->stream));
+            prof_end(c);
+            prof_begin(c, CONCORD_PROF_SPMM);
+        }
         HIPCK(c, launch_obj_parts_cov(O, p, c->S, c->sstore, c->ldp, c->part, gate, c->stream));
         HIPCK(c, launch_colsum(c->part, p, 4, c->objsums, c->colsum_ws, c->stream));
     }

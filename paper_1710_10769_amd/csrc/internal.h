@@ -211,6 +211,16 @@ hipError_t launch_cov_refresh(const Csr& A, int64_t p, const void* S, int sstore
                               const double* smax, double lam1, uint64_t* tbits, int64_t nwords,
                               const RefreshWs& ws, const int* gate, hipStream_t stream,
                               unsigned long long* active = nullptr);
+// The two halves of launch_cov_refresh: the screening (row-tile lists, the list of kept
+// pairs, the words zeroed) and the refresh of the kept pairs.
+hipError_t launch_cov_screen(const Csr& A, int64_t p, int sstore, const double* smax,
+                             double lam1, uint64_t* tbits, int64_t nwords, const RefreshWs& ws,
+                             const int* gate, hipStream_t stream);
+hipError_t launch_cov_refresh_pairs(const Csr& A, int64_t p, const void* S, int sstore,
+                                    int64_t lds, const double* smax, double lam1,
+                                    uint64_t* tbits, int64_t nwords, const RefreshWs& ws,
+                                    const int* gate, hipStream_t stream,
+                                    unsigned long long* active = nullptr);
 // smax[I * T + J] = max |S| over tile (I, J), T = ceil(p / 64), as the refresh reads S.
 hipError_t launch_tile_max(const void* S, int sstore, int64_t p, int64_t lds, double* out,
                            hipStream_t stream);

@@ -1708,11 +1708,10 @@ __global__ void reset_count_kernel(int* c) {
     if (threadIdx.x == 0) *c = 0;
 }
 
-hipError_t launch_cov_refresh(const Csr& A, int64_t p, const void* S, int sstore, int64_t lds,
-                              const double* smax, double lam1, uint64_t* tbits, int64_t nwords,
-                              const RefreshWs& ws, const int* gate, hipStream_t stream,
-                              unsigned long long* active) {
-    if (!tbits || !smax || nwords != (p + 63) / 64 || lds < nwords * 64) return hipErrorInvalidValue;
+hipError_t launch_cov_screen(const Csr& A, int64_t p, int sstore, const double* smax,
+                             double lam1, uint64_t* tbits, int64_t nwords, const RefreshWs& ws,
+                             const int* gate, hipStream_t stream) {
+    if (!tbits || !smax || nwords != (p + 63) / 64) return hipErrorInvalidValue;
     if (!ws.lcnt || !ws.lK || !ws.lW || !ws.lcmax || !ws.plist || !ws.pcount)
         return hipErrorInvalidValue;
     const int T = (int)((p + 63) / 64);
@@ -1732,6 +1731,20 @@ hipError_t launch_cov_refresh(const Csr& A, int64_t p, const void* S, int sstore
     const int64_t nw = p * nwords;
     const unsigned zb = (unsigned)std::min<int64_t>((nw + NT - 1) / NT, 8192);
     hipLaunchKernelGGL(zero_words_kernel, dim3(zb), dim3(NT), 0, stream, tbits, nw, gate);
+    return hipGetLastError();
+}
+
+hipError_t launch_cov_refresh_pairs(const Csr& A, int64_t p, const void* S, int sstore,
+                                    int64_t lds, const double* smax, double lam1,
+                                    uint64_t* tbits, int64_t nwords, const RefreshWs& ws,
+                                    const int* gate, hipStream_t stream,
+                                    unsigned long long* active) {
+    if (!tbits || !smax || nwords != (p + 63) / 64 || lds < nwords * 64 || !ws.plist || !ws.pcount)
+        return hipErrorInvalidValue;
+    const int T = (int)((p + 63) / 64);
+    const int64_t nt = (int64_t)T * (T + 1) / 2;
+    if (nt == 0) return hipSuccess;
+    if (nt > INT32_MAX) return hipErrorInvalidValue;
     const unsigned g = (unsigned)nt;
 #define REFRESH(BS)                                                                      \
     hipLaunchKernelGGL((cov_refresh_kernel<BS>), dim3(g), dim3(NT), 0, stream, A.rowptr,   \
@@ -1743,6 +1756,16 @@ hipError_t launch_cov_refresh(const Csr& A, int64_t p, const void* S, int sstore
     else return hipErrorInvalidValue;
 #undef REFRESH
     return hipGetLastError();
+}
+
+hipError_t launch_cov_refresh(const Csr& A, int64_t p, const void* S, int sstore, int64_t lds,
+                              const double* smax, double lam1, uint64_t* tbits, int64_t nwords,
+                              const RefreshWs& ws, const int* gate, hipStream_t stream,
+                              unsigned long long* active) {
+    hipError_t e = launch_cov_screen(A, p, sstore, smax, lam1, tbits, nwords, ws, gate, stream);
+    if (e != hipSuccess) return e;
+    return launch_cov_refresh_pairs(A, p, S, sstore, lds, smax, lam1, tbits, nwords, ws, gate,
+                                    stream, active);
 }
 
 hipError_t launch_tile_max(const void* S, int sstore, int64_t p, int64_t lds, double* out,
