@@ -627,21 +627,32 @@ trial_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
             }
         }
     }
+    // The 4 * MAXQ = 32 lane partials (value k = 4q + t) summed over the wave by a
+    // reduce-scatter butterfly: each step keeps half of the values and adds the partner
+    // lane's copy of them (16 + 8 + 4 + 2 + 1 shuffles), leaving value lane >> 1 summed
+    // over the 32 lanes that share bit 0, and a last exchange adds the other 32.  Fixed
+    // order, so the sums are reproducible.
+    double v[4 * MAXQ];
 #pragma unroll
     for (int q = 0; q < MAXQ; ++q) {
-        if (q < m) {
-            const double a = wave_sum(slog[q]);
-            const double b2 = wave_sum(sdd[q]);
-            const double c2 = wave_sum(squad[q]);
-            const double d2 = wave_sum(snp[q]);
-            if (lane == 0) {
-                part[((int64_t)(q * 4 + 0) * nsplit + split) * p + row] = a;
-                part[((int64_t)(q * 4 + 1) * nsplit + split) * p + row] = b2;
-                part[((int64_t)(q * 4 + 2) * nsplit + split) * p + row] = c2;
-                part[((int64_t)(q * 4 + 3) * nsplit + split) * p + row] = d2;
-            }
+        v[4 * q + 0] = slog[q];
+        v[4 * q + 1] = sdd[q];
+        v[4 * q + 2] = squad[q];
+        v[4 * q + 3] = snp[q];
+    }
+#pragma unroll
+    for (int n = 4 * MAXQ, o = 32; n > 1; n >>= 1, o >>= 1) {
+        const bool upper = (lane & o) != 0;   // keep the upper half of the n values
+#pragma unroll
+        for (int i = 0; i < n / 2; ++i) {
+            const double send = upper ? v[i] : v[i + n / 2];
+            const double keep = upper ? v[i + n / 2] : v[i];
+            v[i] = keep + __shfl_xor(send, o, 64);
         }
     }
+    const double tot = v[0] + __shfl_xor(v[0], 1, 64);
+    const int k = lane >> 1, q = k >> 2, t = k & 3;
+    if ((lane & 1) == 0 && q < m) part[((int64_t)(q * 4 + t) * nsplit + split) * p + row] = tot;
 }
 
 // ---- column sums -----------------------------------------------------------------
