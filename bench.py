@@ -249,6 +249,26 @@ def bench_c3(args, torch, np, datagen):
                      "refresh_algorithmic_MB": (s_bytes + words_b) / 1e6,
                      "kernel_ms_per_iter": {k: v[0] / max(si.iters, 1) for k, v in prof.items()}}
         log(f"{form}: {si.iters} iterations, {t_solve:.3f} s, S in {t_s:.3f} s")
+    # the BF16x3 form once more with the screening off: the refresh then forms every tile
+    # pair (the plain product of Algorithm 2), reading all of S each iteration
+    s = Solver(w.p, w.n, variant="cov", precision="bf16x3", screen=False)
+    s.set_profiling(True)
+    s.set_data(X32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    si = s.solve(w.lam1, w.lam2, w.tol, w.max_iter)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    prof = s.profile()
+    same = bool((s.get_omega_scipy() != oms["bf16x3"]).nnz == 0)
+    s.close()
+    ref_ms = prof["refresh"][0] / max(prof["refresh"][1], 1)
+    unscreened = {"iters": si.iters, "iters_per_s": si.iters / t_solve, "F": si.F,
+                  "same_omega_as_screened": same, "refresh_ms": ref_ms,
+                  # every pair: S read once (p^2 entries, 4 bytes) + p^2 / 8 bytes of words
+                  "refresh_GBps": (w.p * w.p * 4.0 + w.p * w.p / 8.0) / (ref_ms * 1e-3) / 1e9,
+                  "kernel_ms_per_iter": {k: v[0] / max(si.iters, 1) for k, v in prof.items()}}
+    log(f"bf16x3 unscreened: {si.iters} iterations, {t_solve:.3f} s")
     ref = oms["fp64"]
     scale = float(np.abs(ref.data).max())
     for form in ("fp32", "bf16x3"):
@@ -268,6 +288,11 @@ def bench_c3(args, torch, np, datagen):
         "config": {"workload": "cov_random_deg8_p16384_n4096", "p": w.p, "n": w.n,
                    "lam1": w.lam1, "lam2": w.lam2, "tol": w.tol},
         "forms": res,
+        "bf16x3_unscreened": unscreened,
+        # the unscreened refresh is a plain streaming pass over S: its rate against the peak
+        "roofline_unscreened": {"bound": "hbm", "kernel": "cov_refresh_kernel",
+                                "achieved": unscreened["refresh_GBps"], "peak": 8000.0,
+                                "unit": "GB/s", "frac": unscreened["refresh_GBps"] / 8000.0},
         # the Cov refresh kernel of the BF16x3 form: the S tiles (packed hi|lo, 4 bytes an
         # entry) of the pairs kept by the screening, read once, and their threshold words
         "roofline": {"bound": "hbm", "kernel": "cov_refresh_kernel", "achieved": ref_gbps,

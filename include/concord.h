@@ -93,6 +93,10 @@ typedef struct concord_config {
                                `stream` at every call) and replays each iteration's common
                                path (contraction, candidates, first trial batch, accept) as
                                one captured HIP graph; 0 (default): direct launches */
+    int32_t no_screen;      /* Cov: 1 = the refresh forms every tile pair of M (the plain
+                               product of Algorithm 2); 0 (default) = exact tile screening
+                               (see concord_refresh_screen_stats).  Same results. */
+    int32_t reserved;       /* set to 0 */
 } concord_config;
 
 /* Per-iteration record (Algorithm 1, one pass of the outer loop). */

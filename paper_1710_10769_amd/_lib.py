@@ -43,7 +43,8 @@ class concord_config(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int64), ("n", ctypes.c_int64), ("variant", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("device", ctypes.c_int32), ("max_backtracks", ctypes.c_int32),
-                ("trial_batch", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("trial_batch", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("no_screen", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class concord_step_info(ctypes.Structure):
@@ -312,7 +313,7 @@ class Solver:
 
     def __init__(self, p: int, n: int, variant: str = "obs", precision: str = "fp32",
                  stream=None, device: Optional[int] = None, trial_batch: int = 8,
-                 max_backtracks: int = 60, use_graph: bool = False):
+                 max_backtracks: int = 60, use_graph: bool = False, screen: bool = True):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the HIP library needs a gfx950 device")
@@ -325,6 +326,7 @@ class Solver:
         cfg.trial_batch = trial_batch
         cfg.max_backtracks = max_backtracks
         cfg.use_graph = 1 if use_graph else 0
+        cfg.no_screen = 0 if screen else 1
         self.p, self.n, self.variant, self.precision = p, n, variant, precision
         self.device = torch.device("cuda", cfg.device)
         self._h = concord_create(cfg)

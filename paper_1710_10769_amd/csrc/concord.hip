@@ -129,6 +129,7 @@ struct concord_ctx {
 
     // graph replay of the common step path
     bool use_graph = false;
+    bool screen = true;   // Cov refresh: exact tile screening
     hipStream_t user_stream = nullptr;   // caller's stream when the handle runs on its own
     hipEvent_t enter_ev = nullptr;
     int64_t gen = 0;                     // bumped whenever a captured buffer is reallocated
@@ -329,11 +330,12 @@ int products_at(concord_ctx* c, int which, const int* gate, double bits_lam1 = -
         if (bits_lam1 >= 0.0) {
             // the refresh kernel alone gets its own timing class
             HIPCK(c, launch_cov_screen(O, p, c->sstore, c->smax, bits_lam1, c->bitmap, c->nwords,
-                                       c->rws, gate, c->stream));
+                                       c->rws, gate, c->stream, c->screen));
             prof_end(c);
             prof_begin(c, CONCORD_PROF_REFRESH);
-            HIPCK(c, launch_cov_refresh_pairs(O, p, c->S, c->sstore, c->ldp, c->smax, bits_lam1,
-                                              c->bitmap, c->nwords, c->rws, gate, c->stream));
+            HIPCK(c, launch_cov_refresh_pairs(O, p, c->S, c->sstore, c->ldp,
+                                              c->screen ? c->smax : nullptr, bits_lam1, c->bitmap,
+                                              c->nwords, c->rws, gate, c->stream));
             prof_end(c);
             prof_begin(c, CONCORD_PROF_SPMM);
         }
@@ -442,7 +444,8 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
         const bool cov = c->variant == CONCORD_COV;
         if (cov && !merge)
             HIPCK(c, launch_cov_refresh(c->om[c->cur], p, c->S, c->sstore, c->ldp, c->smax, lam1,
-                                        c->bitmap, c->nwords, c->rws, c->d_one, c->stream));
+                                        c->bitmap, c->nwords, c->rws, c->d_one, c->stream,
+                                        nullptr, c->screen));
         if (merge || cov)
             HIPCK(c, launch_cand_merge(c->om[c->cur], p, c->bitmap, c->nwords, c->cnt, c->stream));
         else
@@ -699,6 +702,7 @@ int concord_create(const concord_config* cfg, concord_ctx** out) {
     c->max_bt = cfg->max_backtracks;
     c->tb = cfg->trial_batch;
     c->use_graph = cfg->use_graph != 0;
+    c->screen = cfg->no_screen == 0;
     DeviceGuard g(dev);
     if (c->use_graph) {
         // captures need a stream of our own (the caller's may be the null stream)
@@ -933,7 +937,8 @@ int concord_refresh_screen_stats(concord_ctx* c, double lam1, int64_t* host_pair
     if (!c->d_active && (rc = dalloc_t(c, &c->d_active, 1, false))) return rc;
     hipLaunchKernelGGL(set_u64_kernel, dim3(1), dim3(64), 0, c->stream, c->d_active, 0ull);
     HIPCK(c, launch_cov_refresh(c->om[c->cur], c->p, c->S, c->sstore, c->ldp, c->smax, lam1,
-                                c->bitmap, c->nwords, c->rws, c->d_one, c->stream, c->d_active));
+                                c->bitmap, c->nwords, c->rws, c->d_one, c->stream, c->d_active,
+                                c->screen));
     unsigned long long act = 0;
     HIPCK(c, hipMemcpyAsync(&act, c->d_active, sizeof(act), hipMemcpyDeviceToHost, c->stream));
     HIPCK(c, hipStreamSynchronize(c->stream));

@@ -210,12 +210,13 @@ struct RefreshWs {
 hipError_t launch_cov_refresh(const Csr& A, int64_t p, const void* S, int sstore, int64_t lds,
                               const double* smax, double lam1, uint64_t* tbits, int64_t nwords,
                               const RefreshWs& ws, const int* gate, hipStream_t stream,
-                              unsigned long long* active = nullptr);
+                              unsigned long long* active = nullptr, bool screen = true);
 // The two halves of launch_cov_refresh: the screening (row-tile lists, the list of kept
-// pairs, the words zeroed) and the refresh of the kept pairs.
+// pairs, the words zeroed) and the refresh of the kept pairs (smax null: no screening in
+// the refresh either).  screen = false keeps every pair (the unscreened product).
 hipError_t launch_cov_screen(const Csr& A, int64_t p, int sstore, const double* smax,
                              double lam1, uint64_t* tbits, int64_t nwords, const RefreshWs& ws,
-                             const int* gate, hipStream_t stream);
+                             const int* gate, hipStream_t stream, bool screen = true);
 hipError_t launch_cov_refresh_pairs(const Csr& A, int64_t p, const void* S, int sstore,
                                     int64_t lds, const double* smax, double lam1,
                                     uint64_t* tbits, int64_t nwords, const RefreshWs& ws,

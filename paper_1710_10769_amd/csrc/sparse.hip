@@ -930,7 +930,8 @@ __device__ __forceinline__ void refresh_pair(const int I, const int J,
     // chains' rounding) is at most the threshold, no test in the pair passes and the
     // S loads are skipped.  Diagonal pairs (which hold the j == i bits) always run.
     double rbound = 0.0;
-    if (I != J) {
+    const bool screen = smax != nullptr;
+    if (I != J && screen) {
         const int64_t other = hl < 16 ? J : I;
         for (int m = 0; m < my_cnt; ++m)
             rbound += fabs(val[my_s0 + m]) * smax[(int64_t)(col[my_s0 + m] >> 6) * T + other];
@@ -947,7 +948,7 @@ __device__ __forceinline__ void refresh_pair(const int I, const int J,
     const E thr = test_threshold<E>(lam1);
     const int64_t gj = j0 + lane;
     __shared__ uint32_t cms[4][64];
-    if (I != J) {
+    if (I != J && screen) {
         __shared__ double bnd[4][2];
         if (lane == 0) bnd[wave][0] = rbound;
         if (lane == 16) bnd[wave][1] = rbound;
@@ -1165,7 +1166,7 @@ __global__ void __launch_bounds__(NT)
 screen_pairs_kernel(int T, const int* __restrict__ lcnt, const int* __restrict__ lK,
                     const double* __restrict__ lW, const int* __restrict__ lcmax,
                     const double* __restrict__ smax, double lam1, int* __restrict__ plist,
-                    int* __restrict__ pcount, const int* gate) {
+                    int* __restrict__ pcount, const int* gate, int keep_all) {
     if (gate && *gate == 0) return;
     __shared__ int wsum[WPB];
     __shared__ int bbase;
@@ -1176,7 +1177,7 @@ screen_pairs_kernel(int T, const int* __restrict__ lcnt, const int* __restrict__
         const int2 ij = refresh_tile(t, T, nt);
         const int I = ij.x, J = ij.y;
         const int cI = lcnt[I], cJ = lcnt[J];
-        if (I == J || cI > SCREEN_L || cJ > SCREEN_L) {
+        if (keep_all || I == J || cI > SCREEN_L || cJ > SCREEN_L) {
             keep = true;
         } else {
             double bw = 0.0, bv = 0.0;
@@ -1721,7 +1722,7 @@ __global__ void reset_count_kernel(int* c) {
 
 hipError_t launch_cov_screen(const Csr& A, int64_t p, int sstore, const double* smax,
                              double lam1, uint64_t* tbits, int64_t nwords, const RefreshWs& ws,
-                             const int* gate, hipStream_t stream) {
+                             const int* gate, hipStream_t stream, bool screen) {
     if (!tbits || !smax || nwords != (p + 63) / 64) return hipErrorInvalidValue;
     if (!ws.lcnt || !ws.lK || !ws.lW || !ws.lcmax || !ws.plist || !ws.pcount)
         return hipErrorInvalidValue;
@@ -1733,15 +1734,18 @@ hipError_t launch_cov_screen(const Csr& A, int64_t p, int sstore, const double* 
     hipLaunchKernelGGL(screen_rows_kernel, dim3(T), dim3(64), (size_t)T * 8, stream, A.rowptr,
                        A.col, A.val, p, T, ws.lcnt, ws.lK, ws.lW, ws.lcmax, gate);
     const unsigned pb = (unsigned)((nt + NT - 1) / NT);
+    const int keep_all = screen ? 0 : 1;
     if (sstore == ST_F64)
         hipLaunchKernelGGL(screen_pairs_kernel<double>, dim3(pb), dim3(NT), 0, stream, T, ws.lcnt,
-                           ws.lK, ws.lW, ws.lcmax, smax, lam1, ws.plist, ws.pcount, gate);
+                           ws.lK, ws.lW, ws.lcmax, smax, lam1, ws.plist, ws.pcount, gate, keep_all);
     else
         hipLaunchKernelGGL(screen_pairs_kernel<float>, dim3(pb), dim3(NT), 0, stream, T, ws.lcnt,
-                           ws.lK, ws.lW, ws.lcmax, smax, lam1, ws.plist, ws.pcount, gate);
-    const int64_t nw = p * nwords;
-    const unsigned zb = (unsigned)std::min<int64_t>((nw + NT - 1) / NT, 8192);
-    hipLaunchKernelGGL(zero_words_kernel, dim3(zb), dim3(NT), 0, stream, tbits, nw, gate);
+                           ws.lK, ws.lW, ws.lcmax, smax, lam1, ws.plist, ws.pcount, gate, keep_all);
+    if (screen) {   // without screening every pair writes its own words
+        const int64_t nw = p * nwords;
+        const unsigned zb = (unsigned)std::min<int64_t>((nw + NT - 1) / NT, 8192);
+        hipLaunchKernelGGL(zero_words_kernel, dim3(zb), dim3(NT), 0, stream, tbits, nw, gate);
+    }
     return hipGetLastError();
 }
 
@@ -1750,7 +1754,7 @@ hipError_t launch_cov_refresh_pairs(const Csr& A, int64_t p, const void* S, int 
                                     uint64_t* tbits, int64_t nwords, const RefreshWs& ws,
                                     const int* gate, hipStream_t stream,
                                     unsigned long long* active) {
-    if (!tbits || !smax || nwords != (p + 63) / 64 || lds < nwords * 64 || !ws.plist || !ws.pcount)
+    if (!tbits || nwords != (p + 63) / 64 || lds < nwords * 64 || !ws.plist || !ws.pcount)
         return hipErrorInvalidValue;
     const int T = (int)((p + 63) / 64);
     const int64_t nt = (int64_t)T * (T + 1) / 2;
@@ -1772,11 +1776,12 @@ hipError_t launch_cov_refresh_pairs(const Csr& A, int64_t p, const void* S, int 
 hipError_t launch_cov_refresh(const Csr& A, int64_t p, const void* S, int sstore, int64_t lds,
                               const double* smax, double lam1, uint64_t* tbits, int64_t nwords,
                               const RefreshWs& ws, const int* gate, hipStream_t stream,
-                              unsigned long long* active) {
-    hipError_t e = launch_cov_screen(A, p, sstore, smax, lam1, tbits, nwords, ws, gate, stream);
+                              unsigned long long* active, bool screen) {
+    hipError_t e = launch_cov_screen(A, p, sstore, smax, lam1, tbits, nwords, ws, gate, stream,
+                                     screen);
     if (e != hipSuccess) return e;
-    return launch_cov_refresh_pairs(A, p, S, sstore, lds, smax, lam1, tbits, nwords, ws, gate,
-                                    stream, active);
+    return launch_cov_refresh_pairs(A, p, S, sstore, lds, screen ? smax : nullptr, lam1, tbits,
+                                    nwords, ws, gate, stream, active);
 }
 
 hipError_t launch_tile_max(const void* S, int sstore, int64_t p, int64_t lds, double* out,

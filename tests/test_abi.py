@@ -57,7 +57,8 @@ def test_config_defaults(lib):
     cfg = _lib.concord_config_init()
     assert (cfg.variant, cfg.precision, cfg.device) == (_lib.COV, _lib.FP64, -1)
     assert (cfg.max_backtracks, cfg.trial_batch) == (60, 8)
-    assert ctypes.sizeof(_lib.concord_config) == 48
+    assert ctypes.sizeof(_lib.concord_config) == 56
+    assert cfg.no_screen == 0
 
 
 @pytest.mark.parametrize("field,value", [("p", 0), ("variant", 7), ("precision", 9),
