@@ -566,25 +566,36 @@ trial_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
             for (int q = 0; q < MAXQ; ++q)
 #pragma unroll
                 for (int t = 0; t < V; ++t) acc[q][t] = 0;
-            for (int64_t k = s; k < e; ++k) {
-                const int64_t j = acol[k];
-                const double om = aom[k], g = agr[k];
-                const bool diag = j == row;
-                T b[V];
-                if (act) Ch::load(B, j * ldb + c, b);
-                else {
+            // entries in groups of 4: the group's row loads are issued before its FMAs
+            // (one memory latency per group instead of per entry); same FMA order
+            constexpr int EG = 4;
+            for (int64_t k0 = s; k0 < e; k0 += EG) {
+                T b[EG][V];
 #pragma unroll
-                    for (int t = 0; t < V; ++t) b[t] = 0;
-                }
-                double tau = tau0;
+                for (int u = 0; u < EG; ++u) {
+                    const int64_t k = k0 + u;
+                    if (act && k < e) Ch::load(B, (int64_t)acol[k] * ldb + c, b[u]);
+                    else {
 #pragma unroll
-                for (int q = 0; q < MAXQ; ++q) {
-                    if (q < m) {
-                        const T d = (T)(prox_one(om, g, tau, tau * lam1, diag) - om);
-#pragma unroll
-                        for (int t = 0; t < V; ++t) acc[q][t] = fma(d, b[t], acc[q][t]);
+                        for (int t = 0; t < V; ++t) b[u][t] = 0;
                     }
-                    tau *= 0.5;
+                }
+#pragma unroll
+                for (int u = 0; u < EG; ++u) {
+                    const int64_t k = k0 + u;
+                    if (k >= e) break;
+                    const double om = aom[k], g = agr[k];
+                    const bool diag = acol[k] == row;
+                    double tau = tau0;
+#pragma unroll
+                    for (int q = 0; q < MAXQ; ++q) {
+                        if (q < m) {
+                            const T d = (T)(prox_one(om, g, tau, tau * lam1, diag) - om);
+#pragma unroll
+                            for (int t = 0; t < V; ++t) acc[q][t] = fma(d, b[u][t], acc[q][t]);
+                        }
+                        tau *= 0.5;
+                    }
                 }
             }
 #pragma unroll
@@ -1249,20 +1260,20 @@ tile_max_kernel(const void* __restrict__ S, int64_t p, int64_t lds, int T, doubl
 __global__ void __launch_bounds__(NT)
 cand_merge_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col, int64_t p,
                   uint64_t* __restrict__ bitmap, int64_t nwords, int64_t* __restrict__ cnt) {
-    extern __shared__ uint32_t sbits[];
-    const int64_t nw32 = nwords * 2;
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
     if (row >= p) return;
-    uint32_t* bits = sbits + wave * nw32;
-    build_supp_bits(bits, nw32, col, rowptr[row], rowptr[row + 1]);
-    int64_t total = 0;
-    for (int64_t w = lane; w < nwords; w += 64) {
-        const uint64_t supp = (uint64_t)bits[2 * w] | ((uint64_t)bits[2 * w + 1] << 32);
-        const uint64_t word = bitmap[row * nwords + w] | supp;
-        bitmap[row * nwords + w] = word;
-        total += __popcll(word);
+    uint64_t* rw = bitmap + row * nwords;
+    // the support bits go in by atomic OR on the few words they touch (the row's other
+    // words are only read); the count reads after every OR has completed (the line is
+    // in no L1: this kernel reads the row only after its ORs)
+    for (int64_t k = rowptr[row] + lane; k < rowptr[row + 1]; k += 64) {
+        const int32_t c = col[k];
+        atomicOr((unsigned long long*)&rw[c >> 6], 1ull << (c & 63));
     }
+    __builtin_amdgcn_s_waitcnt(0);
+    int64_t total = 0;
+    for (int64_t w = lane; w < nwords; w += 64) total += __popcll(rw[w]);
     double tt = (double)total;
     tt = wave_sum(tt);
     if (lane == 0) cnt[row] = (int64_t)tt;
@@ -1557,8 +1568,7 @@ hipError_t launch_cand_count(const void* M, int mstore, int64_t ldm, const Csr& 
 hipError_t launch_cand_merge(const Csr& om, int64_t p, uint64_t* bitmap, int64_t nwords,
                              int64_t* cnt, hipStream_t stream) {
     if (p == 0) return hipSuccess;
-    const size_t lds = (size_t)WPB * nwords * 8;
-    hipLaunchKernelGGL(cand_merge_kernel, dim3(blocks_for(p, WPB)), dim3(NT), lds, stream,
+    hipLaunchKernelGGL(cand_merge_kernel, dim3(blocks_for(p, WPB)), dim3(NT), 0, stream,
                        om.rowptr, om.col, p, bitmap, nwords, cnt);
     return hipGetLastError();
 }
