@@ -95,7 +95,8 @@ typedef struct concord_config {
                                one captured HIP graph; 0 (default): direct launches */
     int32_t no_screen;      /* Cov: 1 = the refresh forms every tile pair of M (the plain
                                product of Algorithm 2); 0 (default) = exact tile screening
-                               (see concord_refresh_screen_stats).  Same results. */
+                               (see concord_refresh_screen_stats) when p > 448 (smaller
+                               problems refresh every pair).  Same results either way. */
     int32_t reserved;       /* set to 0 */
 } concord_config;
 

@@ -302,6 +302,11 @@ int ensure_dense(concord_ctx* c) {
     return CONCORD_OK;
 }
 
+// Screening pays for its three launches only with enough tile pairs: below 8 tile rows
+// (p <= 448, at most 36 pairs) the steps refresh every pair.  (The screening statistics
+// entry point always screens when the handle does.)
+bool screen_now(const concord_ctx* c) { return c->screen && (c->p + 63) / 64 >= 8; }
+
 // Products and objective sums at om[which], gated on `gate` (device int).  Cov: the
 // objective gathers M on the support; with bits_lam1 >= 0 the refresh writes the
 // candidate threshold words of om[which] for that lambda1.
@@ -329,13 +334,14 @@ int products_at(concord_ctx* c, int which, const int* gate, double bits_lam1 = -
     } else {
         if (bits_lam1 >= 0.0) {
             // the refresh kernel alone gets its own timing class
+            const bool scr = screen_now(c);
             HIPCK(c, launch_cov_screen(O, p, c->sstore, c->smax, bits_lam1, c->bitmap, c->nwords,
-                                       c->rws, gate, c->stream, c->screen));
+                                       c->rws, gate, c->stream, scr));
             prof_end(c);
             prof_begin(c, CONCORD_PROF_REFRESH);
-            HIPCK(c, launch_cov_refresh_pairs(O, p, c->S, c->sstore, c->ldp,
-                                              c->screen ? c->smax : nullptr, bits_lam1, c->bitmap,
-                                              c->nwords, c->rws, gate, c->stream));
+            HIPCK(c, launch_cov_refresh_pairs(O, p, c->S, c->sstore, c->ldp, scr ? c->smax : nullptr,
+                                              bits_lam1, c->bitmap, c->nwords, c->rws, gate,
+                                              c->stream));
             prof_end(c);
             prof_begin(c, CONCORD_PROF_SPMM);
         }
@@ -445,7 +451,7 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
         if (cov && !merge)
             HIPCK(c, launch_cov_refresh(c->om[c->cur], p, c->S, c->sstore, c->ldp, c->smax, lam1,
                                         c->bitmap, c->nwords, c->rws, c->d_one, c->stream,
-                                        nullptr, c->screen));
+                                        nullptr, screen_now(c)));
         if (merge || cov)
             HIPCK(c, launch_cand_merge(c->om[c->cur], p, c->bitmap, c->nwords, c->cnt, c->stream));
         else

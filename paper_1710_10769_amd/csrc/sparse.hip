@@ -1102,9 +1102,13 @@ cov_refresh_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict
                    unsigned long long* __restrict__ active, const int* __restrict__ plist,
                    const int* __restrict__ pcount) {
     if (gate && *gate == 0) return;
-    const int n = __builtin_amdgcn_readfirstlane(*pcount);
-    if ((int)blockIdx.x >= n) return;
-    const int2 ij = refresh_tile(plist[blockIdx.x], T, T * (T + 1) / 2);
+    int t = blockIdx.x;   // without a list: every pair in the refresh's order
+    if (plist) {
+        const int n = __builtin_amdgcn_readfirstlane(*pcount);
+        if (t >= n) return;
+        t = plist[t];
+    }
+    const int2 ij = refresh_tile(t, T, T * (T + 1) / 2);
     const int I = __builtin_amdgcn_readfirstlane(ij.x);
     const int J = __builtin_amdgcn_readfirstlane(ij.y);
     refresh_pair<BS>(I, J, rowptr, col, val, p, S, lds, smax, T, lam1, tbits, nwords, active);
@@ -1118,10 +1122,11 @@ __global__ void __launch_bounds__(64)
 screen_rows_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                    const double* __restrict__ val, int64_t p, int T, int* __restrict__ lcnt,
                    int* __restrict__ lK, double* __restrict__ lW, int* __restrict__ lcmax,
-                   const int* gate) {
+                   int* __restrict__ pcount, const int* gate) {
     if (gate && *gate == 0) return;
     extern __shared__ unsigned long long wk[];   // T weights (bits of non-negative doubles)
     const int I = blockIdx.x, lane = threadIdx.x;
+    if (I == 0 && lane == 0) *pcount = 0;   // the pair kernel (next launch) appends from 0
     for (int k = lane; k < T; k += 64) wk[k] = 0ull;
     __syncthreads();
     const int64_t row = (int64_t)I * 64 + lane;
@@ -1177,7 +1182,7 @@ __global__ void __launch_bounds__(NT)
 screen_pairs_kernel(int T, const int* __restrict__ lcnt, const int* __restrict__ lK,
                     const double* __restrict__ lW, const int* __restrict__ lcmax,
                     const double* __restrict__ smax, double lam1, int* __restrict__ plist,
-                    int* __restrict__ pcount, const int* gate, int keep_all) {
+                    int* __restrict__ pcount, const int* gate) {
     if (gate && *gate == 0) return;
     __shared__ int wsum[WPB];
     __shared__ int bbase;
@@ -1188,7 +1193,7 @@ screen_pairs_kernel(int T, const int* __restrict__ lcnt, const int* __restrict__
         const int2 ij = refresh_tile(t, T, nt);
         const int I = ij.x, J = ij.y;
         const int cI = lcnt[I], cJ = lcnt[J];
-        if (keep_all || I == J || cI > SCREEN_L || cJ > SCREEN_L) {
+        if (I == J || cI > SCREEN_L || cJ > SCREEN_L) {
             keep = true;
         } else {
             double bw = 0.0, bv = 0.0;
@@ -1597,7 +1602,8 @@ hipError_t launch_scan(const int64_t* cnt, int64_t p, int64_t* out, int64_t cap,
         return hipGetLastError();
     }
     const unsigned nb = (unsigned)((p + SCAN_CHUNK - 1) / SCAN_CHUNK);
-    hipLaunchKernelGGL(scan_part_kernel, dim3(nb), dim3(NT), 0, stream, cnt, p, ws);
+    if (nb > 1)   // one chunk needs no chunk sums
+        hipLaunchKernelGGL(scan_part_kernel, dim3(nb), dim3(NT), 0, stream, cnt, p, ws);
     hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(NT), 0, stream, cnt, p, ws, out, cap,
                        overflow);
     return hipGetLastError();
@@ -1726,10 +1732,6 @@ hipError_t launch_identity(const Csr& om, int64_t p, hipStream_t stream) {
     return hipGetLastError();
 }
 
-__global__ void reset_count_kernel(int* c) {
-    if (threadIdx.x == 0) *c = 0;
-}
-
 hipError_t launch_cov_screen(const Csr& A, int64_t p, int sstore, const double* smax,
                              double lam1, uint64_t* tbits, int64_t nwords, const RefreshWs& ws,
                              const int* gate, hipStream_t stream, bool screen) {
@@ -1740,22 +1742,19 @@ hipError_t launch_cov_screen(const Csr& A, int64_t p, int sstore, const double* 
     const int64_t nt = (int64_t)T * (T + 1) / 2;
     if (nt == 0) return hipSuccess;
     if (nt > INT32_MAX || (size_t)T * 8 > 64 * 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(reset_count_kernel, dim3(1), dim3(64), 0, stream, ws.pcount);
+    if (!screen) return hipSuccess;   // the refresh then runs every pair without a list
     hipLaunchKernelGGL(screen_rows_kernel, dim3(T), dim3(64), (size_t)T * 8, stream, A.rowptr,
-                       A.col, A.val, p, T, ws.lcnt, ws.lK, ws.lW, ws.lcmax, gate);
+                       A.col, A.val, p, T, ws.lcnt, ws.lK, ws.lW, ws.lcmax, ws.pcount, gate);
     const unsigned pb = (unsigned)((nt + NT - 1) / NT);
-    const int keep_all = screen ? 0 : 1;
     if (sstore == ST_F64)
         hipLaunchKernelGGL(screen_pairs_kernel<double>, dim3(pb), dim3(NT), 0, stream, T, ws.lcnt,
-                           ws.lK, ws.lW, ws.lcmax, smax, lam1, ws.plist, ws.pcount, gate, keep_all);
+                           ws.lK, ws.lW, ws.lcmax, smax, lam1, ws.plist, ws.pcount, gate);
     else
         hipLaunchKernelGGL(screen_pairs_kernel<float>, dim3(pb), dim3(NT), 0, stream, T, ws.lcnt,
-                           ws.lK, ws.lW, ws.lcmax, smax, lam1, ws.plist, ws.pcount, gate, keep_all);
-    if (screen) {   // without screening every pair writes its own words
-        const int64_t nw = p * nwords;
-        const unsigned zb = (unsigned)std::min<int64_t>((nw + NT - 1) / NT, 8192);
-        hipLaunchKernelGGL(zero_words_kernel, dim3(zb), dim3(NT), 0, stream, tbits, nw, gate);
-    }
+                           ws.lK, ws.lW, ws.lcmax, smax, lam1, ws.plist, ws.pcount, gate);
+    const int64_t nw = p * nwords;
+    const unsigned zb = (unsigned)std::min<int64_t>((nw + NT - 1) / NT, 8192);
+    hipLaunchKernelGGL(zero_words_kernel, dim3(zb), dim3(NT), 0, stream, tbits, nw, gate);
     return hipGetLastError();
 }
 
@@ -1771,10 +1770,12 @@ hipError_t launch_cov_refresh_pairs(const Csr& A, int64_t p, const void* S, int 
     if (nt == 0) return hipSuccess;
     if (nt > INT32_MAX) return hipErrorInvalidValue;
     const unsigned g = (unsigned)nt;
+    // smax null: no screening, every pair in order without the list
+    const int* pl = smax ? ws.plist : nullptr;
 #define REFRESH(BS)                                                                      \
     hipLaunchKernelGGL((cov_refresh_kernel<BS>), dim3(g), dim3(NT), 0, stream, A.rowptr,   \
                        A.col, A.val, p, S, lds, smax, T, lam1, tbits, nwords, gate, active, \
-                       ws.plist, ws.pcount)
+                       pl, ws.pcount)
     if (sstore == ST_F64) REFRESH(ST_F64);
     else if (sstore == ST_F32) REFRESH(ST_F32);
     else if (sstore == ST_B16P) REFRESH(ST_B16P);
