@@ -401,6 +401,10 @@ class Solver:
     def iterations(self) -> int:
         return concord_iterations(self._h)
 
+    def nnz(self) -> int:
+        """Stored entries of the current iterate."""
+        return concord_get_omega(self._h)
+
     def get_omega(self, dtype=None):
         """Current iterate as CUDA tensors (rowptr int64, col int32, val)."""
         torch = _torch()
