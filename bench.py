@@ -86,7 +86,11 @@ def run_form(torch, X32, p, n, lam1, lam2, form, steps, warmup):
         "contraction_variant": variant,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[form],
                      "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[form],
-                     "traffic": stored_traffic(form, variant)},
+                     "traffic": stored_traffic(form, variant),
+                     # the BF16 split runs three BF16 products (hi*hi, hi*lo, lo*hi) per
+                     # useful flop: the rate the matrix cores actually execute
+                     "executed_per_useful_flop": 3 if form == "bf16x3" else 1,
+                     "frac_executed": achieved * (3 if form == "bf16x3" else 1) / PEAK_TFLOPS[form]},
         "trials_per_step": sum(i.n_trials for i in infos) / steps,
         "final_F": infos[-1].F,
         "final_nnz": infos[-1].nnz,

@@ -301,6 +301,7 @@ def test_contraction_variant_reports_tuned_choice(variant, precision):
     ("cov", "fp64", 0.3, 200, 100),      # the C1 shape
     ("obs", "bf16x3", 0.12, 700, 300),
     ("cov", "fp32", 0.01, 300, 120),     # dense candidate sets: capacity regrowth under graphs
+    ("cov", "bf16x3", 0.12, 700, 300),   # screened refresh (p > 448) inside the captured graph
 ])
 def test_graph_replay_matches_direct_launches(variant, precision, lam1, p, n):
     torch = _torch()
