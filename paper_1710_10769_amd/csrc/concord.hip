@@ -114,7 +114,6 @@ struct concord_ctx {
     int64_t* scan_ws = nullptr;  // chunk sums of launch_scan
     DevState* st = nullptr;
     DevState* st_host = nullptr; // pinned
-    int64_t* h_stage = nullptr;  // pinned, 4 int64
     int* d_one = nullptr;
     int* d_flags = nullptr;      // 8 ints
 
@@ -458,7 +457,7 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
             HIPCK(c, launch_cand_count(c->M, c->dstore, c->ldp, c->om[c->cur], p, lam1,
                                        c->bitmap, c->nwords, c->cnt, c->stream));
         HIPCK(c, launch_scan(c->cnt, p, c->A.rowptr, c->a_cap, &c->st->overflow, c->scan_ws,
-                             c->stream));
+                             c->stream, &c->st->n_cand));
         HIPCK(c, launch_cand_fill(cov ? nullptr : c->M, c->dstore, c->ldp, c->om[c->cur], p, lam2,
                                   c->bitmap, c->nwords, c->A, c->a_cap, &c->st->overflow,
                                   c->stream));
@@ -483,16 +482,12 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
         prof_begin(c, CONCORD_PROF_EMIT);
         HIPCK(c, launch_emit_count(c->A, p, lam1, c->st, c->cnt, c->stream));
         HIPCK(c, launch_scan(c->cnt, p, c->om[nxt].rowptr, c->om_cap[nxt], nullptr, c->scan_ws,
-                             c->stream));
+                             c->stream, &c->st->nnz_next));
         HIPCK(c, launch_emit_fill(c->A, p, lam1, c->st, c->om[nxt], c->stream));
         prof_end(c);
         int rc2 = products_at(c, nxt, &c->st->accepted,
                               c->variant == CONCORD_COV ? lam1 : -1.0);
         if (rc2) return rc2;
-        HIPCK(c, hipMemcpyAsync(c->h_stage, c->om[nxt].rowptr + p, sizeof(int64_t),
-                                hipMemcpyDeviceToHost, c->stream));
-        HIPCK(c, hipMemcpyAsync(c->h_stage + 1, c->A.rowptr + p, sizeof(int64_t),
-                                hipMemcpyDeviceToHost, c->stream));
         HIPCK(c, hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost,
                                 c->stream));
         return CONCORD_OK;
@@ -565,7 +560,7 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
             q_base += m;
         }
         if (overflow) {
-            const int64_t need = c->h_stage[1];
+            const int64_t need = c->st_host->n_cand;
             if ((rc = ensure_cand_cap(c, need + need / 2 + 1024))) return rc;
             continue;
         }
@@ -582,7 +577,7 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
                         "line search exhausted max_backtracks; iterate unchanged");
         const DevState& s = *c->st_host;
         c->cur = nxt;
-        c->nnz = c->h_stage[0];
+        c->nnz = c->st_host->nnz_next;
         c->k += 1;
         for (int i = 0; i < 5; ++i) c->obj[i] = s.obj[i];
         c->prod_valid = true;
@@ -594,7 +589,7 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
             objective_from(c, c->obj, lam1, lam2, &info->f, &info->F);
             info->nnz = c->nnz;
             info->delta_fro = std::sqrt(s.dd);
-            info->n_candidates = c->h_stage[1];
+            info->n_candidates = c->st_host->n_cand;
             info->lhs = s.lhs;
             info->rhs = s.rhs;
         }
@@ -674,7 +669,6 @@ void concord_destroy(concord_ctx* ctx) {
         for (void* a : ctx->allocs)
             if (a) hipFree(a);
         if (ctx->st_host) hipHostFree(ctx->st_host);
-        if (ctx->h_stage) hipHostFree(ctx->h_stage);
     }
     delete ctx;
 }
@@ -782,8 +776,6 @@ int concord_create(const concord_config* cfg, concord_ctx** out) {
     if ((rc = dalloc_t(c, &c->d_flags, 8, true))) return bail(rc);
     hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, c->stream, c->d_one, 1);
     if (hipHostMalloc((void**)&c->st_host, sizeof(DevState), hipHostMallocDefault) != hipSuccess)
-        return bail(CONCORD_ENOMEM);
-    if (hipHostMalloc((void**)&c->h_stage, 4 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
         return bail(CONCORD_ENOMEM);
     if ((rc = set_identity(c))) return bail(rc);
     if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(CONCORD_EHIP);

@@ -138,10 +138,11 @@ hipError_t launch_cand_grad_cov(const Csr& om, int64_t p, const void* S, int sst
                                 hipStream_t stream);
 
 // Exclusive scan of cnt[0..p) into out[0..p] (out[p] = total); sets
-// *overflow = 1 if total > cap (overflow may be null).  Two launches (chunk sums into
+// *overflow = 1 if total > cap (overflow may be null), and copies the total to
+// *total_out (may be null).  Two launches (chunk sums into
 // ws, scan_ws_len(p) int64, then per-chunk scans); integer, so deterministic.
 hipError_t launch_scan(const int64_t* cnt, int64_t p, int64_t* out, int64_t cap, int* overflow,
-                       int64_t* ws, hipStream_t stream);
+                       int64_t* ws, hipStream_t stream, int64_t* total_out = nullptr);
 // int64 workspace length launch_scan needs for p rows.
 int64_t scan_ws_len(int64_t p);
 
@@ -252,6 +253,8 @@ struct DevState {
     double obj[5];          // objective sums at the last evaluated iterate:
                             // log-diagonal, sum of squares, off-diagonal |.|,
                             // sum W o Omega (Cov), ||Y||^2 (Obs)
+    int64_t n_cand;         // |A| of the last candidate pass (its scan's total)
+    int64_t nnz_next;       // stored entries of the emitted iterate (its scan's total)
     int accepted_q;         // -1: none passed yet in this iteration
     int accepted;           // 1 once a step is accepted (gate of the accept kernels)
     int nonpos;             // forced step leaves the domain

@@ -400,31 +400,6 @@ cand_grad_cov_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restri
 }
 
 // ---- scan ---------------------------------------------------------------------
-__global__ void __launch_bounds__(1024)
-scan_kernel(const int64_t* __restrict__ cnt, int64_t p, int64_t* __restrict__ out, int64_t cap,
-            int* overflow) {
-    __shared__ int64_t part[1024];
-    const int t = threadIdx.x;
-    const int64_t per = (p + 1023) / 1024;
-    const int64_t a = t * per, b = a + per < p ? a + per : p;
-    int64_t s = 0;
-    for (int64_t i = a; i < b; ++i) s += cnt[i];
-    part[t] = s;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        int64_t v = t >= o ? part[t - o] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    int64_t run = part[t] - s;
-    for (int64_t i = a; i < b; ++i) { out[i] = run; run += cnt[i]; }
-    if (t == 1023) {
-        out[p] = part[1023];
-        if (overflow) *overflow = part[1023] > cap ? 1 : 0;
-    }
-}
-
 // Two-kernel exclusive scan: chunk sums, then each chunk adds the sums before it and
 // scans itself.  Integer sums, so the result does not depend on the split.
 constexpr int SCAN_CHUNK = 2048;   // 8 per thread
@@ -457,7 +432,7 @@ scan_part_kernel(const int64_t* __restrict__ cnt, int64_t p, int64_t* __restrict
 
 __global__ void __launch_bounds__(NT)
 scan_apply_kernel(const int64_t* __restrict__ cnt, int64_t p, const int64_t* __restrict__ part,
-                  int64_t* __restrict__ out, int64_t cap, int* overflow) {
+                  int64_t* __restrict__ out, int64_t cap, int* overflow, int64_t* total_out) {
     __shared__ int64_t red[WPB];
     __shared__ int64_t wtot[WPB];
     const int64_t b = blockIdx.x;
@@ -499,6 +474,7 @@ scan_apply_kernel(const int64_t* __restrict__ cnt, int64_t p, const int64_t* __r
         const int64_t total = off + btotal;
         out[p] = total;
         if (overflow) *overflow = total > cap ? 1 : 0;
+        if (total_out) *total_out = total;
     }
 }
 
@@ -1596,16 +1572,13 @@ hipError_t launch_cand_fill(const void* M, int mstore, int64_t ldm, const Csr& o
 }
 
 hipError_t launch_scan(const int64_t* cnt, int64_t p, int64_t* out, int64_t cap, int* overflow,
-                       int64_t* ws, hipStream_t stream) {
-    if (p == 0) {
-        hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, stream, cnt, p, out, cap, overflow);
-        return hipGetLastError();
-    }
+                       int64_t* ws, hipStream_t stream, int64_t* total_out) {
+    if (p == 0) return hipErrorInvalidValue;   // every handle has p >= 1
     const unsigned nb = (unsigned)((p + SCAN_CHUNK - 1) / SCAN_CHUNK);
     if (nb > 1)   // one chunk needs no chunk sums
         hipLaunchKernelGGL(scan_part_kernel, dim3(nb), dim3(NT), 0, stream, cnt, p, ws);
     hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(NT), 0, stream, cnt, p, ws, out, cap,
-                       overflow);
+                       overflow, total_out);
     return hipGetLastError();
 }
 
