@@ -201,7 +201,8 @@ int concord_solve(concord_ctx* ctx, double lambda1, double lambda2, double tol, 
    skipped pairs' candidate words are provably empty, so results are unchanged.
    This call runs the refresh once at the current iterate for lambda1 and writes the
    number of tile pairs, T (T + 1) / 2 with T = ceil(p / 64), and the number that
-   loaded S (diagonal pairs always do).  Host pointers; either may be NULL.
+   loaded S (diagonal pairs always do; with no_screen set, or p <= 448, every pair
+   does).  Host pointers; either may be NULL.
    Errors: EINVAL (null handle, Obs handle, lambda1 < 0), ENODATA, ENOMEM, EHIP. */
 int concord_refresh_screen_stats(concord_ctx* ctx, double lambda1, int64_t* host_pairs,
                                  int64_t* host_active);

@@ -302,8 +302,7 @@ int ensure_dense(concord_ctx* c) {
 }
 
 // Screening pays for its three launches only with enough tile pairs: below 8 tile rows
-// (p <= 448, at most 36 pairs) the steps refresh every pair.  (The screening statistics
-// entry point always screens when the handle does.)
+// (p <= 448, at most 36 pairs) every refresh covers every pair.
 bool screen_now(const concord_ctx* c) { return c->screen && (c->p + 63) / 64 >= 8; }
 
 // Products and objective sums at om[which], gated on `gate` (device int).  Cov: the
@@ -451,8 +450,12 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
             HIPCK(c, launch_cov_refresh(c->om[c->cur], p, c->S, c->sstore, c->ldp, c->smax, lam1,
                                         c->bitmap, c->nwords, c->rws, c->d_one, c->stream,
                                         nullptr, screen_now(c)));
+        // the screened refresh leaves the words of screened-out tiles stale: merge and fill
+        // read only kept tiles and support words
+        const uint64_t* tm = cov && screen_now(c) ? c->rws.tmask : nullptr;
         if (merge || cov)
-            HIPCK(c, launch_cand_merge(c->om[c->cur], p, c->bitmap, c->nwords, c->cnt, c->stream));
+            HIPCK(c, launch_cand_merge(c->om[c->cur], p, c->bitmap, c->nwords, c->cnt, c->stream,
+                                       tm));
         else
             HIPCK(c, launch_cand_count(c->M, c->dstore, c->ldp, c->om[c->cur], p, lam1,
                                        c->bitmap, c->nwords, c->cnt, c->stream));
@@ -460,7 +463,7 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
                              c->stream, &c->st->n_cand));
         HIPCK(c, launch_cand_fill(cov ? nullptr : c->M, c->dstore, c->ldp, c->om[c->cur], p, lam2,
                                   c->bitmap, c->nwords, c->A, c->a_cap, &c->st->overflow,
-                                  c->stream));
+                                  c->stream, tm));
         if (cov)
             HIPCK(c, launch_cand_grad_cov(c->om[c->cur], p, c->S, c->sstore, c->ldp, lam2, c->A,
                                           &c->st->overflow, c->stream));
@@ -753,7 +756,8 @@ int concord_create(const concord_config* cfg, concord_ctx** out) {
         if ((rc = dalloc_t(c, &r.lcnt, (size_t)T, true)) || (rc = dalloc_t(c, &r.lK, (size_t)T * 64, true)) ||
             (rc = dalloc_t(c, &r.lW, (size_t)T * 64, true)) || (rc = dalloc_t(c, &r.lcmax, (size_t)T, true)) ||
             (rc = dalloc_t(c, &r.plist, (size_t)(T * (T + 1) / 2), true)) ||
-            (rc = dalloc_t(c, &r.pcount, 1, true)))
+            (rc = dalloc_t(c, &r.pcount, 1, true)) ||
+            (rc = dalloc_t(c, &r.tmask, (size_t)(T * ((T + 63) / 64)), true)))
             return bail(rc);
     }
     for (int w = 0; w < 2; ++w)
@@ -936,7 +940,7 @@ int concord_refresh_screen_stats(concord_ctx* c, double lam1, int64_t* host_pair
     hipLaunchKernelGGL(set_u64_kernel, dim3(1), dim3(64), 0, c->stream, c->d_active, 0ull);
     HIPCK(c, launch_cov_refresh(c->om[c->cur], c->p, c->S, c->sstore, c->ldp, c->smax, lam1,
                                 c->bitmap, c->nwords, c->rws, c->d_one, c->stream, c->d_active,
-                                c->screen));
+                                screen_now(c)));
     unsigned long long act = 0;
     HIPCK(c, hipMemcpyAsync(&act, c->d_active, sizeof(act), hipMemcpyDeviceToHost, c->stream));
     HIPCK(c, hipStreamSynchronize(c->stream));

@@ -114,8 +114,11 @@ struct Cand {
 // Candidate bitmap and counts from threshold words written by launch_cov_refresh for
 // the same iterate and lambda1: ORs supp(Omega_i) into row i's words (in place) and
 // writes cnt[i] = |A_i|; the result equals launch_cand_count's.
+// With tmask (the kept-tile bits of a screened Cov refresh, T x ceil(T/64) uint64) only
+// the words of kept tiles and the support's words are read; words outside both are stale
+// and never read.
 hipError_t launch_cand_merge(const Csr& om, int64_t p, uint64_t* bitmap, int64_t nwords,
-                             int64_t* cnt, hipStream_t stream);
+                             int64_t* cnt, hipStream_t stream, const uint64_t* tmask = nullptr);
 
 // Count pass: for every row, A_i = {j != i : |M_ij| > lam1} U supp(Omega_i) U {i}.
 // Writes the candidate bitmap (p x nwords64 uint64, row-major, word w bit b
@@ -129,7 +132,7 @@ hipError_t launch_cand_count(const void* M, int mstore, int64_t ldm, const Csr& 
 hipError_t launch_cand_fill(const void* M, int mstore, int64_t ldm, const Csr& om, int64_t p,
                             double lam2, const uint64_t* bitmap, int64_t nwords,
                             const Cand& A, int64_t cap, const int* overflow,
-                            hipStream_t stream);
+                            hipStream_t stream, const uint64_t* tmask = nullptr);
 
 // Cov form: G on the candidates of A (filled for the same iterate), with M_ij gathered
 // from S and the CSR rows i and j of Omega; bitwise the value the Cov refresh tests.
@@ -207,6 +210,7 @@ struct RefreshWs {
     int* lcmax;     // T
     int* plist;     // T (T + 1) / 2
     int* pcount;    // 1
+    uint64_t* tmask;  // T * ceil(T / 64): bit (I, J) = tile pair {I, J} kept
 };
 hipError_t launch_cov_refresh(const Csr& A, int64_t p, const void* S, int sstore, int64_t lds,
                               const double* smax, double lam1, uint64_t* tbits, int64_t nwords,

@@ -322,20 +322,44 @@ cand_fill_kernel(const void* __restrict__ M, int64_t ldm, const int64_t* __restr
                  const int32_t* __restrict__ col, const double* __restrict__ val, int64_t p,
                  double lam2, const uint64_t* __restrict__ bitmap, int64_t nwords,
                  const int64_t* __restrict__ arow, int32_t* __restrict__ acol,
-                 double* __restrict__ aom, double* __restrict__ agr, const int* overflow) {
+                 double* __restrict__ aom, double* __restrict__ agr, const int* overflow,
+                 const uint64_t* __restrict__ tmask) {
     if (*overflow) return;
     typedef typename Chunk<MS>::T E;
+    extern __shared__ uint64_t swords[];   // with a tile mask: the row's words holding support
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
     if (row >= p) return;
     const int64_t s = rowptr[row], e = rowptr[row + 1];
     int64_t out = arow[row];
     const E* Mrow = M ? (const E*)M + row * ldm : nullptr;
+    // With a tile mask (screened Cov refresh), a word can be nonzero only if its tile pair
+    // was kept or the support of the row has an entry in it: only those words are read.
+    const int64_t TW = (nwords + 63) / 64;
+    const uint64_t* mrow = tmask ? tmask + (row >> 6) * TW : nullptr;
+    uint64_t* sw = swords + wave * TW;   // bit w: the support has an entry in word w
+    if (mrow) {
+        for (int64_t t = lane; t < TW; t += 64) sw[t] = 0ull;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (int64_t k = s + lane; k < e; k += 64) {
+            const int64_t ww = col[k] >> 6;
+            atomicOr((unsigned long long*)&sw[ww >> 6], 1ull << (ww & 63));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     // 64 bitmap words (4096 columns) per step, one per lane; an exclusive prefix of
     // their popcounts places each lane's candidates, so the row stays sorted
     for (int64_t w0 = 0; w0 < nwords; w0 += 64) {
         const int64_t w = w0 + lane;
-        uint64_t word = w < nwords ? bitmap[row * nwords + w] : 0ull;
+        bool need = w < nwords;
+        if (mrow) {
+            const uint64_t mk = mrow[w0 >> 6] | sw[w0 >> 6];
+            need = need && ((mk >> lane) & 1ull);
+        }
+        uint64_t word = need ? bitmap[row * nwords + w] : 0ull;
         const int pc = __popcll(word);
         int incl = pc;
 #pragma unroll
@@ -1098,11 +1122,13 @@ __global__ void __launch_bounds__(64)
 screen_rows_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                    const double* __restrict__ val, int64_t p, int T, int* __restrict__ lcnt,
                    int* __restrict__ lK, double* __restrict__ lW, int* __restrict__ lcmax,
-                   int* __restrict__ pcount, const int* gate) {
+                   int* __restrict__ pcount, uint64_t* __restrict__ tmask, const int* gate) {
     if (gate && *gate == 0) return;
     extern __shared__ unsigned long long wk[];   // T weights (bits of non-negative doubles)
     const int I = blockIdx.x, lane = threadIdx.x;
     if (I == 0 && lane == 0) *pcount = 0;   // the pair kernel (next launch) appends from 0
+    const int TW = (T + 63) / 64;
+    for (int k = lane; k < TW; k += 64) tmask[(int64_t)I * TW + k] = 0ull;   // kept-tile bits
     for (int k = lane; k < T; k += 64) wk[k] = 0ull;
     __syncthreads();
     const int64_t row = (int64_t)I * 64 + lane;
@@ -1158,7 +1184,7 @@ __global__ void __launch_bounds__(NT)
 screen_pairs_kernel(int T, const int* __restrict__ lcnt, const int* __restrict__ lK,
                     const double* __restrict__ lW, const int* __restrict__ lcmax,
                     const double* __restrict__ smax, double lam1, int* __restrict__ plist,
-                    int* __restrict__ pcount, const int* gate) {
+                    int* __restrict__ pcount, uint64_t* __restrict__ tmask, const int* gate) {
     if (gate && *gate == 0) return;
     __shared__ int wsum[WPB];
     __shared__ int bbase;
@@ -1194,15 +1220,15 @@ screen_pairs_kernel(int T, const int* __restrict__ lcnt, const int* __restrict__
     __syncthreads();
     int before = 0;
     for (int v = 0; v < wave; ++v) before += wsum[v];
-    if (keep) plist[bbase + before + __popcll(m & lanemask_lt())] = t;
-}
-
-// Zero words (the screened-out pairs' words stay zero), gated like the refresh.
-__global__ void __launch_bounds__(NT)
-zero_words_kernel(uint64_t* __restrict__ w, int64_t n, const int* gate) {
-    if (gate && *gate == 0) return;
-    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
-        w[i] = 0ull;
+    if (keep) {
+        plist[bbase + before + __popcll(m & lanemask_lt())] = t;
+        // kept-tile bits of both row tiles (the words the refresh writes for this pair)
+        const int2 ij = refresh_tile(t, T, nt);
+        const int TW = (T + 63) / 64;
+        atomicOr((unsigned long long*)&tmask[(int64_t)ij.x * TW + (ij.y >> 6)], 1ull << (ij.y & 63));
+        if (ij.x != ij.y)
+            atomicOr((unsigned long long*)&tmask[(int64_t)ij.y * TW + (ij.x >> 6)], 1ull << (ij.x & 63));
+    }
 }
 
 // Largest |S| of every 64 x 64 tile (as the refresh reads S), for its screening.
@@ -1240,21 +1266,47 @@ tile_max_kernel(const void* __restrict__ S, int64_t p, int64_t lds, int T, doubl
 // instead of the row of M.
 __global__ void __launch_bounds__(NT)
 cand_merge_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col, int64_t p,
-                  uint64_t* __restrict__ bitmap, int64_t nwords, int64_t* __restrict__ cnt) {
+                  uint64_t* __restrict__ bitmap, int64_t nwords, int64_t* __restrict__ cnt,
+                  const uint64_t* __restrict__ tmask) {
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
     if (row >= p) return;
     uint64_t* rw = bitmap + row * nwords;
+    const int64_t s = rowptr[row], e = rowptr[row + 1];
+    // With a tile mask (screened Cov refresh), only the words of kept tile pairs were
+    // written this time; a support word outside them may hold an older refresh's bits,
+    // so it is cleared first (all writers store 0), then the support bits go in.
+    const int64_t TW = (nwords + 63) / 64;
+    const uint64_t* mrow = tmask ? tmask + (row >> 6) * TW : nullptr;
+    auto kept = [&](int64_t w) { return (mrow[w >> 6] >> (w & 63)) & 1ull; };
+    int64_t extra = 0;   // support entries in words outside the kept tiles
+    if (mrow) {
+        for (int64_t k = s + lane; k < e; k += 64) {
+            const int64_t w = col[k] >> 6;
+            if (!kept(w)) {
+                rw[w] = 0ull;
+                ++extra;
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+    }
     // the support bits go in by atomic OR on the few words they touch (the row's other
     // words are only read); the count reads after every OR has completed (the line is
     // in no L1: this kernel reads the row only after its ORs)
-    for (int64_t k = rowptr[row] + lane; k < rowptr[row + 1]; k += 64) {
+    for (int64_t k = s + lane; k < e; k += 64) {
         const int32_t c = col[k];
         atomicOr((unsigned long long*)&rw[c >> 6], 1ull << (c & 63));
     }
     __builtin_amdgcn_s_waitcnt(0);
-    int64_t total = 0;
-    for (int64_t w = lane; w < nwords; w += 64) total += __popcll(rw[w]);
+    int64_t total = extra;   // each such entry is one bit of a word counted nowhere else
+    if (mrow) {
+        for (int64_t w0 = 0; w0 < nwords; w0 += 64) {
+            const int64_t w = w0 + lane;
+            if (w < nwords && ((mrow[w0 >> 6] >> lane) & 1ull)) total += __popcll(rw[w]);
+        }
+    } else {
+        for (int64_t w = lane; w < nwords; w += 64) total += __popcll(rw[w]);
+    }
     double tt = (double)total;
     tt = wave_sum(tt);
     if (lane == 0) cnt[row] = (int64_t)tt;
@@ -1547,27 +1599,28 @@ hipError_t launch_cand_count(const void* M, int mstore, int64_t ldm, const Csr& 
 }
 
 hipError_t launch_cand_merge(const Csr& om, int64_t p, uint64_t* bitmap, int64_t nwords,
-                             int64_t* cnt, hipStream_t stream) {
+                             int64_t* cnt, hipStream_t stream, const uint64_t* tmask) {
     if (p == 0) return hipSuccess;
     hipLaunchKernelGGL(cand_merge_kernel, dim3(blocks_for(p, WPB)), dim3(NT), 0, stream,
-                       om.rowptr, om.col, p, bitmap, nwords, cnt);
+                       om.rowptr, om.col, p, bitmap, nwords, cnt, tmask);
     return hipGetLastError();
 }
 
 hipError_t launch_cand_fill(const void* M, int mstore, int64_t ldm, const Csr& om, int64_t p,
                             double lam2, const uint64_t* bitmap, int64_t nwords,
                             const Cand& A, int64_t cap, const int* overflow,
-                            hipStream_t stream) {
+                            hipStream_t stream, const uint64_t* tmask) {
     (void)cap;
     if (p == 0) return hipSuccess;
+    const size_t lds = tmask ? (size_t)WPB * ((nwords + 63) / 64) * 8 : 0;
     if (mstore == ST_F64)
-        hipLaunchKernelGGL(cand_fill_kernel<ST_F64>, dim3(blocks_for(p, WPB)), dim3(NT), 0,
+        hipLaunchKernelGGL(cand_fill_kernel<ST_F64>, dim3(blocks_for(p, WPB)), dim3(NT), lds,
                            stream, M, ldm, om.rowptr, om.col, om.val, p, lam2, bitmap, nwords,
-                           A.rowptr, A.col, A.omega, A.grad, overflow);
+                           A.rowptr, A.col, A.omega, A.grad, overflow, tmask);
     else
-        hipLaunchKernelGGL(cand_fill_kernel<ST_F32>, dim3(blocks_for(p, WPB)), dim3(NT), 0,
+        hipLaunchKernelGGL(cand_fill_kernel<ST_F32>, dim3(blocks_for(p, WPB)), dim3(NT), lds,
                            stream, M, ldm, om.rowptr, om.col, om.val, p, lam2, bitmap, nwords,
-                           A.rowptr, A.col, A.omega, A.grad, overflow);
+                           A.rowptr, A.col, A.omega, A.grad, overflow, tmask);
     return hipGetLastError();
 }
 
@@ -1717,17 +1770,17 @@ hipError_t launch_cov_screen(const Csr& A, int64_t p, int sstore, const double* 
     if (nt > INT32_MAX || (size_t)T * 8 > 64 * 1024) return hipErrorInvalidValue;
     if (!screen) return hipSuccess;   // the refresh then runs every pair without a list
     hipLaunchKernelGGL(screen_rows_kernel, dim3(T), dim3(64), (size_t)T * 8, stream, A.rowptr,
-                       A.col, A.val, p, T, ws.lcnt, ws.lK, ws.lW, ws.lcmax, ws.pcount, gate);
+                       A.col, A.val, p, T, ws.lcnt, ws.lK, ws.lW, ws.lcmax, ws.pcount, ws.tmask,
+                       gate);
     const unsigned pb = (unsigned)((nt + NT - 1) / NT);
     if (sstore == ST_F64)
         hipLaunchKernelGGL(screen_pairs_kernel<double>, dim3(pb), dim3(NT), 0, stream, T, ws.lcnt,
-                           ws.lK, ws.lW, ws.lcmax, smax, lam1, ws.plist, ws.pcount, gate);
+                           ws.lK, ws.lW, ws.lcmax, smax, lam1, ws.plist, ws.pcount, ws.tmask, gate);
     else
         hipLaunchKernelGGL(screen_pairs_kernel<float>, dim3(pb), dim3(NT), 0, stream, T, ws.lcnt,
-                           ws.lK, ws.lW, ws.lcmax, smax, lam1, ws.plist, ws.pcount, gate);
-    const int64_t nw = p * nwords;
-    const unsigned zb = (unsigned)std::min<int64_t>((nw + NT - 1) / NT, 8192);
-    hipLaunchKernelGGL(zero_words_kernel, dim3(zb), dim3(NT), 0, stream, tbits, nw, gate);
+                           ws.lK, ws.lW, ws.lcmax, smax, lam1, ws.plist, ws.pcount, ws.tmask, gate);
+    // the screened-out pairs' words are not cleared: the candidate merge and fill read only
+    // the words of kept tiles (ws.tmask) and the row's support words
     return hipGetLastError();
 }
 
