@@ -120,11 +120,17 @@ def test_screening_does_not_change_the_solve(precision, source):
             s.set_covariance(data)
         else:
             s.set_data(data)
-        info = s.solve(lam1, lam2, 1e-7, 60)
+        # step by step, with a lambda1 change in the middle: the candidate counts must match
+        # too (stale candidate words of screened-out tiles would show up as extra candidates)
+        seq = [lam1] * 8 + [lam1 * 1.3] * 4 + [lam1] * 4
+        steps = [s.step(l1, lam2) for l1 in seq]
+        info = s.solve(lam1, lam2, 1e-7, 40)
         om = s.get_omega_scipy()
-        out.append((info.iters, info.F, info.nnz, om))
+        out.append(([(i.tau, i.F, i.nnz, i.n_candidates) for i in steps], info.iters, info.F,
+                     info.nnz, om))
         s.close()
-    (i0, F0, z0, o0), (i1, F1, z1, o1) = out
+    (t0, i0, F0, z0, o0), (t1, i1, F1, z1, o1) = out
+    assert t0 == t1
     assert (i0, z0) == (i1, z1)
     assert F0 == F1
     assert np.array_equal(o0.indptr, o1.indptr) and np.array_equal(o0.indices, o1.indices)
