@@ -357,6 +357,7 @@ cand_fill_kernel(const void* __restrict__ M, int64_t ldm, const int64_t* __restr
         bool need = w < nwords;
         if (mrow) {
             const uint64_t mk = mrow[w0 >> 6] | sw[w0 >> 6];
+            if (__builtin_amdgcn_readfirstlane((int)(mk != 0ull)) == 0) continue;   // empty block
             need = need && ((mk >> lane) & 1ull);
         }
         uint64_t word = need ? bitmap[row * nwords + w] : 0ull;
@@ -664,6 +665,104 @@ trial_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
     const double tot = v[0] + __shfl_xor(v[0], 1, 64);
     const int k = lane >> 1, q = k >> 2, t = k & 3;
     if ((lane & 1) == 0 && q < m) part[((int64_t)(q * 4 + t) * nsplit + split) * p + row] = tot;
+}
+
+// Cov trials with 8 lanes per row (8 rows per wave): a Cov candidate row holds a few
+// entries, so a whole wave per row would leave most lanes idle.  Same terms as
+// trial_kernel's Cov path; the 32 partials are reduced over the row's 8 lanes by a
+// reduce-scatter (16 + 8 + 4 shuffles), after which lane g of the group holds the four
+// sums of step size q = g.
+constexpr int TG = 8;
+constexpr int64_t COV_GROUP_MIN_P = 4096;
+template <int BS>
+__global__ void __launch_bounds__(NT)
+trial_cov_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
+                 const double* __restrict__ aom, const double* __restrict__ agr, int64_t p,
+                 double tau0, int m, double lam1, const void* __restrict__ B, int64_t ldb,
+                 double* __restrict__ part, const DevState* st) {
+    if (st->overflow || st->accepted_q >= 0) return;   // capacity exceeded or already decided
+    const int lane = lane_id(), g = lane & (TG - 1);
+    const int64_t row = ((int64_t)blockIdx.x * WPB + (threadIdx.x >> 6)) * (64 / TG) + (lane / TG);
+    const bool act = row < p;
+    const int64_t s = act ? arow[row] : 0, e = act ? arow[row + 1] : 0;
+    double slog[MAXQ], sdd[MAXQ], squad[MAXQ], snp[MAXQ];
+#pragma unroll
+    for (int q = 0; q < MAXQ; ++q) { slog[q] = 0; sdd[q] = 0; squad[q] = 0; snp[q] = 0; }
+    for (int64_t k = s + g; k < e; k += TG) {
+        const int64_t j = acol[k];
+        const double om = aom[k], gr = agr[k];
+        const bool diag = j == row;
+        double tau = tau0;
+#pragma unroll
+        for (int q = 0; q < MAXQ; ++q) {
+            if (q < m) {
+                const double wp = prox_one(om, gr, tau, tau * lam1, diag);
+                const double d = wp - om;
+                sdd[q] += d * d;
+                if (diag) {
+                    if (wp <= 0.0) snp[q] += 1.0;
+                    else {
+                        const double x = d / om;
+                        slog[q] += x - log1p(x);
+                    }
+                }
+            }
+            tau *= 0.5;
+        }
+    }
+    // sum_{a,b in A_i} Delta_a S[j_a, j_b] Delta_b : the group's lanes over b, loop over a
+    for (int64_t kb = s + g; kb < e; kb += TG) {
+        const int64_t jb = acol[kb];
+        const double omb = aom[kb], gb = agr[kb];
+        const bool diagb = jb == row;
+        double db[MAXQ];
+        {
+            double tau = tau0;
+#pragma unroll
+            for (int q = 0; q < MAXQ; ++q) {
+                db[q] = q < m ? prox_one(omb, gb, tau, tau * lam1, diagb) - omb : 0.0;
+                tau *= 0.5;
+            }
+        }
+        for (int64_t ka = s; ka < e; ++ka) {
+            const int64_t ja = acol[ka];
+            const double oma = aom[ka], ga = agr[ka];
+            const bool diaga = ja == row;
+            const double sab = load_one_d<BS>(B, ja * ldb + jb);
+            double tau = tau0;
+#pragma unroll
+            for (int q = 0; q < MAXQ; ++q) {
+                if (q < m) {
+                    const double da = prox_one(oma, ga, tau, tau * lam1, diaga) - oma;
+                    squad[q] += da * sab * db[q];
+                }
+                tau *= 0.5;
+            }
+        }
+    }
+    double v[4 * MAXQ];
+#pragma unroll
+    for (int q = 0; q < MAXQ; ++q) {
+        v[4 * q + 0] = slog[q];
+        v[4 * q + 1] = sdd[q];
+        v[4 * q + 2] = squad[q];
+        v[4 * q + 3] = snp[q];
+    }
+#pragma unroll
+    for (int n = 4 * MAXQ, o = TG / 2; n > 4; n >>= 1, o >>= 1) {
+        const bool upper = (g & o) != 0;   // keep the upper half of the n values
+#pragma unroll
+        for (int i = 0; i < n / 2; ++i) {
+            const double send = upper ? v[i] : v[i + n / 2];
+            const double keep = upper ? v[i + n / 2] : v[i];
+            v[i] = keep + __shfl_xor(send, o, 64);
+        }
+    }
+    // lane g now holds values 4g .. 4g + 3: the four sums of step size q = g
+    if (act && g < m) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) part[(int64_t)(g * 4 + t) * p + row] = v[t];
+    }
 }
 
 // ---- column sums -----------------------------------------------------------------
@@ -1656,6 +1755,23 @@ hipError_t launch_trial(const Cand& A, int64_t p, double tau0, int m, double lam
     hipLaunchKernelGGL((trial_kernel<BS, OBS>), grid, dim3(NT), 0, stream, A.rowptr, A.col,   \
                        A.omega, A.grad, p, tau0, m, lam1, B, ldb, ncols, part, st)
     const bool obs = variant == 1;
+    // Cov rows hold a few candidates each.  Below COV_GROUP_MIN_P rows the wave-per-row
+    // kernel's p waves fit on the chip at once and the step is latency bound, so packing
+    // rows into fewer waves only lengthens each wave's serial loop (p = 200: 17% slower
+    // solves); above it, 8 rows per wave leave far fewer lanes idle (p = 16,384: 20%
+    // faster solves).
+    if (!obs && p >= COV_GROUP_MIN_P) {   // Cov: 8 lanes per row
+        static_assert(MAXQ == TG, "lane g of a row group holds step size q = g");
+        dim3 cg(blocks_for(p, WPB * (64 / TG)));
+#define TRIALC(BS)                                                                           \
+        hipLaunchKernelGGL((trial_cov_kernel<BS>), cg, dim3(NT), 0, stream, A.rowptr, A.col, \
+                           A.omega, A.grad, p, tau0, m, lam1, B, ldb, part, st)
+        if (bstore == ST_F64) TRIALC(ST_F64);
+        else if (bstore == ST_F32) TRIALC(ST_F32);
+        else TRIALC(ST_B16P);
+#undef TRIALC
+        return hipGetLastError();
+    }
     if (bstore == ST_F64) { if (obs) TRIAL(ST_F64, true); else TRIAL(ST_F64, false); }
     else if (bstore == ST_F32) { if (obs) TRIAL(ST_F32, true); else TRIAL(ST_F32, false); }
     else { if (obs) return hipErrorInvalidValue; TRIAL(ST_B16P, false); }

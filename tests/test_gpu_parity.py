@@ -112,8 +112,18 @@ def test_first_step_dense_product(variant, precision):
     ("cov", "fp32", 0.2), ("cov", "bf16x3", 0.2), ("cov", "fp64", 0.2),
 ])
 def test_replay_parity(variant, precision, lam1):
+    _replay_parity(variant, precision, lam1, 700, 300, 12)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_replay_parity_cov_grouped_trials(precision):
+    """p >= 4096: the Cov trials run 8 rows per wave; p = 4133 leaves a ragged last
+    wave (4133 = 129 * 32 + 5) and a ragged 64-column tile."""
+    _replay_parity("cov", precision, 0.2, 4133, 300, 4)
+
+
+def _replay_parity(variant, precision, lam1, p, n, iters):
     torch = _torch()
-    p, n, iters = 700, 300, 12
     w = datagen.make_workload("c2_obs_p20000", p=p, n=n)
     X = _rounded(w.X, precision)
     lam2 = w.lam2
