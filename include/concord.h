@@ -145,7 +145,10 @@ int concord_create(const concord_config* cfg, concord_ctx** out);
      stored unchanged).  The Cov products rely on that exact symmetry.
    dtype: CONCORD_F64 or CONCORD_F32.  Resets Omega to I and k to 0.
    Errors: EINVAL (shape/dtype/kind mismatch, S with Obs), ENONFINITE
-   (NaN/Inf in the input), EHIP. */
+   (NaN/Inf in the input; X is checked while it is copied, so after this
+   error for an X the handle holds no data and calls that need data return
+   ENODATA until a set_data succeeds; a rejected S leaves the handle as it
+   was), EHIP. */
 int concord_set_data(concord_ctx* ctx, int32_t kind, const void* dev_data, int32_t dtype,
                      int64_t rows, int64_t cols, int64_t ld);
 

@@ -805,18 +805,31 @@ int concord_set_data(concord_ctx* c, int32_t kind, const void* dev_data, int32_t
     } else {
         return fail(c, CONCORD_EINVAL, "unknown data kind");
     }
+    // X: the non-finite check rides on the transpose into the library layout, so a
+    // rejected X leaves the handle without data; S is checked before it is copied.
     hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, c->stream, c->d_flags, 0);
-    HIPCK(c, launch_check_finite(dev_data, is64, rows, cols, ld, c->d_flags, c->stream));
-    int hflag = 0;
-    HIPCK(c, hipMemcpyAsync(&hflag, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    HIPCK(c, hipStreamSynchronize(c->stream));
-    if (hflag) return fail(c, CONCORD_ENONFINITE, "data holds NaN or Inf");
-
     if (kind == CONCORD_DATA_X) {
         const bool split = c->precision == CONCORD_BF16X3;
         HIPCK(c, launch_transpose_in(dev_data, is64, rows, cols, ld, c->Xt, c->dstore, c->ldk,
                                      split ? c->Xt_hi : nullptr, split ? c->Xt_lo : nullptr,
-                                     kblk_stride(c->prow), c->stream));
+                                     kblk_stride(c->prow), c->d_flags, c->stream));
+    } else {
+        HIPCK(c, launch_check_finite(dev_data, is64, rows, cols, ld, c->d_flags, c->stream));
+    }
+    int hflag = 0;
+    HIPCK(c, hipMemcpyAsync(&hflag, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    if (hflag) {
+        if (kind == CONCORD_DATA_X) {
+            c->has_data = false;
+            c->prod_valid = false;
+            c->bits_valid = false;
+        }
+        return fail(c, CONCORD_ENONFINITE, "data holds NaN or Inf");
+    }
+
+    if (kind == CONCORD_DATA_X) {
+        const bool split = c->precision == CONCORD_BF16X3;
         if (c->variant == CONCORD_COV) {
             const void* P0 = split ? (const void*)c->Xt_hi : c->Xt;
             const void* P1 = split ? (const void*)c->Xt_lo : nullptr;

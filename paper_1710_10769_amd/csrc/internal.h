@@ -68,10 +68,11 @@ int gemm_sym_choice(int kind, bool syr2k, int64_t p, int64_t ldk, const char** n
 
 // X (rows x cols, ld, F64 or F32) -> Xt (cols x ldo) in `store` (F64/F32);
 // optionally bf16 hi/lo planes (hi, lo may be null), K-blocked with block stride
-// kbs elements.
+// kbs elements.  Sets *flag (int) to 1 if any entry of X is NaN/Inf (the
+// transposed data is written regardless).
 hipError_t launch_transpose_in(const void* X, int x_is_f64, int64_t rows, int64_t cols,
                                int64_t ld, void* Xt, int store, int64_t ldo, uint16_t* hi,
-                               uint16_t* lo, int64_t kbs, hipStream_t stream);
+                               uint16_t* lo, int64_t kbs, int* flag, hipStream_t stream);
 
 // (S + S^T) / 2 of a square p x p (ld) F64/F32 matrix into `store` layout with ldo,
 // exactly symmetric in the stored type (a symmetric S is copied unchanged).

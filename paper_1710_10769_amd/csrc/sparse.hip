@@ -1412,33 +1412,90 @@ cand_merge_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict_
 }
 
 // ---- ingest ----------------------------------------------------------------------
-template <typename In, typename Out>
+// X (rows x cols, ld) -> Xt (cols x ldo), one 64 x 64 tile per block through LDS, and
+// *flag = 1 if any entry read is NaN or Inf.  V4 (F32 in and out, X and ld 16-byte
+// aligned): each lane reads 4 consecutive columns of an X row and writes 4 consecutive
+// entries of an Xt row (16-byte accesses); entries of Xt past `rows` in a written
+// group of 4 are the zero padding (ldo is a multiple of 4, at least rows).
+template <typename In, typename Out, bool V4>
 __global__ void __launch_bounds__(NT)
 transpose_in_kernel(const In* __restrict__ X, int64_t rows, int64_t cols, int64_t ld,
                     Out* __restrict__ Xt, int64_t ldo, uint16_t* __restrict__ hi,
-                    uint16_t* __restrict__ lo, int64_t kbs) {
+                    uint16_t* __restrict__ lo, int64_t kbs, int* __restrict__ flag) {
     __shared__ Out tile[64][65];
     const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int r = ty; r < 64; r += 4) {
-        const int64_t gr = r0 + r, gc = c0 + tx;
-        tile[r][tx] = (gr < rows && gc < cols) ? (Out)X[gr * ld + gc] : (Out)0;
-    }
-    __syncthreads();
-    for (int r = ty; r < 64; r += 4) {
-        const int64_t oc = c0 + r, orr = r0 + tx;   // output row = input col
-        if (oc < cols && orr < rows) {
-            const Out v = tile[tx][r];
-            Xt[oc * ldo + orr] = v;
-            if (hi) {
-                const float x = (float)v;
-                const uint16_t h = f2bf_rne(x);
-                const int64_t o = kblk_index(oc, orr, kbs);
-                hi[o] = h;
-                lo[o] = f2bf_rne(x - bf2f(h));
+    bool bad = false;
+    if (V4) {
+        const int q = threadIdx.x & 15, rr = threadIdx.x >> 4;   // 16 lanes per row
+        for (int r = rr; r < 64; r += NT / 16) {
+            const int64_t gr = r0 + r, gc = c0 + 4 * q;
+            float v[4] = {0.f, 0.f, 0.f, 0.f};
+            if (gr < rows) {
+                const In* src = X + gr * ld + gc;
+                if (gc + 3 < cols) {
+                    const float4 w = *(const float4*)src;
+                    v[0] = w.x; v[1] = w.y; v[2] = w.z; v[3] = w.w;
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        if (gc + t < cols) v[t] = (float)src[t];
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                bad |= !isfinite(v[t]);
+                tile[r][4 * q + t] = (Out)v[t];
+            }
+        }
+        __syncthreads();
+        for (int c = rr; c < 64; c += NT / 16) {
+            const int64_t oc = c0 + c, orr = r0 + 4 * q;   // output row = input col
+            if (oc < cols && orr < rows) {
+                float w[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) w[t] = (float)tile[4 * q + t][c];
+                *(float4*)((float*)Xt + oc * ldo + orr) = make_float4(w[0], w[1], w[2], w[3]);
+                if (hi) {
+                    uint16_t h[4], l[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        h[t] = f2bf_rne(w[t]);
+                        l[t] = f2bf_rne(w[t] - bf2f(h[t]));
+                    }
+                    // 4 consecutive K entries (orr % 4 == 0) stay inside one K block
+                    const int64_t o = kblk_index(oc, orr, kbs);
+                    *(uint2*)(hi + o) = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16),
+                                                   (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+                    *(uint2*)(lo + o) = make_uint2((uint32_t)l[0] | ((uint32_t)l[1] << 16),
+                                                   (uint32_t)l[2] | ((uint32_t)l[3] << 16));
+                }
+            }
+        }
+    } else {
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+        for (int r = ty; r < 64; r += 4) {
+            const int64_t gr = r0 + r, gc = c0 + tx;
+            const In x = (gr < rows && gc < cols) ? X[gr * ld + gc] : (In)0;
+            bad |= !isfinite((double)x);
+            tile[r][tx] = (Out)x;
+        }
+        __syncthreads();
+        for (int r = ty; r < 64; r += 4) {
+            const int64_t oc = c0 + r, orr = r0 + tx;   // output row = input col
+            if (oc < cols && orr < rows) {
+                const Out v = tile[tx][r];
+                Xt[oc * ldo + orr] = v;
+                if (hi) {
+                    const float x = (float)v;
+                    const uint16_t h = f2bf_rne(x);
+                    const int64_t o = kblk_index(oc, orr, kbs);
+                    hi[o] = h;
+                    lo[o] = f2bf_rne(x - bf2f(h));
+                }
             }
         }
     }
+    if (bad) *flag = 1;
 }
 
 // (S + S^T) / 2 into `store` layout, one 64 x 64 tile per block: tile (bj, bi) is staged
@@ -1474,24 +1531,27 @@ sym_copy_kernel(const In* __restrict__ S, int64_t p, int64_t ld, void* out, int 
 }
 
 template <typename In>
-__global__ void check_finite_kernel(const In* __restrict__ A, int64_t rows, int64_t cols,
-                                    int64_t ld, int* flag) {
-    const int64_t n = rows * cols;
+__global__ void __launch_bounds__(NT)
+check_finite_kernel(const In* __restrict__ A, int64_t rows, int64_t cols, int64_t ld,
+                    int* flag) {
     bool bad = false;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const double v = (double)A[(idx / cols) * ld + idx % cols];
-        if (!isfinite(v)) bad = true;
-    }
+    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x)
+        for (int64_t c = threadIdx.x; c < cols; c += NT)
+            if (!isfinite((double)A[r * ld + c])) bad = true;
     if (bad) *flag = 1;
 }
 
 // ---- differentiation form ------------------------------------------------------
 // G_ij on the stored entries: ( <Y_i, Xt_j> + <Y_j, Xt_i> ) / (2n) + lam2 w_ij - [i==j]/w_ii.
 // One wave per row i keeps Y_i and Xt_i in registers (up to RC chunks of 64*V
-// columns) and computes each unordered pair once: for j > i it writes G_ij to
-// entry (i,j) and, mirrored, to entry (j,i) (found by binary search of row j);
-// entries with j < i are written by row j's wave.
+// columns) and computes each unordered pair once: for j >= i it writes G_ij to
+// entry (i,j) and, mirrored, to entry (j,i); entries with j < i are written by
+// row j's wave.  The row's entries are taken 64 at a time, one per lane: each lane
+// finds its entry's mirror position by binary search of row j (all lanes at once),
+// the pairs j >= i are walked from a ballot mask, and the wave sums of 8 pairs are
+// done together by a reduce-scatter (4 + 2 + 1 shuffles, then 3 more for the whole
+// wave) instead of 6 shuffles per pair.
+constexpr int SDDMM_GROUP = 8;
 template <int S, int RC>
 __global__ void __launch_bounds__(NT)
 sddmm_grad_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
@@ -1518,13 +1578,8 @@ sddmm_grad_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict_
             for (int t = 0; t < V; ++t) { yi[q][t] = 0; xi[q][t] = 0; }
         }
     }
-    auto emit = [&](int64_t k, double g) {
-        if (out_f64) ((double*)out)[k] = g;
-        else ((float*)out)[k] = (float)g;
-    };
-    for (int64_t k = s; k < e; ++k) {
-        const int64_t j = col[k];
-        if (j < row) continue;
+    // <Y_i, Xt_j> + <Y_j, Xt_i>: this lane's share
+    auto pair_part = [&](int64_t j) -> double {
         double acc = 0.0;
         if (nch <= RC) {
 #pragma unroll
@@ -1553,19 +1608,74 @@ sddmm_grad_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict_
                 acc += (double)a;
             }
         }
-        acc = wave_sum(acc);
-        const double v = val[k];
-        double g = acc / (2.0 * (double)n) + lam2 * v;
-        if (j == row) g -= 1.0 / v;
-        if (lane == 0) {
-            emit(k, g);
-            if (j != row) {
-                int64_t lo_ = rowptr[j], hi_ = rowptr[j + 1];
+        return acc;
+    };
+    const double inv2n = 1.0 / (2.0 * (double)n);
+    for (int64_t b = s; b < e; b += 64) {
+        const int cnt = (int)(e - b < 64 ? e - b : 64);
+        // lane t: entry b + t, its column and its mirror's position (-1: none or j <= i)
+        int jl = -1;
+        int64_t mpos = -1;
+        if (lane < cnt) {
+            jl = col[b + lane];
+            if (jl > row) {
+                const int64_t me = rowptr[jl + 1];
+                int64_t lo_ = rowptr[jl], hi_ = me;
                 while (lo_ < hi_) {
                     const int64_t mid = (lo_ + hi_) >> 1;
                     if (col[mid] < row) lo_ = mid + 1; else hi_ = mid;
                 }
-                if (lo_ < rowptr[j + 1] && col[lo_] == row) emit(lo_, g);
+                if (lo_ < me && col[lo_] == row) mpos = lo_;
+            }
+        }
+        uint64_t todo = __ballot(lane < cnt && jl >= row);
+        while (todo) {
+            // up to SDDMM_GROUP pairs, then one reduce-scatter for all of them
+            double v[SDDMM_GROUP];
+            int my_t = 0;   // lane g holds the entry index of slot g
+            int m = 0;
+#pragma unroll
+            for (int g = 0; g < SDDMM_GROUP; ++g) {
+                v[g] = 0.0;
+                if (todo) {
+                    const int t = __builtin_ctzll(todo);
+                    todo &= todo - 1;
+                    const int64_t j = __shfl(jl, t, 64);
+                    v[g] = pair_part(uni(j));
+                    if (lane == g) my_t = t;
+                    m = g + 1;
+                }
+            }
+#pragma unroll
+            for (int w = SDDMM_GROUP, o = 32; w > 1; w >>= 1, o >>= 1) {
+                const bool upper = (lane & o) != 0;   // keep the upper half of the w values
+#pragma unroll
+                for (int i = 0; i < w / 2; ++i) {
+                    const double send = upper ? v[i] : v[i + w / 2];
+                    const double keep = upper ? v[i + w / 2] : v[i];
+                    v[i] = keep + __shfl_xor(send, o, 64);
+                }
+            }
+            // v[0]: slot (lane >> 3) & 7 summed over the 8 lanes that share bits 0..2
+            double tot = v[0];
+#pragma unroll
+            for (int o = 4; o >= 1; o >>= 1) tot += __shfl_xor(tot, o, 64);
+            const int g = (lane >> 3) & 7;
+            const int t = __shfl(my_t, g, 64);
+            const int64_t mp = __shfl(mpos, t, 64);
+            const int j = __shfl(jl, t, 64);
+            if ((lane & 7) == 0 && g < m) {
+                const int64_t k = b + t;
+                const double wv = val[k];
+                double gr = tot * inv2n + lam2 * wv;
+                if (j == row) gr -= 1.0 / wv;
+                if (out_f64) {
+                    ((double*)out)[k] = gr;
+                    if (mp >= 0) ((double*)out)[mp] = gr;
+                } else {
+                    ((float*)out)[k] = (float)gr;
+                    if (mp >= 0) ((float*)out)[mp] = (float)gr;
+                }
             }
         }
     }
@@ -1596,13 +1706,51 @@ dense_grad_kernel(const void* __restrict__ M, int64_t ldm, const int64_t* __rest
     else ((float*)out)[idx] = (float)g;
 }
 
-template <typename E>
+// A (p x n, ld) -> out (n x p), each entry times `scale` (in FP64, then rounded to the
+// output type).  V4 (F32 in and out, 16-byte aligned rows): 16-byte loads of 4
+// consecutive columns of an A row and 16-byte stores of 4 consecutive out entries.
+template <typename E, bool V4>
 __global__ void __launch_bounds__(NT)
 transpose_out_kernel(const E* __restrict__ A, int64_t p, int64_t n, int64_t ld, double scale,
                      void* out, int out_f64) {
-    // A: p x n (ld) -> out: n x p, scaled
-    __shared__ double tile[64][65];
     const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    if (V4) {
+        __shared__ float tf[64][65];
+        const int q = threadIdx.x & 15, rr = threadIdx.x >> 4;
+        for (int r = rr; r < 64; r += NT / 16) {
+            const int64_t gr = r0 + r, gc = c0 + 4 * q;
+            float v[4] = {0.f, 0.f, 0.f, 0.f};
+            if (gr < p) {
+                const E* src = A + gr * ld + gc;
+                if (gc + 3 < n) {
+                    const float4 w = *(const float4*)src;
+                    v[0] = w.x; v[1] = w.y; v[2] = w.z; v[3] = w.w;
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        if (gc + t < n) v[t] = (float)src[t];
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) tf[r][4 * q + t] = (float)((double)v[t] * scale);
+        }
+        __syncthreads();
+        for (int c = rr; c < 64; c += NT / 16) {
+            const int64_t orow = c0 + c, ocol = r0 + 4 * q;
+            if (orow >= n || ocol >= p) continue;
+            float* dst = (float*)out + orow * p + ocol;
+            if (ocol + 3 < p) {
+                *(float4*)dst = make_float4(tf[4 * q][c], tf[4 * q + 1][c], tf[4 * q + 2][c],
+                                            tf[4 * q + 3][c]);
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (ocol + t < p) dst[t] = tf[4 * q + t][c];
+            }
+        }
+        return;
+    }
+    __shared__ double tile[64][65];
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     for (int r = ty; r < 64; r += 4) {
         const int64_t gr = r0 + r, gc = c0 + tx;
@@ -1956,22 +2104,34 @@ hipError_t launch_tile_max(const void* S, int sstore, int64_t p, int64_t lds, do
 
 hipError_t launch_transpose_in(const void* X, int x_is_f64, int64_t rows, int64_t cols,
                                int64_t ld, void* Xt, int store, int64_t ldo, uint16_t* hi,
-                               uint16_t* lo, int64_t kbs, hipStream_t stream) {
+                               uint16_t* lo, int64_t kbs, int* flag, hipStream_t stream) {
+    if (rows == 0 || cols == 0) return hipSuccess;
     dim3 grid(blocks_for(cols, 64), blocks_for(rows, 64));
+    if (grid.y > 65535u) return hipErrorInvalidValue;
     if (x_is_f64) {
         if (store == ST_F64)
-            hipLaunchKernelGGL((transpose_in_kernel<double, double>), grid, dim3(NT), 0, stream,
-                               (const double*)X, rows, cols, ld, (double*)Xt, ldo, hi, lo, kbs);
+            hipLaunchKernelGGL((transpose_in_kernel<double, double, false>), grid, dim3(NT), 0,
+                               stream, (const double*)X, rows, cols, ld, (double*)Xt, ldo, hi, lo,
+                               kbs, flag);
         else
-            hipLaunchKernelGGL((transpose_in_kernel<double, float>), grid, dim3(NT), 0, stream,
-                               (const double*)X, rows, cols, ld, (float*)Xt, ldo, hi, lo, kbs);
+            hipLaunchKernelGGL((transpose_in_kernel<double, float, false>), grid, dim3(NT), 0,
+                               stream, (const double*)X, rows, cols, ld, (float*)Xt, ldo, hi, lo,
+                               kbs, flag);
     } else {
+        const bool v4 = store != ST_F64 && ((uintptr_t)X & 15) == 0 && ld % 4 == 0 &&
+                        ldo % 4 == 0 && ((uintptr_t)Xt & 15) == 0;
         if (store == ST_F64)
-            hipLaunchKernelGGL((transpose_in_kernel<float, double>), grid, dim3(NT), 0, stream,
-                               (const float*)X, rows, cols, ld, (double*)Xt, ldo, hi, lo, kbs);
+            hipLaunchKernelGGL((transpose_in_kernel<float, double, false>), grid, dim3(NT), 0,
+                               stream, (const float*)X, rows, cols, ld, (double*)Xt, ldo, hi, lo,
+                               kbs, flag);
+        else if (v4)
+            hipLaunchKernelGGL((transpose_in_kernel<float, float, true>), grid, dim3(NT), 0,
+                               stream, (const float*)X, rows, cols, ld, (float*)Xt, ldo, hi, lo,
+                               kbs, flag);
         else
-            hipLaunchKernelGGL((transpose_in_kernel<float, float>), grid, dim3(NT), 0, stream,
-                               (const float*)X, rows, cols, ld, (float*)Xt, ldo, hi, lo, kbs);
+            hipLaunchKernelGGL((transpose_in_kernel<float, float, false>), grid, dim3(NT), 0,
+                               stream, (const float*)X, rows, cols, ld, (float*)Xt, ldo, hi, lo,
+                               kbs, flag);
     }
     return hipGetLastError();
 }
@@ -1992,9 +2152,8 @@ hipError_t launch_sym_copy(const void* S, int s_is_f64, int64_t p, int64_t ld, v
 
 hipError_t launch_check_finite(const void* A, int is_f64, int64_t rows, int64_t cols,
                                int64_t ld, int* flag, hipStream_t stream) {
-    if (rows * cols == 0) return hipSuccess;
-    unsigned nb = blocks_for(rows * cols, NT);
-    if (nb > 4096) nb = 4096;
+    if (rows == 0 || cols == 0) return hipSuccess;
+    const unsigned nb = (unsigned)std::min<int64_t>(rows, 8192);
     if (is_f64)
         hipLaunchKernelGGL(check_finite_kernel<double>, dim3(nb), dim3(NT), 0, stream,
                            (const double*)A, rows, cols, ld, flag);
@@ -2009,12 +2168,13 @@ hipError_t launch_sddmm_grad(const Csr& om, int64_t p, const void* Y, const void
                              int out_f64, hipStream_t stream) {
     if (p == 0) return hipSuccess;
     dim3 grid(blocks_for(p, WPB));
-    // register cache of 8 column chunks: n <= 2048 (FP32) / 1024 (FP64) stay resident
+    // register cache of 4 column chunks: rows of n <= 1024 (FP32) / 512 (FP64) stay
+    // resident (beyond that every pair re-reads them; 8 chunks cost a wave per SIMD)
     if (store == ST_F64)
-        hipLaunchKernelGGL((sddmm_grad_kernel<ST_F64, 8>), grid, dim3(NT), 0, stream, om.rowptr,
+        hipLaunchKernelGGL((sddmm_grad_kernel<ST_F64, 4>), grid, dim3(NT), 0, stream, om.rowptr,
                            om.col, om.val, p, Y, Xt, ld, n, lam2, out, out_f64);
     else
-        hipLaunchKernelGGL((sddmm_grad_kernel<ST_F32, 8>), grid, dim3(NT), 0, stream, om.rowptr,
+        hipLaunchKernelGGL((sddmm_grad_kernel<ST_F32, 4>), grid, dim3(NT), 0, stream, om.rowptr,
                            om.col, om.val, p, Y, Xt, ld, n, lam2, out, out_f64);
     return hipGetLastError();
 }
@@ -2034,12 +2194,19 @@ hipError_t launch_gather_dense_grad(const void* M, int mstore, int64_t ldm, cons
 
 hipError_t launch_transpose_out(const void* Yt, int store, int64_t p, int64_t n, int64_t ld,
                                 double scale, void* out, int out_f64, hipStream_t stream) {
+    if (p == 0 || n == 0) return hipSuccess;
     dim3 grid(blocks_for(n, 64), blocks_for(p, 64));
+    if (grid.y > 65535u) return hipErrorInvalidValue;
+    const bool v4 = store == ST_F32 && !out_f64 && ld % 4 == 0 && p % 4 == 0 &&
+                    ((uintptr_t)Yt & 15) == 0 && ((uintptr_t)out & 15) == 0;
     if (store == ST_F64)
-        hipLaunchKernelGGL(transpose_out_kernel<double>, grid, dim3(NT), 0, stream,
+        hipLaunchKernelGGL((transpose_out_kernel<double, false>), grid, dim3(NT), 0, stream,
                            (const double*)Yt, p, n, ld, scale, out, out_f64);
+    else if (v4)
+        hipLaunchKernelGGL((transpose_out_kernel<float, true>), grid, dim3(NT), 0, stream,
+                           (const float*)Yt, p, n, ld, scale, out, out_f64);
     else
-        hipLaunchKernelGGL(transpose_out_kernel<float>, grid, dim3(NT), 0, stream,
+        hipLaunchKernelGGL((transpose_out_kernel<float, false>), grid, dim3(NT), 0, stream,
                            (const float*)Yt, p, n, ld, scale, out, out_f64);
     return hipGetLastError();
 }

@@ -67,6 +67,40 @@ def test_forward_backward_vs_oracle_p500(precision):
     s.close()
 
 
+@pytest.mark.parametrize("precision,n,deg", [("fp64", 700, 90), ("fp32", 1100, 70),
+                                              ("fp32", 300, 90)])
+def test_backward_long_rows_vs_oracle(precision, n, deg):
+    """Rows with more than 64 stored entries (the pair walk takes them 64 at a time)
+    and, for n past the register-resident width (FP64 n > 512, FP32 n > 1024), the
+    path that re-reads row i for every pair."""
+    torch = _torch()
+    from paper_1710_10769_amd import Solver
+    from paper_1710_10769_amd.autograd import concord_smooth
+    p, lam2 = 300, 0.1
+    _say(f"autograd long rows {precision} p={p} n={n} deg={deg} seed=56")
+    _, om, X = _case(p, n, 56, deg=deg)
+    assert np.diff(sp.csr_matrix(om).indptr).max() > 64
+    if precision == "fp32":
+        X = X.astype(np.float32).astype(np.float64)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    f_ref, G_ref, dX_ref = oc.smooth_value_and_grads(om, X, lam2)
+    s = Solver(p, n, variant="obs", precision=precision)
+    rp, cl, v = _csr_tensors(torch, om, dt)
+    v.requires_grad_(True)
+    Xt = torch.from_numpy(X).to("cuda", dt).requires_grad_(True)
+    f = concord_smooth(v, Xt, rp, cl, lam2, s)
+    f.backward()
+    tol = 1e-10 if precision == "fp64" else 1e-4
+    omc = sp.csr_matrix(om)
+    rows = np.repeat(np.arange(p), np.diff(omc.indptr))
+    g_ref = G_ref[rows, omc.indices]
+    g = v.grad.double().cpu().numpy()
+    assert np.abs(g - g_ref).max() <= tol * np.abs(g_ref).max()
+    dx = Xt.grad.double().cpu().numpy()
+    assert np.abs(dx - dX_ref).max() <= tol * np.abs(dX_ref).max()
+    s.close()
+
+
 def test_finite_differences_fp64_p500():
     """Symmetric directions on the stored pattern and random directions in X,
     evaluated with the GPU's own forward (central differences)."""
