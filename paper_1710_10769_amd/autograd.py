@@ -50,9 +50,15 @@ class ConcordSmooth(torch.autograd.Function):
         dtype = torch.float64 if torch.float64 in (ctx.vdtype, ctx.xdtype) else torch.float32
         dv, dX = ctx.solver.gradient(ctx.lam2, mode="masked", want_omega=want_v, want_x=want_x,
                                      dtype=dtype)
+        # the usual incoming gradient is 1: then the library's outputs are returned as
+        # they are, without another pass over the n x p d f / d X
+        unit = float(grad_f) == 1.0
         g = grad_f.to(dtype)
-        gv = (g * dv).to(ctx.vdtype) if dv is not None else None
-        gx = (g * dX).to(ctx.xdtype) if dX is not None else None
+        gv = gx = None
+        if dv is not None:
+            gv = (dv if unit else g * dv).to(ctx.vdtype)
+        if dX is not None:
+            gx = (dX if unit else g * dX).to(ctx.xdtype)
         return gv, gx, None, None, None, None
 
 

@@ -101,6 +101,30 @@ def test_backward_long_rows_vs_oracle(precision, n, deg):
     s.close()
 
 
+def test_incoming_gradient_scales_outputs():
+    """backward of c * f returns c times the gradients of f (the unit case skips the
+    multiply; any other incoming gradient takes it)."""
+    torch = _torch()
+    from paper_1710_10769_amd import Solver
+    from paper_1710_10769_amd.autograd import concord_smooth
+    p, n, lam2 = 200, 120, 0.1
+    _say(f"autograd incoming gradient fp32 p={p} n={n} seed=57")
+    _, om, X = _case(p, n, 57, deg=10)
+    s = Solver(p, n, variant="obs", precision="fp32")
+    rp, cl, v0 = _csr_tensors(torch, om, torch.float32)
+    X0 = torch.from_numpy(X).to("cuda", torch.float32)
+    grads = []
+    for c in (1.0, 2.5):
+        v = v0.clone().requires_grad_(True)
+        x = X0.clone().requires_grad_(True)
+        (c * concord_smooth(v, x, rp, cl, lam2, s)).backward()
+        grads.append((v.grad.clone(), x.grad.clone()))
+    (gv1, gx1), (gv2, gx2) = grads
+    c = torch.tensor(2.5, dtype=torch.float32, device="cuda")
+    assert torch.equal(gv2, c * gv1) and torch.equal(gx2, c * gx1)
+    s.close()
+
+
 def test_finite_differences_fp64_p500():
     """Symmetric directions on the stored pattern and random directions in X,
     evaluated with the GPU's own forward (central differences)."""
