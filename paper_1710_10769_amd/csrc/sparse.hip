@@ -1543,16 +1543,17 @@ check_finite_kernel(const In* __restrict__ A, int64_t rows, int64_t cols, int64_
 
 // ---- differentiation form ------------------------------------------------------
 // G_ij on the stored entries: ( <Y_i, Xt_j> + <Y_j, Xt_i> ) / (2n) + lam2 w_ij - [i==j]/w_ii.
-// One wave per row i keeps Y_i and Xt_i in registers (up to RC chunks of 64*V
-// columns) and computes each unordered pair once: for j >= i it writes G_ij to
-// entry (i,j) and, mirrored, to entry (j,i); entries with j < i are written by
-// row j's wave.  The row's entries are taken 64 at a time, one per lane: each lane
-// finds its entry's mirror position by binary search of row j (all lanes at once),
-// the pairs j >= i are walked from a ballot mask, and the wave sums of 8 pairs are
-// done together by a reduce-scatter (4 + 2 + 1 shuffles, then 3 more for the whole
-// wave) instead of 6 shuffles per pair.
+// One wave per row i computes each unordered pair once: for j >= i it writes G_ij to
+// entry (i,j) and, mirrored, to entry (j,i); entries with j < i are written by row j's
+// wave.  The row's entries are taken 64 at a time, one per lane: each lane finds its
+// entry's mirror position by binary search of row j (all lanes at once), the pairs
+// j >= i are walked from a ballot mask, and the wave sums of 8 pairs are done together
+// by a reduce-scatter (4 + 2 + 1 shuffles, then 3 more for the whole wave) instead of 6
+// shuffles per pair.  RES: Y_i and Xt_i stay in registers (up to RC chunks of 64*V
+// columns) and the rows j of the next pair are loaded before the current pair's
+// arithmetic; otherwise every pair re-reads row i.
 constexpr int SDDMM_GROUP = 8;
-template <int S, int RC>
+template <int S, int RC, bool RES>
 __global__ void __launch_bounds__(NT)
 sddmm_grad_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                   const double* __restrict__ val, int64_t p, const void* __restrict__ Y,
@@ -1570,7 +1571,7 @@ sddmm_grad_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict_
 #pragma unroll
     for (int q = 0; q < RC; ++q) {
         const int64_t c = (int64_t)q * 64 * V + lane * V;
-        if (q < nch && c < n) {
+        if (RES && q < nch && c < n) {
             Ch::load(Y, row * ld + c, yi[q]);
             Ch::load(Xt, row * ld + c, xi[q]);
         } else {
@@ -1581,21 +1582,7 @@ sddmm_grad_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict_
     // <Y_i, Xt_j> + <Y_j, Xt_i>: this lane's share
     auto pair_part = [&](int64_t j) -> double {
         double acc = 0.0;
-        if (nch <= RC) {
-#pragma unroll
-            for (int q = 0; q < RC; ++q) {
-                const int64_t c = (int64_t)q * 64 * V + lane * V;
-                if (q < nch && c < n) {
-                    T xj[V], yj[V];
-                    Ch::load(Xt, j * ld + c, xj);
-                    Ch::load(Y, j * ld + c, yj);
-                    T a = 0;
-#pragma unroll
-                    for (int t = 0; t < V; ++t) a += yi[q][t] * xj[t] + yj[t] * xi[q][t];
-                    acc += (double)a;
-                }
-            }
-        } else {
+        {
             for (int64_t c = lane * V; c < n; c += 64 * V) {
                 T a4[V], b4[V], c4[V], d4[V];
                 Ch::load(Y, row * ld + c, a4);
@@ -1632,19 +1619,59 @@ sddmm_grad_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict_
         while (todo) {
             // up to SDDMM_GROUP pairs, then one reduce-scatter for all of them
             double v[SDDMM_GROUP];
+            int64_t jj[SDDMM_GROUP];
             int my_t = 0;   // lane g holds the entry index of slot g
             int m = 0;
 #pragma unroll
             for (int g = 0; g < SDDMM_GROUP; ++g) {
                 v[g] = 0.0;
+                jj[g] = row;
                 if (todo) {
                     const int t = __builtin_ctzll(todo);
                     todo &= todo - 1;
-                    const int64_t j = __shfl(jl, t, 64);
-                    v[g] = pair_part(uni(j));
+                    jj[g] = uni((int64_t)__shfl(jl, t, 64));
                     if (lane == g) my_t = t;
                     m = g + 1;
                 }
+            }
+            if (RES) {
+                // rows j of the group's pairs, the next pair's loads issued before the
+                // current pair's arithmetic
+                T bx[2][RC][V], by[2][RC][V];
+                auto fetch = [&](int64_t j, T (&x)[RC][V], T (&y)[RC][V]) {
+#pragma unroll
+                    for (int q = 0; q < RC; ++q) {
+                        const int64_t c = (int64_t)q * 64 * V + lane * V;
+                        if (q < nch && c < n) {
+                            Ch::load(Xt, j * ld + c, x[q]);
+                            Ch::load(Y, j * ld + c, y[q]);
+                        }
+                    }
+                };
+                fetch(jj[0], bx[0], by[0]);
+#pragma unroll
+                for (int g = 0; g < SDDMM_GROUP; ++g) {
+                    if (g + 1 < SDDMM_GROUP && g + 1 < m) fetch(jj[g + 1], bx[(g + 1) & 1], by[(g + 1) & 1]);
+                    if (g < m) {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int q = 0; q < RC; ++q) {
+                            const int64_t c = (int64_t)q * 64 * V + lane * V;
+                            if (q < nch && c < n) {
+                                T a = 0;
+#pragma unroll
+                                for (int t = 0; t < V; ++t)
+                                    a += yi[q][t] * bx[g & 1][q][t] + by[g & 1][q][t] * xi[q][t];
+                                acc += (double)a;
+                            }
+                        }
+                        v[g] = acc;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int g = 0; g < SDDMM_GROUP; ++g)
+                    if (g < m) v[g] = pair_part(jj[g]);
             }
 #pragma unroll
             for (int w = SDDMM_GROUP, o = 32; w > 1; w >>= 1, o >>= 1) {
@@ -2169,13 +2196,19 @@ hipError_t launch_sddmm_grad(const Csr& om, int64_t p, const void* Y, const void
     if (p == 0) return hipSuccess;
     dim3 grid(blocks_for(p, WPB));
     // register cache of 4 column chunks: rows of n <= 1024 (FP32) / 512 (FP64) stay
-    // resident (beyond that every pair re-reads them; 8 chunks cost a wave per SIMD)
-    if (store == ST_F64)
-        hipLaunchKernelGGL((sddmm_grad_kernel<ST_F64, 4>), grid, dim3(NT), 0, stream, om.rowptr,
-                           om.col, om.val, p, Y, Xt, ld, n, lam2, out, out_f64);
-    else
-        hipLaunchKernelGGL((sddmm_grad_kernel<ST_F32, 4>), grid, dim3(NT), 0, stream, om.rowptr,
-                           om.col, om.val, p, Y, Xt, ld, n, lam2, out, out_f64);
+    // resident; longer rows are re-read for every pair
+#define SDDMM(SS)                                                                             \
+    do {                                                                                      \
+        if (n <= 4 * 64 * Chunk<SS>::V)                                                       \
+            hipLaunchKernelGGL((sddmm_grad_kernel<SS, 4, true>), grid, dim3(NT), 0, stream,   \
+                               om.rowptr, om.col, om.val, p, Y, Xt, ld, n, lam2, out, out_f64); \
+        else                                                                                  \
+            hipLaunchKernelGGL((sddmm_grad_kernel<SS, 1, false>), grid, dim3(NT), 0, stream,  \
+                               om.rowptr, om.col, om.val, p, Y, Xt, ld, n, lam2, out, out_f64); \
+    } while (0)
+    if (store == ST_F64) SDDMM(ST_F64);
+    else SDDMM(ST_F32);
+#undef SDDMM
     return hipGetLastError();
 }
 
