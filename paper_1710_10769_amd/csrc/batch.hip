@@ -7,7 +7,10 @@
 // the path from Omega = I with the single-problem solver on its stream, and
 // copies each estimate into batch-owned CSR buffers.  Independent instances
 // thus overlap on the GPU instead of serialising on launch latency and on the
-// host synchronisation of each step.
+// host synchronisation of each step.  A worker keeps its solver handles for the
+// whole call, one per (p, n) it has met, and loads the next instance of the same
+// shape into the same handle: no device allocation or free (a free waits for
+// every stream of the device) between instances of one shape.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -55,24 +58,43 @@ void free_result(BatchResult& r) {
     r = BatchResult();
 }
 
-// One instance, every lambda1, on `stream`.  Returns a status and a message.
-int solve_instance(concord_batch* b, int i, hipStream_t stream, double lam2, double tol,
-                   int64_t max_iter, std::string* msg) {
-    concord_config cfg;
-    concord_config_init(&cfg);
-    cfg.p = b->p[i];
-    cfg.n = b->n[i];
-    cfg.variant = CONCORD_COV;
-    cfg.precision = CONCORD_FP32;
-    cfg.stream = stream;
-    cfg.device = b->device;
-    concord_ctx* c = nullptr;
-    int rc = concord_create(&cfg, &c);
-    if (rc) {
-        *msg = "concord_create failed for instance " + std::to_string(i);
-        return rc;
+// A worker's solver handles, one per problem shape.
+struct HandlePool {
+    struct Entry {
+        int64_t p, n;
+        concord_ctx* c;
+    };
+    std::vector<Entry> e;
+    ~HandlePool() {
+        for (auto& x : e) concord_destroy(x.c);
     }
-    rc = concord_set_data(c, CONCORD_DATA_X, b->X[i], CONCORD_F32, b->n[i], b->p[i], b->ld[i]);
+};
+
+// One instance, every lambda1, on `stream`, in the worker's handle of that shape
+// (created on first use).  Returns a status and a message.
+int solve_instance(concord_batch* b, int i, hipStream_t stream, double lam2, double tol,
+                   int64_t max_iter, std::string* msg, HandlePool& pool) {
+    concord_ctx* c = nullptr;
+    for (auto& x : pool.e)
+        if (x.p == b->p[i] && x.n == b->n[i]) c = x.c;
+    if (!c) {
+        concord_config cfg;
+        concord_config_init(&cfg);
+        cfg.p = b->p[i];
+        cfg.n = b->n[i];
+        cfg.variant = CONCORD_COV;
+        cfg.precision = CONCORD_FP32;
+        cfg.stream = stream;
+        cfg.device = b->device;
+        const int rc0 = concord_create(&cfg, &c);
+        if (rc0) {
+            *msg = "concord_create failed for instance " + std::to_string(i);
+            return rc0;
+        }
+        pool.e.push_back({b->p[i], b->n[i], c});
+    }
+    // set_data starts the instance from Omega = I with k = 0
+    int rc = concord_set_data(c, CONCORD_DATA_X, b->X[i], CONCORD_F32, b->n[i], b->p[i], b->ld[i]);
     int worst = CONCORD_OK;
     for (int l = 0; rc >= 0 && l < b->n_l1; ++l) {
         if ((rc = concord_reset(c))) break;
@@ -101,7 +123,6 @@ int solve_instance(concord_batch* b, int i, hipStream_t stream, double lam2, dou
         rc = CONCORD_OK;
     }
     if (rc < 0) *msg = std::string("instance ") + std::to_string(i) + ": " + concord_last_error(c);
-    concord_destroy(c);
     return rc < 0 ? rc : worst;
 }
 }  // namespace
@@ -179,20 +200,23 @@ int concord_batch_solve(concord_batch* b, double lambda2, double tol, int64_t ma
             if (status >= 0) { status = CONCORD_EHIP; first_err = "stream creation failed"; }
             return;
         }
-        for (;;) {
-            {
+        {
+            HandlePool pool;   // destroyed before the stream its handles use
+            for (;;) {
+                {
+                    std::lock_guard<std::mutex> g(mu);
+                    if (status < 0) break;
+                }
+                const int k = next.fetch_add(1);
+                if (k >= b->count) break;
+                std::string msg;
+                const int rc = solve_instance(b, order[k], s, lambda2, tol, max_iter, &msg, pool);
                 std::lock_guard<std::mutex> g(mu);
-                if (status < 0) break;
+                if (rc < 0 && status >= 0) { status = rc; first_err = msg; }
+                else if (rc > status && status >= 0) status = rc;
             }
-            const int k = next.fetch_add(1);
-            if (k >= b->count) break;
-            std::string msg;
-            const int rc = solve_instance(b, order[k], s, lambda2, tol, max_iter, &msg);
-            std::lock_guard<std::mutex> g(mu);
-            if (rc < 0 && status >= 0) { status = rc; first_err = msg; }
-            else if (rc > status && status >= 0) status = rc;
+            (void)hipStreamSynchronize(s);
         }
-        (void)hipStreamSynchronize(s);
         (void)hipStreamDestroy(s);
     };
     const int nw = std::min(b->workers, b->count);

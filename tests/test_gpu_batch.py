@@ -11,13 +11,20 @@ from tests.gpu_common import max_abs_diff
 pytestmark = pytest.mark.gpu
 
 
-def test_batch_matches_single_solves_and_oracle():
+@pytest.mark.parametrize("workers", [None, "1"])
+def test_batch_matches_single_solves_and_oracle(workers, monkeypatch):
+    """With one worker every instance of a shape after the first reuses that
+    worker's handle; the results must not depend on it."""
     import torch
     from paper_1710_10769_amd import Batch, Solver
     assert torch.cuda.is_available()
+    if workers:
+        monkeypatch.setenv("CONCORD_BATCH_WORKERS", workers)
     l1s, lam2 = datagen.lambda_path_c4()
     inst = datagen.c4_instances(count=6, scale=0.05)   # p in {50, 100, 200, 400}
-    print("[case] batch 6 instances, p =", [p for p, _, _ in inst], flush=True)
+    print("[case] batch 6 instances, workers", workers, "p =", [p for p, _, _ in inst],
+          flush=True)
+    assert len({p for p, _, _ in inst}) < len(inst), "some shape must repeat"
     Xs = [torch.from_numpy(X.astype(np.float32)).cuda() for _, X, _ in inst]
     b = Batch(Xs, l1s)
     iters, Fs, rc = b.solve(lam2, 1e-5, 200)
