@@ -557,7 +557,72 @@ trial_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
         }
     }
     // quadratic term
-    if (OBS) {
+    if (OBS && e > s && e - s <= 4) {
+        // A row of at most 4 candidates (the common case): the same sums as the general
+        // loop below, with the next column chunk's row loads issued before the current
+        // chunk's FMAs.  The Delta values do not depend on the column and are formed once.
+        const int cnt = (int)(e - s);
+        T dq[4][MAXQ];
+        int64_t rb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t k = s + (u < cnt ? u : 0);
+            rb[u] = (int64_t)acol[k] * ldb;
+            const double om = aom[k], g = agr[k];
+            const bool diag = acol[k] == row;
+            double tau = tau0;
+#pragma unroll
+            for (int q = 0; q < MAXQ; ++q) {
+                dq[u][q] = (T)(prox_one(om, g, tau, tau * lam1, diag) - om);
+                tau *= 0.5;
+            }
+        }
+        const int64_t cstep = (int64_t)nsplit * 64 * V;
+        auto fetch = [&](int64_t c0, T (&b)[4][V]) {
+            const int64_t c = c0 + lane * V;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (u < cnt && c < ncols) Ch::load(B, rb[u] + c, b[u]);
+                else {
+#pragma unroll
+                    for (int t = 0; t < V; ++t) b[u][t] = 0;
+                }
+            }
+        };
+        T bc[4][V], bn[4][V];
+        int64_t c0 = (int64_t)split * 64 * V;
+        if (c0 < ncols) fetch(c0, bc);
+        for (; c0 < ncols; c0 += cstep) {
+            if (c0 + cstep < ncols) fetch(c0 + cstep, bn);
+            T acc[MAXQ][V];
+#pragma unroll
+            for (int q = 0; q < MAXQ; ++q)
+#pragma unroll
+                for (int t = 0; t < V; ++t) acc[q][t] = 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (u >= cnt) break;
+#pragma unroll
+                for (int q = 0; q < MAXQ; ++q) {
+                    if (q < m) {
+#pragma unroll
+                        for (int t = 0; t < V; ++t) acc[q][t] = fma(dq[u][q], bc[u][t], acc[q][t]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < MAXQ; ++q) {
+                if (q < m) {
+#pragma unroll
+                    for (int t = 0; t < V; ++t) squad[q] += (double)acc[q][t] * (double)acc[q][t];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int t = 0; t < V; ++t) bc[u][t] = bn[u][t];
+        }
+    } else if (OBS) {
         // ||Delta_i X^T||^2 over n columns: lanes over columns, loop over entries
         for (int64_t c0 = (int64_t)split * 64 * V; c0 < ncols; c0 += (int64_t)nsplit * 64 * V) {
             const int64_t c = c0 + lane * V;
