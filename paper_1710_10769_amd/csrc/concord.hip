@@ -38,19 +38,6 @@ __global__ void state_reset_kernel(DevState* st) {
     }
 }
 
-// copy objective sums (lg, sq, l1, wsum, ysq) into the state when gated on
-__global__ void obj_finish_kernel(const double* sums, int nysq, DevState* st, const int* gate) {
-    if (threadIdx.x != 0) return;
-    if (gate && *gate == 0) return;
-    st->obj[0] = sums[0];
-    st->obj[1] = sums[1];
-    st->obj[2] = sums[2];
-    st->obj[3] = sums[3];
-    double y = 0.0;
-    for (int i = 0; i < nysq; ++i) y += sums[4 + i];
-    st->obj[4] = y;
-}
-
 __global__ void set_u64_kernel(unsigned long long* p, unsigned long long v) {
     if (threadIdx.x == 0) *p = v;
 }
@@ -328,7 +315,6 @@ int products_at(concord_ctx* c, int which, const int* gate, double bits_lam1 = -
                              c->stream));
         nysq = nch;
         HIPCK(c, launch_obj_parts(O, p, nullptr, c->dstore, 0, c->part, gate, c->stream));
-        HIPCK(c, launch_colsum(c->part, p, 4 + nch, c->objsums, c->colsum_ws, c->stream));
     } else {
         if (bits_lam1 >= 0.0) {
             // the refresh kernel alone gets its own timing class
@@ -344,11 +330,9 @@ int products_at(concord_ctx* c, int which, const int* gate, double bits_lam1 = -
             prof_begin(c, CONCORD_PROF_SPMM);
         }
         HIPCK(c, launch_obj_parts_cov(O, p, c->S, c->sstore, c->ldp, c->part, gate, c->stream));
-        HIPCK(c, launch_colsum(c->part, p, 4, c->objsums, c->colsum_ws, c->stream));
     }
-    hipLaunchKernelGGL(obj_finish_kernel, dim3(1), dim3(64), 0, c->stream, c->objsums, nysq, c->st,
-                       gate);
-    HIPCK(c, hipGetLastError());
+    HIPCK(c, launch_colsum_obj(c->part, p, 4 + nysq, c->objsums, c->colsum_ws, nysq, gate, c->st,
+                               c->stream));
     prof_end(c);
     return CONCORD_OK;
 }
@@ -478,9 +462,8 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
         HIPCK(c, launch_trial(c->A, p, tau0, m, lam1, c->variant, TB, tbstore, tld,
                               c->variant == CONCORD_OBS ? c->ldk : 0, c->part, c->st, c->stream));
         const int S = trial_splits(c->variant, tbstore, c->variant == CONCORD_OBS ? c->ldk : 0);
-        HIPCK(c, launch_colsum(c->part, (int64_t)S * p, 4 * m, c->sums, c->colsum_ws, c->stream));
-        HIPCK(c, launch_decide(c->sums, m, tau0, q_base, lam2, c->variant, inv_n, forced_q, c->st,
-                               c->stream));
+        HIPCK(c, launch_colsum_decide(c->part, (int64_t)S * p, 4 * m, c->sums, c->colsum_ws, m,
+                                      tau0, q_base, lam2, inv_n, forced_q, c->st, c->stream));
         prof_end(c);
         prof_begin(c, CONCORD_PROF_EMIT);
         HIPCK(c, launch_emit_count(c->A, p, lam1, c->st, c->cnt, c->stream));

@@ -163,17 +163,18 @@ hipError_t launch_trial(const Cand& A, int64_t p, double tau0, int m, double lam
                         const void* B, int bstore, int64_t ldb, int64_t ncols, double* part,
                         const struct DevState* st, hipStream_t stream);
 
-// Deterministic FP64 column sums: in[c * rows + r] -> out[c], c < ncol.  ws holds
-// at least ncol * COLSUM_MAXSEG doubles (segment sums).
+// Deterministic FP64 column sums in[c * rows + r] -> out[c], c < ncol, and in the same
+// launch the step that uses them.  ws holds at least ncol * COLSUM_MAXSEG doubles
+// (segment sums); st->ticket must be 0 (it is 0 again when the launch completes).
 constexpr int COLSUM_MAXSEG = 256;
-hipError_t launch_colsum(const double* in, int64_t rows, int ncol, double* out, double* ws,
-                         hipStream_t stream);
-
-// Decision: given per-q sums (sum[q*4 + t]), picks the first passing q
-// (or the forced one) and writes the state.
-hipError_t launch_decide(const double* sums, int m, double tau0, int q_base, double lam2,
-                         int variant, double inv_n, int forced_q, DevState* st,
-                         hipStream_t stream);
+// Trial sums (ncol = 4m, out[q*4 + t]), then the decision: the first passing q (or the
+// forced one) is written to the state.
+hipError_t launch_colsum_decide(const double* in, int64_t rows, int ncol, double* out,
+                                double* ws, int m, double tau0, int q_base, double lam2,
+                                double inv_n, int forced_q, DevState* st, hipStream_t stream);
+// Objective sums (ncol = 4 + nysq), then, when gated on, copied into st->obj.
+hipError_t launch_colsum_obj(const double* in, int64_t rows, int ncol, double* out, double* ws,
+                             int nysq, const int* gate, DevState* st, hipStream_t stream);
 
 // Emission: new CSR from A at the chosen step (state->accepted_q).
 hipError_t launch_emit_count(const Cand& A, int64_t p, double lam1, const DevState* st,
@@ -264,6 +265,7 @@ struct DevState {
     int accepted;           // 1 once a step is accepted (gate of the accept kernels)
     int nonpos;             // forced step leaves the domain
     int overflow;           // candidate capacity exceeded
+    unsigned ticket;        // blocks finished in the running column-sum launch (0 between)
 };
 
 }  // namespace concord

@@ -830,41 +830,9 @@ trial_cov_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ a
     }
 }
 
-// ---- column sums -----------------------------------------------------------------
-// Two fixed-order stages: block (c, b) sums segment b of column c (thread-strided,
-// then an LDS tree) into ws[c * nseg + b]; then one block per column adds its
-// nseg segment sums in order.  The association depends only on (rows, nseg), so
-// results are bitwise reproducible.
-__global__ void __launch_bounds__(NT)
-colsum_seg_kernel(const double* __restrict__ in, int64_t rows, int64_t seg, double* __restrict__ ws) {
-    __shared__ double red[NT];
-    const int c = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
-    const double* a = in + (int64_t)c * rows;
-    const int64_t lo = (int64_t)b * seg, hi = lo + seg < rows ? lo + seg : rows;
-    double s = 0.0;
-    for (int64_t i = lo + t; i < hi; i += NT) s += a[i];
-    red[t] = s;
-    __syncthreads();
-    for (int o = NT / 2; o >= 1; o >>= 1) {
-        if (t < o) red[t] += red[t + o];
-        __syncthreads();
-    }
-    if (t == 0) ws[(int64_t)c * gridDim.y + b] = red[0];
-}
-
-__global__ void __launch_bounds__(64)
-colsum_fin_kernel(const double* __restrict__ ws, int nseg, double* __restrict__ out) {
-    if (threadIdx.x != 0) return;
-    const int c = blockIdx.x;
-    double s = 0.0;
-    for (int b = 0; b < nseg; ++b) s += ws[(int64_t)c * nseg + b];
-    out[c] = s;
-}
-
 // ---- decision ----------------------------------------------------------------
-__global__ void decide_kernel(const double* __restrict__ sums, int m, double tau0, int q_base,
-                              double lam2, double inv_n, int forced_q, DevState* st) {
-    if (threadIdx.x != 0) return;
+__device__ void decide_one(const double* __restrict__ sums, int m, double tau0, int q_base,
+                           double lam2, double inv_n, int forced_q, DevState* st) {
     if (st->overflow || st->accepted_q >= 0) return;   // capacity exceeded / decided earlier
     double tau = tau0;
     for (int q = 0; q < m; ++q) {
@@ -890,6 +858,78 @@ __global__ void decide_kernel(const double* __restrict__ sums, int m, double tau
             return;
         }
         tau *= 0.5;
+    }
+}
+
+// objective sums (log-diagonal, squares, off-diagonal |.|, sum W o Omega) and the nysq
+// ||Y||^2 chunk sums into the state, when gated on
+__device__ void obj_finish_one(const double* __restrict__ sums, int nysq, DevState* st,
+                               const int* gate) {
+    if (gate && *gate == 0) return;
+    st->obj[0] = sums[0];
+    st->obj[1] = sums[1];
+    st->obj[2] = sums[2];
+    st->obj[3] = sums[3];
+    double y = 0.0;
+    for (int i = 0; i < nysq; ++i) y += sums[4 + i];
+    st->obj[4] = y;
+}
+
+struct FinArgs {
+    int m, q_base, forced_q, nysq;
+    double tau0, lam2, inv_n;
+    const int* gate;
+};
+enum { FIN_DECIDE = 0, FIN_OBJ = 1 };
+
+// ---- column sums ---------------------------------------------------------------
+// Column sums with the step that consumes them in the same launch, in two fixed-order
+// stages.  Block (c, b) sums segment b of column c (thread-strided, then an LDS tree)
+// into ws[c * nseg + b], then takes a ticket (device-scope atomic after a device-scope
+// release fence); the
+// block that takes the last ticket adds each column's segment sums in segment order,
+// returns the ticket counter to 0 for the next launch and runs the decision (FIN_DECIDE)
+// or the objective copy (FIN_OBJ).  No block waits for another, so the kernel always
+// completes; the association of every sum depends only on (rows, nseg).
+template <int FIN>
+__global__ void __launch_bounds__(NT)
+colsum_finish_kernel(const double* __restrict__ in, int64_t rows, int64_t seg,
+                     double* __restrict__ ws, double* __restrict__ out, unsigned* ticket,
+                     FinArgs fa, DevState* st) {
+    __shared__ double red[NT];
+    __shared__ int last;
+    const int c = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
+    const int ncol = gridDim.x, nseg = gridDim.y;
+    const double* a = in + (int64_t)c * rows;
+    const int64_t lo = (int64_t)b * seg, hi = lo + seg < rows ? lo + seg : rows;
+    double s = 0.0;
+    for (int64_t i = lo + t; i < hi; i += NT) s += a[i];
+    red[t] = s;
+    __syncthreads();
+    for (int o = NT / 2; o >= 1; o >>= 1) {
+        if (t < o) red[t] += red[t + o];
+        __syncthreads();
+    }
+    if (t == 0) {
+        ws[(int64_t)c * nseg + b] = red[0];
+        __threadfence();
+        last = atomicAdd(ticket, 1u) == (unsigned)(ncol * nseg - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    for (int k = t; k < ncol; k += NT) {
+        double v = ws[(int64_t)k * nseg];
+        for (int j = 1; j < nseg; ++j) v += ws[(int64_t)k * nseg + j];
+        out[k] = v;
+    }
+    __syncthreads();
+    if (t == 0) {
+        *ticket = 0u;
+        if (FIN == FIN_DECIDE)
+            decide_one(out, fa.m, fa.tau0, fa.q_base, fa.lam2, fa.inv_n, fa.forced_q, st);
+        else
+            obj_finish_one(out, fa.nysq, st, fa.gate);
     }
 }
 
@@ -2019,28 +2059,41 @@ hipError_t launch_trial(const Cand& A, int64_t p, double tau0, int m, double lam
     return hipGetLastError();
 }
 
-hipError_t launch_colsum(const double* in, int64_t rows, int ncol, double* out, double* ws,
-                         hipStream_t stream) {
-    if (ncol <= 0) return hipSuccess;
+namespace {
+// segments of at most 8192 rows per column, at most COLSUM_MAXSEG of them
+void colsum_shape(int64_t rows, int* nseg, int64_t* seg) {
     const int64_t seg0 = 8192;
-    int nseg = (int)((rows + seg0 - 1) / seg0);
-    if (nseg < 1) nseg = 1;
-    if (nseg > COLSUM_MAXSEG) nseg = COLSUM_MAXSEG;
-    const int64_t seg = (rows + nseg - 1) / nseg;
-    // a single segment writes the column sums directly
-    hipLaunchKernelGGL(colsum_seg_kernel, dim3(ncol, nseg), dim3(NT), 0, stream, in, rows,
-                       seg < 1 ? 1 : seg, nseg == 1 ? out : ws);
-    if (nseg > 1)
-        hipLaunchKernelGGL(colsum_fin_kernel, dim3(ncol), dim3(64), 0, stream, ws, nseg, out);
+    int ns = (int)((rows + seg0 - 1) / seg0);
+    if (ns < 1) ns = 1;
+    if (ns > COLSUM_MAXSEG) ns = COLSUM_MAXSEG;
+    const int64_t sg = (rows + ns - 1) / ns;
+    *nseg = ns;
+    *seg = sg < 1 ? 1 : sg;
+}
+}  // namespace
+
+hipError_t launch_colsum_decide(const double* in, int64_t rows, int ncol, double* out,
+                                double* ws, int m, double tau0, int q_base, double lam2,
+                                double inv_n, int forced_q, DevState* st, hipStream_t stream) {
+    if (ncol <= 0 || ncol > 4 * MAXQ || m < 1 || 4 * m != ncol) return hipErrorInvalidValue;
+    int nseg;
+    int64_t seg;
+    colsum_shape(rows, &nseg, &seg);
+    FinArgs fa{m, q_base, forced_q, 0, tau0, lam2, inv_n, nullptr};
+    hipLaunchKernelGGL((colsum_finish_kernel<FIN_DECIDE>), dim3(ncol, nseg), dim3(NT), 0, stream,
+                       in, rows, seg, ws, out, &st->ticket, fa, st);
     return hipGetLastError();
 }
 
-hipError_t launch_decide(const double* sums, int m, double tau0, int q_base, double lam2,
-                         int variant, double inv_n, int forced_q, DevState* st,
-                         hipStream_t stream) {
-    (void)variant;
-    hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(64), 0, stream, sums, m, tau0, q_base, lam2,
-                       inv_n, forced_q, st);
+hipError_t launch_colsum_obj(const double* in, int64_t rows, int ncol, double* out, double* ws,
+                             int nysq, const int* gate, DevState* st, hipStream_t stream) {
+    if (ncol < 4 || nysq != ncol - 4) return hipErrorInvalidValue;
+    int nseg;
+    int64_t seg;
+    colsum_shape(rows, &nseg, &seg);
+    FinArgs fa{0, 0, -1, nysq, 0.0, 0.0, 0.0, gate};
+    hipLaunchKernelGGL((colsum_finish_kernel<FIN_OBJ>), dim3(ncol, nseg), dim3(NT), 0, stream,
+                       in, rows, seg, ws, out, &st->ticket, fa, st);
     return hipGetLastError();
 }
 

@@ -107,7 +107,7 @@ def test_incoming_gradient_scales_outputs():
     torch = _torch()
     from paper_1710_10769_amd import Solver
     from paper_1710_10769_amd.autograd import concord_smooth
-    p, n, lam2 = 200, 120, 0.1
+    p, n, lam2 = 203, 120, 0.1   # p % 4 != 0: d f / d X leaves by the element-wise transpose
     _say(f"autograd incoming gradient fp32 p={p} n={n} seed=57")
     _, om, X = _case(p, n, 57, deg=10)
     s = Solver(p, n, variant="obs", precision="fp32")
@@ -122,6 +122,10 @@ def test_incoming_gradient_scales_outputs():
     (gv1, gx1), (gv2, gx2) = grads
     c = torch.tensor(2.5, dtype=torch.float32, device="cuda")
     assert torch.equal(gv2, c * gv1) and torch.equal(gx2, c * gx1)
+    f_ref, G_ref, dX_ref = oc.smooth_value_and_grads(om, X.astype(np.float32).astype(np.float64),
+                                                     lam2)
+    dx = gx1.double().cpu().numpy()
+    assert np.abs(dx - dX_ref).max() <= 1e-4 * np.abs(dX_ref).max()
     s.close()
 
 
