@@ -237,6 +237,10 @@ int concord_smooth_value(concord_ctx* ctx, double lambda2, double* host_f);
      row-major (ld = p) holding G.  G is the gradient over symmetric
      matrices, G = -(Omega_D)^{-1} + 1/2 (Omega S + S Omega) + lambda2 Omega
      (a symmetric perturbation E_ij + E_ji changes f by 2 G_ij).  NULL skips it.
+     The iterate must be symmetric in pattern and values (as concord_set_omega
+     requires): each unordered pair is computed once and written to both of
+     its entries, so in MASKED mode an entry whose mirror is not stored is
+     left unwritten.
    dev_dX: n x p row-major (ld = p) receiving d f / d X = (Omega Y)^T / n
      with Y = Omega X^T recomputed here.  NULL skips it.
    dtype: F64 or F32 for both outputs.  Errors: EINVAL, ENODATA, EHIP. */
