@@ -143,13 +143,13 @@ const char* kVersion = "concord-mi355x 0.1 (gfx950)";
 struct DeviceGuard {
     int prev = -1;
     explicit DeviceGuard(int dev) {
-        hipGetDevice(&prev);
-        if (prev != dev) hipSetDevice(dev);
+        (void)hipGetDevice(&prev);
+        if (prev != dev) (void)hipSetDevice(dev);   // a bad device fails at the first call
     }
     ~DeviceGuard() {
         int now = -1;
-        hipGetDevice(&now);
-        if (prev >= 0 && now != prev) hipSetDevice(prev);
+        (void)hipGetDevice(&now);
+        if (prev >= 0 && now != prev) (void)hipSetDevice(prev);
     }
 };
 
@@ -172,7 +172,7 @@ int dalloc(concord_ctx* c, void** out, size_t bytes, bool zero) {
     hipError_t e = hipMalloc(out, bytes);
     if (e != hipSuccess) {
         *out = nullptr;
-        hipGetLastError();
+        (void)hipGetLastError();   // clear the sticky error of the failed allocation
         return fail(c, CONCORD_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
     }
     c->allocs.push_back(*out);
@@ -187,7 +187,7 @@ void dfree(concord_ctx* c, void* p) {
     if (!p) return;
     for (auto& a : c->allocs)
         if (a == p) {
-            hipFree(p);
+            (void)hipFree(p);
             a = nullptr;
         }
 }
@@ -237,13 +237,13 @@ void prof_begin(concord_ctx* c, int cls) {
     if (!c->prof || c->nrec >= 16) return;
     const int s = c->nrec++;
     c->ev_cls[s] = cls;
-    hipEventRecord(c->ev[s][0], c->stream);
+    (void)hipEventRecord(c->ev[s][0], c->stream);   // if it fails, prof_collect skips the sample
     c->open_slot = s;
 }
 
 void prof_end(concord_ctx* c) {
     if (!c->prof || c->open_slot < 0) return;
-    hipEventRecord(c->ev[c->open_slot][1], c->stream);
+    (void)hipEventRecord(c->ev[c->open_slot][1], c->stream);
     c->open_slot = -1;
 }
 
@@ -641,20 +641,20 @@ void concord_destroy(concord_ctx* ctx) {
     if (!ctx) return;
     {
         DeviceGuard g(ctx->device);
-        hipStreamSynchronize(ctx->stream);
+        (void)hipStreamSynchronize(ctx->stream);
         for (int s = 0; s < 16; ++s)
             for (int t = 0; t < 2; ++t)
-                if (ctx->ev[s][t]) hipEventDestroy(ctx->ev[s][t]);
+                if (ctx->ev[s][t]) (void)hipEventDestroy(ctx->ev[s][t]);
         for (auto& sg : ctx->graphs)
-            if (sg.exec) hipGraphExecDestroy(sg.exec);
+            if (sg.exec) (void)hipGraphExecDestroy(sg.exec);
         if (ctx->use_graph) {
-            hipStreamSynchronize(ctx->stream);
-            hipStreamDestroy(ctx->stream);
-            if (ctx->enter_ev) hipEventDestroy(ctx->enter_ev);
+            (void)hipStreamSynchronize(ctx->stream);
+            (void)hipStreamDestroy(ctx->stream);
+            if (ctx->enter_ev) (void)hipEventDestroy(ctx->enter_ev);
         }
         for (void* a : ctx->allocs)
-            if (a) hipFree(a);
-        if (ctx->st_host) hipHostFree(ctx->st_host);
+            if (a) (void)hipFree(a);
+        if (ctx->st_host) (void)hipHostFree(ctx->st_host);
     }
     delete ctx;
 }
