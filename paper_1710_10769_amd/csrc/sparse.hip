@@ -350,6 +350,21 @@ cand_fill_kernel(const void* __restrict__ M, int64_t ldm, const int64_t* __restr
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    // A row of at most 64 stored entries is copied to LDS once, so the per-candidate
+    // search for omega_ij reads LDS instead of making dependent global loads.
+    __shared__ int32_t ccol[WPB][64];
+    __shared__ double cval[WPB][64];
+    const int64_t nrow = e - s;
+    const bool cached = nrow <= 64;
+    if (cached) {
+        if (lane < nrow) {
+            ccol[wave][lane] = col[s + lane];
+            cval[wave][lane] = val[s + lane];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     // 64 bitmap words (4096 columns) per step, one per lane; an exclusive prefix of
     // their popcounts places each lane's candidates, so the row stays sorted
     for (int64_t w0 = 0; w0 < nwords; w0 += 64) {
@@ -376,12 +391,21 @@ cand_fill_kernel(const void* __restrict__ M, int64_t ldm, const int64_t* __restr
             const int64_t j = w * 64 + b;
             // omega_ij: binary search of the sorted CSR row
             double om = 0.0;
-            int64_t lo_ = s, hi_ = e;
-            while (lo_ < hi_) {
-                const int64_t mid = (lo_ + hi_) >> 1;
-                if (col[mid] < j) lo_ = mid + 1; else hi_ = mid;
+            if (cached) {
+                int lo_ = 0, hi_ = (int)nrow;
+                while (lo_ < hi_) {
+                    const int mid = (lo_ + hi_) >> 1;
+                    if (ccol[wave][mid] < j) lo_ = mid + 1; else hi_ = mid;
+                }
+                if (lo_ < nrow && ccol[wave][lo_] == j) om = cval[wave][lo_];
+            } else {
+                int64_t lo_ = s, hi_ = e;
+                while (lo_ < hi_) {
+                    const int64_t mid = (lo_ + hi_) >> 1;
+                    if (col[mid] < j) lo_ = mid + 1; else hi_ = mid;
+                }
+                if (lo_ < e && col[lo_] == j) om = val[lo_];
             }
-            if (lo_ < e && col[lo_] == j) om = val[lo_];
             acol[pos] = (int32_t)j;
             aom[pos] = om;
             if (M) {
@@ -1504,9 +1528,18 @@ cand_merge_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict_
     __builtin_amdgcn_s_waitcnt(0);
     int64_t total = extra;   // each such entry is one bit of a word counted nowhere else
     if (mrow) {
-        for (int64_t w0 = 0; w0 < nwords; w0 += 64) {
-            const int64_t w = w0 + lane;
-            if (w < nwords && ((mrow[w0 >> 6] >> lane) & 1ull)) total += __popcll(rw[w]);
+        // only the 64-word blocks whose mask word is nonzero: the mask row is read 64
+        // words at a time, one per lane, and its nonzero words are walked by ballot
+        for (int64_t m0 = 0; m0 < TW; m0 += 64) {
+            const uint64_t mw = m0 + lane < TW ? mrow[m0 + lane] : 0ull;
+            uint64_t nz = __ballot(mw != 0ull);
+            while (nz) {
+                const int t = __builtin_ctzll(nz);
+                nz &= nz - 1ull;
+                const uint64_t mk = __shfl(mw, t, 64);
+                const int64_t w = (m0 + t) * 64 + lane;
+                if (w < nwords && ((mk >> lane) & 1ull)) total += __popcll(rw[w]);
+            }
         }
     } else {
         for (int64_t w = lane; w < nwords; w += 64) total += __popcll(rw[w]);
