@@ -1029,6 +1029,18 @@ int concord_gradient(concord_ctx* c, double lam2, int32_t mode, void* dev_dOmega
     if (split) return fail(c, CONCORD_EINVAL, "differentiation form supports FP64 and FP32");
     const Csr& O = c->om[c->cur];
     const int out64 = dtype == CONCORD_F64;
+    if (dev_dOmega && dev_dX && mode == CONCORD_GRAD_MASKED && grad_fused_fits(c->dstore, c->n)) {
+        // both gradients from one gather of the rows Y_j; d f / d X^T = Omega Y / n in a
+        // handle-owned p x n buffer, written transposed (n x p)
+        if (!c->dxt && (rc = dalloc(c, &c->dxt, (size_t)c->prow * c->ldk * elem_bytes(c->dstore), true)))
+            return rc;
+        HIPCK(c, launch_grad_fused(O, c->p, c->Y, c->Xt, c->dstore, c->ldk, c->n, lam2, dev_dOmega,
+                                   out64, c->dxt, c->stream));
+        HIPCK(c, launch_transpose_out(c->dxt, c->dstore, c->p, c->n, c->ldk, 1.0 / (double)c->n,
+                                      dev_dX, out64, c->stream));
+        HIPCK(c, hipStreamSynchronize(c->stream));
+        return CONCORD_OK;
+    }
     if (dev_dOmega) {
         if (mode == CONCORD_GRAD_MASKED) {
             HIPCK(c, launch_sddmm_grad(O, c->p, c->Y, c->Xt, c->dstore, c->ldk, c->n, lam2,

@@ -237,6 +237,12 @@ hipError_t launch_tile_max(const void* S, int sstore, int64_t p, int64_t lds, do
 hipError_t launch_sddmm_grad(const Csr& om, int64_t p, const void* Yt, const void* Xt,
                              int store, int64_t ld, int64_t n, double lam2, void* out,
                              int out_f64, hipStream_t stream);
+// G on the stored entries (as launch_sddmm_grad) and Omega Y (p x ld, as launch_spmm with
+// B = Y) in one pass that gathers each row Y_j once for both; n up to 4 * 64 * V columns.
+bool grad_fused_fits(int store, int64_t n);
+hipError_t launch_grad_fused(const Csr& om, int64_t p, const void* Y, const void* Xt, int store,
+                             int64_t ld, int64_t n, double lam2, void* out, int out_f64,
+                             void* oy, hipStream_t stream);
 hipError_t launch_gather_dense_grad(const void* M, int mstore, int64_t ldm, const Csr& om,
                                     int64_t p, double lam2, void* out, int out_f64,
                                     hipStream_t stream);

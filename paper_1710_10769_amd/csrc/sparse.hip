@@ -1846,6 +1846,155 @@ sddmm_grad_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict_
     }
 }
 
+// Both gradients in one pass over the rows: G_ij on the stored entries as in
+// sddmm_grad_kernel (resident form) and row i of Omega Y (for d f / d X) as spmm_kernel
+// forms it.  Every entry j of row i needs Y_j for Omega Y, and the pairs j >= i also
+// need Xt_j, so the rows Y_j are gathered once for both results.  The entries are
+// walked in CSR order: the Omega Y sums take the FMA order of spmm_kernel and the pair
+// sums that of sddmm_grad_kernel, so both outputs equal the separate kernels' bitwise.
+template <int S, int RC>
+__global__ void __launch_bounds__(NT)
+grad_fused_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                  const double* __restrict__ val, int64_t p, const void* __restrict__ Y,
+                  const void* __restrict__ Xt, int64_t ld, int64_t n, double lam2, void* out,
+                  int out_f64, void* __restrict__ oy) {
+    typedef Chunk<S> Ch;
+    typedef typename Ch::T T;
+    constexpr int V = Ch::V;
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
+    if (row >= p) return;
+    const int64_t s = rowptr[row], e = rowptr[row + 1];
+    const int nch = (int)((n + 64 * V - 1) / (64 * V));
+    T yi[RC][V], xi[RC][V], acc[RC][V];
+#pragma unroll
+    for (int q = 0; q < RC; ++q) {
+        const int64_t c = (int64_t)q * 64 * V + lane * V;
+#pragma unroll
+        for (int t = 0; t < V; ++t) acc[q][t] = 0;
+        if (q < nch && c < n) {
+            Ch::load(Y, row * ld + c, yi[q]);
+            Ch::load(Xt, row * ld + c, xi[q]);
+        } else {
+#pragma unroll
+            for (int t = 0; t < V; ++t) { yi[q][t] = 0; xi[q][t] = 0; }
+        }
+    }
+    const double inv2n = 1.0 / (2.0 * (double)n);
+    double v[SDDMM_GROUP];
+#pragma unroll
+    for (int g = 0; g < SDDMM_GROUP; ++g) v[g] = 0.0;
+    int my_t = 0, m = 0;
+    int jl = -1;
+    int64_t mpos = -1, b = s;
+    // the wave sums of up to 8 pairs (entries b + t of the current block) and their writes
+    auto flush = [&]() {
+#pragma unroll
+        for (int w = SDDMM_GROUP, o = 32; w > 1; w >>= 1, o >>= 1) {
+            const bool upper = (lane & o) != 0;
+#pragma unroll
+            for (int i = 0; i < w / 2; ++i) {
+                const double send = upper ? v[i] : v[i + w / 2];
+                const double keep = upper ? v[i + w / 2] : v[i];
+                v[i] = keep + __shfl_xor(send, o, 64);
+            }
+        }
+        double tot = v[0];
+#pragma unroll
+        for (int o = 4; o >= 1; o >>= 1) tot += __shfl_xor(tot, o, 64);
+        const int g = (lane >> 3) & 7;
+        const int t = __shfl(my_t, g, 64);
+        const int64_t mp = __shfl(mpos, t, 64);
+        const int j = __shfl(jl, t, 64);
+        if ((lane & 7) == 0 && g < m) {
+            const int64_t k = b + t;
+            const double wv = val[k];
+            double gr = tot * inv2n + lam2 * wv;
+            if (j == row) gr -= 1.0 / wv;
+            if (out_f64) {
+                ((double*)out)[k] = gr;
+                if (mp >= 0) ((double*)out)[mp] = gr;
+            } else {
+                ((float*)out)[k] = (float)gr;
+                if (mp >= 0) ((float*)out)[mp] = (float)gr;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < SDDMM_GROUP; ++i) v[i] = 0.0;
+        m = 0;
+    };
+    for (; b < e; b += 64) {
+        const int cnt = (int)(e - b < 64 ? e - b : 64);
+        jl = -1;
+        mpos = -1;
+        if (lane < cnt) {
+            jl = col[b + lane];
+            if (jl > row) {
+                const int64_t me = rowptr[jl + 1];
+                int64_t lo_ = rowptr[jl], hi_ = me;
+                while (lo_ < hi_) {
+                    const int64_t mid = (lo_ + hi_) >> 1;
+                    if (col[mid] < row) lo_ = mid + 1; else hi_ = mid;
+                }
+                if (lo_ < me && col[lo_] == row) mpos = lo_;
+            }
+        }
+        const uint64_t own = __ballot(lane < cnt && jl >= row);
+        for (int t = 0; t < cnt; ++t) {
+            const int64_t k = b + t;
+            const int64_t j = (int64_t)col[k];
+            const T wv = (T)val[k];
+            const bool pair = (own >> t) & 1ull;
+            T yj[RC][V], xj[RC][V];
+#pragma unroll
+            for (int q = 0; q < RC; ++q) {
+                const int64_t c = (int64_t)q * 64 * V + lane * V;
+                if (q < nch && c < n) {
+                    Ch::load(Y, j * ld + c, yj[q]);
+                    if (pair) Ch::load(Xt, j * ld + c, xj[q]);
+                }
+            }
+            double a2 = 0.0;
+#pragma unroll
+            for (int q = 0; q < RC; ++q) {
+                const int64_t c = (int64_t)q * 64 * V + lane * V;
+                if (q < nch && c < n) {
+#pragma unroll
+                    for (int u = 0; u < V; ++u) acc[q][u] = fma(wv, yj[q][u], acc[q][u]);
+                    if (pair) {
+                        T a = 0;
+#pragma unroll
+                        for (int u = 0; u < V; ++u) a += yi[q][u] * xj[q][u] + yj[q][u] * xi[q][u];
+                        a2 += (double)a;
+                    }
+                }
+            }
+            if (pair) {
+#pragma unroll
+                for (int g = 0; g < SDDMM_GROUP; ++g) v[g] = g == m ? a2 : v[g];
+                if (lane == m) my_t = t;
+                if (++m == SDDMM_GROUP) flush();
+            }
+        }
+        if (m > 0) flush();
+    }
+#pragma unroll
+    for (int q = 0; q < RC; ++q) {
+        const int64_t c = (int64_t)q * 64 * V + lane * V;
+        if (q < nch && c < n) {
+            if (S == ST_F64) {
+                double* o = (double*)oy + row * ld + c;
+#pragma unroll
+                for (int u = 0; u < V; ++u) o[u] = (double)acc[q][u];
+            } else {
+                float* o = (float*)oy + row * ld + c;
+#pragma unroll
+                for (int u = 0; u < V; ++u) o[u] = (float)acc[q][u];
+            }
+        }
+    }
+}
+
 template <int S>
 __global__ void __launch_bounds__(NT)
 dense_grad_kernel(const void* __restrict__ M, int64_t ldm, const int64_t* __restrict__ rowptr,
@@ -2360,6 +2509,25 @@ hipError_t launch_sddmm_grad(const Csr& om, int64_t p, const void* Y, const void
     if (store == ST_F64) SDDMM(ST_F64);
     else SDDMM(ST_F32);
 #undef SDDMM
+    return hipGetLastError();
+}
+
+bool grad_fused_fits(int store, int64_t n) {
+    return n <= 4 * 64 * (store == ST_F64 ? Chunk<ST_F64>::V : Chunk<ST_F32>::V);
+}
+
+hipError_t launch_grad_fused(const Csr& om, int64_t p, const void* Y, const void* Xt, int store,
+                             int64_t ld, int64_t n, double lam2, void* out, int out_f64,
+                             void* oy, hipStream_t stream) {
+    if (p == 0) return hipSuccess;
+    if (!grad_fused_fits(store, n)) return hipErrorInvalidValue;
+    dim3 grid(blocks_for(p, WPB));
+    if (store == ST_F64)
+        hipLaunchKernelGGL((grad_fused_kernel<ST_F64, 4>), grid, dim3(NT), 0, stream, om.rowptr,
+                           om.col, om.val, p, Y, Xt, ld, n, lam2, out, out_f64, oy);
+    else
+        hipLaunchKernelGGL((grad_fused_kernel<ST_F32, 4>), grid, dim3(NT), 0, stream, om.rowptr,
+                           om.col, om.val, p, Y, Xt, ld, n, lam2, out, out_f64, oy);
     return hipGetLastError();
 }
 

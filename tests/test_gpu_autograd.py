@@ -101,6 +101,27 @@ def test_backward_long_rows_vs_oracle(precision, n, deg):
     s.close()
 
 
+@pytest.mark.parametrize("precision,n,deg", [("fp32", 1000, 20), ("fp64", 400, 90)])
+def test_both_gradients_in_one_pass_equal_separate_passes(precision, n, deg):
+    """Asking for both gradients takes the one-pass kernel (each row Y_j gathered once
+    for both); its outputs equal those of the two separate passes bitwise."""
+    torch = _torch()
+    from paper_1710_10769_amd import Solver
+    p, lam2 = 333, 0.1
+    _say(f"autograd fused vs separate {precision} p={p} n={n} deg={deg} seed=58")
+    _, om, X = _case(p, n, 58, deg=deg)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    s = Solver(p, n, variant="obs", precision=precision)
+    rp, cl, v = _csr_tensors(torch, om, dt)
+    s.set_data(torch.from_numpy(X).to("cuda", dt))
+    s.set_omega(rp, cl, v)
+    g_both, x_both = s.gradient(lam2, want_omega=True, want_x=True, dtype=dt)
+    g_only, _ = s.gradient(lam2, want_omega=True, want_x=False, dtype=dt)
+    _, x_only = s.gradient(lam2, want_omega=False, want_x=True, dtype=dt)
+    assert torch.equal(g_both, g_only) and torch.equal(x_both, x_only)
+    s.close()
+
+
 def test_incoming_gradient_scales_outputs():
     """backward of c * f returns c times the gradients of f (the unit case skips the
     multiply; any other incoming gradient takes it)."""
