@@ -1853,7 +1853,7 @@ sddmm_grad_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict_
 // walked in CSR order: the Omega Y sums take the FMA order of spmm_kernel and the pair
 // sums that of sddmm_grad_kernel, so both outputs equal the separate kernels' bitwise.
 template <int S, int RC>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT, 4)
 grad_fused_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                   const double* __restrict__ val, int64_t p, const void* __restrict__ Y,
                   const void* __restrict__ Xt, int64_t ld, int64_t n, double lam2, void* out,
@@ -1866,18 +1866,24 @@ grad_fused_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict_
     if (row >= p) return;
     const int64_t s = rowptr[row], e = rowptr[row + 1];
     const int nch = (int)((n + 64 * V - 1) / (64 * V));
-    T yi[RC][V], xi[RC][V], acc[RC][V];
+    // rows i of Y and Xt sit in LDS (each lane reads back only its own elements): with
+    // them in registers the kernel needed 160 VGPRs (3 waves per SIMD); so it fits 4
+    __shared__ T rows_i[WPB][2][RC][V][64];
+    T acc[RC][V];
 #pragma unroll
     for (int q = 0; q < RC; ++q) {
         const int64_t c = (int64_t)q * 64 * V + lane * V;
+        T yv[V], xv[V];
 #pragma unroll
-        for (int t = 0; t < V; ++t) acc[q][t] = 0;
+        for (int t = 0; t < V; ++t) { acc[q][t] = 0; yv[t] = 0; xv[t] = 0; }
         if (q < nch && c < n) {
-            Ch::load(Y, row * ld + c, yi[q]);
-            Ch::load(Xt, row * ld + c, xi[q]);
-        } else {
+            Ch::load(Y, row * ld + c, yv);
+            Ch::load(Xt, row * ld + c, xv);
+        }
 #pragma unroll
-            for (int t = 0; t < V; ++t) { yi[q][t] = 0; xi[q][t] = 0; }
+        for (int t = 0; t < V; ++t) {
+            rows_i[wave][0][q][t][lane] = yv[t];
+            rows_i[wave][1][q][t][lane] = xv[t];
         }
     }
     const double inv2n = 1.0 / (2.0 * (double)n);
@@ -1964,7 +1970,9 @@ grad_fused_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict_
                     if (pair) {
                         T a = 0;
 #pragma unroll
-                        for (int u = 0; u < V; ++u) a += yi[q][u] * xj[q][u] + yj[q][u] * xi[q][u];
+                        for (int u = 0; u < V; ++u)
+                            a += rows_i[wave][0][q][u][lane] * xj[q][u] +
+                                 yj[q][u] * rows_i[wave][1][q][u][lane];
                         a2 += (double)a;
                     }
                 }
