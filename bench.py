@@ -472,8 +472,9 @@ def bench_c5(args, torch, np, datagen):
 def bench_c4(args, torch, np, datagen):
     """Batched lambda path: 48 Cov instances (p in {1k, 2k, 4k, 8k}, n = p/2), each
     solved at lambda1 in {0.2, 0.3, 0.5} from Omega = I (FP32 products, FP64
-    reductions, stop at relative F change < 1e-5 or 200 iterations).  A step is
-    one whole path (all 144 solves); value = solves per second."""
+    reductions, stop at relative F change < 1e-5 or 200 iterations), all 144 solves on
+    the device at once (graph replays of 4 iterations, device-side control).  A step is
+    one whole path from the data (S formation included); value = solves per second."""
     from paper_1710_10769_amd import Batch
     l1s, lam2 = datagen.lambda_path_c4()
     log("generating 48 instances")
@@ -482,17 +483,20 @@ def bench_c4(args, torch, np, datagen):
     torch.cuda.synchronize()
     times = []
     iters = None
+    stats = None
     for rep in range(args.warmup + args.steps):
-        b = Batch(Xs, l1s)
+        b = Batch(Xs, l1s, iters_per_launch=args.iters_per_launch)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         iters, Fs, rc = b.solve(lam2, 1e-5, 200)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        stats = b.stats()
         b.close()
         if rep >= args.warmup:
             times.append(t1 - t0)
-        log(f"path {rep}: {t1 - t0:.3f} s, mean iterations {np.mean(iters):.1f}")
+        log(f"path {rep}: {t1 - t0:.4f} s (S {stats['s_ms']:.1f} ms, iterations "
+            f"{stats['iterate_ms']:.1f} ms, {stats['launches']} replays), max iterations {max(iters)}")
     sec = float(np.mean(times))
     nsolve = len(inst) * len(l1s)
     line = {
@@ -502,7 +506,8 @@ def bench_c4(args, torch, np, datagen):
         "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
         "config": {"workload": "cov_batched_lambda_path_48x3", "instances": len(inst),
                    "p": [p for p, _, _ in inst], "lambda1": list(l1s), "lam2": lam2},
-        "mean_iterations": float(np.mean(iters)), "total_iterations": int(np.sum(iters)),
+        "mean_iterations": float(np.mean(iters)), "max_iterations": int(max(iters)),
+        "total_iterations": int(np.sum(iters)), "last_path": stats,
     }
     print(json.dumps(line), flush=True)
 
@@ -516,6 +521,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cov-context", action="store_true",
                     help="skip timing the Cov form on the same problem")
+    ap.add_argument("--iters-per-launch", type=int, default=4,
+                    help="c4 only: iterations captured per graph replay")
     ap.add_argument("--p", type=int, default=20000)
     ap.add_argument("--n", type=int, default=5000)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "c6"],

@@ -52,7 +52,7 @@ extern "C" {
 #define CONCORD_OK            0
 #define CONCORD_WMAXITER      1   /* concord_solve: max_iter reached before tol */
 #define CONCORD_EINVAL       -1   /* bad argument: lambda < 0, tol <= 0, dims, dtype, shape */
-#define CONCORD_ENOMEM       -2   /* device allocation failed */
+#define CONCORD_ENOMEM       -2   /* device allocation failed (or alloc_fn returned NULL) */
 #define CONCORD_EHIP         -3   /* HIP runtime error (message in last_error) */
 #define CONCORD_ENOTPD       -4   /* a supplied Omega has a diagonal entry <= 0 */
 #define CONCORD_ENONFINITE   -5   /* NaN or Inf in X, S or Omega */
@@ -62,6 +62,9 @@ extern "C" {
 /* ---- enums ---- */
 #define CONCORD_COV 0
 #define CONCORD_OBS 1
+#define CONCORD_AUTO 2   /* concord_create picks COV or OBS: Lemma 3.1's work priced with rates
+                            measured on the device (see concord_suggest_variant); the handle
+                            then runs that form (concord_variant_of) */
 
 #define CONCORD_FP64   0   /* products and storage in FP64 */
 #define CONCORD_FP32   1   /* products in FP32 (FP32 MFMA / FP32 FMA), FP64 reductions */
@@ -80,14 +83,25 @@ extern "C" {
 
 typedef struct concord_ctx concord_ctx;
 
+/* Device-memory allocator bridge (e.g. a framework's caching allocator).
+   alloc returns `bytes` of device memory of the handle's device usable on
+   `stream` (the hipStream_t the handle orders its work on), or NULL on
+   failure, which the library reports as CONCORD_ENOMEM.  free returns a block
+   obtained from alloc with the same size; the library has synchronised
+   `stream` before it frees, so no queued work of its own still uses the block.
+   `user` is passed through unchanged.  Both may be called from any host
+   thread that calls into the library. */
+typedef void* (*concord_alloc_fn)(void* user, size_t bytes, void* stream);
+typedef void (*concord_free_fn)(void* user, void* ptr, size_t bytes, void* stream);
+
 typedef struct concord_config {
     int64_t p;              /* number of variables, >= 1 */
     int64_t n;              /* number of observations, >= 1 (ignored when S is supplied) */
-    int32_t variant;        /* CONCORD_COV or CONCORD_OBS */
+    int32_t variant;        /* CONCORD_COV, CONCORD_OBS or CONCORD_AUTO */
     int32_t precision;      /* CONCORD_FP64, CONCORD_FP32 or CONCORD_BF16X3 */
     void*   stream;         /* hipStream_t to order all work on; NULL = null stream */
     int32_t device;         /* HIP device ordinal; -1 = the current device */
-    int32_t max_backtracks; /* step-size halvings allowed per iteration (default 60) */
+    int32_t max_backtracks; /* step-size reductions allowed per iteration (default 60) */
     int32_t trial_batch;    /* step sizes evaluated together per launch, 1..8 (default 8) */
     int32_t use_graph;      /* 1: the handle works on a stream of its own (ordered after
                                `stream` at every call) and replays each iteration's common
@@ -98,6 +112,18 @@ typedef struct concord_config {
                                (see concord_refresh_screen_stats) when p > 448 (smaller
                                problems refresh every pair).  Same results either way. */
     int32_t reserved;       /* set to 0 */
+    /* Step sizes of the backtracking search (Algorithm 1: tau = 1, 1/2, 1/4, ...):
+       every iteration tries tau0, tau0 * shrink, tau0 * shrink^2, ... (each a
+       product formed left to right in FP64), restarting at tau0. */
+    double  tau0;           /* > 0, default 1 */
+    double  shrink;         /* in (0, 1), default 0.5 */
+    /* Device memory for the handle's workspace: both NULL (default) = hipMalloc /
+       hipFree; otherwise both must be set.  Every device buffer the handle owns
+       (data layout, Omega, candidates, products, partial sums) comes from
+       alloc_fn and goes back through free_fn. */
+    concord_alloc_fn alloc_fn;
+    concord_free_fn  free_fn;
+    void*   alloc_user;     /* passed to alloc_fn / free_fn */
 } concord_config;
 
 /* Per-iteration record (Algorithm 1, one pass of the outer loop). */
@@ -124,13 +150,17 @@ typedef struct concord_solve_info {
 } concord_solve_info;
 
 /* Fill *cfg with defaults: variant COV, precision FP64, stream NULL,
-   device -1, max_backtracks 60, trial_batch 8, use_graph 0, p = n = 0. */
+   device -1, max_backtracks 60, trial_batch 8, use_graph 0, tau0 1,
+   shrink 0.5, no allocator bridge, p = n = 0. */
 void concord_config_init(concord_config* cfg);
 
 /* Create a handle for problems of size p (and n).  Allocates the workspace
-   for X/S, Omega and the products on cfg->device.  Omega starts at I
-   (Algorithm 1, first line).  Errors: EINVAL (p < 1, n < 1 when needed,
-   unknown variant/precision, trial_batch outside 1..8), ENOMEM, EHIP. */
+   for X/S, Omega and the products on cfg->device (through cfg->alloc_fn when
+   set).  Omega starts at I (Algorithm 1, first line).  Errors: EINVAL (p < 1,
+   n < 1 when needed, unknown variant/precision, trial_batch outside 1..8,
+   tau0 <= 0, shrink outside (0, 1), only one of alloc_fn / free_fn set),
+   ENOMEM (an allocation failed or alloc_fn returned NULL; everything allocated
+   so far has been returned), EHIP. */
 int concord_create(const concord_config* cfg, concord_ctx** out);
 
 /* Load the data (device pointer, row-major, leading dimension ld >= cols).
@@ -152,8 +182,10 @@ int concord_create(const concord_config* cfg, concord_ctx** out);
 int concord_set_data(concord_ctx* ctx, int32_t kind, const void* dev_data, int32_t dtype,
                      int64_t rows, int64_t cols, int64_t ld);
 
-/* Replace the iterate by a caller-supplied symmetric CSR matrix (warm start,
-   checkpoint resume).  Device arrays: row_ptr int64[p+1] (row_ptr[0] = 0),
+/* Replace the iterate by a caller-supplied symmetric CSR matrix: the starting
+   point Omega^0 of Algorithm 1 (its first line sets Omega^0 = I; any positive-
+   diagonal symmetric start is as valid for the method), used for warm starts
+   along a lambda path (Section 5) and to resume from a checkpoint.  Device arrays: row_ptr int64[p+1] (row_ptr[0] = 0),
    col int32[nnz] (sorted and unique within each row, both triangles, the
    diagonal present in every row), val[nnz] of dtype.  Symmetry is the
    caller's promise and is not checked.  Sets k to 0.
@@ -162,7 +194,8 @@ int concord_set_data(concord_ctx* ctx, int32_t kind, const void* dev_data, int32
 int concord_set_omega(concord_ctx* ctx, int64_t nnz, const int64_t* dev_row_ptr,
                       const int32_t* dev_col, const void* dev_val, int32_t dtype);
 
-/* Omega <- I, k <- 0. */
+/* Omega <- I, k <- 0: the initialisation of Algorithm 1 (its first line) and of
+   Algorithms 2 and 3. */
 int concord_reset(concord_ctx* ctx);
 
 /* One outer iteration of Algorithm 1 (Algorithm 2 or 3 for the products):
@@ -179,7 +212,8 @@ int concord_reset(concord_ctx* ctx);
    (Omega and k unchanged), EHIP. */
 int concord_step(concord_ctx* ctx, double lambda1, double lambda2, concord_step_info* info);
 
-/* As concord_step, but the step size is forced: tau = 2^-(trials-1) is
+/* As concord_step, but the step size is forced: tau = tau0 * shrink^(trials-1)
+   (2^-(trials-1) with the defaults) is
    accepted without the test (its terms are still reported).  trials >= 1.
    Used to replay a reference run's step sizes.  Errors as concord_step, plus
    ENOTPD if the forced step leaves a diagonal entry <= 0. */
@@ -211,16 +245,35 @@ int concord_refresh_screen_stats(concord_ctx* ctx, double lambda1, int64_t* host
                                  int64_t* host_active);
 
 /* f and F at the current iterate, FP64 (host pointers; either may be NULL).
-   Errors: EINVAL, ENODATA, EHIP. */
+   f is the smooth value Algorithm 1 evaluates before each search (the
+   log-diagonal, trace and Frobenius terms; Algorithm 2 forms the trace from
+   W = Omega S, Algorithm 3 from ||Omega X^T||^2 / n), F adds the l1 term of
+   eq. (1) over the off-diagonal entries.  Errors: EINVAL, ENODATA, EHIP. */
 int concord_objective(concord_ctx* ctx, double lambda1, double lambda2, double* host_f,
                       double* host_F);
 
-/* Copy the current iterate out as CSR (same layout as concord_set_omega).
+/* Copy the current iterate out as CSR (same layout as concord_set_omega): the
+   estimate Algorithm 1 returns (its output) after the last accepted step.
    Always writes *host_nnz.  If dev_row_ptr is NULL only the size is
    returned; otherwise dev_row_ptr (p+1), dev_col and dev_val (capacity >=
    *host_nnz as returned by a sizing call) are filled.  dtype: F64 or F32. */
 int concord_get_omega(concord_ctx* ctx, int64_t* host_nnz, int64_t* dev_row_ptr,
                       int32_t* dev_col, void* dev_val, int32_t dtype);
+
+/* Candidate set of the last step and the gradient on it (Algorithm 1's
+   gradient step and prox argument).  A = supp(Omega^k) U {i != j : |G_ij| >
+   lambda1 restricted to where omega_ij = 0} U diag holds every entry the
+   step's soft threshold (eq. (2)) could leave nonzero at any step size; for
+   each entry the call returns omega^k_ij and G_ij = (W + W^T)_ij / 2 +
+   lambda2 omega^k_ij - [i == j] / omega^k_ii at the iterate Omega^k the step
+   started from (W = Omega^k S).  Layout: CSR over p rows, row_ptr int64[p+1],
+   col int32 (sorted), omega and grad double[nnz]; device arrays.  Always
+   writes *host_nnz = |A|; with dev_row_ptr NULL only the size is returned.
+   The set belongs to the last successful concord_step / concord_step_replay
+   / step of concord_solve on this handle.  Errors: EINVAL, ENODATA (no step
+   since the iterate or the data was last set), EHIP. */
+int concord_get_candidates(concord_ctx* ctx, int64_t* host_nnz, int64_t* dev_row_ptr,
+                           int32_t* dev_col, double* dev_omega, double* dev_grad);
 
 /* Number of completed iterations of the current iterate. */
 int64_t concord_iterations(const concord_ctx* ctx);
@@ -247,23 +300,67 @@ int concord_smooth_value(concord_ctx* ctx, double lambda2, double* host_f);
 int concord_gradient(concord_ctx* ctx, double lambda2, int32_t mode, void* dev_dOmega,
                      void* dev_dX, int32_t dtype);
 
-/* Batched lambda path over several independent Cov problems.
-   count instances; instance b has p_b variables and its data X_b (device,
-   n_b x p_b row-major, ld_b, FP32) given by the descriptor arrays.  Every
-   instance is solved at every lambda1 in host_lambda1[0..n_l1-1] (lambda2
-   common), each from Omega = I, with the stopping rule of concord_solve.
-   Results: host_iters[b*n_l1 + l] and host_F[b*n_l1 + l] (host arrays of
-   count*n_l1); the estimates stay in the batch handle and are read with
-   concord_batch_get_omega.  Precision FP32 products, FP64 reductions. */
+/* ---- batched lambda path (Section 5 solves a grid of lambda values; Section S.3.1) ----
+   Many independent Cov problems (Algorithm 2), each solved at every lambda1 of a path
+   from Omega = I with the stopping rule of concord_solve, all at once on one device:
+   every phase of an iteration (candidates, trials and decision, emission, the refresh
+   of W = Omega S and the objective, the stopping test) is one launch over all solves
+   still running, with the control state of every solve (iteration, step-size index,
+   phase, objective) in device memory and no host decision between phases.  Up to
+   iters_per_launch iterations are captured as one HIP graph and replayed until every
+   solve has stopped; the host reads two counters per replay.  The refresh is
+   lambda-stacked: each tile pair any solve of an instance keeps is processed once for
+   all of that instance's lambda1 values, which read the same S tiles.
+   Each solve's iterates are bitwise those of the single solver (concord_solve on a Cov
+   handle of the same precision, trial batch, tau0, shrink and max_backtracks).
+   S = X_b^T X_b / n_b is formed for every instance (MFMA, the autotuned contraction of
+   its shape) by the first concord_batch_solve and kept for later calls. */
 typedef struct concord_batch concord_batch;
-int concord_batch_create(int32_t count, const int64_t* host_p, const int64_t* host_n,
-                         const void* const* host_dev_X, const int64_t* host_ld, int32_t n_l1,
-                         const double* host_lambda1, void* stream, concord_batch** out);
+typedef struct concord_batch_config {
+    int32_t precision;        /* CONCORD_FP32 (default) or CONCORD_FP64 products */
+    int32_t device;           /* -1 = the current device */
+    void*   stream;           /* hipStream_t; NULL = null stream */
+    int32_t max_backtracks;   /* 60 */
+    int32_t trial_batch;      /* 1..8, default 8 */
+    double  tau0, shrink;     /* 1, 0.5 (as concord_config) */
+    int32_t iters_per_launch; /* iterations per graph replay, 1..64 (default 4) */
+    int32_t use_graph;        /* 1 (default): replay captured iterations; 0: direct launches */
+    concord_alloc_fn alloc_fn;   /* device memory bridge, as in concord_config */
+    concord_free_fn  free_fn;
+    void*   alloc_user;
+} concord_batch_config;
+void concord_batch_config_init(concord_batch_config* cfg);
+
+/* count instances; instance b has p_b variables and data X_b (device, n_b x p_b
+   row-major with leading dimension ld_b, FP32 for the FP32 form, FP64 for FP64),
+   borrowed until the first concord_batch_solve has formed its S.  Every instance is
+   solved at every lambda1 in host_lambda1[0 .. n_l1 - 1].  cfg may be NULL (defaults).
+   Errors: EINVAL (count or n_l1 < 1, p, n < 1, ld < p, null data, lambda1 < 0, bad
+   config), ENOMEM, EHIP. */
+int concord_batch_create(const concord_batch_config* cfg, int32_t count, const int64_t* host_p,
+                         const int64_t* host_n, const void* const* host_dev_X,
+                         const int64_t* host_ld, int32_t n_l1, const double* host_lambda1,
+                         concord_batch** out);
+/* Solve every (instance, lambda1) with lambda2, tol and max_iter (concord_solve's rule),
+   each from Omega = I.  Per solve s = b * n_l1 + l (host arrays of count * n_l1, any
+   may be NULL): accepted iterations, F at the estimate, and the solve's status
+   (CONCORD_OK, CONCORD_WMAXITER or CONCORD_ELINESEARCH).  Returns the largest warning,
+   or the first error.  Errors: EINVAL, ENOMEM, EHIP. */
 int concord_batch_solve(concord_batch* b, double lambda2, double tol, int64_t max_iter,
-                        int64_t* host_iters, double* host_F);
+                        int64_t* host_iters, double* host_F, int32_t* host_status);
+/* The estimate of (instance, l1_index) as CSR (layout of concord_get_omega, values
+   double); with dev_row_ptr NULL only *host_nnz is written. */
 int concord_batch_get_omega(concord_batch* b, int32_t instance, int32_t l1_index,
                             int64_t* host_nnz, int64_t* dev_row_ptr, int32_t* dev_col,
                             double* dev_val);
+/* Counters of the last concord_batch_solve: graph replays (or direct iteration
+   groups), host synchronisations, iterations launched (the longest solve's count plus
+   the replays' idle tail), milliseconds forming S and iterating. */
+typedef struct concord_batch_stats {
+    int64_t launches, host_syncs, iterations_launched, regrows;
+    double  s_ms, iterate_ms;
+} concord_batch_stats;
+int concord_batch_stats_get(const concord_batch* b, concord_batch_stats* out);
 const char* concord_batch_last_error(const concord_batch* b);
 void concord_batch_destroy(concord_batch* b);
 
@@ -297,20 +394,24 @@ int concord_get_profile(const concord_ctx* ctx, concord_profile* host_out);
    never tuned), or CONCORD_EINVAL for a null handle. */
 int concord_contraction_variant(const concord_ctx* ctx, char* host_name, int32_t host_cap);
 
-/* ---- choice of the product form (Section 3, Lemma 3.1; Section S.1) ----
+/* ---- choice of the product form (Section 3, Lemma 3.1; Section S.1; Section 4) ----
    Lemma 3.1 counts F_Cov = 2np^2 + 2dp^2(st+1) and F_Obs = 2np^2 s + 2dnp(st+1)
    flops for s iterations with t step sizes tried per iteration and d nonzeros
    per row of Omega on average; paper_choice is the form with fewer flops.
-   choice is the form with the shorter modelled time on this library's kernels:
-     Cov: S once (symmetric, n p^2 flops at dense_tflops) + per iteration the
-          streaming passes of W = Omega S, its symmetrisation and the candidate
-          scan, 5 p^2 elements at hbm_gbps;
-     Obs: per iteration the symmetric rank-2n contraction (2 n p^2 flops at
-          dense_tflops) + the candidate scan and the Y refresh, p^2 + 3 p n
-          elements at hbm_gbps.
-   dense_tflops / hbm_gbps <= 0 select rates measured on MI355X for `precision`
-   (BF16 split 330, FP32 125, FP64 60 TFLOP/s useful; 3200 GB/s).  Host-only:
-   no GPU is touched.  Errors: EINVAL (p, n < 1; d, t, s < 0; precision). */
+   Section 4 notes that the two terms run at very different rates (sparse-dense
+   products far slower per flop than dense ones), so choice prices the work this
+   library does, with dense_tflops the useful rate of its dense contraction and
+   hbm_gbps its memory rate:
+     Cov: S once (symmetric: n p^2 flops) + per iteration the refresh of
+          W = Omega S, which reads the S tiles of the kept tile pairs
+          (screen_fraction of them; 1 = no screening, an upper bound) and writes
+          and reads the candidate threshold words (p^2 / 4 bytes);
+     Obs: per iteration the symmetric rank-2n contraction (2 n p^2 flops) and the
+          write and read of its dense result (2 p^2 elements) and of Y (2 p n).
+   dense_tflops / hbm_gbps <= 0 select built-in MI355X figures for `precision`
+   (BF16 split 330, FP32 125, FP64 60 TFLOP/s useful; 3200 GB/s); screen_fraction
+   <= 0 selects 1.  Host-only: no GPU is touched.
+   Errors: EINVAL (p, n < 1; d, t, s < 0; precision). */
 typedef struct concord_variant_estimate {
     int32_t paper_choice;   /* CONCORD_COV or CONCORD_OBS by flop count */
     int32_t choice;         /* CONCORD_COV or CONCORD_OBS by modelled time */
@@ -318,7 +419,21 @@ typedef struct concord_variant_estimate {
     double  cov_seconds, obs_seconds;
 } concord_variant_estimate;
 int concord_suggest_variant(int64_t p, int64_t n, double d, double t, double s, int32_t precision,
-                            double dense_tflops, double hbm_gbps, concord_variant_estimate* out);
+                            double dense_tflops, double hbm_gbps, double screen_fraction,
+                            concord_variant_estimate* out);
+
+/* Rates of this library measured on `device` (-1: current) for `precision`, once per
+   process and cached: the useful FP rate of the dense symmetric contraction on a
+   p = 4096, K = 2048 problem (its autotuned tile variant) and the device-to-device
+   copy rate of 256 MiB (bytes read + written per second).  CONCORD_AUTO prices
+   concord_suggest_variant with them (d = 5, t = 3, s = 30, screen_fraction 1).
+   Output pointers may be NULL.  Errors: EINVAL (precision), ENOMEM, EHIP. */
+int concord_measure_rates(int32_t device, int32_t precision, double* host_dense_tflops,
+                          double* host_hbm_gbps);
+
+/* The product form a handle runs (CONCORD_COV or CONCORD_OBS; for a CONCORD_AUTO
+   handle, the one concord_create picked), or CONCORD_EINVAL for a null handle. */
+int32_t concord_variant_of(const concord_ctx* ctx);
 
 /* Description of the last error on this handle ("" if none). Never NULL. */
 const char* concord_last_error(const concord_ctx* ctx);

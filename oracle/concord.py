@@ -336,3 +336,53 @@ def smooth_value_and_sampled_grads(omega: sp.spmatrix, X: np.ndarray, lam2: floa
             acc += v * Y[k]
         dX.append(acc / n)
     return f, np.array(G), np.array(dX).T
+
+
+# --------------------------------------------------------------------------
+# Tuning lambda1 to a target average degree (Section 4) and support recovery (Table 1)
+# --------------------------------------------------------------------------
+
+def lambda1_search(X: np.ndarray, target_degree: float, lam2: float, lo: float, hi: float,
+                   probes: int, rounds: int, rel_tol: float, tol: float = 1e-5,
+                   max_iter: int = 200, variant: str = "cov"):
+    """Multisection search for the lambda1 whose estimate has the target average degree
+    (off-diagonal stored entries per row), written out plainly: each round solves
+    (Algorithm 1, from Omega = I) at `probes` lambda1 values evenly spaced strictly
+    inside the bracket; the bracket becomes the two probes around the first one whose
+    degree is at or below the target (the degree falls as lambda1 grows); the search
+    stops when the probe closest to the target so far (the first such probe on ties) is
+    within rel_tol of it, or after `rounds` rounds.
+    Returns (best lambda1, its degree, its estimate, [(lambda1, degree, iterations)])."""
+    p = X.shape[1]
+    history = []
+    best = None
+    a, b = lo, hi
+    for _ in range(rounds):
+        lams = [a + (b - a) * (j + 1) / (probes + 1) for j in range(probes)]
+        degs = []
+        for lam1 in lams:
+            r = solve(lam1, lam2, variant, X=X, tol=tol, max_iter=max_iter, check_literal=False)
+            deg = (r.omega.nnz - int(np.count_nonzero(r.omega.diagonal()))) / p
+            degs.append(deg)
+            history.append((lam1, deg, len(r.log)))
+            if best is None or abs(deg - target_degree) < abs(best[1] - target_degree):
+                best = (lam1, deg, r.omega)
+        if abs(best[1] - target_degree) <= rel_tol * max(target_degree, 1e-12):
+            break
+        i = 0
+        while i < len(degs) and degs[i] > target_degree:
+            i += 1
+        a, b = (lams[i - 1] if i > 0 else a), (lams[i] if i < len(lams) else b)
+    return best[0], best[1], best[2], history
+
+
+def edge_scores(estimate: sp.spmatrix, truth: sp.spmatrix):
+    """Positive predictive value and false discovery rate of the estimated edges (unordered
+    pairs i < j with a nonzero entry) against the true ones: PPV = TP/(TP+FP),
+    FDR = FP/(TP+FP) (both 0 for an empty estimate)."""
+    def edges(m):
+        u = sp.triu(sp.csr_matrix(m), k=1).tocoo()
+        return {(int(i), int(j)) for i, j, v in zip(u.row, u.col, u.data) if v != 0}
+    e, t = edges(estimate), edges(truth)
+    tp, fp = len(e & t), len(e - t)
+    return (tp / (tp + fp), fp / (tp + fp)) if tp + fp else (0.0, 0.0)

@@ -5,7 +5,7 @@ The iteration runs in hand-written HIP kernels behind the C-ABI of
 ``autograd`` the differentiable smooth objective.
 """
 from ._lib import (  # noqa: F401
-    Solver, Batch, ConcordError, StepInfo, SolveInfo, load, EXPORTED, LIB_PATH,
+    Solver, Batch, TorchAllocator, ConcordError, StepInfo, SolveInfo, load, EXPORTED, LIB_PATH,
     concord_version, concord_suggest_variant,
 )
 

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libconcord.so")
 
 OK, WMAXITER = 0, 1
 EINVAL, ENOMEM, EHIP, ENOTPD, ENONFINITE, ELINESEARCH, ENODATA = -1, -2, -3, -4, -5, -6, -7
-COV, OBS = 0, 1
+COV, OBS, AUTO = 0, 1, 2
 FP64, FP32, BF16X3 = 0, 1, 2
 F64, F32 = 0, 1
 DATA_X, DATA_S = 0, 1
@@ -29,7 +29,7 @@ GRAD_MASKED, GRAD_DENSE = 0, 1
 _CODES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", ENOTPD: "ENOTPD",
           ENONFINITE: "ENONFINITE", ELINESEARCH: "ELINESEARCH", ENODATA: "ENODATA"}
 
-_VARIANTS = {"cov": COV, "obs": OBS}
+_VARIANTS = {"cov": COV, "obs": OBS, "auto": AUTO}
 _PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
 
 
@@ -39,12 +39,21 @@ class ConcordError(RuntimeError):
         self.code = code
 
 
+# allocator bridge: void* alloc(void* user, size_t bytes, void* stream);
+#                   void free(void* user, void* ptr, size_t bytes, void* stream)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                           ctypes.c_void_p)
+
+
 class concord_config(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int64), ("n", ctypes.c_int64), ("variant", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("device", ctypes.c_int32), ("max_backtracks", ctypes.c_int32),
                 ("trial_batch", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("no_screen", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("no_screen", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tau0", ctypes.c_double), ("shrink", ctypes.c_double),
+                ("alloc_fn", ALLOC_FN), ("free_fn", FREE_FN), ("alloc_user", ctypes.c_void_p)]
 
 
 class concord_step_info(ctypes.Structure):
@@ -68,6 +77,21 @@ class concord_variant_estimate(ctypes.Structure):
                 ("cov_seconds", ctypes.c_double), ("obs_seconds", ctypes.c_double)]
 
 
+class concord_batch_config(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("stream", ctypes.c_void_p), ("max_backtracks", ctypes.c_int32),
+                ("trial_batch", ctypes.c_int32), ("tau0", ctypes.c_double),
+                ("shrink", ctypes.c_double), ("iters_per_launch", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("alloc_fn", ALLOC_FN), ("free_fn", FREE_FN),
+                ("alloc_user", ctypes.c_void_p)]
+
+
+class concord_batch_stats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("host_syncs", ctypes.c_int64),
+                ("iterations_launched", ctypes.c_int64), ("regrows", ctypes.c_int64),
+                ("s_ms", ctypes.c_double), ("iterate_ms", ctypes.c_double)]
+
+
 class concord_solve_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("f", ctypes.c_double), ("F", ctypes.c_double),
                 ("nnz", ctypes.c_int64), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
@@ -88,17 +112,24 @@ _SIGS = {
     "concord_solve": (_I32, [_P, _D, _D, _D, _I64, ctypes.POINTER(concord_solve_info)]),
     "concord_objective": (_I32, [_P, _D, _D, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "concord_get_omega": (_I32, [_P, ctypes.POINTER(_I64), _P, _P, _P, _I32]),
+    "concord_get_candidates": (_I32, [_P, ctypes.POINTER(_I64), _P, _P, _P, _P]),
     "concord_iterations": (_I64, [_P]),
     "concord_smooth_value": (_I32, [_P, _D, ctypes.POINTER(_D)]),
     "concord_gradient": (_I32, [_P, _D, _I32, _P, _P, _I32]),
-    "concord_batch_create": (_I32, [_I32, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
-                                    ctypes.POINTER(_P), ctypes.POINTER(_I64), _I32,
-                                    ctypes.POINTER(_D), _P, ctypes.POINTER(_P)]),
-    "concord_batch_solve": (_I32, [_P, _D, _D, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
+    "concord_batch_config_init": (None, [ctypes.POINTER(concord_batch_config)]),
+    "concord_batch_create": (_I32, [ctypes.POINTER(concord_batch_config), _I32,
+                                    ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_P),
+                                    ctypes.POINTER(_I64), _I32, ctypes.POINTER(_D),
+                                    ctypes.POINTER(_P)]),
+    "concord_batch_solve": (_I32, [_P, _D, _D, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_D),
+                                   ctypes.POINTER(_I32)]),
+    "concord_batch_stats_get": (_I32, [_P, ctypes.POINTER(concord_batch_stats)]),
     "concord_batch_get_omega": (_I32, [_P, _I32, _I32, ctypes.POINTER(_I64), _P, _P, _P]),
     "concord_batch_last_error": (ctypes.c_char_p, [_P]),
     "concord_batch_destroy": (None, [_P]),
-    "concord_suggest_variant": (_I32, [_I64, _I64, _D, _D, _D, _I32, _D, _D, ctypes.c_void_p]),
+    "concord_suggest_variant": (_I32, [_I64, _I64, _D, _D, _D, _I32, _D, _D, _D, ctypes.c_void_p]),
+    "concord_measure_rates": (_I32, [_I32, _I32, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "concord_variant_of": (_I32, [_P]),
     "concord_set_profiling": (_I32, [_P, _I32]),
     "concord_get_profile": (_I32, [_P, ctypes.c_void_p]),
     "concord_contraction_variant": (_I32, [_P, ctypes.c_char_p, _I32]),
@@ -233,17 +264,40 @@ def concord_get_omega(h, rowptr: int = 0, col: int = 0, val: int = 0, dtype: int
     return nnz.value
 
 
+def concord_get_candidates(h, rowptr: int = 0, col: int = 0, omega: int = 0,
+                           grad: int = 0) -> int:
+    nnz = ctypes.c_int64()
+    _check(load().concord_get_candidates(h, ctypes.byref(nnz), rowptr or None, col or None,
+                                         omega or None, grad or None), h)
+    return nnz.value
+
+
 def concord_suggest_variant(p: int, n: int, d: float, t: float, s: float,
                             precision: str = "bf16x3", dense_tflops: float = 0.0,
-                            hbm_gbps: float = 0.0) -> dict:
+                            hbm_gbps: float = 0.0, screen_fraction: float = 1.0) -> dict:
     """Product form for a problem (Lemma 3.1 flop rule and the library's time model)."""
     est = concord_variant_estimate()
     _check(load().concord_suggest_variant(p, n, d, t, s, _PRECISIONS[precision], dense_tflops,
-                                          hbm_gbps, ctypes.byref(est)))
+                                          hbm_gbps, screen_fraction, ctypes.byref(est)))
     names = {COV: "cov", OBS: "obs"}
     return {"paper_choice": names[est.paper_choice], "choice": names[est.choice],
             "cov_flops": est.cov_flops, "obs_flops": est.obs_flops,
             "cov_seconds": est.cov_seconds, "obs_seconds": est.obs_seconds}
+
+
+def concord_measure_rates(device: int = -1, precision: str = "bf16x3") -> Tuple[float, float]:
+    """(dense contraction TFLOP/s, device copy GB/s) measured on the device (cached)."""
+    d, h = ctypes.c_double(), ctypes.c_double()
+    _check(load().concord_measure_rates(device, _PRECISIONS[precision], ctypes.byref(d),
+                                        ctypes.byref(h)))
+    return d.value, h.value
+
+
+def concord_variant_of(h) -> str:
+    v = load().concord_variant_of(h)
+    if v < 0:
+        _check(v, h)
+    return {COV: "cov", OBS: "obs"}[v]
 
 
 def concord_set_profiling(h, on: bool) -> int:
@@ -308,12 +362,59 @@ def _stream_ptr(stream) -> Optional[int]:
     return s.cuda_stream or None
 
 
+class TorchAllocator:
+    """Allocator bridge to PyTorch's caching allocator: the library's device
+    workspace comes from torch.cuda.caching_allocator_alloc on the handle's
+    stream and goes back through caching_allocator_delete (the library has
+    synchronised that stream first).  `fail_after` (tests) makes the bridge
+    return NULL once that many blocks have been handed out."""
+
+    def __init__(self, device: int, fail_after: Optional[int] = None):
+        self.device = device
+        self.fail_after = fail_after
+        self.live = {}
+        self.n_alloc = 0
+        self.n_free = 0
+        self.alloc_fn = ALLOC_FN(self._alloc)
+        self.free_fn = FREE_FN(self._free)
+
+    def _alloc(self, user, nbytes, stream):
+        torch = _torch()
+        if self.fail_after is not None and self.n_alloc >= self.fail_after:
+            return None
+        try:
+            ptr = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, stream or 0)
+        except Exception:   # out of memory: the library reports ENOMEM
+            return None
+        self.live[ptr] = int(nbytes)
+        self.n_alloc += 1
+        return ptr
+
+    def _free(self, user, ptr, nbytes, stream):
+        if ptr in self.live:
+            del self.live[ptr]
+            self.n_free += 1
+            try:
+                _torch().cuda.caching_allocator_delete(ptr)
+            except Exception:   # interpreter shutdown: torch's allocator is gone already
+                pass
+
+    def install(self, cfg: "concord_config") -> None:
+        cfg.alloc_fn = self.alloc_fn
+        cfg.free_fn = self.free_fn
+        cfg.alloc_user = None
+
+
 class Solver:
     """One CONCORD problem on the current GPU (a library handle)."""
 
     def __init__(self, p: int, n: int, variant: str = "obs", precision: str = "fp32",
                  stream=None, device: Optional[int] = None, trial_batch: int = 8,
-                 max_backtracks: int = 60, use_graph: bool = False, screen: bool = True):
+                 max_backtracks: int = 60, use_graph: bool = False, screen: bool = True,
+                 tau0: float = 1.0, shrink: float = 0.5, allocator="torch"):
+        """allocator: "torch" (default) routes the library's device workspace through
+        PyTorch's caching allocator, None lets the library use hipMalloc, or a
+        TorchAllocator instance."""
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the HIP library needs a gfx950 device")
@@ -327,9 +428,16 @@ class Solver:
         cfg.max_backtracks = max_backtracks
         cfg.use_graph = 1 if use_graph else 0
         cfg.no_screen = 0 if screen else 1
-        self.p, self.n, self.variant, self.precision = p, n, variant, precision
+        cfg.tau0, cfg.shrink = tau0, shrink
+        if allocator == "torch":
+            allocator = TorchAllocator(cfg.device)
+        self._alloc = allocator   # keeps the callbacks alive as long as the handle
+        if allocator is not None:
+            allocator.install(cfg)
+        self.p, self.n, self.precision = p, n, precision
         self.device = torch.device("cuda", cfg.device)
         self._h = concord_create(cfg)
+        self.variant = concord_variant_of(self._h)   # the form an "auto" handle picked
         self._keep = None
 
     def close(self):
@@ -417,6 +525,29 @@ class Solver:
                           F64 if dtype == torch.float64 else F32)
         return rowptr, col[:nnz], val[:nnz]
 
+    def get_candidates(self):
+        """Candidate set of the last step and the gradient on it: CUDA tensors
+        (rowptr int64, col int32, omega float64, grad float64)."""
+        torch = _torch()
+        nnz = concord_get_candidates(self._h)
+        rowptr = torch.empty(self.p + 1, dtype=torch.int64, device=self.device)
+        col = torch.empty(max(nnz, 1), dtype=torch.int32, device=self.device)
+        om = torch.empty(max(nnz, 1), dtype=torch.float64, device=self.device)
+        gr = torch.empty(max(nnz, 1), dtype=torch.float64, device=self.device)
+        concord_get_candidates(self._h, rowptr.data_ptr(), col.data_ptr(), om.data_ptr(),
+                               gr.data_ptr())
+        return rowptr, col[:nnz], om[:nnz], gr[:nnz]
+
+    def get_candidates_scipy(self):
+        """(omega, grad) of the last step's candidate set as SciPy CSR matrices."""
+        import numpy as np
+        import scipy.sparse as sp
+        r, c, o, g = self.get_candidates()
+        r, c = r.cpu().numpy(), c.cpu().numpy().astype(np.int64)
+        shape = (self.p, self.p)
+        return (sp.csr_matrix((o.cpu().numpy(), c, r), shape=shape),
+                sp.csr_matrix((g.cpu().numpy(), c, r), shape=shape))
+
     def get_omega_scipy(self):
         import numpy as np
         import scipy.sparse as sp
@@ -445,35 +576,63 @@ class Solver:
 
 
 class Batch:
-    """A batch of independent Cov problems solved over one lambda1 path."""
+    """Many independent Cov problems solved over one lambda1 path at once on the GPU
+    (the batched form of the C-ABI): every (instance, lambda1) solve runs from Omega = I
+    with concord_solve's stopping rule, in launches shared by all solves."""
 
-    def __init__(self, Xs, lambda1s, stream=None):
+    def __init__(self, Xs, lambda1s, stream=None, precision: str = "fp32",
+                 iters_per_launch: int = 4, use_graph: bool = True, trial_batch: int = 8,
+                 max_backtracks: int = 60, tau0: float = 1.0, shrink: float = 0.5,
+                 allocator="torch"):
         torch = _torch()
         self.count = len(Xs)
         self._Xs = [x.contiguous() for x in Xs]
+        want = torch.float64 if precision == "fp64" else torch.float32
+        for x in self._Xs:
+            assert x.dtype == want and x.is_cuda and x.dim() == 2
         ps = (ctypes.c_int64 * self.count)(*[x.shape[1] for x in self._Xs])
         ns = (ctypes.c_int64 * self.count)(*[x.shape[0] for x in self._Xs])
         lds = (ctypes.c_int64 * self.count)(*[x.stride(0) for x in self._Xs])
         ptrs = (ctypes.c_void_p * self.count)(*[x.data_ptr() for x in self._Xs])
-        for x in self._Xs:
-            assert x.dtype == torch.float32 and x.is_cuda
         self.lambda1s = list(lambda1s)
         l1 = (ctypes.c_double * len(self.lambda1s))(*self.lambda1s)
+        cfg = concord_batch_config()
+        load().concord_batch_config_init(ctypes.byref(cfg))
+        cfg.precision = _PRECISIONS[precision]
+        cfg.device = self._Xs[0].device.index
+        cfg.stream = _stream_ptr(stream)
+        cfg.iters_per_launch = iters_per_launch
+        cfg.use_graph = 1 if use_graph else 0
+        cfg.trial_batch, cfg.max_backtracks = trial_batch, max_backtracks
+        cfg.tau0, cfg.shrink = tau0, shrink
+        if allocator == "torch":
+            allocator = TorchAllocator(cfg.device)
+        self._alloc = allocator
+        if allocator is not None:
+            allocator.install(cfg)
         h = ctypes.c_void_p()
-        rc = load().concord_batch_create(self.count, ps, ns, ptrs, lds, len(self.lambda1s), l1,
-                                         _stream_ptr(stream), ctypes.byref(h))
-        _check(rc)
+        _check(load().concord_batch_create(ctypes.byref(cfg), self.count, ps, ns, ptrs, lds,
+                                           len(self.lambda1s), l1, ctypes.byref(h)))
         self._h = h.value
         self.ps = [x.shape[1] for x in self._Xs]
         self.device = self._Xs[0].device
 
     def solve(self, lam2: float, tol: float, max_iter: int):
+        """(iterations, F, status) per solve s = instance * len(lambda1s) + l, and the
+        call's status."""
         m = self.count * len(self.lambda1s)
         iters = (ctypes.c_int64 * m)()
         Fs = (ctypes.c_double * m)()
-        rc = load().concord_batch_solve(self._h, lam2, tol, max_iter, iters, Fs)
+        st = (ctypes.c_int32 * m)()
+        rc = load().concord_batch_solve(self._h, lam2, tol, max_iter, iters, Fs, st)
         _check(rc, self._h, batch=True)
+        self.status = list(st)
         return list(iters), list(Fs), rc
+
+    def stats(self) -> dict:
+        s = concord_batch_stats()
+        _check(load().concord_batch_stats_get(self._h, ctypes.byref(s)), self._h, batch=True)
+        return {k: getattr(s, k) for k, _ in concord_batch_stats._fields_}
 
     def get_omega(self, instance: int, l1_index: int):
         torch = _torch()

@@ -17,7 +17,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/concord.h"
@@ -53,12 +56,22 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// Device memory of a handle: the caller's allocator bridge when one is configured,
+// else hipMalloc / hipFree.
+struct DevAlloc {
+    concord_alloc_fn afn = nullptr;
+    concord_free_fn ffn = nullptr;
+    void* user = nullptr;
+};
+
 struct concord_ctx {
     int64_t p = 0, n = 0;
     int variant = CONCORD_COV, precision = CONCORD_FP64;
     hipStream_t stream = nullptr;
     int device = 0;
     int max_bt = 60, tb = 8;
+    double tau0 = 1.0, shrink = 0.5;   // step sizes tau0 * shrink^q
+    DevAlloc alloc;
     std::string err;
 
     int64_t prow = 0, ldk = 0, ldp = 0;
@@ -79,7 +92,6 @@ struct concord_ctx {
     unsigned long long* d_active = nullptr;   // screening statistics counter
     RefreshWs rws = {};                         // Cov refresh screening workspace
     void* M = nullptr;
-    void* dxt = nullptr;   // differentiation form: Omega Y before its transpose
 
     Csr om[2] = {};
     int64_t om_cap[2] = {0, 0};
@@ -89,6 +101,7 @@ struct concord_ctx {
 
     Cand A = {};
     int64_t a_cap = 0;
+    int64_t a_nnz = -1;          // |A| of the last accepted step (-1: none since the iterate was set)
     int64_t* cnt = nullptr;
     uint64_t* bitmap = nullptr;
     int64_t nwords = 0;
@@ -111,7 +124,7 @@ struct concord_ctx {
     bool bits_valid = false;
     double bits_lam1 = -1.0;
 
-    std::vector<void*> allocs;
+    std::vector<DevBuf> allocs;
 
     // graph replay of the common step path
     bool use_graph = false;
@@ -166,18 +179,32 @@ int fail(concord_ctx* c, int code, const std::string& msg) {
                         std::string(#expr) + ": " + hipGetErrorString(e_));              \
     } while (0)
 
+// Return one device block to where it came from (the stream has been synchronised).
+void release(concord_ctx* c, const DevBuf& b) {
+    if (!b.ptr) return;
+    if (c->alloc.ffn) c->alloc.ffn(c->alloc.user, b.ptr, b.bytes, (void*)c->stream);
+    else (void)hipFree(b.ptr);
+}
+
 int dalloc(concord_ctx* c, void** out, size_t bytes, bool zero) {
     *out = nullptr;
     if (bytes == 0) bytes = 256;
-    hipError_t e = hipMalloc(out, bytes);
-    if (e != hipSuccess) {
-        *out = nullptr;
-        (void)hipGetLastError();   // clear the sticky error of the failed allocation
-        return fail(c, CONCORD_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    if (c->alloc.afn) {
+        *out = c->alloc.afn(c->alloc.user, bytes, (void*)c->stream);
+        if (!*out)
+            return fail(c, CONCORD_ENOMEM,
+                        "allocator returned NULL for " + std::to_string(bytes) + " bytes");
+    } else {
+        hipError_t e = hipMalloc(out, bytes);
+        if (e != hipSuccess) {
+            *out = nullptr;
+            (void)hipGetLastError();   // clear the sticky error of the failed allocation
+            return fail(c, CONCORD_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        }
     }
-    c->allocs.push_back(*out);
+    c->allocs.push_back(DevBuf{*out, bytes});
     if (zero) {
-        e = hipMemsetAsync(*out, 0, bytes, c->stream);
+        hipError_t e = hipMemsetAsync(*out, 0, bytes, c->stream);
         if (e != hipSuccess) return fail(c, CONCORD_EHIP, "hipMemsetAsync failed");
     }
     return CONCORD_OK;
@@ -186,9 +213,12 @@ int dalloc(concord_ctx* c, void** out, size_t bytes, bool zero) {
 void dfree(concord_ctx* c, void* p) {
     if (!p) return;
     for (auto& a : c->allocs)
-        if (a == p) {
-            (void)hipFree(p);
-            a = nullptr;
+        if (a.ptr == p) {
+            // work queued on the stream may still read the block (hipFree would wait for
+            // the device; a caller's allocator need not)
+            (void)hipStreamSynchronize(c->stream);
+            release(c, a);
+            a.ptr = nullptr;
         }
 }
 
@@ -202,18 +232,30 @@ int dalloc_t(concord_ctx* c, T** out, size_t count, bool zero = false) {
 
 int elem_bytes(int store) { return store == ST_F64 ? 8 : 4; }
 
-// capacity for candidate / iterate arrays
+// capacity for candidate / iterate arrays.  The new arrays are allocated before the old
+// ones are released, so a failed allocation leaves the handle as it was; growing the
+// current iterate's arrays keeps its entries.
 int ensure_csr_cap(concord_ctx* c, int which, int64_t cap) {
     if (c->om_cap[which] >= cap) return CONCORD_OK;
     Csr& o = c->om[which];
-    // rowptr is kept; col/val regrown
+    int32_t* ncol = nullptr;
+    double* nval = nullptr;
+    int rc;
+    if ((rc = dalloc_t(c, &ncol, cap))) return rc;
+    if ((rc = dalloc_t(c, &nval, cap))) {
+        dfree(c, ncol);
+        return rc;
+    }
+    if (which == c->cur && o.col && c->nnz > 0) {
+        HIPCK(c, hipMemcpyAsync(ncol, o.col, (size_t)c->nnz * sizeof(int32_t),
+                                hipMemcpyDeviceToDevice, c->stream));
+        HIPCK(c, hipMemcpyAsync(nval, o.val, (size_t)c->nnz * sizeof(double),
+                                hipMemcpyDeviceToDevice, c->stream));
+    }
     dfree(c, o.col);
     dfree(c, o.val);
-    o.col = nullptr;
-    o.val = nullptr;
-    int rc;
-    if ((rc = dalloc_t(c, &o.col, cap))) return rc;
-    if ((rc = dalloc_t(c, &o.val, cap))) return rc;
+    o.col = ncol;
+    o.val = nval;
     c->om_cap[which] = cap;
     c->gen += 1;
     return CONCORD_OK;
@@ -221,13 +263,23 @@ int ensure_csr_cap(concord_ctx* c, int which, int64_t cap) {
 
 int ensure_cand_cap(concord_ctx* c, int64_t cap) {
     if (c->a_cap >= cap) return CONCORD_OK;
+    int32_t* ncol = nullptr;
+    double* nom = nullptr;
+    double* ngr = nullptr;
+    int rc;
+    if ((rc = dalloc_t(c, &ncol, cap)) || (rc = dalloc_t(c, &nom, cap)) ||
+        (rc = dalloc_t(c, &ngr, cap))) {
+        dfree(c, ncol);
+        dfree(c, nom);
+        dfree(c, ngr);
+        return rc;
+    }
     dfree(c, c->A.col);
     dfree(c, c->A.omega);
     dfree(c, c->A.grad);
-    int rc;
-    if ((rc = dalloc_t(c, &c->A.col, cap))) return rc;
-    if ((rc = dalloc_t(c, &c->A.omega, cap))) return rc;
-    if ((rc = dalloc_t(c, &c->A.grad, cap))) return rc;
+    c->A.col = ncol;
+    c->A.omega = nom;
+    c->A.grad = ngr;
     c->a_cap = cap;
     c->gen += 1;
     return CONCORD_OK;
@@ -303,6 +355,10 @@ int products_at(concord_ctx* c, int which, const int* gate, double bits_lam1 = -
     const Csr& O = c->om[which];
     const int64_t p = c->p;
     int nysq = 0;
+    if (c->variant == CONCORD_OBS && c->precision != CONCORD_BF16X3 && !c->Y) {
+        int rc = dalloc(c, &c->Y, (size_t)c->prow * c->ldk * elem_bytes(c->dstore), true);
+        if (rc) return rc;
+    }
     prof_begin(c, CONCORD_PROF_SPMM);
     if (c->variant == CONCORD_OBS) {
         const bool split = c->precision == CONCORD_BF16X3;
@@ -357,10 +413,14 @@ int ensure_products(concord_ctx* c, double bits_lam1 = -1.0) {
 
 void objective_from(const concord_ctx* c, const double* o, double lam1, double lam2, double* f,
                     double* F) {
-    const double quad = c->variant == CONCORD_OBS ? o[4] / (double)c->n : o[3];
-    const double fv = -o[0] + 0.5 * quad + 0.5 * lam2 * o[1];
-    *f = fv;
-    *F = fv + lam1 * o[2];
+    objective_value(o, c->variant == CONCORD_OBS, (double)c->n, lam1, lam2, f, F);
+}
+
+// tau0 * shrink^q as the trial kernels form it: q successive multiplications
+double step_size(const concord_ctx* c, int q) {
+    double t = c->tau0;
+    for (int i = 0; i < q; ++i) t *= c->shrink;
+    return t;
 }
 
 int set_identity(concord_ctx* c) {
@@ -369,6 +429,7 @@ int set_identity(concord_ctx* c) {
     HIPCK(c, launch_identity(c->om[c->cur], c->p, c->stream));
     c->nnz = c->p;
     c->k = 0;
+    c->a_nnz = -1;
     c->prod_valid = false;
     c->bits_valid = false;
     return CONCORD_OK;
@@ -387,6 +448,7 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
     if (rc) return rc;
     if ((rc = ensure_products(c, lam1))) return rc;
     const int64_t p = c->p;
+    c->a_nnz = -1;   // the candidate set is rebuilt below; valid again once a step is accepted
 
     const int nxt = c->cur ^ 1;
     const double inv_n = c->variant == CONCORD_OBS ? 1.0 / (double)c->n : 1.0;
@@ -457,13 +519,14 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
     // one batch of step sizes tau0 * 2^-q, q < m, then emission, products and
     // objective at Omega+ (gated on the device-side decision) and the read-back
     auto enqueue_batch = [&](int q_base, int m) -> int {
-        const double tau0 = std::ldexp(1.0, -q_base);
+        const double tau0 = step_size(c, q_base);
         prof_begin(c, CONCORD_PROF_TRIAL);
-        HIPCK(c, launch_trial(c->A, p, tau0, m, lam1, c->variant, TB, tbstore, tld,
+        HIPCK(c, launch_trial(c->A, p, tau0, c->shrink, m, lam1, c->variant, TB, tbstore, tld,
                               c->variant == CONCORD_OBS ? c->ldk : 0, c->part, c->st, c->stream));
         const int S = trial_splits(c->variant, tbstore, c->variant == CONCORD_OBS ? c->ldk : 0);
         HIPCK(c, launch_colsum_decide(c->part, (int64_t)S * p, 4 * m, c->sums, c->colsum_ws, m,
-                                      tau0, q_base, lam2, inv_n, forced_q, c->st, c->stream));
+                                      tau0, c->shrink, q_base, lam2, inv_n, forced_q, c->st,
+                                      c->stream));
         prof_end(c);
         prof_begin(c, CONCORD_PROF_EMIT);
         HIPCK(c, launch_emit_count(c->A, p, lam1, c->st, c->cnt, c->stream));
@@ -565,6 +628,7 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
         c->cur = nxt;
         c->nnz = c->st_host->nnz_next;
         c->k += 1;
+        c->a_nnz = c->st_host->n_cand;
         for (int i = 0; i < 5; ++i) c->obj[i] = s.obj[i];
         c->prod_valid = true;
         if (info) {
@@ -584,6 +648,79 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
     return fail(c, CONCORD_ENOMEM, "candidate capacity did not converge");
 }
 
+// Rates for CONCORD_AUTO, measured once per (device, precision) and cached: the useful
+// rate of the dense symmetric contraction (syr2k, p = 4096, K = 2048, zero operands; the
+// tuner picks its variant on the first call) and the device copy rate of 256 MiB.
+std::mutex g_rate_mu;
+std::map<std::pair<int, int>, std::pair<double, double>> g_rates;
+
+int measured_rates(int dev, int precision, double (&out)[2]) {
+    std::lock_guard<std::mutex> lk(g_rate_mu);
+    auto it = g_rates.find({dev, precision});
+    if (it != g_rates.end()) {
+        out[0] = it->second.first;
+        out[1] = it->second.second;
+        return CONCORD_OK;
+    }
+    DeviceGuard g(dev);
+    const int64_t p = 4096, K = 2048;
+    const int kind = precision == CONCORD_FP64 ? GK_F64 : (precision == CONCORD_FP32 ? GK_F32 : GK_BF16X3);
+    const int ostore = precision == CONCORD_FP64 ? ST_F64 : ST_F32;
+    const size_t eb = precision == CONCORD_FP64 ? 8 : (precision == CONCORD_FP32 ? 4 : 2);
+    const size_t op = (size_t)p * K * eb, cb = (size_t)p * p * (ostore == ST_F64 ? 8 : 4);
+    const size_t copy_bytes = (size_t)256 << 20;
+    void *P0 = nullptr, *P1 = nullptr, *C = nullptr, *src = nullptr, *dst = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&](int rc) {
+        if (st) (void)hipStreamSynchronize(st);
+        for (void* q : {P0, P1, C, src, dst})
+            if (q) (void)hipFree(q);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (st) (void)hipStreamDestroy(st);
+        return rc;
+    };
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return cleanup(CONCORD_EHIP);
+    if (hipMalloc(&P0, op) != hipSuccess || hipMalloc(&P1, op) != hipSuccess ||
+        hipMalloc(&C, cb) != hipSuccess || hipMalloc(&src, copy_bytes) != hipSuccess ||
+        hipMalloc(&dst, copy_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return cleanup(CONCORD_ENOMEM);
+    }
+    if (hipMemsetAsync(P0, 0, op, st) != hipSuccess || hipMemsetAsync(P1, 0, op, st) != hipSuccess ||
+        hipMemsetAsync(src, 0, copy_bytes, st) != hipSuccess)
+        return cleanup(CONCORD_EHIP);
+    const bool split = kind == GK_BF16X3;
+    auto gemm = [&]() {
+        return launch_gemm_sym(kind, true, P0, split ? P1 : nullptr, P1, split ? P0 : nullptr, K, p,
+                               1.0, C, ostore, p, st);
+    };
+    float ms_g = 0.f, ms_c = 0.f;
+    if (gemm() != hipSuccess || gemm() != hipSuccess) return cleanup(CONCORD_EHIP);   // tune, warm
+    if (hipEventRecord(e0, st) != hipSuccess) return cleanup(CONCORD_EHIP);
+    for (int r = 0; r < 3; ++r)
+        if (gemm() != hipSuccess) return cleanup(CONCORD_EHIP);
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms_g, e0, e1) != hipSuccess)
+        return cleanup(CONCORD_EHIP);
+    if (hipMemcpyAsync(dst, src, copy_bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipEventRecord(e0, st) != hipSuccess)
+        return cleanup(CONCORD_EHIP);
+    for (int r = 0; r < 3; ++r)
+        if (hipMemcpyAsync(dst, src, copy_bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return cleanup(CONCORD_EHIP);
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms_c, e0, e1) != hipSuccess)
+        return cleanup(CONCORD_EHIP);
+    out[0] = 3.0 * 2.0 * (double)K * (double)p * (double)p / (ms_g * 1e-3) / 1e12;
+    out[1] = 3.0 * 2.0 * (double)copy_bytes / (ms_c * 1e-3) / 1e9;
+    g_rates[{dev, precision}] = {out[0], out[1]};
+    return cleanup(CONCORD_OK);
+}
+
 }  // namespace
 
 extern "C" {
@@ -597,6 +734,8 @@ void concord_config_init(concord_config* cfg) {
     cfg->device = -1;
     cfg->max_backtracks = 60;
     cfg->trial_batch = 8;
+    cfg->tau0 = 1.0;
+    cfg->shrink = 0.5;
 }
 
 const char* concord_version(void) { return kVersion; }
@@ -652,8 +791,7 @@ void concord_destroy(concord_ctx* ctx) {
             (void)hipStreamDestroy(ctx->stream);
             if (ctx->enter_ev) (void)hipEventDestroy(ctx->enter_ev);
         }
-        for (void* a : ctx->allocs)
-            if (a) (void)hipFree(a);
+        for (const DevBuf& a : ctx->allocs) release(ctx, a);
         if (ctx->st_host) (void)hipHostFree(ctx->st_host);
     }
     delete ctx;
@@ -664,12 +802,17 @@ int concord_create(const concord_config* cfg, concord_ctx** out) {
     *out = nullptr;
     if (!cfg) return CONCORD_EINVAL;
     if (cfg->p < 1 || cfg->p > (int64_t)1 << 30) return CONCORD_EINVAL;
-    if (cfg->variant != CONCORD_COV && cfg->variant != CONCORD_OBS) return CONCORD_EINVAL;
+    if (cfg->variant != CONCORD_COV && cfg->variant != CONCORD_OBS && cfg->variant != CONCORD_AUTO)
+        return CONCORD_EINVAL;
     if (cfg->precision < CONCORD_FP64 || cfg->precision > CONCORD_BF16X3) return CONCORD_EINVAL;
-    if (cfg->variant == CONCORD_OBS && cfg->n < 1) return CONCORD_EINVAL;
+    if ((cfg->variant == CONCORD_OBS || cfg->variant == CONCORD_AUTO) && cfg->n < 1)
+        return CONCORD_EINVAL;
     if (cfg->n < 0) return CONCORD_EINVAL;
     if (cfg->trial_batch < 1 || cfg->trial_batch > MAXQ) return CONCORD_EINVAL;
     if (cfg->max_backtracks < 0 || cfg->max_backtracks > 1000) return CONCORD_EINVAL;
+    if (!(cfg->tau0 > 0.0) || !std::isfinite(cfg->tau0)) return CONCORD_EINVAL;
+    if (!(cfg->shrink > 0.0 && cfg->shrink < 1.0)) return CONCORD_EINVAL;
+    if ((cfg->alloc_fn == nullptr) != (cfg->free_fn == nullptr)) return CONCORD_EINVAL;
 
     int dev = cfg->device;
     if (dev < 0) {
@@ -678,15 +821,33 @@ int concord_create(const concord_config* cfg, concord_ctx** out) {
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || dev >= ndev) return CONCORD_EHIP;
 
+    int variant = cfg->variant;
+    if (variant == CONCORD_AUTO) {
+        // Lemma 3.1's work priced with this device's measured rates (the kept fraction of
+        // the Cov refresh is unknown before S exists: 1, an upper bound on Cov's cost)
+        double r[2];
+        const int rc0 = measured_rates(dev, cfg->precision, r);
+        if (rc0) return rc0;
+        concord_variant_estimate est;
+        if (concord_suggest_variant(cfg->p, cfg->n, 5.0, 3.0, 30.0, cfg->precision, r[0], r[1], 1.0,
+                                    &est) != CONCORD_OK)
+            return CONCORD_EINVAL;
+        variant = est.choice;
+    }
     concord_ctx* c = new concord_ctx();
     c->p = cfg->p;
     c->n = cfg->n;
-    c->variant = cfg->variant;
+    c->variant = variant;
     c->precision = cfg->precision;
     c->stream = (hipStream_t)cfg->stream;
     c->device = dev;
     c->max_bt = cfg->max_backtracks;
     c->tb = cfg->trial_batch;
+    c->tau0 = cfg->tau0;
+    c->shrink = cfg->shrink;
+    c->alloc.afn = cfg->alloc_fn;
+    c->alloc.ffn = cfg->free_fn;
+    c->alloc.user = cfg->alloc_user;
     c->use_graph = cfg->use_graph != 0;
     c->screen = cfg->no_screen == 0;
     DeviceGuard g(dev);
@@ -727,9 +888,9 @@ int concord_create(const concord_config* cfg, concord_ctx** out) {
         if (split) {
             if ((rc = dalloc_t(c, &c->Y_hi, (size_t)c->prow * c->ldk, true))) return bail(rc);
             if ((rc = dalloc_t(c, &c->Y_lo, (size_t)c->prow * c->ldk, true))) return bail(rc);
-        } else {
-            if ((rc = dalloc(c, &c->Y, (size_t)c->prow * c->ldk * eb, true))) return bail(rc);
         }
+        // the FP64/FP32 Y is allocated by the first solver step (a handle used only for
+        // the differentiation form never holds it)
     } else {
         if ((rc = dalloc(c, &c->S, (size_t)p * c->ldp * (c->sstore == ST_F64 ? 8 : 4), true)))
             return bail(rc);
@@ -863,6 +1024,7 @@ int concord_set_omega(concord_ctx* c, int64_t nnz, const int64_t* dev_row_ptr,
     HIPCK(c, hipStreamSynchronize(c->stream));
     c->nnz = nnz;
     c->k = 0;
+    c->a_nnz = -1;
     c->prod_valid = false;
     c->bits_valid = false;
     return CONCORD_OK;
@@ -983,10 +1145,36 @@ int concord_get_omega(concord_ctx* c, int64_t* host_nnz, int64_t* dev_row_ptr, i
     return CONCORD_OK;
 }
 
+int concord_get_candidates(concord_ctx* c, int64_t* host_nnz, int64_t* dev_row_ptr,
+                           int32_t* dev_col, double* dev_omega, double* dev_grad) {
+    if (!c || !host_nnz) return CONCORD_EINVAL;
+    if (c->a_nnz < 0) return fail(c, CONCORD_ENODATA, "no step since the iterate was set");
+    *host_nnz = c->a_nnz;
+    if (!dev_row_ptr) return CONCORD_OK;
+    if (!dev_col || !dev_omega || !dev_grad)
+        return fail(c, CONCORD_EINVAL, "col/omega/grad must be given with row_ptr");
+    DeviceGuard g(c->device);
+    if (int rc0 = enter(c)) return rc0;
+    const size_t n = (size_t)c->a_nnz;
+    HIPCK(c, hipMemcpyAsync(dev_row_ptr, c->A.rowptr, (c->p + 1) * sizeof(int64_t),
+                            hipMemcpyDeviceToDevice, c->stream));
+    if (n) {
+        HIPCK(c, hipMemcpyAsync(dev_col, c->A.col, n * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                                c->stream));
+        HIPCK(c, hipMemcpyAsync(dev_omega, c->A.omega, n * sizeof(double),
+                                hipMemcpyDeviceToDevice, c->stream));
+        HIPCK(c, hipMemcpyAsync(dev_grad, c->A.grad, n * sizeof(double), hipMemcpyDeviceToDevice,
+                                c->stream));
+    }
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    return CONCORD_OK;
+}
+
 int64_t concord_iterations(const concord_ctx* c) { return c ? c->k : -1; }
 
 int concord_suggest_variant(int64_t p, int64_t n, double d, double t, double s, int32_t precision,
-                            double dense_tflops, double hbm_gbps, concord_variant_estimate* out) {
+                            double dense_tflops, double hbm_gbps, double screen_fraction,
+                            concord_variant_estimate* out) {
     if (!out || p < 1 || n < 1 || !(d >= 0.0) || !(t >= 0.0) || !(s >= 0.0)) return CONCORD_EINVAL;
     if (precision < CONCORD_FP64 || precision > CONCORD_BF16X3) return CONCORD_EINVAL;
     const double P = (double)p, N = (double)n;
@@ -994,22 +1182,56 @@ int concord_suggest_variant(int64_t p, int64_t n, double d, double t, double s, 
     out->cov_flops = 2.0 * N * P * P + 2.0 * d * P * P * (s * t + 1.0);
     out->obs_flops = 2.0 * N * P * P * s + 2.0 * d * N * P * (s * t + 1.0);
     out->paper_choice = out->cov_flops < out->obs_flops ? CONCORD_COV : CONCORD_OBS;
-    // time model of this library's pipeline
+    // the same work priced as this library does it
     const double rate = (dense_tflops > 0.0 ? dense_tflops
                          : precision == CONCORD_BF16X3 ? 330.0
                          : precision == CONCORD_FP32 ? 125.0 : 60.0) * 1e12;
     const double bw = (hbm_gbps > 0.0 ? hbm_gbps : 3200.0) * 1e9;
     const double b = precision == CONCORD_FP64 ? 8.0 : 4.0;
-    out->cov_seconds = N * P * P / rate + s * 5.0 * P * P * b / bw;
-    out->obs_seconds = s * (2.0 * N * P * P / rate + (P * P + 3.0 * P * N) * b / bw);
+    const double f = screen_fraction > 0.0 ? std::min(screen_fraction, 1.0) : 1.0;
+    out->cov_seconds = N * P * P / rate + s * (f * P * P * b + 0.25 * P * P) / bw;
+    out->obs_seconds = s * (2.0 * N * P * P / rate + (2.0 * P * P * b + 2.0 * P * N * b) / bw);
     out->choice = out->cov_seconds < out->obs_seconds ? CONCORD_COV : CONCORD_OBS;
+    return CONCORD_OK;
+}
+
+int32_t concord_variant_of(const concord_ctx* c) { return c ? c->variant : CONCORD_EINVAL; }
+
+int concord_measure_rates(int32_t device, int32_t precision, double* host_dense_tflops,
+                          double* host_hbm_gbps) {
+    if (precision < CONCORD_FP64 || precision > CONCORD_BF16X3) return CONCORD_EINVAL;
+    int dev = device;
+    if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return CONCORD_EHIP;
+    double r[2] = {0.0, 0.0};
+    const int rc = measured_rates(dev, precision, r);
+    if (rc) return rc;
+    if (host_dense_tflops) *host_dense_tflops = r[0];
+    if (host_hbm_gbps) *host_hbm_gbps = r[1];
     return CONCORD_OK;
 }
 
 int concord_smooth_value(concord_ctx* c, double lam2, double* host_f) {
     if (!c) return CONCORD_EINVAL;
     if (c->variant != CONCORD_OBS) return fail(c, CONCORD_EINVAL, "differentiation form needs Obs");
-    return concord_objective(c, 0.0, lam2, host_f, nullptr);
+    if (!c->has_data) return fail(c, CONCORD_ENODATA, "no data: call concord_set_data first");
+    if (!(lam2 >= 0.0)) return fail(c, CONCORD_EINVAL, "lambda2 must be >= 0");
+    DeviceGuard g(c->device);
+    if (int rc0 = enter(c)) return rc0;
+    // ||Omega X^T||^2 reduced per row and column chunk by the SpMM without writing Y,
+    // the other sums per row, fixed-order column sums, then f on the device
+    const Csr& O = c->om[c->cur];
+    const int64_t p = c->p;
+    const int nch = spmm_nchunks(c->dstore, c->ldk);
+    HIPCK(c, launch_spmm(O, p, c->Xt, c->dstore, c->ldk, c->ldk, nullptr, c->dstore, c->ldk,
+                         nullptr, nullptr, 0, c->part + 4 * p, nullptr, c->stream));
+    HIPCK(c, launch_obj_parts(O, p, nullptr, c->dstore, 0, c->part, nullptr, c->stream));
+    HIPCK(c, launch_colsum_obj(c->part, p, 4 + nch, c->objsums, c->colsum_ws, nch, nullptr, c->st,
+                               c->stream));
+    HIPCK(c, launch_smooth_finish(c->st, c->n, lam2, &c->st->fval, c->stream));
+    int rc = sync_state(c);
+    if (rc) return rc;
+    if (host_f) *host_f = c->st_host->fval;
+    return CONCORD_OK;
 }
 
 int concord_gradient(concord_ctx* c, double lam2, int32_t mode, void* dev_dOmega, void* dev_dX,
@@ -1021,50 +1243,68 @@ int concord_gradient(concord_ctx* c, double lam2, int32_t mode, void* dev_dOmega
     if (mode != CONCORD_GRAD_MASKED && mode != CONCORD_GRAD_DENSE)
         return fail(c, CONCORD_EINVAL, "mode");
     if (dtype != CONCORD_F64 && dtype != CONCORD_F32) return fail(c, CONCORD_EINVAL, "dtype");
+    if (c->precision == CONCORD_BF16X3)
+        return fail(c, CONCORD_EINVAL, "differentiation form supports FP64 and FP32");
     DeviceGuard g(c->device);
     if (int rc0 = enter(c)) return rc0;
-    int rc = ensure_products(c);   // Y at the current iterate (recomputed if stale)
-    if (rc) return rc;
-    const bool split = c->precision == CONCORD_BF16X3;
-    if (split) return fail(c, CONCORD_EINVAL, "differentiation form supports FP64 and FP32");
     const Csr& O = c->om[c->cur];
     const int out64 = dtype == CONCORD_F64;
-    if (dev_dOmega && dev_dX && mode == CONCORD_GRAD_MASKED && grad_fused_fits(c->dstore, c->n)) {
-        // both gradients from one gather of the rows Y_j; d f / d X^T = Omega Y / n in a
-        // handle-owned p x n buffer, written transposed (n x p)
-        if (!c->dxt && (rc = dalloc(c, &c->dxt, (size_t)c->prow * c->ldk * elem_bytes(c->dstore), true)))
-            return rc;
-        HIPCK(c, launch_grad_fused(O, c->p, c->Y, c->Xt, c->dstore, c->ldk, c->n, lam2, dev_dOmega,
-                                   out64, c->dxt, c->stream));
-        HIPCK(c, launch_transpose_out(c->dxt, c->dstore, c->p, c->n, c->ldk, 1.0 / (double)c->n,
-                                      dev_dX, out64, c->stream));
-        HIPCK(c, hipStreamSynchronize(c->stream));
-        return CONCORD_OK;
+    const int64_t p = c->p, nnz = c->nnz;
+    const size_t dense_bytes = (size_t)c->prow * c->ldk * elem_bytes(c->dstore);
+    // Buffers of this call only (returned before it ends): Y when the handle holds none,
+    // Omega Y before its transpose, and the two halves of every masked entry.
+    void* ybuf = nullptr;
+    void* oy = nullptr;
+    double* D = nullptr;
+    double* E = nullptr;
+    auto done = [&](int rc) {
+        dfree(c, ybuf);
+        dfree(c, oy);
+        dfree(c, D);
+        dfree(c, E);
+        return rc;
+    };
+    int rc;
+    // Y = Omega X^T: kept only by a solver whose products are current; otherwise
+    // recomputed here (the forward pass reduces ||Y||^2 without storing Y)
+    void* Y = c->Y;
+    if (!(c->prod_valid && c->Y)) {
+        if (!Y) {
+            if ((rc = dalloc(c, &ybuf, dense_bytes, true))) return done(rc);
+            Y = ybuf;
+        }
+        HIPCK(c, launch_spmm(O, p, c->Xt, c->dstore, c->ldk, c->ldk, Y, c->dstore, c->ldk, nullptr,
+                             nullptr, 0, nullptr, c->d_one, c->stream));
     }
-    if (dev_dOmega) {
-        if (mode == CONCORD_GRAD_MASKED) {
-            HIPCK(c, launch_sddmm_grad(O, c->p, c->Y, c->Xt, c->dstore, c->ldk, c->n, lam2,
-                                       dev_dOmega, out64, c->stream));
-        } else {
-            if ((rc = ensure_dense(c))) return rc;
-            HIPCK(c, launch_gemm_sym(c->gkind, true, c->Y, nullptr, c->Xt, nullptr, c->ldk, c->p,
+    if (dev_dX && (rc = dalloc(c, &oy, dense_bytes, true))) return done(rc);
+    if (dev_dOmega && mode == CONCORD_GRAD_MASKED) {
+        // both halves of every entry and, when d f / d X is wanted too, Omega Y, from one
+        // gather of the rows Y_j
+        const int ncb = grad_col_blocks(c->dstore, c->n);
+        const size_t len = (size_t)std::max<int64_t>(nnz, 1) * ncb;
+        if ((rc = dalloc_t(c, &D, len)) || (rc = dalloc_t(c, &E, len))) return done(rc);
+        HIPCK(c, launch_grad_rows(O, p, nnz, Y, c->Xt, c->dstore, c->ldk, c->n, D, E, oy,
+                                  c->stream));
+        HIPCK(c, launch_grad_combine(O, p, nnz, ncb, D, E, c->n, lam2, dev_dOmega, out64,
+                                     c->stream));
+    } else {
+        if (dev_dOmega) {   // dense G: the contraction of Algorithm 3 at the current iterate
+            if ((rc = ensure_dense(c))) return done(rc);
+            HIPCK(c, launch_gemm_sym(c->gkind, true, Y, nullptr, c->Xt, nullptr, c->ldk, p,
                                      0.5 / (double)c->n, c->M, c->dstore, c->ldp, c->stream));
-            HIPCK(c, launch_gather_dense_grad(c->M, c->dstore, c->ldp, O, c->p, lam2, dev_dOmega,
+            HIPCK(c, launch_gather_dense_grad(c->M, c->dstore, c->ldp, O, p, lam2, dev_dOmega,
                                               out64, c->stream));
         }
+        if (dev_dX)
+            HIPCK(c, launch_spmm(O, p, Y, c->dstore, c->ldk, c->ldk, oy, c->dstore, c->ldk,
+                                 nullptr, nullptr, 0, nullptr, c->d_one, c->stream));
     }
-    if (dev_dX) {
-        // d f / d X^T = Omega Y / n, formed in a handle-owned p x n buffer (kept for
-        // later calls) and written transposed (n x p).
-        if (!c->dxt && (rc = dalloc(c, &c->dxt, (size_t)c->prow * c->ldk * elem_bytes(c->dstore), true)))
-            return rc;
-        HIPCK(c, launch_spmm(O, c->p, c->Y, c->dstore, c->ldk, c->ldk, c->dxt, c->dstore, c->ldk,
-                             nullptr, nullptr, 0, nullptr, c->d_one, c->stream));
-        HIPCK(c, launch_transpose_out(c->dxt, c->dstore, c->p, c->n, c->ldk, 1.0 / (double)c->n,
-                                      dev_dX, out64, c->stream));
-    }
+    // d f / d X = (Omega Y)^T / n, written transposed (n x p)
+    if (dev_dX)
+        HIPCK(c, launch_transpose_out(oy, c->dstore, p, c->n, c->ldk, 1.0 / (double)c->n, dev_dX,
+                                      out64, c->stream));
     HIPCK(c, hipStreamSynchronize(c->stream));
-    return CONCORD_OK;
+    return done(CONCORD_OK);
 }
 
 }  // extern "C"

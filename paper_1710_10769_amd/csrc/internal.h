@@ -153,15 +153,16 @@ int64_t scan_ws_len(int64_t p);
 struct DevState;
 // Column splits of the Obs quadratic term in launch_trial (1 for Cov).
 int trial_splits(int variant, int bstore, int64_t ncols);
-// Trial evaluation for `m` step sizes tau_q = tau0 * 2^-q (q < m) at once.
+// Trial evaluation for `m` step sizes tau_q = tau0 * shrink^q (q < m) at once (tau_q
+// formed by q successive multiplications).
 // Per row partials part[((q*4 + t) * S + s) * p + row] for column split s < S =
 // trial_splits(...), t = 0: sum x - log1p x over the
 // diagonal, 1: ||Delta_i||^2, 2: quadratic term of row i, 3: 1 if the
 // diagonal entry is <= 0.  Obs quadratic: ||Delta_i X^T||^2 (B = Xt, ncols = n);
 // Cov quadratic: sum_{j,k in A_i} Delta_ij S_jk Delta_ik (B = S).
-hipError_t launch_trial(const Cand& A, int64_t p, double tau0, int m, double lam1, int variant,
-                        const void* B, int bstore, int64_t ldb, int64_t ncols, double* part,
-                        const struct DevState* st, hipStream_t stream);
+hipError_t launch_trial(const Cand& A, int64_t p, double tau0, double shrink, int m, double lam1,
+                        int variant, const void* B, int bstore, int64_t ldb, int64_t ncols,
+                        double* part, const struct DevState* st, hipStream_t stream);
 
 // Deterministic FP64 column sums in[c * rows + r] -> out[c], c < ncol, and in the same
 // launch the step that uses them.  ws holds at least ncol * COLSUM_MAXSEG doubles
@@ -170,8 +171,9 @@ constexpr int COLSUM_MAXSEG = 256;
 // Trial sums (ncol = 4m, out[q*4 + t]), then the decision: the first passing q (or the
 // forced one) is written to the state.
 hipError_t launch_colsum_decide(const double* in, int64_t rows, int ncol, double* out,
-                                double* ws, int m, double tau0, int q_base, double lam2,
-                                double inv_n, int forced_q, DevState* st, hipStream_t stream);
+                                double* ws, int m, double tau0, double shrink, int q_base,
+                                double lam2, double inv_n, int forced_q, DevState* st,
+                                hipStream_t stream);
 // Objective sums (ncol = 4 + nysq), then, when gated on, copied into st->obj.
 hipError_t launch_colsum_obj(const double* in, int64_t rows, int ncol, double* out, double* ws,
                              int nysq, const int* gate, DevState* st, hipStream_t stream);
@@ -191,6 +193,11 @@ hipError_t launch_obj_parts(const Csr& om, int64_t p, const void* W, int wstore,
 // the support of Omega (no dense M).
 hipError_t launch_obj_parts_cov(const Csr& om, int64_t p, const void* S, int sstore, int64_t lds,
                                 double* part, const int* gate, hipStream_t stream);
+
+// f = -obj[0] + 1/2 obj[4] / n + lam2/2 obj[1] from the objective sums in st->obj (the
+// smooth value of the differentiation form), written to *f (device) in stream order.
+hipError_t launch_smooth_finish(const DevState* st, int64_t n, double lam2, double* f,
+                                hipStream_t stream);
 
 // Identity CSR (omega = I) into `om`.
 hipError_t launch_identity(const Csr& om, int64_t p, hipStream_t stream);
@@ -234,15 +241,20 @@ hipError_t launch_tile_max(const void* S, int sstore, int64_t p, int64_t lds, do
                            hipStream_t stream);
 
 // Differentiation form.
-hipError_t launch_sddmm_grad(const Csr& om, int64_t p, const void* Yt, const void* Xt,
-                             int store, int64_t ld, int64_t n, double lam2, void* out,
-                             int out_f64, hipStream_t stream);
-// G on the stored entries (as launch_sddmm_grad) and Omega Y (p x ld, as launch_spmm with
-// B = Y) in one pass that gathers each row Y_j once for both; n up to 4 * 64 * V columns.
-bool grad_fused_fits(int store, int64_t n);
-hipError_t launch_grad_fused(const Csr& om, int64_t p, const void* Y, const void* Xt, int store,
-                             int64_t ld, int64_t n, double lam2, void* out, int out_f64,
-                             void* oy, hipStream_t stream);
+// Masked gradient on the stored entries and Omega Y (d f / d X^T times n) in one row
+// pass (Y = Omega X^T, p x ld rows): d_ij = <Y_j, Xt_i> goes to D at entry (i, j) and to E
+// at its mirror (j, i), per column block cb at offset cb * nnz (grad_col_blocks(store, n)
+// blocks; D and E hold that many times nnz doubles); oy (p x ld, may be null) receives
+// Omega Y.  launch_grad_combine then writes G_ij = (d_ij + d_ji) / (2n) + lam2 w_ij -
+// [i == j] / w_ii to out (nnz, FP64 or FP32).  The pattern must be symmetric (an entry
+// whose mirror is not stored gets an unspecified value).
+int grad_col_blocks(int store, int64_t n);
+hipError_t launch_grad_rows(const Csr& om, int64_t p, int64_t nnz, const void* Y, const void* Xt,
+                            int store, int64_t ld, int64_t n, double* D, double* E, void* oy,
+                            hipStream_t stream);
+hipError_t launch_grad_combine(const Csr& om, int64_t p, int64_t nnz, int ncb, const double* D,
+                               const double* E, int64_t n, double lam2, void* out, int out_f64,
+                               hipStream_t stream);
 hipError_t launch_gather_dense_grad(const void* M, int mstore, int64_t ldm, const Csr& om,
                                     int64_t p, double lam2, void* out, int out_f64,
                                     hipStream_t stream);
@@ -255,6 +267,23 @@ hipError_t launch_csr_import(const int32_t* col, const void* val, int val_f64, i
                              int32_t* col_out, double* val_out, hipStream_t stream);
 hipError_t launch_csr_export(const double* val, int64_t nnz, void* out, int out_f64,
                              hipStream_t stream);
+
+// Smooth value f and full objective F from the objective sums o[] of an iterate
+// (o[0] sum of log omega_ii, o[1] sum of squares, o[2] off-diagonal sum of |omega_ij|,
+// o[3] sum M o Omega (Cov), o[4] ||Y||^2 (Obs)):
+//   f = -o[0] + 1/2 quad + lam2/2 o[1],  quad = o[4] / n (Obs) or o[3] (Cov),
+//   F = f + lam1 o[2].
+// One definition for host and device code, without contraction into FMAs, so the
+// batched solves' stopping tests see bitwise the values the single solver computes.
+__host__ __device__ inline void objective_value(const double* o, bool obs, double dn,
+                                                double lam1, double lam2, double* f,
+                                                double* F) {
+#pragma clang fp contract(off)
+    const double quad = obs ? o[4] / dn : o[3];
+    const double fv = -o[0] + 0.5 * quad + 0.5 * lam2 * o[1];
+    *f = fv;
+    *F = fv + lam1 * o[2];
+}
 
 // Device-side solver state (one per handle, in device memory).
 struct DevState {
@@ -272,6 +301,86 @@ struct DevState {
     int nonpos;             // forced step leaves the domain
     int overflow;           // candidate capacity exceeded
     unsigned ticket;        // blocks finished in the running column-sum launch (0 between)
+    double fval;            // smooth value written by launch_smooth_finish
 };
+
+// ---- batched solves (many Cov problems and lambda1 values in one set of launches) ----
+//
+// One SolveDesc per (instance, lambda1) solve, in device memory; the solves of one
+// instance share its S.  Every phase kernel walks work items (solve, local block) of the
+// solves that still run, from tables a plan kernel builds at the start of each iteration,
+// with a fixed grid whose blocks loop over the items (no host decision between phases).
+struct SolveCtl {
+    int cur;            // CSR buffer holding the iterate
+    int phase;          // BPH_* below
+    int q_base;         // first step-size index of the next trial batch
+    int status;         // CONCORD_OK, CONCORD_WMAXITER, CONCORD_ELINESEARCH (when done)
+    int grow;           // 1: the candidate capacity was exceeded; the host regrows
+    int pad_;
+    int64_t k;          // accepted iterations
+    double F;           // full objective at the iterate
+};
+enum { BPH_CAND = 0, BPH_TRIAL = 1, BPH_DONE = 2 };
+
+struct SolveDesc {
+    int64_t p, nwords;
+    int T, inst, screen, grouped;   // tile rows; instance; exact screening; 8 lanes per trial row
+    const void* S;
+    int64_t lds;
+    const double* smax;
+    Csr om[2];
+    Cand A;
+    int64_t a_cap;
+    int64_t* cnt;
+    uint64_t* bitmap;
+    double* part;       // 4 * MAXQ * p trial partials, then 4 * p objective partials
+    double* tsums;      // 64
+    double* osums;      // 64
+    double* colws;      // 4 * MAXQ * COLSUM_MAXSEG
+    int64_t* scanws;    // scan_ws_len(p)
+    RefreshWs rws;
+    DevState* st;
+    SolveCtl* ctl;
+    double lam1;
+};
+
+// Per-instance lists of the tile pairs any of its solves keeps in a refresh (the
+// lambda-stacked refresh walks each listed pair once for all of them).
+struct InstDesc {
+    int T, nsolve, first;   // tile rows, solves of the instance (consecutive from `first`)
+    int screen;
+    int* ulist;             // T (T + 1) / 2 pair indices
+    int* ucount;            // 1
+    uint32_t* ubits;        // ceil(T (T + 1) / 2 / 32): pair already listed
+};
+
+// Work tables of one iteration.  off[ph][a] = first item of active solve act[a] in phase
+// ph (a = 0 .. nact), for the static phases; roff[i] the same for the refresh over the
+// instances.  status[0] = solves still running, status[1] = solves asking for more
+// candidate capacity.
+enum { BP_ROW = 0, BP_ROWG, BP_SCAN, BP_COLT, BP_COLO, BP_SROWS, BP_SPAIRS, BP_SOLVE, BP_N };
+struct BatchPlan {
+    int nact;
+    int* act;      // nsolve
+    int* off;      // BP_N * (nsolve + 1)
+    int* roff;     // ninst + 1
+    int* status;   // 2
+};
+
+struct BatchArgs {
+    int nsolve, ninst, maxT;   // maxT: largest tile-row count (dynamic LDS of two phases)
+    int bstore;            // S storage (ST_F64 or ST_F32)
+    int tb, total;         // step sizes per trial batch, max_backtracks + 1
+    int64_t max_iter;
+    double lam2, tol, tau0, shrink;
+};
+
+// Iteration of every running solve (the plan, candidates, trials and decision, emission,
+// the stacked refresh and objective of the accepted iterates, the stopping test), as
+// kernel launches on `stream` that read all control state from the device (graph
+// capturable).  init = true instead evaluates the products, threshold words and
+// objective of every solve's current iterate (the start, Omega = I).
+hipError_t launch_batch_iteration(const SolveDesc* sd, const InstDesc* idesc, const BatchPlan& pl,
+                                  const BatchArgs& a, bool init, int grid, hipStream_t stream);
 
 }  // namespace concord

@@ -18,6 +18,7 @@
 #include <cstdint>
 #include <type_traits>
 
+#include "../../include/concord.h"
 #include "internal.h"
 
 namespace concord {
@@ -164,7 +165,18 @@ spmm_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
 #pragma unroll
     for (int t = 0; t < V; ++t) acc[t] = 0;
     const int64_t s = rowptr[row], e = rowptr[row + 1];
-    if (active) {
+    // a last chunk that ncols cuts (ncols not a multiple of V; never with the library's
+    // padded layouts): element loads, nothing read past ncols, the FMA order unchanged
+    const int nv = active ? (ncols - c0 < V ? (int)(ncols - c0) : V) : 0;
+    if (active && nv < V) {
+        for (int64_t k = s; k < e; ++k) {
+            const T v0 = (T)val[k];
+            const int64_t jb = (int64_t)col[k] * ldb + c0;
+#pragma unroll
+            for (int t = 0; t < V; ++t)
+                if (t < nv) acc[t] = fma(v0, Ch::one(B, jb + t), acc[t]);
+        }
+    } else if (active) {
         int64_t k = s;
         for (; k + 4 <= e; k += 4) {
             T b0[V], b1[V], b2[V], b3[V];
@@ -195,12 +207,20 @@ spmm_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
         if (C) {
             if (CS == ST_F64) {
                 double* o = (double*)C + row * ldc + c0;
+                if (nv == V) {
 #pragma unroll
-                for (int t = 0; t < V; ++t) o[t] = (double)acc[t];
+                    for (int t = 0; t < V; ++t) o[t] = (double)acc[t];
+                } else {
+                    for (int t = 0; t < nv; ++t) o[t] = (double)acc[t];
+                }
             } else {
                 float* o = (float*)C + row * ldc + c0;
+                if (nv == V) {
 #pragma unroll
-                for (int t = 0; t < V; ++t) o[t] = (float)acc[t];
+                    for (int t = 0; t < V; ++t) o[t] = (float)acc[t];
+                } else {
+                    for (int t = 0; t < nv; ++t) o[t] = (float)acc[t];
+                }
             }
         }
         if (hi) {
@@ -317,8 +337,7 @@ cand_count_kernel(const void* __restrict__ M, int64_t ldm, const int64_t* __rest
 }
 
 template <int MS>
-__global__ void __launch_bounds__(NT)
-cand_fill_kernel(const void* __restrict__ M, int64_t ldm, const int64_t* __restrict__ rowptr,
+__device__ __forceinline__ void cand_fill_body(int64_t bx_, const void* __restrict__ M, int64_t ldm, const int64_t* __restrict__ rowptr,
                  const int32_t* __restrict__ col, const double* __restrict__ val, int64_t p,
                  double lam2, const uint64_t* __restrict__ bitmap, int64_t nwords,
                  const int64_t* __restrict__ arow, int32_t* __restrict__ acol,
@@ -328,7 +347,7 @@ cand_fill_kernel(const void* __restrict__ M, int64_t ldm, const int64_t* __restr
     typedef typename Chunk<MS>::T E;
     extern __shared__ uint64_t swords[];   // with a tile mask: the row's words holding support
     const int wave = threadIdx.x >> 6, lane = lane_id();
-    const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
+    const int64_t row = uni(bx_ * WPB + wave);
     if (row >= p) return;
     const int64_t s = rowptr[row], e = rowptr[row + 1];
     int64_t out = arow[row];
@@ -419,19 +438,29 @@ cand_fill_kernel(const void* __restrict__ M, int64_t ldm, const int64_t* __restr
     }
 }
 
+template <int MS>
+__global__ void __launch_bounds__(NT)
+cand_fill_kernel(const void* __restrict__ M, int64_t ldm, const int64_t* __restrict__ rowptr,
+                 const int32_t* __restrict__ col, const double* __restrict__ val, int64_t p,
+                 double lam2, const uint64_t* __restrict__ bitmap, int64_t nwords,
+                 const int64_t* __restrict__ arow, int32_t* __restrict__ acol,
+                 double* __restrict__ aom, double* __restrict__ agr, const int* overflow,
+                 const uint64_t* __restrict__ tmask) {
+    cand_fill_body<MS>(blockIdx.x, M, ldm, rowptr, col, val, p, lam2, bitmap, nwords, arow, acol, aom, agr, overflow, tmask);
+}
+
 // Cov form: the gradient on the candidates, G_ij = M_ij + lam2 omega_ij - [i == j] / omega_ii,
 // with M_ij gathered from S by m_entry (no dense M).  Wave per row, lanes over the row's
 // candidates; the row-i half of every entry walks the same nonzeros in every lane.
 template <int BS>
-__global__ void __launch_bounds__(NT)
-cand_grad_cov_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+__device__ __forceinline__ void cand_grad_cov_body(int64_t bx_, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                      const double* __restrict__ val, int64_t p, const void* __restrict__ S,
                      int64_t lds, double lam2, const int64_t* __restrict__ arow,
                      const int32_t* __restrict__ acol, const double* __restrict__ aom,
                      double* __restrict__ agr, const int* overflow) {
     if (*overflow) return;
     const int wave = threadIdx.x >> 6, lane = lane_id();
-    const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
+    const int64_t row = uni(bx_ * WPB + wave);
     if (row >= p) return;
     const int64_t s = arow[row], e = arow[row + 1];
     for (int64_t k0 = s; k0 < e; k0 += 64) {
@@ -446,6 +475,16 @@ cand_grad_cov_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restri
             agr[k] = g;
         }
     }
+}
+
+template <int BS>
+__global__ void __launch_bounds__(NT)
+cand_grad_cov_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                     const double* __restrict__ val, int64_t p, const void* __restrict__ S,
+                     int64_t lds, double lam2, const int64_t* __restrict__ arow,
+                     const int32_t* __restrict__ acol, const double* __restrict__ aom,
+                     double* __restrict__ agr, const int* overflow) {
+    cand_grad_cov_body<BS>(blockIdx.x, rowptr, col, val, p, S, lds, lam2, arow, acol, aom, agr, overflow);
 }
 
 // ---- scan ---------------------------------------------------------------------
@@ -465,10 +504,9 @@ __device__ inline int64_t block_sum_i64(int64_t v, int64_t* red) {
     return t;
 }
 
-__global__ void __launch_bounds__(NT)
-scan_part_kernel(const int64_t* __restrict__ cnt, int64_t p, int64_t* __restrict__ part) {
+__device__ __forceinline__ void scan_part_body(int64_t bx_, const int64_t* __restrict__ cnt, int64_t p, int64_t* __restrict__ part) {
     __shared__ int64_t red[WPB];
-    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
+    const int64_t base = bx_ * SCAN_CHUNK;
     int64_t s = 0;
 #pragma unroll
     for (int e = 0; e < SCAN_CHUNK / NT; ++e) {
@@ -476,15 +514,19 @@ scan_part_kernel(const int64_t* __restrict__ cnt, int64_t p, int64_t* __restrict
         if (i < p) s += cnt[i];
     }
     s = block_sum_i64(s, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    if (threadIdx.x == 0) part[bx_] = s;
 }
 
 __global__ void __launch_bounds__(NT)
-scan_apply_kernel(const int64_t* __restrict__ cnt, int64_t p, const int64_t* __restrict__ part,
+scan_part_kernel(const int64_t* __restrict__ cnt, int64_t p, int64_t* __restrict__ part) {
+    scan_part_body(blockIdx.x, cnt, p, part);
+}
+
+__device__ __forceinline__ void scan_apply_body(int64_t bx_, int64_t nb_, const int64_t* __restrict__ cnt, int64_t p, const int64_t* __restrict__ part,
                   int64_t* __restrict__ out, int64_t cap, int* overflow, int64_t* total_out) {
     __shared__ int64_t red[WPB];
     __shared__ int64_t wtot[WPB];
-    const int64_t b = blockIdx.x;
+    const int64_t b = bx_;
     int64_t o = 0;
     for (int64_t k = threadIdx.x; k < b; k += NT) o += part[k];
     const int64_t off = block_sum_i64(o, red);
@@ -519,12 +561,18 @@ scan_apply_kernel(const int64_t* __restrict__ cnt, int64_t p, const int64_t* __r
         if (i0 + e < p) out[i0 + e] = run;
         run += v[e];
     }
-    if (b == gridDim.x - 1 && threadIdx.x == 0) {
+    if (b == nb_ - 1 && threadIdx.x == 0) {
         const int64_t total = off + btotal;
         out[p] = total;
         if (overflow) *overflow = total > cap ? 1 : 0;
         if (total_out) *total_out = total;
     }
+}
+
+__global__ void __launch_bounds__(NT)
+scan_apply_kernel(const int64_t* __restrict__ cnt, int64_t p, const int64_t* __restrict__ part,
+                  int64_t* __restrict__ out, int64_t cap, int* overflow, int64_t* total_out) {
+    scan_apply_body(blockIdx.x, gridDim.x, cnt, p, part, out, cap, overflow, total_out);
 }
 
 // ---- trial evaluation ---------------------------------------------------------
@@ -537,22 +585,20 @@ __device__ inline double prox_one(double om, double g, double tau, double thr, b
 }
 
 template <int BS, bool OBS>
-__global__ void __launch_bounds__(NT)
-trial_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
+__device__ __forceinline__ void trial_body(int64_t bx_, int split, int nsplit, const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
              const double* __restrict__ aom, const double* __restrict__ agr, int64_t p,
-             double tau0, int m, double lam1, const void* __restrict__ B, int64_t ldb,
-             int64_t ncols, double* __restrict__ part, const DevState* st) {
+             double tau0, double shrink, int m, double lam1, const void* __restrict__ B,
+             int64_t ldb, int64_t ncols, double* __restrict__ part, const DevState* st) {
     if (st->overflow || st->accepted_q >= 0) return;   // capacity exceeded or already decided
     typedef Chunk<BS> Ch;
     typedef typename Ch::T T;
     constexpr int V = Ch::V;
     const int wave = threadIdx.x >> 6, lane = lane_id();
-    const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
+    const int64_t row = uni(bx_ * WPB + wave);
     if (row >= p) return;
     const int64_t s = arow[row], e = arow[row + 1];
     // blockIdx.y = column split of the Obs quadratic term; split 0 also does the
     // elementwise terms.  Partials land in part[((q*4 + t) * nsplit + split) * p + row].
-    const int split = blockIdx.y, nsplit = gridDim.y;
     double slog[MAXQ], sdd[MAXQ], squad[MAXQ], snp[MAXQ];
 #pragma unroll
     for (int q = 0; q < MAXQ; ++q) { slog[q] = 0; sdd[q] = 0; squad[q] = 0; snp[q] = 0; }
@@ -577,7 +623,7 @@ trial_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
                     }
                 }
             }
-            tau *= 0.5;
+            tau *= shrink;
         }
     }
     // quadratic term
@@ -598,7 +644,7 @@ trial_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
 #pragma unroll
             for (int q = 0; q < MAXQ; ++q) {
                 dq[u][q] = (T)(prox_one(om, g, tau, tau * lam1, diag) - om);
-                tau *= 0.5;
+                tau *= shrink;
             }
         }
         const int64_t cstep = (int64_t)nsplit * 64 * V;
@@ -684,7 +730,7 @@ trial_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
 #pragma unroll
                             for (int t = 0; t < V; ++t) acc[q][t] = fma(d, b[u][t], acc[q][t]);
                         }
-                        tau *= 0.5;
+                        tau *= shrink;
                     }
                 }
             }
@@ -708,7 +754,7 @@ trial_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
 #pragma unroll
                 for (int q = 0; q < MAXQ; ++q) {
                     db[q] = q < m ? prox_one(omb, gb, tau, tau * lam1, diagb) - omb : 0.0;
-                    tau *= 0.5;
+                    tau *= shrink;
                 }
             }
             for (int64_t ka = s; ka < e; ++ka) {
@@ -723,7 +769,7 @@ trial_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
                         const double da = prox_one(oma, ga, tau, tau * lam1, diaga) - oma;
                         squad[q] += da * sab * db[q];
                     }
-                    tau *= 0.5;
+                    tau *= shrink;
                 }
             }
         }
@@ -756,6 +802,15 @@ trial_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
     if ((lane & 1) == 0 && q < m) part[((int64_t)(q * 4 + t) * nsplit + split) * p + row] = tot;
 }
 
+template <int BS, bool OBS>
+__global__ void __launch_bounds__(NT)
+trial_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
+             const double* __restrict__ aom, const double* __restrict__ agr, int64_t p,
+             double tau0, double shrink, int m, double lam1, const void* __restrict__ B,
+             int64_t ldb, int64_t ncols, double* __restrict__ part, const DevState* st) {
+    trial_body<BS, OBS>(blockIdx.x, blockIdx.y, gridDim.y, arow, acol, aom, agr, p, tau0, shrink, m, lam1, B, ldb, ncols, part, st);
+}
+
 // Cov trials with 8 lanes per row (8 rows per wave): a Cov candidate row holds a few
 // entries, so a whole wave per row would leave most lanes idle.  Same terms as
 // trial_kernel's Cov path; the 32 partials are reduced over the row's 8 lanes by a
@@ -764,14 +819,13 @@ trial_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
 constexpr int TG = 8;
 constexpr int64_t COV_GROUP_MIN_P = 4096;
 template <int BS>
-__global__ void __launch_bounds__(NT)
-trial_cov_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
+__device__ __forceinline__ void trial_cov_body(int64_t bx_, const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
                  const double* __restrict__ aom, const double* __restrict__ agr, int64_t p,
-                 double tau0, int m, double lam1, const void* __restrict__ B, int64_t ldb,
-                 double* __restrict__ part, const DevState* st) {
+                 double tau0, double shrink, int m, double lam1, const void* __restrict__ B,
+                 int64_t ldb, double* __restrict__ part, const DevState* st) {
     if (st->overflow || st->accepted_q >= 0) return;   // capacity exceeded or already decided
     const int lane = lane_id(), g = lane & (TG - 1);
-    const int64_t row = ((int64_t)blockIdx.x * WPB + (threadIdx.x >> 6)) * (64 / TG) + (lane / TG);
+    const int64_t row = (bx_ * WPB + (threadIdx.x >> 6)) * (64 / TG) + (lane / TG);
     const bool act = row < p;
     const int64_t s = act ? arow[row] : 0, e = act ? arow[row + 1] : 0;
     double slog[MAXQ], sdd[MAXQ], squad[MAXQ], snp[MAXQ];
@@ -796,7 +850,7 @@ trial_cov_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ a
                     }
                 }
             }
-            tau *= 0.5;
+            tau *= shrink;
         }
     }
     // sum_{a,b in A_i} Delta_a S[j_a, j_b] Delta_b : the group's lanes over b, loop over a
@@ -810,7 +864,7 @@ trial_cov_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ a
 #pragma unroll
             for (int q = 0; q < MAXQ; ++q) {
                 db[q] = q < m ? prox_one(omb, gb, tau, tau * lam1, diagb) - omb : 0.0;
-                tau *= 0.5;
+                tau *= shrink;
             }
         }
         for (int64_t ka = s; ka < e; ++ka) {
@@ -825,7 +879,7 @@ trial_cov_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ a
                     const double da = prox_one(oma, ga, tau, tau * lam1, diaga) - oma;
                     squad[q] += da * sab * db[q];
                 }
-                tau *= 0.5;
+                tau *= shrink;
             }
         }
     }
@@ -854,9 +908,18 @@ trial_cov_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ a
     }
 }
 
+template <int BS>
+__global__ void __launch_bounds__(NT)
+trial_cov_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
+                 const double* __restrict__ aom, const double* __restrict__ agr, int64_t p,
+                 double tau0, double shrink, int m, double lam1, const void* __restrict__ B,
+                 int64_t ldb, double* __restrict__ part, const DevState* st) {
+    trial_cov_body<BS>(blockIdx.x, arow, acol, aom, agr, p, tau0, shrink, m, lam1, B, ldb, part, st);
+}
+
 // ---- decision ----------------------------------------------------------------
-__device__ void decide_one(const double* __restrict__ sums, int m, double tau0, int q_base,
-                           double lam2, double inv_n, int forced_q, DevState* st) {
+__device__ void decide_one(const double* __restrict__ sums, int m, double tau0, double shrink,
+                           int q_base, double lam2, double inv_n, int forced_q, DevState* st) {
     if (st->overflow || st->accepted_q >= 0) return;   // capacity exceeded / decided earlier
     double tau = tau0;
     for (int q = 0; q < m; ++q) {
@@ -881,7 +944,7 @@ __device__ void decide_one(const double* __restrict__ sums, int m, double tau0, 
             st->dd = dd;
             return;
         }
-        tau *= 0.5;
+        tau *= shrink;
     }
 }
 
@@ -901,7 +964,7 @@ __device__ void obj_finish_one(const double* __restrict__ sums, int nysq, DevSta
 
 struct FinArgs {
     int m, q_base, forced_q, nysq;
-    double tau0, lam2, inv_n;
+    double tau0, shrink, lam2, inv_n;
     const int* gate;
 };
 enum { FIN_DECIDE = 0, FIN_OBJ = 1 };
@@ -916,14 +979,13 @@ enum { FIN_DECIDE = 0, FIN_OBJ = 1 };
 // or the objective copy (FIN_OBJ).  No block waits for another, so the kernel always
 // completes; the association of every sum depends only on (rows, nseg).
 template <int FIN>
-__global__ void __launch_bounds__(NT)
-colsum_finish_kernel(const double* __restrict__ in, int64_t rows, int64_t seg,
+__device__ __forceinline__ void colsum_finish_body(int c_, int b_, int ncol_, int nseg_, const double* __restrict__ in, int64_t rows, int64_t seg,
                      double* __restrict__ ws, double* __restrict__ out, unsigned* ticket,
                      FinArgs fa, DevState* st) {
     __shared__ double red[NT];
     __shared__ int last;
-    const int c = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
-    const int ncol = gridDim.x, nseg = gridDim.y;
+    const int c = c_, b = b_, t = threadIdx.x;
+    const int ncol = ncol_, nseg = nseg_;
     const double* a = in + (int64_t)c * rows;
     const int64_t lo = (int64_t)b * seg, hi = lo + seg < rows ? lo + seg : rows;
     double s = 0.0;
@@ -951,21 +1013,28 @@ colsum_finish_kernel(const double* __restrict__ in, int64_t rows, int64_t seg,
     if (t == 0) {
         *ticket = 0u;
         if (FIN == FIN_DECIDE)
-            decide_one(out, fa.m, fa.tau0, fa.q_base, fa.lam2, fa.inv_n, fa.forced_q, st);
+            decide_one(out, fa.m, fa.tau0, fa.shrink, fa.q_base, fa.lam2, fa.inv_n, fa.forced_q, st);
         else
             obj_finish_one(out, fa.nysq, st, fa.gate);
     }
 }
 
-// ---- emission ----------------------------------------------------------------
+template <int FIN>
 __global__ void __launch_bounds__(NT)
-emit_count_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
+colsum_finish_kernel(const double* __restrict__ in, int64_t rows, int64_t seg,
+                     double* __restrict__ ws, double* __restrict__ out, unsigned* ticket,
+                     FinArgs fa, DevState* st) {
+    colsum_finish_body<FIN>(blockIdx.x, blockIdx.y, gridDim.x, gridDim.y, in, rows, seg, ws, out, ticket, fa, st);
+}
+
+// ---- emission ----------------------------------------------------------------
+__device__ __forceinline__ void emit_count_body(int64_t bx_, const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
                   const double* __restrict__ aom, const double* __restrict__ agr, int64_t p,
                   double lam1, const DevState* st, int64_t* __restrict__ cnt) {
     if (st->accepted_q < 0 || st->nonpos) return;
     const double tau = st->tau;
     const int wave = threadIdx.x >> 6, lane = lane_id();
-    const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
+    const int64_t row = uni(bx_ * WPB + wave);
     if (row >= p) return;
     const int64_t s = arow[row], e = arow[row + 1];
     int c = 0;
@@ -979,14 +1048,20 @@ emit_count_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ 
 }
 
 __global__ void __launch_bounds__(NT)
-emit_fill_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
+emit_count_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
+                  const double* __restrict__ aom, const double* __restrict__ agr, int64_t p,
+                  double lam1, const DevState* st, int64_t* __restrict__ cnt) {
+    emit_count_body(blockIdx.x, arow, acol, aom, agr, p, lam1, st, cnt);
+}
+
+__device__ __forceinline__ void emit_fill_body(int64_t bx_, const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
                  const double* __restrict__ aom, const double* __restrict__ agr, int64_t p,
                  double lam1, const DevState* st, const int64_t* __restrict__ orow,
                  int32_t* __restrict__ ocol, double* __restrict__ oval) {
     if (st->accepted_q < 0 || st->nonpos) return;
     const double tau = st->tau;
     const int wave = threadIdx.x >> 6, lane = lane_id();
-    const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
+    const int64_t row = uni(bx_ * WPB + wave);
     if (row >= p) return;
     const int64_t s = arow[row], e = arow[row + 1];
     int64_t out = orow[row];
@@ -1009,6 +1084,14 @@ emit_fill_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ a
         }
         out += __popcll(mask);
     }
+}
+
+__global__ void __launch_bounds__(NT)
+emit_fill_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
+                 const double* __restrict__ aom, const double* __restrict__ agr, int64_t p,
+                 double lam1, const DevState* st, const int64_t* __restrict__ orow,
+                 int32_t* __restrict__ ocol, double* __restrict__ oval) {
+    emit_fill_body(blockIdx.x, arow, acol, aom, agr, p, lam1, st, orow, ocol, oval);
 }
 
 // ---- objective partials --------------------------------------------------------
@@ -1043,13 +1126,12 @@ obj_parts_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__
 // Cov form: the same four partials, the last as sum_j M_ij omega_ij with M_ij gathered
 // from S (m_entry) on the support.
 template <int BS>
-__global__ void __launch_bounds__(NT)
-obj_parts_cov_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+__device__ __forceinline__ void obj_parts_cov_body(int64_t bx_, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                      const double* __restrict__ val, int64_t p, const void* __restrict__ S,
                      int64_t lds, double* __restrict__ part, const int* gate) {
     if (gate && *gate == 0) return;
     const int wave = threadIdx.x >> 6, lane = lane_id();
-    const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
+    const int64_t row = uni(bx_ * WPB + wave);
     if (row >= p) return;
     const int64_t s = rowptr[row], e = rowptr[row + 1];
     double lg = 0, sq = 0, l1 = 0, wv = 0;
@@ -1072,6 +1154,21 @@ obj_parts_cov_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restri
         part[1 * p + row] = sq;
         part[2 * p + row] = l1;
         part[3 * p + row] = wv;
+    }
+}
+
+template <int BS>
+__global__ void __launch_bounds__(NT)
+obj_parts_cov_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                     const double* __restrict__ val, int64_t p, const void* __restrict__ S,
+                     int64_t lds, double* __restrict__ part, const int* gate) {
+    obj_parts_cov_body<BS>(blockIdx.x, rowptr, col, val, p, S, lds, part, gate);
+}
+
+__global__ void smooth_finish_kernel(const DevState* st, double dn, double lam2, double* f) {
+    if (threadIdx.x == 0) {
+        double F;
+        objective_value(st->obj, true, dn, 0.0, lam2, f, &F);
     }
 }
 
@@ -1346,14 +1443,13 @@ cov_refresh_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict
 // fall in, with weight w(I, K) = max_{i in I} sum_{k in supp_i, k/64 = K} |omega_ik|, and
 // the largest row count.  More than SCREEN_L tiles marks I as unscreened (count > L).
 constexpr int SCREEN_L = 64;
-__global__ void __launch_bounds__(64)
-screen_rows_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+__device__ __forceinline__ void screen_rows_body(int I_, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                    const double* __restrict__ val, int64_t p, int T, int* __restrict__ lcnt,
                    int* __restrict__ lK, double* __restrict__ lW, int* __restrict__ lcmax,
                    int* __restrict__ pcount, uint64_t* __restrict__ tmask, const int* gate) {
     if (gate && *gate == 0) return;
     extern __shared__ unsigned long long wk[];   // T weights (bits of non-negative doubles)
-    const int I = blockIdx.x, lane = threadIdx.x;
+    const int I = I_, lane = threadIdx.x;
     if (I == 0 && lane == 0) *pcount = 0;   // the pair kernel (next launch) appends from 0
     const int TW = (T + 63) / 64;
     for (int k = lane; k < TW; k += 64) tmask[(int64_t)I * TW + k] = 0ull;   // kept-tile bits
@@ -1401,6 +1497,14 @@ screen_rows_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict
     }
 }
 
+__global__ void __launch_bounds__(64)
+screen_rows_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                   const double* __restrict__ val, int64_t p, int T, int* __restrict__ lcnt,
+                   int* __restrict__ lK, double* __restrict__ lW, int* __restrict__ lcmax,
+                   int* __restrict__ pcount, uint64_t* __restrict__ tmask, const int* gate) {
+    screen_rows_body(blockIdx.x, rowptr, col, val, p, T, lcnt, lK, lW, lcmax, pcount, tmask, gate);
+}
+
 // Pair screening, second part: one thread per tile pair t (the refresh's order).  The
 // pair is kept if it is diagonal, if a tile is unscreened, or if
 //   (sum_K w(I, K) smax[K][J] + sum_K w(J, K) smax[K][I]) / 2,
@@ -1408,16 +1512,16 @@ screen_rows_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict
 // threshold after the same widening.  Kept pairs are appended to plist (one atomic per
 // block; the order of blocks is free, the refresh's result does not depend on it).
 template <typename E>
-__global__ void __launch_bounds__(NT)
-screen_pairs_kernel(int T, const int* __restrict__ lcnt, const int* __restrict__ lK,
+__device__ __forceinline__ void screen_pairs_body(int bx_, int T, const int* __restrict__ lcnt, const int* __restrict__ lK,
                     const double* __restrict__ lW, const int* __restrict__ lcmax,
                     const double* __restrict__ smax, double lam1, int* __restrict__ plist,
-                    int* __restrict__ pcount, uint64_t* __restrict__ tmask, const int* gate) {
+                    int* __restrict__ pcount, uint64_t* __restrict__ tmask, const int* gate, int* __restrict__ ulist = nullptr, int* __restrict__ ucount = nullptr,
+    uint32_t* __restrict__ ubits = nullptr) {
     if (gate && *gate == 0) return;
     __shared__ int wsum[WPB];
     __shared__ int bbase;
     const int nt = T * (T + 1) / 2;
-    const int t = blockIdx.x * NT + threadIdx.x;
+    const int t = bx_ * NT + threadIdx.x;
     bool keep = false;
     if (t < nt) {
         const int2 ij = refresh_tile(t, T, nt);
@@ -1456,7 +1560,21 @@ screen_pairs_kernel(int T, const int* __restrict__ lcnt, const int* __restrict__
         atomicOr((unsigned long long*)&tmask[(int64_t)ij.x * TW + (ij.y >> 6)], 1ull << (ij.y & 63));
         if (ij.x != ij.y)
             atomicOr((unsigned long long*)&tmask[(int64_t)ij.y * TW + (ij.x >> 6)], 1ull << (ij.x & 63));
+        // batched solves: the pair joins its instance's list once for all of its solves
+        if (ulist) {
+            const uint32_t bit = 1u << (t & 31);
+            if (!(atomicOr(&ubits[t >> 5], bit) & bit)) ulist[atomicAdd(ucount, 1)] = t;
+        }
     }
+}
+
+template <typename E>
+__global__ void __launch_bounds__(NT)
+screen_pairs_kernel(int T, const int* __restrict__ lcnt, const int* __restrict__ lK,
+                    const double* __restrict__ lW, const int* __restrict__ lcmax,
+                    const double* __restrict__ smax, double lam1, int* __restrict__ plist,
+                    int* __restrict__ pcount, uint64_t* __restrict__ tmask, const int* gate) {
+    screen_pairs_body<E>(blockIdx.x, T, lcnt, lK, lW, lcmax, smax, lam1, plist, pcount, tmask, gate);
 }
 
 // Largest |S| of every 64 x 64 tile (as the refresh reads S), for its screening.
@@ -1492,12 +1610,11 @@ tile_max_kernel(const void* __restrict__ S, int64_t p, int64_t lds, int T, doubl
 // Row i's words already hold {j : j == i or |M_ij| > lam1}; OR in supp(Omega_i) and
 // count: the same bitmap and counts as cand_count_kernel, reading p/8 bytes per row
 // instead of the row of M.
-__global__ void __launch_bounds__(NT)
-cand_merge_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col, int64_t p,
+__device__ __forceinline__ void cand_merge_body(int64_t bx_, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col, int64_t p,
                   uint64_t* __restrict__ bitmap, int64_t nwords, int64_t* __restrict__ cnt,
                   const uint64_t* __restrict__ tmask) {
     const int wave = threadIdx.x >> 6, lane = lane_id();
-    const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
+    const int64_t row = uni(bx_ * WPB + wave);
     if (row >= p) return;
     uint64_t* rw = bitmap + row * nwords;
     const int64_t s = rowptr[row], e = rowptr[row + 1];
@@ -1547,6 +1664,13 @@ cand_merge_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict_
     double tt = (double)total;
     tt = wave_sum(tt);
     if (lane == 0) cnt[row] = (int64_t)tt;
+}
+
+__global__ void __launch_bounds__(NT)
+cand_merge_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col, int64_t p,
+                  uint64_t* __restrict__ bitmap, int64_t nwords, int64_t* __restrict__ cnt,
+                  const uint64_t* __restrict__ tmask) {
+    cand_merge_body(blockIdx.x, rowptr, col, p, bitmap, nwords, cnt, tmask);
 }
 
 // ---- ingest ----------------------------------------------------------------------
@@ -1680,184 +1804,25 @@ check_finite_kernel(const In* __restrict__ A, int64_t rows, int64_t cols, int64_
 }
 
 // ---- differentiation form ------------------------------------------------------
-// G_ij on the stored entries: ( <Y_i, Xt_j> + <Y_j, Xt_i> ) / (2n) + lam2 w_ij - [i==j]/w_ii.
-// One wave per row i computes each unordered pair once: for j >= i it writes G_ij to
-// entry (i,j) and, mirrored, to entry (j,i); entries with j < i are written by row j's
-// wave.  The row's entries are taken 64 at a time, one per lane: each lane finds its
-// entry's mirror position by binary search of row j (all lanes at once), the pairs
-// j >= i are walked from a ballot mask, and the wave sums of 8 pairs are done together
-// by a reduce-scatter (4 + 2 + 1 shuffles, then 3 more for the whole wave) instead of 6
-// shuffles per pair.  RES: Y_i and Xt_i stay in registers (up to RC chunks of 64*V
-// columns) and the rows j of the next pair are loaded before the current pair's
-// arithmetic; otherwise every pair re-reads row i.
-constexpr int SDDMM_GROUP = 8;
-template <int S, int RC, bool RES>
-__global__ void __launch_bounds__(NT)
-sddmm_grad_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                  const double* __restrict__ val, int64_t p, const void* __restrict__ Y,
-                  const void* __restrict__ Xt, int64_t ld, int64_t n, double lam2, void* out,
-                  int out_f64) {
-    typedef Chunk<S> Ch;
-    typedef typename Ch::T T;
-    constexpr int V = Ch::V;
-    const int wave = threadIdx.x >> 6, lane = lane_id();
-    const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
-    if (row >= p) return;
-    const int64_t s = rowptr[row], e = rowptr[row + 1];
-    const int nch = (int)((n + 64 * V - 1) / (64 * V));
-    T yi[RC][V], xi[RC][V];
-#pragma unroll
-    for (int q = 0; q < RC; ++q) {
-        const int64_t c = (int64_t)q * 64 * V + lane * V;
-        if (RES && q < nch && c < n) {
-            Ch::load(Y, row * ld + c, yi[q]);
-            Ch::load(Xt, row * ld + c, xi[q]);
-        } else {
-#pragma unroll
-            for (int t = 0; t < V; ++t) { yi[q][t] = 0; xi[q][t] = 0; }
-        }
-    }
-    // <Y_i, Xt_j> + <Y_j, Xt_i>: this lane's share
-    auto pair_part = [&](int64_t j) -> double {
-        double acc = 0.0;
-        {
-            for (int64_t c = lane * V; c < n; c += 64 * V) {
-                T a4[V], b4[V], c4[V], d4[V];
-                Ch::load(Y, row * ld + c, a4);
-                Ch::load(Xt, j * ld + c, b4);
-                Ch::load(Y, j * ld + c, c4);
-                Ch::load(Xt, row * ld + c, d4);
-                T a = 0;
-#pragma unroll
-                for (int t = 0; t < V; ++t) a += a4[t] * b4[t] + c4[t] * d4[t];
-                acc += (double)a;
-            }
-        }
-        return acc;
-    };
-    const double inv2n = 1.0 / (2.0 * (double)n);
-    for (int64_t b = s; b < e; b += 64) {
-        const int cnt = (int)(e - b < 64 ? e - b : 64);
-        // lane t: entry b + t, its column and its mirror's position (-1: none or j <= i)
-        int jl = -1;
-        int64_t mpos = -1;
-        if (lane < cnt) {
-            jl = col[b + lane];
-            if (jl > row) {
-                const int64_t me = rowptr[jl + 1];
-                int64_t lo_ = rowptr[jl], hi_ = me;
-                while (lo_ < hi_) {
-                    const int64_t mid = (lo_ + hi_) >> 1;
-                    if (col[mid] < row) lo_ = mid + 1; else hi_ = mid;
-                }
-                if (lo_ < me && col[lo_] == row) mpos = lo_;
-            }
-        }
-        uint64_t todo = __ballot(lane < cnt && jl >= row);
-        while (todo) {
-            // up to SDDMM_GROUP pairs, then one reduce-scatter for all of them
-            double v[SDDMM_GROUP];
-            int64_t jj[SDDMM_GROUP];
-            int my_t = 0;   // lane g holds the entry index of slot g
-            int m = 0;
-#pragma unroll
-            for (int g = 0; g < SDDMM_GROUP; ++g) {
-                v[g] = 0.0;
-                jj[g] = row;
-                if (todo) {
-                    const int t = __builtin_ctzll(todo);
-                    todo &= todo - 1;
-                    jj[g] = uni((int64_t)__shfl(jl, t, 64));
-                    if (lane == g) my_t = t;
-                    m = g + 1;
-                }
-            }
-            if (RES) {
-                // rows j of the group's pairs, the next pair's loads issued before the
-                // current pair's arithmetic
-                T bx[2][RC][V], by[2][RC][V];
-                auto fetch = [&](int64_t j, T (&x)[RC][V], T (&y)[RC][V]) {
-#pragma unroll
-                    for (int q = 0; q < RC; ++q) {
-                        const int64_t c = (int64_t)q * 64 * V + lane * V;
-                        if (q < nch && c < n) {
-                            Ch::load(Xt, j * ld + c, x[q]);
-                            Ch::load(Y, j * ld + c, y[q]);
-                        }
-                    }
-                };
-                fetch(jj[0], bx[0], by[0]);
-#pragma unroll
-                for (int g = 0; g < SDDMM_GROUP; ++g) {
-                    if (g + 1 < SDDMM_GROUP && g + 1 < m) fetch(jj[g + 1], bx[(g + 1) & 1], by[(g + 1) & 1]);
-                    if (g < m) {
-                        double acc = 0.0;
-#pragma unroll
-                        for (int q = 0; q < RC; ++q) {
-                            const int64_t c = (int64_t)q * 64 * V + lane * V;
-                            if (q < nch && c < n) {
-                                T a = 0;
-#pragma unroll
-                                for (int t = 0; t < V; ++t)
-                                    a += yi[q][t] * bx[g & 1][q][t] + by[g & 1][q][t] * xi[q][t];
-                                acc += (double)a;
-                            }
-                        }
-                        v[g] = acc;
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int g = 0; g < SDDMM_GROUP; ++g)
-                    if (g < m) v[g] = pair_part(jj[g]);
-            }
-#pragma unroll
-            for (int w = SDDMM_GROUP, o = 32; w > 1; w >>= 1, o >>= 1) {
-                const bool upper = (lane & o) != 0;   // keep the upper half of the w values
-#pragma unroll
-                for (int i = 0; i < w / 2; ++i) {
-                    const double send = upper ? v[i] : v[i + w / 2];
-                    const double keep = upper ? v[i + w / 2] : v[i];
-                    v[i] = keep + __shfl_xor(send, o, 64);
-                }
-            }
-            // v[0]: slot (lane >> 3) & 7 summed over the 8 lanes that share bits 0..2
-            double tot = v[0];
-#pragma unroll
-            for (int o = 4; o >= 1; o >>= 1) tot += __shfl_xor(tot, o, 64);
-            const int g = (lane >> 3) & 7;
-            const int t = __shfl(my_t, g, 64);
-            const int64_t mp = __shfl(mpos, t, 64);
-            const int j = __shfl(jl, t, 64);
-            if ((lane & 7) == 0 && g < m) {
-                const int64_t k = b + t;
-                const double wv = val[k];
-                double gr = tot * inv2n + lam2 * wv;
-                if (j == row) gr -= 1.0 / wv;
-                if (out_f64) {
-                    ((double*)out)[k] = gr;
-                    if (mp >= 0) ((double*)out)[mp] = gr;
-                } else {
-                    ((float*)out)[k] = (float)gr;
-                    if (mp >= 0) ((float*)out)[mp] = (float)gr;
-                }
-            }
-        }
-    }
-}
-
-// Both gradients in one pass over the rows: G_ij on the stored entries as in
-// sddmm_grad_kernel (resident form) and row i of Omega Y (for d f / d X) as spmm_kernel
-// forms it.  Every entry j of row i needs Y_j for Omega Y, and the pairs j >= i also
-// need Xt_j, so the rows Y_j are gathered once for both results.  The entries are
-// walked in CSR order: the Omega Y sums take the FMA order of spmm_kernel and the pair
-// sums that of sddmm_grad_kernel, so both outputs equal the separate kernels' bitwise.
+// Masked gradient and Omega Y in one pass over the rows.  With d_ij = <Y_j, Xt_i>
+// (= n (S Omega)_ij) for every stored entry (i, j),
+//   G_ij = (d_ij + d_ji) / (2n) + lam2 w_ij - [i == j] / w_ii,
+// since (Omega S)_ij = <Y_i, Xt_j> / n = d_ji / n.  Wave i gathers each row Y_j of its
+// entries once, for row i of Omega Y (d f / d X^T = Omega Y / n; FMA order of
+// spmm_kernel, so the row equals that kernel's bitwise) and for d_ij against its own row
+// Xt_i (held in LDS).  It writes d_ij to D at the entry and to E at the entry's mirror
+// (j, i), so grad_combine_kernel finds both halves of every entry in place; G_ij and G_ji
+// are then the same FP64 sum and bitwise equal.  Columns are taken in blocks of RC
+// chunks of 64 V; with more than one block the per-block partial sums go to D and E at
+// block offset cb * nnz (summed in block order by the combine).  The wave sums of 8
+// entries share one reduce-scatter (4 + 2 + 1 shuffles, then 3 for the whole wave).
+constexpr int GRAD_GROUP = 8;
 template <int S, int RC>
 __global__ void __launch_bounds__(NT, 4)
-grad_fused_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                  const double* __restrict__ val, int64_t p, const void* __restrict__ Y,
-                  const void* __restrict__ Xt, int64_t ld, int64_t n, double lam2, void* out,
-                  int out_f64, void* __restrict__ oy) {
+grad_rows_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                 const double* __restrict__ val, int64_t p, const void* __restrict__ Y,
+                 const void* __restrict__ Xt, int64_t ld, int64_t n, int64_t nnz,
+                 double* __restrict__ D, double* __restrict__ E, void* __restrict__ oy) {
     typedef Chunk<S> Ch;
     typedef typename Ch::T T;
     constexpr int V = Ch::V;
@@ -1866,38 +1831,16 @@ grad_fused_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict_
     if (row >= p) return;
     const int64_t s = rowptr[row], e = rowptr[row + 1];
     const int nch = (int)((n + 64 * V - 1) / (64 * V));
-    // rows i of Y and Xt sit in LDS (each lane reads back only its own elements): with
-    // them in registers the kernel needed 160 VGPRs (3 waves per SIMD); so it fits 4
-    __shared__ T rows_i[WPB][2][RC][V][64];
-    T acc[RC][V];
-#pragma unroll
-    for (int q = 0; q < RC; ++q) {
-        const int64_t c = (int64_t)q * 64 * V + lane * V;
-        T yv[V], xv[V];
-#pragma unroll
-        for (int t = 0; t < V; ++t) { acc[q][t] = 0; yv[t] = 0; xv[t] = 0; }
-        if (q < nch && c < n) {
-            Ch::load(Y, row * ld + c, yv);
-            Ch::load(Xt, row * ld + c, xv);
-        }
-#pragma unroll
-        for (int t = 0; t < V; ++t) {
-            rows_i[wave][0][q][t][lane] = yv[t];
-            rows_i[wave][1][q][t][lane] = xv[t];
-        }
-    }
-    const double inv2n = 1.0 / (2.0 * (double)n);
-    double v[SDDMM_GROUP];
-#pragma unroll
-    for (int g = 0; g < SDDMM_GROUP; ++g) v[g] = 0.0;
-    int my_t = 0, m = 0;
-    int jl = -1;
-    int64_t mpos = -1, b = s;
-    // the wave sums of up to 8 pairs (entries b + t of the current block) and their writes
+    const int ncb = (nch + RC - 1) / RC;
+    __shared__ T xrow[WPB][RC][V][64];   // this block of columns of Xt_i; each lane reads its own
+    double v[GRAD_GROUP];
+    int my_t = 0, m = 0, jl = -1;
+    int64_t mpos = -1, b = s, boff = 0;
+    // the wave sums of up to GRAD_GROUP entries (b + t of the current 64-entry block)
     auto flush = [&]() {
 #pragma unroll
-        for (int w = SDDMM_GROUP, o = 32; w > 1; w >>= 1, o >>= 1) {
-            const bool upper = (lane & o) != 0;
+        for (int w = GRAD_GROUP, o = 32; w > 1; w >>= 1, o >>= 1) {
+            const bool upper = (lane & o) != 0;   // keep the upper half of the w values
 #pragma unroll
             for (int i = 0; i < w / 2; ++i) {
                 const double send = upper ? v[i] : v[i + w / 2];
@@ -1905,101 +1848,128 @@ grad_fused_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict_
                 v[i] = keep + __shfl_xor(send, o, 64);
             }
         }
+        // v[0]: slot (lane >> 3) & 7 summed over the 8 lanes sharing bits 0..2
         double tot = v[0];
 #pragma unroll
         for (int o = 4; o >= 1; o >>= 1) tot += __shfl_xor(tot, o, 64);
         const int g = (lane >> 3) & 7;
         const int t = __shfl(my_t, g, 64);
         const int64_t mp = __shfl(mpos, t, 64);
-        const int j = __shfl(jl, t, 64);
         if ((lane & 7) == 0 && g < m) {
-            const int64_t k = b + t;
-            const double wv = val[k];
-            double gr = tot * inv2n + lam2 * wv;
-            if (j == row) gr -= 1.0 / wv;
-            if (out_f64) {
-                ((double*)out)[k] = gr;
-                if (mp >= 0) ((double*)out)[mp] = gr;
-            } else {
-                ((float*)out)[k] = (float)gr;
-                if (mp >= 0) ((float*)out)[mp] = (float)gr;
-            }
+            D[boff + b + t] = tot;
+            if (mp >= 0) E[boff + mp] = tot;
         }
 #pragma unroll
-        for (int i = 0; i < SDDMM_GROUP; ++i) v[i] = 0.0;
+        for (int i = 0; i < GRAD_GROUP; ++i) v[i] = 0.0;
         m = 0;
     };
-    for (; b < e; b += 64) {
-        const int cnt = (int)(e - b < 64 ? e - b : 64);
-        jl = -1;
-        mpos = -1;
-        if (lane < cnt) {
-            jl = col[b + lane];
-            if (jl > row) {
-                const int64_t me = rowptr[jl + 1];
-                int64_t lo_ = rowptr[jl], hi_ = me;
-                while (lo_ < hi_) {
-                    const int64_t mid = (lo_ + hi_) >> 1;
-                    if (col[mid] < row) lo_ = mid + 1; else hi_ = mid;
-                }
-                if (lo_ < me && col[lo_] == row) mpos = lo_;
-            }
+#pragma unroll
+    for (int i = 0; i < GRAD_GROUP; ++i) v[i] = 0.0;
+    for (int cb = 0; cb < ncb; ++cb) {
+        boff = (int64_t)cb * nnz;
+        T acc[RC][V];
+#pragma unroll
+        for (int q = 0; q < RC; ++q) {
+            const int64_t c = (int64_t)(cb * RC + q) * 64 * V + lane * V;
+            T xv[V];
+#pragma unroll
+            for (int t = 0; t < V; ++t) { acc[q][t] = 0; xv[t] = 0; }
+            if (c < n) Ch::load(Xt, row * ld + c, xv);
+#pragma unroll
+            for (int t = 0; t < V; ++t) xrow[wave][q][t][lane] = xv[t];
         }
-        const uint64_t own = __ballot(lane < cnt && jl >= row);
-        for (int t = 0; t < cnt; ++t) {
-            const int64_t k = b + t;
-            const int64_t j = (int64_t)col[k];
-            const T wv = (T)val[k];
-            const bool pair = (own >> t) & 1ull;
-            T yj[RC][V], xj[RC][V];
-#pragma unroll
-            for (int q = 0; q < RC; ++q) {
-                const int64_t c = (int64_t)q * 64 * V + lane * V;
-                if (q < nch && c < n) {
-                    Ch::load(Y, j * ld + c, yj[q]);
-                    if (pair) Ch::load(Xt, j * ld + c, xj[q]);
+        for (b = s; b < e; b += 64) {
+            const int cnt = (int)(e - b < 64 ? e - b : 64);
+            // lane t: entry b + t, its column and its mirror's position (-1: not stored)
+            jl = -1;
+            mpos = -1;
+            if (lane < cnt) {
+                jl = col[b + lane];
+                if (jl == row) {
+                    mpos = b + lane;
+                } else {
+                    const int64_t me = rowptr[jl + 1];
+                    int64_t lo_ = rowptr[jl], hi_ = me;
+                    while (lo_ < hi_) {
+                        const int64_t mid = (lo_ + hi_) >> 1;
+                        if (col[mid] < row) lo_ = mid + 1; else hi_ = mid;
+                    }
+                    if (lo_ < me && col[lo_] == row) mpos = lo_;
                 }
             }
-            double a2 = 0.0;
+            for (int t = 0; t < cnt; ++t) {
+                const int64_t k = b + t;
+                const int64_t j = (int64_t)col[k];
+                const T wv = (T)val[k];
+                T yj[RC][V];
 #pragma unroll
-            for (int q = 0; q < RC; ++q) {
-                const int64_t c = (int64_t)q * 64 * V + lane * V;
-                if (q < nch && c < n) {
+                for (int q = 0; q < RC; ++q) {
+                    const int64_t c = (int64_t)(cb * RC + q) * 64 * V + lane * V;
+                    if (c < n) Ch::load(Y, j * ld + c, yj[q]);
+                }
+                double a2 = 0.0;
 #pragma unroll
-                    for (int u = 0; u < V; ++u) acc[q][u] = fma(wv, yj[q][u], acc[q][u]);
-                    if (pair) {
+                for (int q = 0; q < RC; ++q) {
+                    const int64_t c = (int64_t)(cb * RC + q) * 64 * V + lane * V;
+                    if (c < n) {
                         T a = 0;
 #pragma unroll
-                        for (int u = 0; u < V; ++u)
-                            a += rows_i[wave][0][q][u][lane] * xj[q][u] +
-                                 yj[q][u] * rows_i[wave][1][q][u][lane];
+                        for (int u = 0; u < V; ++u) {
+                            acc[q][u] = fma(wv, yj[q][u], acc[q][u]);
+                            a += yj[q][u] * xrow[wave][q][u][lane];
+                        }
                         a2 += (double)a;
                     }
                 }
-            }
-            if (pair) {
 #pragma unroll
-                for (int g = 0; g < SDDMM_GROUP; ++g) v[g] = g == m ? a2 : v[g];
+                for (int g = 0; g < GRAD_GROUP; ++g) v[g] = g == m ? a2 : v[g];
                 if (lane == m) my_t = t;
-                if (++m == SDDMM_GROUP) flush();
+                if (++m == GRAD_GROUP) flush();
+            }
+            if (m > 0) flush();
+        }
+        if (oy) {
+#pragma unroll
+            for (int q = 0; q < RC; ++q) {
+                const int64_t c = (int64_t)(cb * RC + q) * 64 * V + lane * V;
+                if (c < n) {
+                    if (S == ST_F64) {
+                        double* o = (double*)oy + row * ld + c;
+#pragma unroll
+                        for (int u = 0; u < V; ++u) o[u] = (double)acc[q][u];
+                    } else {
+                        float* o = (float*)oy + row * ld + c;
+#pragma unroll
+                        for (int u = 0; u < V; ++u) o[u] = (float)acc[q][u];
+                    }
+                }
             }
         }
-        if (m > 0) flush();
     }
-#pragma unroll
-    for (int q = 0; q < RC; ++q) {
-        const int64_t c = (int64_t)q * 64 * V + lane * V;
-        if (q < nch && c < n) {
-            if (S == ST_F64) {
-                double* o = (double*)oy + row * ld + c;
-#pragma unroll
-                for (int u = 0; u < V; ++u) o[u] = (double)acc[q][u];
-            } else {
-                float* o = (float*)oy + row * ld + c;
-#pragma unroll
-                for (int u = 0; u < V; ++u) o[u] = (float)acc[q][u];
-            }
+}
+
+// G on the stored entries from the two halves grad_rows_kernel left at every entry:
+// G_ij = (sum_cb D + sum_cb E) / (2n) + lam2 w_ij - [i == j] / w_ii (blocks in order).
+__global__ void __launch_bounds__(NT)
+grad_combine_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                    const double* __restrict__ val, int64_t p, int64_t nnz, int ncb,
+                    const double* __restrict__ D, const double* __restrict__ E, double inv2n,
+                    double lam2, void* out, int out_f64) {
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
+    if (row >= p) return;
+    const int64_t s = rowptr[row], e = rowptr[row + 1];
+    for (int64_t k = s + lane; k < e; k += 64) {
+        double dsum = D[k], esum = E[k];
+        for (int cb = 1; cb < ncb; ++cb) {
+            dsum += D[(int64_t)cb * nnz + k];
+            esum += E[(int64_t)cb * nnz + k];
         }
+        const double wv = val[k];
+        double gr = (dsum + esum) * inv2n + lam2 * wv;
+        if (col[k] == row) gr -= 1.0 / wv;
+        if (out_f64) ((double*)out)[k] = gr;
+        else ((float*)out)[k] = (float)gr;
     }
 }
 
@@ -2215,15 +2185,15 @@ int trial_splits(int variant, int bstore, int64_t ncols) {
     return 1;
 }
 
-hipError_t launch_trial(const Cand& A, int64_t p, double tau0, int m, double lam1, int variant,
-                        const void* B, int bstore, int64_t ldb, int64_t ncols, double* part,
-                        const DevState* st, hipStream_t stream) {
+hipError_t launch_trial(const Cand& A, int64_t p, double tau0, double shrink, int m, double lam1,
+                        int variant, const void* B, int bstore, int64_t ldb, int64_t ncols,
+                        double* part, const DevState* st, hipStream_t stream) {
     if (p == 0) return hipSuccess;
     if (m < 1 || m > MAXQ) return hipErrorInvalidValue;
     dim3 grid(blocks_for(p, WPB), trial_splits(variant, bstore, ncols));
 #define TRIAL(BS, OBS)                                                                       \
     hipLaunchKernelGGL((trial_kernel<BS, OBS>), grid, dim3(NT), 0, stream, A.rowptr, A.col,   \
-                       A.omega, A.grad, p, tau0, m, lam1, B, ldb, ncols, part, st)
+                       A.omega, A.grad, p, tau0, shrink, m, lam1, B, ldb, ncols, part, st)
     const bool obs = variant == 1;
     // Cov rows hold a few candidates each.  Below COV_GROUP_MIN_P rows the wave-per-row
     // kernel's p waves fit on the chip at once and the step is latency bound, so packing
@@ -2235,7 +2205,7 @@ hipError_t launch_trial(const Cand& A, int64_t p, double tau0, int m, double lam
         dim3 cg(blocks_for(p, WPB * (64 / TG)));
 #define TRIALC(BS)                                                                           \
         hipLaunchKernelGGL((trial_cov_kernel<BS>), cg, dim3(NT), 0, stream, A.rowptr, A.col, \
-                           A.omega, A.grad, p, tau0, m, lam1, B, ldb, part, st)
+                           A.omega, A.grad, p, tau0, shrink, m, lam1, B, ldb, part, st)
         if (bstore == ST_F64) TRIALC(ST_F64);
         else if (bstore == ST_F32) TRIALC(ST_F32);
         else TRIALC(ST_B16P);
@@ -2251,7 +2221,7 @@ hipError_t launch_trial(const Cand& A, int64_t p, double tau0, int m, double lam
 
 namespace {
 // segments of at most 8192 rows per column, at most COLSUM_MAXSEG of them
-void colsum_shape(int64_t rows, int* nseg, int64_t* seg) {
+__host__ __device__ void colsum_shape(int64_t rows, int* nseg, int64_t* seg) {
     const int64_t seg0 = 8192;
     int ns = (int)((rows + seg0 - 1) / seg0);
     if (ns < 1) ns = 1;
@@ -2263,13 +2233,14 @@ void colsum_shape(int64_t rows, int* nseg, int64_t* seg) {
 }  // namespace
 
 hipError_t launch_colsum_decide(const double* in, int64_t rows, int ncol, double* out,
-                                double* ws, int m, double tau0, int q_base, double lam2,
-                                double inv_n, int forced_q, DevState* st, hipStream_t stream) {
+                                double* ws, int m, double tau0, double shrink, int q_base,
+                                double lam2, double inv_n, int forced_q, DevState* st,
+                                hipStream_t stream) {
     if (ncol <= 0 || ncol > 4 * MAXQ || m < 1 || 4 * m != ncol) return hipErrorInvalidValue;
     int nseg;
     int64_t seg;
     colsum_shape(rows, &nseg, &seg);
-    FinArgs fa{m, q_base, forced_q, 0, tau0, lam2, inv_n, nullptr};
+    FinArgs fa{m, q_base, forced_q, 0, tau0, shrink, lam2, inv_n, nullptr};
     hipLaunchKernelGGL((colsum_finish_kernel<FIN_DECIDE>), dim3(ncol, nseg), dim3(NT), 0, stream,
                        in, rows, seg, ws, out, &st->ticket, fa, st);
     return hipGetLastError();
@@ -2281,7 +2252,7 @@ hipError_t launch_colsum_obj(const double* in, int64_t rows, int ncol, double* o
     int nseg;
     int64_t seg;
     colsum_shape(rows, &nseg, &seg);
-    FinArgs fa{0, 0, -1, nysq, 0.0, 0.0, 0.0, gate};
+    FinArgs fa{0, 0, -1, nysq, 0.0, 0.5, 0.0, 0.0, gate};
     hipLaunchKernelGGL((colsum_finish_kernel<FIN_OBJ>), dim3(ncol, nseg), dim3(NT), 0, stream,
                        in, rows, seg, ws, out, &st->ticket, fa, st);
     return hipGetLastError();
@@ -2348,6 +2319,12 @@ hipError_t launch_cand_grad_cov(const Csr& om, int64_t p, const void* S, int sst
     else if (sstore == ST_B16P) CGRAD(ST_B16P);
     else return hipErrorInvalidValue;
 #undef CGRAD
+    return hipGetLastError();
+}
+
+hipError_t launch_smooth_finish(const DevState* st, int64_t n, double lam2, double* f,
+                                hipStream_t stream) {
+    hipLaunchKernelGGL(smooth_finish_kernel, dim3(1), dim3(64), 0, stream, st, (double)n, lam2, f);
     return hipGetLastError();
 }
 
@@ -2498,44 +2475,33 @@ hipError_t launch_check_finite(const void* A, int is_f64, int64_t rows, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_sddmm_grad(const Csr& om, int64_t p, const void* Y, const void* Xt,
-                             int store, int64_t ld, int64_t n, double lam2, void* out,
-                             int out_f64, hipStream_t stream) {
+// column blocks of the masked-gradient row pass: RC = 4 chunks of 64 V columns each
+int grad_col_blocks(int store, int64_t n) {
+    const int64_t w = 4 * 64 * (store == ST_F64 ? Chunk<ST_F64>::V : Chunk<ST_F32>::V);
+    return (int)((n + w - 1) / w);
+}
+
+hipError_t launch_grad_rows(const Csr& om, int64_t p, int64_t nnz, const void* Y, const void* Xt,
+                            int store, int64_t ld, int64_t n, double* D, double* E, void* oy,
+                            hipStream_t stream) {
     if (p == 0) return hipSuccess;
     dim3 grid(blocks_for(p, WPB));
-    // register cache of 4 column chunks: rows of n <= 1024 (FP32) / 512 (FP64) stay
-    // resident; longer rows are re-read for every pair
-#define SDDMM(SS)                                                                             \
-    do {                                                                                      \
-        if (n <= 4 * 64 * Chunk<SS>::V)                                                       \
-            hipLaunchKernelGGL((sddmm_grad_kernel<SS, 4, true>), grid, dim3(NT), 0, stream,   \
-                               om.rowptr, om.col, om.val, p, Y, Xt, ld, n, lam2, out, out_f64); \
-        else                                                                                  \
-            hipLaunchKernelGGL((sddmm_grad_kernel<SS, 1, false>), grid, dim3(NT), 0, stream,  \
-                               om.rowptr, om.col, om.val, p, Y, Xt, ld, n, lam2, out, out_f64); \
-    } while (0)
-    if (store == ST_F64) SDDMM(ST_F64);
-    else SDDMM(ST_F32);
-#undef SDDMM
+    if (store == ST_F64)
+        hipLaunchKernelGGL((grad_rows_kernel<ST_F64, 4>), grid, dim3(NT), 0, stream, om.rowptr,
+                           om.col, om.val, p, Y, Xt, ld, n, nnz, D, E, oy);
+    else
+        hipLaunchKernelGGL((grad_rows_kernel<ST_F32, 4>), grid, dim3(NT), 0, stream, om.rowptr,
+                           om.col, om.val, p, Y, Xt, ld, n, nnz, D, E, oy);
     return hipGetLastError();
 }
 
-bool grad_fused_fits(int store, int64_t n) {
-    return n <= 4 * 64 * (store == ST_F64 ? Chunk<ST_F64>::V : Chunk<ST_F32>::V);
-}
-
-hipError_t launch_grad_fused(const Csr& om, int64_t p, const void* Y, const void* Xt, int store,
-                             int64_t ld, int64_t n, double lam2, void* out, int out_f64,
-                             void* oy, hipStream_t stream) {
+hipError_t launch_grad_combine(const Csr& om, int64_t p, int64_t nnz, int ncb, const double* D,
+                               const double* E, int64_t n, double lam2, void* out, int out_f64,
+                               hipStream_t stream) {
     if (p == 0) return hipSuccess;
-    if (!grad_fused_fits(store, n)) return hipErrorInvalidValue;
-    dim3 grid(blocks_for(p, WPB));
-    if (store == ST_F64)
-        hipLaunchKernelGGL((grad_fused_kernel<ST_F64, 4>), grid, dim3(NT), 0, stream, om.rowptr,
-                           om.col, om.val, p, Y, Xt, ld, n, lam2, out, out_f64, oy);
-    else
-        hipLaunchKernelGGL((grad_fused_kernel<ST_F32, 4>), grid, dim3(NT), 0, stream, om.rowptr,
-                           om.col, om.val, p, Y, Xt, ld, n, lam2, out, out_f64, oy);
+    hipLaunchKernelGGL(grad_combine_kernel, dim3(blocks_for(p, WPB)), dim3(NT), 0, stream,
+                       om.rowptr, om.col, om.val, p, nnz, ncb, D, E, 1.0 / (2.0 * (double)n),
+                       lam2, out, out_f64);
     return hipGetLastError();
 }
 
@@ -2600,6 +2566,523 @@ hipError_t launch_csr_export(const double* val, int64_t nnz, void* out, int out_
     if (nnz == 0) return hipSuccess;
     hipLaunchKernelGGL(csr_export_kernel, dim3(blocks_for(nnz, NT)), dim3(NT), 0, stream, val, nnz,
                        out, out_f64);
+    return hipGetLastError();
+}
+
+// ================================ batched solves ==================================
+// Phase kernels over many Cov solves at once (see BatchPlan in internal.h).  Each one
+// runs the single solver's kernel body on work items (solve, local block) taken from the
+// iteration's tables by a fixed grid whose blocks loop over the items, so a solve's
+// arithmetic is exactly the single solver's.
+namespace {
+
+constexpr int SCAN_BLOCK = 1024;   // threads of the plan kernels
+
+// active index a with off[a] <= it < off[a + 1]
+__device__ inline int find_item(const int* __restrict__ off, int nact, int it) {
+    int lo = 0, hi = nact;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= it) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// f(solve, local block) for every item of phase ph; a block barrier after each item
+// keeps the block-wide LDS of one item from being overwritten by the next
+template <class F>
+__device__ __forceinline__ void for_items(const BatchPlan& pl, int nsolve, int ph, F&& f) {
+    const int nact = __builtin_amdgcn_readfirstlane(pl.status[2]);
+    const int* off = pl.off + ph * (nsolve + 1);
+    const int total = __builtin_amdgcn_readfirstlane(off[nact]);
+    for (int it = blockIdx.x; it < total; it += gridDim.x) {
+        const int a = __builtin_amdgcn_readfirstlane(find_item(off, nact, it));
+        const int si = __builtin_amdgcn_readfirstlane(pl.act[a]);
+        f(si, (int64_t)(it - off[a]));
+        __syncthreads();
+    }
+}
+
+__device__ inline bool in_accept(const SolveDesc& d, bool init) {
+    return init || d.st->accepted != 0;
+}
+
+// trial step size of the batch starting at q_base: tau0 * shrink^q_base, formed by
+// q_base successive multiplications as the single solver forms it
+__device__ inline double batch_tau(const BatchArgs& a, int q_base) {
+    double t = a.tau0;
+    for (int i = 0; i < q_base; ++i) t *= a.shrink;
+    return t;
+}
+
+// Block-wide exclusive scan of BP_N counters per thread (blockDim.x == SCAN_BLOCK).
+__device__ void block_scan_counts(int (&v)[BP_N], int (&tot)[BP_N]) {
+    __shared__ int ws[SCAN_BLOCK / 64][BP_N];
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int ph = 0; ph < BP_N; ++ph) {
+        int x = v[ph];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int up = __shfl_up(x, o, 64);
+            if (lane >= o) x += up;
+        }
+        if (lane == 63) ws[wave][ph] = x;
+        v[ph] = x - v[ph];   // exclusive within the wave
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ph = 0; ph < BP_N; ++ph) {
+        int before = 0, all = 0;
+        for (int w = 0; w < SCAN_BLOCK / 64; ++w) {
+            before += w < wave ? ws[w][ph] : 0;
+            all += ws[w][ph];
+        }
+        v[ph] += before;
+        tot[ph] = all;
+    }
+    __syncthreads();
+}
+
+// Start of an iteration: the running solves, their work counts per phase and the reset
+// of their search state; one block.
+__global__ void __launch_bounds__(SCAN_BLOCK)
+batch_plan_kernel(const SolveDesc* __restrict__ sd, const InstDesc* __restrict__ idesc,
+                  BatchPlan pl, BatchArgs a, int init) {
+    const int N = a.nsolve;
+    int carry[BP_N];
+#pragma unroll
+    for (int ph = 0; ph < BP_N; ++ph) carry[ph] = 0;
+    int grow = 0;
+    for (int base = 0; base < N; base += SCAN_BLOCK) {
+        const int si = base + threadIdx.x;
+        int cnt[BP_N];
+#pragma unroll
+        for (int ph = 0; ph < BP_N; ++ph) cnt[ph] = 0;
+        int run = 0;
+        if (si < N) {
+            const SolveDesc& d = sd[si];
+            SolveCtl* c = d.ctl;
+            if (c->grow) ++grow;
+            if (c->phase != BPH_DONE && !c->grow) {
+                run = 1;
+                const int64_t p = d.p;
+                const int m = a.tb < a.total - c->q_base ? a.tb : a.total - c->q_base;
+                int nseg;
+                int64_t seg;
+                colsum_shape(p, &nseg, &seg);
+                cnt[BP_ROW] = (int)((p + WPB - 1) / WPB);
+                cnt[BP_ROWG] = (int)((p + WPB * (64 / TG) - 1) / (WPB * (64 / TG)));
+                cnt[BP_SCAN] = (int)((p + SCAN_CHUNK - 1) / SCAN_CHUNK);
+                cnt[BP_COLT] = 4 * m * nseg;
+                cnt[BP_COLO] = 4 * nseg;
+                const int64_t nt = (int64_t)d.T * (d.T + 1) / 2;
+                cnt[BP_SROWS] = d.screen ? d.T : 0;
+                cnt[BP_SPAIRS] = d.screen ? (int)((nt + NT - 1) / NT) : 0;
+                cnt[BP_SOLVE] = 1;
+                if (!init) {
+                    DevState* st = d.st;
+                    st->accepted_q = -1;
+                    st->accepted = 0;
+                    st->nonpos = 0;
+                    if (c->phase == BPH_CAND) st->overflow = 0;
+                }
+            }
+        }
+        // a running solve has one BP_SOLVE item, so that scan is its active index
+        int v[BP_N], tot[BP_N];
+#pragma unroll
+        for (int ph = 0; ph < BP_N; ++ph) v[ph] = cnt[ph];
+        block_scan_counts(v, tot);
+        if (run) {
+            const int ai = carry[BP_SOLVE] + v[BP_SOLVE];
+            pl.act[ai] = si;
+#pragma unroll
+            for (int ph = 0; ph < BP_N; ++ph) pl.off[ph * (N + 1) + ai] = carry[ph] + v[ph];
+        }
+#pragma unroll
+        for (int ph = 0; ph < BP_N; ++ph) carry[ph] += tot[ph];
+    }
+    // every running solve has exactly one item of BP_SOLVE: carry[BP_SOLVE] = nact
+    if (threadIdx.x == 0) {
+        const int nact = carry[BP_SOLVE];
+#pragma unroll
+        for (int ph = 0; ph < BP_N; ++ph) pl.off[ph * (N + 1) + nact] = carry[ph];
+        pl.status[2] = nact;
+        pl.status[0] = 0;
+    }
+    // solves waiting for more candidate capacity (counted once: sums over threads)
+    __shared__ int gsum;
+    if (threadIdx.x == 0) gsum = 0;
+    __syncthreads();
+    if (grow) atomicAdd(&gsum, grow);
+    __syncthreads();
+    if (threadIdx.x == 0) pl.status[1] = gsum;
+    for (int i = threadIdx.x; i < a.ninst; i += SCAN_BLOCK) *idesc[i].ucount = 0;
+}
+
+// Omega = I for every solve (the start of Algorithm 1)
+__global__ void __launch_bounds__(NT)
+batch_identity_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, int nsolve) {
+    for_items(pl, nsolve, BP_ROW, [&](int si, int64_t lb) {
+        const SolveDesc& d = sd[si];
+        const Csr& o = d.om[d.ctl->cur];
+        const int64_t i = lb * WPB + (threadIdx.x >> 6);
+        if (i < d.p && lane_id() == 0) {
+            o.rowptr[i] = i;
+            o.col[i] = (int32_t)i;
+            o.val[i] = 1.0;
+            if (i == d.p - 1) o.rowptr[d.p] = d.p;
+        }
+    });
+}
+
+// ---- candidates: merge of the threshold words, scan, fill, gradient ----
+__global__ void __launch_bounds__(NT)
+batch_merge_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, int nsolve) {
+    for_items(pl, nsolve, BP_ROW, [&](int si, int64_t lb) {
+        const SolveDesc& d = sd[si];
+        if (d.ctl->phase != BPH_CAND) return;
+        const Csr& o = d.om[d.ctl->cur];
+        cand_merge_body(lb, o.rowptr, o.col, d.p, d.bitmap, d.nwords, d.cnt,
+                        d.screen ? d.rws.tmask : nullptr);
+    });
+}
+
+// scan of cnt into A.rowptr (cands) or into the next iterate's rowptr (emission)
+template <bool EMIT>
+__global__ void __launch_bounds__(NT)
+batch_scan_part_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, int nsolve, int init) {
+    for_items(pl, nsolve, BP_SCAN, [&](int si, int64_t lb) {
+        const SolveDesc& d = sd[si];
+        if (EMIT ? !in_accept(d, init) : d.ctl->phase != BPH_CAND) return;
+        scan_part_body(lb, d.cnt, d.p, d.scanws);
+    });
+}
+
+template <bool EMIT>
+__global__ void __launch_bounds__(NT)
+batch_scan_apply_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, int nsolve, int init) {
+    for_items(pl, nsolve, BP_SCAN, [&](int si, int64_t lb) {
+        const SolveDesc& d = sd[si];
+        if (EMIT ? !in_accept(d, init) : d.ctl->phase != BPH_CAND) return;
+        const int64_t nb = (d.p + SCAN_CHUNK - 1) / SCAN_CHUNK;
+        if (EMIT)
+            scan_apply_body(lb, nb, d.cnt, d.p, d.scanws, d.om[d.ctl->cur ^ 1].rowptr, d.a_cap,
+                            nullptr, &d.st->nnz_next);
+        else
+            scan_apply_body(lb, nb, d.cnt, d.p, d.scanws, d.A.rowptr, d.a_cap, &d.st->overflow,
+                            &d.st->n_cand);
+    });
+}
+
+__global__ void __launch_bounds__(NT)
+batch_fill_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, int nsolve) {
+    for_items(pl, nsolve, BP_ROW, [&](int si, int64_t lb) {
+        const SolveDesc& d = sd[si];
+        if (d.ctl->phase != BPH_CAND) return;
+        const Csr& o = d.om[d.ctl->cur];
+        cand_fill_body<ST_F32>(lb, nullptr, 0, o.rowptr, o.col, o.val, d.p, 0.0, d.bitmap,
+                               d.nwords, d.A.rowptr, d.A.col, d.A.omega, d.A.grad,
+                               &d.st->overflow, d.screen ? d.rws.tmask : nullptr);
+    });
+}
+
+template <int BS>
+__global__ void __launch_bounds__(NT)
+batch_grad_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, BatchArgs a) {
+    for_items(pl, a.nsolve, BP_ROW, [&](int si, int64_t lb) {
+        const SolveDesc& d = sd[si];
+        if (d.ctl->phase != BPH_CAND) return;
+        const Csr& o = d.om[d.ctl->cur];
+        cand_grad_cov_body<BS>(lb, o.rowptr, o.col, o.val, d.p, d.S, d.lds, a.lam2, d.A.rowptr,
+                               d.A.col, d.A.omega, d.A.grad, &d.st->overflow);
+    });
+}
+
+// ---- trials and the decision ----
+template <int BS>
+__global__ void __launch_bounds__(NT)
+batch_trial_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, BatchArgs a) {
+    for_items(pl, a.nsolve, BP_ROW, [&](int si, int64_t lb) {
+        const SolveDesc& d = sd[si];
+        if (d.grouped) return;
+        const int q = d.ctl->q_base;
+        const int m = a.tb < a.total - q ? a.tb : a.total - q;
+        trial_body<BS, false>(lb, 0, 1, d.A.rowptr, d.A.col, d.A.omega, d.A.grad, d.p,
+                              batch_tau(a, q), a.shrink, m, d.lam1, d.S, d.lds, 0, d.part, d.st);
+    });
+}
+
+template <int BS>
+__global__ void __launch_bounds__(NT)
+batch_trial_grouped_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, BatchArgs a) {
+    for_items(pl, a.nsolve, BP_ROWG, [&](int si, int64_t lb) {
+        const SolveDesc& d = sd[si];
+        if (!d.grouped) return;
+        const int q = d.ctl->q_base;
+        const int m = a.tb < a.total - q ? a.tb : a.total - q;
+        trial_cov_body<BS>(lb, d.A.rowptr, d.A.col, d.A.omega, d.A.grad, d.p, batch_tau(a, q),
+                           a.shrink, m, d.lam1, d.S, d.lds, d.part, d.st);
+    });
+}
+
+__global__ void __launch_bounds__(NT)
+batch_decide_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, BatchArgs a) {
+    for_items(pl, a.nsolve, BP_COLT, [&](int si, int64_t lb) {
+        const SolveDesc& d = sd[si];
+        const int q = d.ctl->q_base;
+        const int m = a.tb < a.total - q ? a.tb : a.total - q;
+        int nseg;
+        int64_t seg;
+        colsum_shape(d.p, &nseg, &seg);
+        FinArgs fa{m, q, -1, 0, batch_tau(a, q), a.shrink, a.lam2, 1.0, nullptr};
+        colsum_finish_body<FIN_DECIDE>((int)(lb % (4 * m)), (int)(lb / (4 * m)), 4 * m, nseg,
+                                       d.part, d.p, seg, d.colws, d.tsums, &d.st->ticket, fa,
+                                       d.st);
+    });
+}
+
+// ---- emission of the accepted iterates ----
+__global__ void __launch_bounds__(NT)
+batch_emit_count_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, int nsolve) {
+    for_items(pl, nsolve, BP_ROW, [&](int si, int64_t lb) {
+        const SolveDesc& d = sd[si];
+        emit_count_body(lb, d.A.rowptr, d.A.col, d.A.omega, d.A.grad, d.p, d.lam1, d.st, d.cnt);
+    });
+}
+
+__global__ void __launch_bounds__(NT)
+batch_emit_fill_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, int nsolve) {
+    for_items(pl, nsolve, BP_ROW, [&](int si, int64_t lb) {
+        const SolveDesc& d = sd[si];
+        const Csr& o = d.om[d.ctl->cur ^ 1];
+        emit_fill_body(lb, d.A.rowptr, d.A.col, d.A.omega, d.A.grad, d.p, d.lam1, d.st, o.rowptr,
+                       o.col, o.val);
+    });
+}
+
+// ---- products at the accepted iterates (or at the start, init) ----
+__device__ inline const Csr& prod_csr(const SolveDesc& d, bool init) {
+    return d.om[init ? d.ctl->cur : d.ctl->cur ^ 1];
+}
+
+__global__ void __launch_bounds__(64)
+batch_screen_rows_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, int nsolve, int init) {
+    for_items(pl, nsolve, BP_SROWS, [&](int si, int64_t lb) {
+        const SolveDesc& d = sd[si];
+        if (!in_accept(d, init)) return;
+        const Csr& o = prod_csr(d, init);
+        screen_rows_body((int)lb, o.rowptr, o.col, o.val, d.p, d.T, d.rws.lcnt, d.rws.lK,
+                         d.rws.lW, d.rws.lcmax, d.rws.pcount, d.rws.tmask, nullptr);
+    });
+}
+
+template <typename E>
+__global__ void __launch_bounds__(NT)
+batch_screen_pairs_kernel(const SolveDesc* __restrict__ sd, const InstDesc* __restrict__ idesc,
+                          BatchPlan pl, int nsolve, int init) {
+    for_items(pl, nsolve, BP_SPAIRS, [&](int si, int64_t lb) {
+        const SolveDesc& d = sd[si];
+        if (!in_accept(d, init)) return;
+        const InstDesc& id = idesc[d.inst];
+        screen_pairs_body<E>((int)lb, d.T, d.rws.lcnt, d.rws.lK, d.rws.lW, d.rws.lcmax, d.smax,
+                             d.lam1, d.rws.plist, d.rws.pcount, d.rws.tmask, nullptr, id.ulist,
+                             id.ucount, id.ubits);
+    });
+}
+
+// per instance: how many tile pairs its refresh walks (its list, or every pair when the
+// instance is not screened and one of its solves refreshes)
+__global__ void __launch_bounds__(SCAN_BLOCK)
+batch_refresh_plan_kernel(const SolveDesc* __restrict__ sd, const InstDesc* __restrict__ idesc,
+                          BatchPlan pl, int ninst, int init) {
+    int carry = 0;
+    for (int base = 0; base < ninst; base += SCAN_BLOCK) {
+        const int i = base + threadIdx.x;
+        int v[BP_N], tot[BP_N];
+#pragma unroll
+        for (int ph = 0; ph < BP_N; ++ph) v[ph] = 0;
+        if (i < ninst) {
+            const InstDesc& id = idesc[i];
+            if (id.screen) {
+                v[0] = *id.ucount;
+            } else {
+                bool any = false;
+                for (int l = 0; l < id.nsolve; ++l) {
+                    const SolveDesc& d = sd[id.first + l];
+                    any = any || (d.ctl->phase != BPH_DONE && !d.ctl->grow && in_accept(d, init));
+                }
+                v[0] = any ? id.T * (id.T + 1) / 2 : 0;
+            }
+        }
+        block_scan_counts(v, tot);
+        if (i < ninst) pl.roff[i] = carry + v[0];
+        carry += tot[0];
+    }
+    if (threadIdx.x == 0) pl.roff[ninst] = carry;
+}
+
+// The refresh of Algorithm 2's product at the accepted iterates, lambda-stacked: one work
+// item per (instance, listed tile pair) refreshes the pair for every solve of the
+// instance that kept it, one after the other in the same workgroup, so the S tiles the
+// pair reads are fetched once and served from the cache for the other lambda1 values.
+template <int BS>
+__global__ void __launch_bounds__(NT)
+batch_refresh_kernel(const SolveDesc* __restrict__ sd, const InstDesc* __restrict__ idesc,
+                     BatchPlan pl, int ninst, int init) {
+    const int total = __builtin_amdgcn_readfirstlane(pl.roff[ninst]);
+    for (int it = blockIdx.x; it < total; it += gridDim.x) {
+        const int i = __builtin_amdgcn_readfirstlane(find_item(pl.roff, ninst, it));
+        const InstDesc& id = idesc[i];
+        const int t0 = it - pl.roff[i];
+        const int T = id.T, nt = T * (T + 1) / 2;
+        const int t = __builtin_amdgcn_readfirstlane(id.screen ? id.ulist[t0] : t0);
+        if (id.screen && threadIdx.x == 0) atomicAnd(&id.ubits[t >> 5], ~(1u << (t & 31)));
+        const int2 ij = refresh_tile(t, T, nt);
+        const int I = __builtin_amdgcn_readfirstlane(ij.x), J = __builtin_amdgcn_readfirstlane(ij.y);
+        const int TW = (T + 63) / 64;
+        for (int l = 0; l < id.nsolve; ++l) {
+            const SolveDesc& d = sd[id.first + l];
+            const SolveCtl* c = d.ctl;
+            if (c->phase == BPH_DONE || c->grow || !in_accept(d, init)) continue;
+            if (id.screen && !((d.rws.tmask[(int64_t)I * TW + (J >> 6)] >> (J & 63)) & 1ull)) continue;
+            const Csr& o = prod_csr(d, init);
+            refresh_pair<BS>(I, J, o.rowptr, o.col, o.val, d.p, d.S, d.lds,
+                             id.screen ? d.smax : nullptr, T, d.lam1, d.bitmap, d.nwords, nullptr);
+            __syncthreads();   // the pair's LDS is reused by the next solve
+        }
+    }
+}
+
+template <int BS>
+__global__ void __launch_bounds__(NT)
+batch_obj_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, int nsolve, int init) {
+    for_items(pl, nsolve, BP_ROW, [&](int si, int64_t lb) {
+        const SolveDesc& d = sd[si];
+        if (!in_accept(d, init)) return;
+        const Csr& o = prod_csr(d, init);
+        obj_parts_cov_body<BS>(lb, o.rowptr, o.col, o.val, d.p, d.S, d.lds,
+                               d.part + 4 * MAXQ * d.p, nullptr);
+    });
+}
+
+__global__ void __launch_bounds__(NT)
+batch_obj_sum_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, int nsolve, int init) {
+    for_items(pl, nsolve, BP_COLO, [&](int si, int64_t lb) {
+        const SolveDesc& d = sd[si];
+        if (!in_accept(d, init)) return;
+        int nseg;
+        int64_t seg;
+        colsum_shape(d.p, &nseg, &seg);
+        FinArgs fa{0, 0, -1, 0, 0.0, 0.5, 0.0, 0.0, nullptr};
+        colsum_finish_body<FIN_OBJ>((int)(lb % 4), (int)(lb / 4), 4, nseg,
+                                    d.part + 4 * MAXQ * d.p, d.p, seg, d.colws, d.osums,
+                                    &d.st->ticket, fa, d.st);
+    });
+}
+
+// End of an iteration: accept (the iterate is the emitted one), the stopping test of
+// concord_solve, or the next trial batch; counts the solves still running.
+__global__ void __launch_bounds__(NT)
+batch_finish_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, BatchArgs a, int init) {
+    for_items(pl, a.nsolve, BP_SOLVE, [&](int si, int64_t) {
+        if (threadIdx.x != 0) return;
+        const SolveDesc& d = sd[si];
+        SolveCtl* c = d.ctl;
+        DevState* st = d.st;
+        double f, F;
+        if (init) {
+            objective_value(st->obj, false, 1.0, d.lam1, a.lam2, &f, &F);
+            c->F = F;
+            atomicAdd(&pl.status[0], 1);
+            return;
+        }
+        if (st->overflow) {   // the host grows the candidate arrays, then the step restarts
+            c->grow = 1;
+            c->phase = BPH_CAND;
+            atomicAdd(&pl.status[1], 1);
+            return;
+        }
+        const int m = a.tb < a.total - c->q_base ? a.tb : a.total - c->q_base;
+        if (st->accepted_q < 0) {   // every step size of the batch failed the test
+            c->q_base += m;
+            if (c->q_base >= a.total) {
+                c->status = CONCORD_ELINESEARCH;
+                c->phase = BPH_DONE;
+            } else {
+                c->phase = BPH_TRIAL;
+                atomicAdd(&pl.status[0], 1);
+            }
+            return;
+        }
+        c->cur ^= 1;
+        c->k += 1;
+        c->q_base = 0;
+        objective_value(st->obj, false, 1.0, d.lam1, a.lam2, &f, &F);
+        const double F_old = c->F;
+        c->F = F;
+        if (a.tol > 0.0 && fabs(F - F_old) < a.tol * fabs(F_old)) {
+            c->status = CONCORD_OK;
+            c->phase = BPH_DONE;
+        } else if (c->k >= a.max_iter) {
+            c->status = a.tol > 0.0 ? CONCORD_WMAXITER : CONCORD_OK;
+            c->phase = BPH_DONE;
+        } else {
+            c->phase = BPH_CAND;
+            atomicAdd(&pl.status[0], 1);
+        }
+    });
+}
+
+}  // namespace
+
+hipError_t launch_batch_iteration(const SolveDesc* sd, const InstDesc* idesc, const BatchPlan& pl,
+                                  const BatchArgs& a, bool init, int grid, hipStream_t stream) {
+    const int N = a.nsolve, ini = init ? 1 : 0;
+    const dim3 g(grid), b(NT);
+    hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(SCAN_BLOCK), 0, stream, sd, idesc, pl, a, ini);
+    if (init) {
+        hipLaunchKernelGGL(batch_identity_kernel, g, b, 0, stream, sd, pl, N);
+    } else {
+        hipLaunchKernelGGL(batch_merge_kernel, g, b, 0, stream, sd, pl, N);
+        hipLaunchKernelGGL(batch_scan_part_kernel<false>, g, b, 0, stream, sd, pl, N, 0);
+        hipLaunchKernelGGL(batch_scan_apply_kernel<false>, g, b, 0, stream, sd, pl, N, 0);
+        hipLaunchKernelGGL(batch_fill_kernel, g, b, (size_t)WPB * ((a.maxT + 63) / 64) * 8, stream,
+                           sd, pl, N);
+        if (a.bstore == ST_F64) {
+            hipLaunchKernelGGL(batch_grad_kernel<ST_F64>, g, b, 0, stream, sd, pl, a);
+            hipLaunchKernelGGL(batch_trial_kernel<ST_F64>, g, b, 0, stream, sd, pl, a);
+            hipLaunchKernelGGL(batch_trial_grouped_kernel<ST_F64>, g, b, 0, stream, sd, pl, a);
+        } else {
+            hipLaunchKernelGGL(batch_grad_kernel<ST_F32>, g, b, 0, stream, sd, pl, a);
+            hipLaunchKernelGGL(batch_trial_kernel<ST_F32>, g, b, 0, stream, sd, pl, a);
+            hipLaunchKernelGGL(batch_trial_grouped_kernel<ST_F32>, g, b, 0, stream, sd, pl, a);
+        }
+        hipLaunchKernelGGL(batch_decide_kernel, g, b, 0, stream, sd, pl, a);
+        hipLaunchKernelGGL(batch_emit_count_kernel, g, b, 0, stream, sd, pl, N);
+        hipLaunchKernelGGL(batch_scan_part_kernel<true>, g, b, 0, stream, sd, pl, N, 0);
+        hipLaunchKernelGGL(batch_scan_apply_kernel<true>, g, b, 0, stream, sd, pl, N, 0);
+        hipLaunchKernelGGL(batch_emit_fill_kernel, g, b, 0, stream, sd, pl, N);
+    }
+    hipLaunchKernelGGL(batch_screen_rows_kernel, dim3(grid * WPB), dim3(64), (size_t)8 * a.maxT,
+                       stream, sd, pl, N, ini);
+    if (a.bstore == ST_F64) {
+        hipLaunchKernelGGL(batch_screen_pairs_kernel<double>, g, b, 0, stream, sd, idesc, pl, N, ini);
+    } else {
+        hipLaunchKernelGGL(batch_screen_pairs_kernel<float>, g, b, 0, stream, sd, idesc, pl, N, ini);
+    }
+    hipLaunchKernelGGL(batch_refresh_plan_kernel, dim3(1), dim3(SCAN_BLOCK), 0, stream, sd, idesc,
+                       pl, a.ninst, ini);
+    if (a.bstore == ST_F64) {
+        hipLaunchKernelGGL(batch_refresh_kernel<ST_F64>, g, b, 0, stream, sd, idesc, pl, a.ninst, ini);
+        hipLaunchKernelGGL(batch_obj_kernel<ST_F64>, g, b, 0, stream, sd, pl, N, ini);
+    } else {
+        hipLaunchKernelGGL(batch_refresh_kernel<ST_F32>, g, b, 0, stream, sd, idesc, pl, a.ninst, ini);
+        hipLaunchKernelGGL(batch_obj_kernel<ST_F32>, g, b, 0, stream, sd, pl, N, ini);
+    }
+    hipLaunchKernelGGL(batch_obj_sum_kernel, g, b, 0, stream, sd, pl, N, ini);
+    hipLaunchKernelGGL(batch_finish_kernel, g, b, 0, stream, sd, pl, a, ini);
     return hipGetLastError();
 }
 

@@ -83,6 +83,53 @@ def lambda1_for_degree(solver, target_degree: float, lam2: float, lo: float = 0.
     return best
 
 
+def multisection_round(lo: float, hi: float, k: int):
+    """The k probes of one round: evenly spaced strictly inside (lo, hi)."""
+    return [lo + (hi - lo) * (j + 1) / (k + 1) for j in range(k)]
+
+
+def next_bracket(lo: float, hi: float, lams, degrees, target: float):
+    """The degree falls as lambda1 grows: the new bracket runs from the last probe whose
+    degree is above the target to the first one at or below it (or the old ends)."""
+    i = next((j for j, d in enumerate(degrees) if d <= target), len(degrees))
+    return (lams[i - 1] if i > 0 else lo), (lams[i] if i < len(lams) else hi)
+
+
+def lambda1_for_degree_batched(X, target_degree: float, lam2: float, lo: float = 0.0,
+                               hi: float = 1.0, probes: int = 8, rounds: int = 6,
+                               rel_tol: float = 0.02, tol: float = 1e-5, max_iter: int = 200,
+                               precision: str = "fp32") -> SearchResult:
+    """Multisection on lambda1 through the batched path: every round solves ``probes``
+    lambda1 values of the bracket at once (one batch of one instance, each from
+    Omega = I), keeps the sub-bracket where the degree crosses the target, and stops
+    once a probe's average degree is within ``rel_tol`` of the target or after
+    ``rounds`` rounds.  X: (n, p) CUDA tensor (float32, or float64 for FP64)."""
+    from ._lib import Batch
+    p = X.shape[1]
+    history = []
+    best: Optional[SearchResult] = None
+    a, b = lo, hi
+    for _ in range(rounds):
+        lams = multisection_round(a, b, probes)
+        bt = Batch([X], lams, precision=precision)
+        iters, _, _ = bt.solve(lam2, tol, max_iter)
+        degs = []
+        for j, lam1 in enumerate(lams):
+            r, c, v = bt.get_omega(0, j)
+            om = sp.csr_matrix((v.cpu().numpy(), c.cpu().numpy(), r.cpu().numpy()), shape=(p, p))
+            deg = average_degree(om)
+            degs.append(deg)
+            history.append((lam1, deg, iters[j]))
+            if best is None or abs(deg - target_degree) < abs(best.degree - target_degree):
+                best = SearchResult(lam1, deg, iters[j], om, history)
+        bt.close()
+        if abs(best.degree - target_degree) <= rel_tol * max(target_degree, 1e-12):
+            break
+        a, b = next_bracket(a, b, lams, degs, target_degree)
+    best.history = history
+    return best
+
+
 def scale_for_lambda_grid(max_offdiag_s: float, lam1_top: float, lam2: float) -> float:
     """Factor c for data whose sample covariance S has unit diagonal, such that the
     estimate from c^2 S turns diagonal exactly at lambda1 = lam1_top for this lambda2.

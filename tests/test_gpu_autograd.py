@@ -71,8 +71,8 @@ def test_forward_backward_vs_oracle_p500(precision):
                                               ("fp32", 300, 90)])
 def test_backward_long_rows_vs_oracle(precision, n, deg):
     """Rows with more than 64 stored entries (the pair walk takes them 64 at a time)
-    and, for n past the register-resident width (FP64 n > 512, FP32 n > 1024), the
-    path that re-reads row i for every pair."""
+    and, for n past one column block of the row pass (FP64 n > 512, FP32 n > 1024),
+    the per-block partial sums."""
     torch = _torch()
     from paper_1710_10769_amd import Solver
     from paper_1710_10769_amd.autograd import concord_smooth
@@ -103,8 +103,9 @@ def test_backward_long_rows_vs_oracle(precision, n, deg):
 
 @pytest.mark.parametrize("precision,n,deg", [("fp32", 1000, 20), ("fp64", 400, 90)])
 def test_both_gradients_in_one_pass_equal_separate_passes(precision, n, deg):
-    """Asking for both gradients takes the one-pass kernel (each row Y_j gathered once
-    for both); its outputs equal those of the two separate passes bitwise."""
+    """Asking for both gradients takes the one row pass (each row Y_j gathered once for
+    both); its outputs equal those of asking for one at a time bitwise (d f / d X alone
+    is the plain SpMM Omega Y, whose FMA order the row pass keeps)."""
     torch = _torch()
     from paper_1710_10769_amd import Solver
     p, lam2 = 333, 0.1
@@ -119,6 +120,37 @@ def test_both_gradients_in_one_pass_equal_separate_passes(precision, n, deg):
     g_only, _ = s.gradient(lam2, want_omega=True, want_x=False, dtype=dt)
     _, x_only = s.gradient(lam2, want_omega=False, want_x=True, dtype=dt)
     assert torch.equal(g_both, g_only) and torch.equal(x_both, x_only)
+    s.close()
+
+
+def test_forward_stores_no_y_and_backward_returns_its_buffers():
+    """The forward reduces ||Omega X^T||^2 without forming Y in memory; the backward
+    recomputes Y in buffers of its own call and returns them (allocator bridge counts)."""
+    torch = _torch()
+    from paper_1710_10769_amd import Solver, TorchAllocator
+    from paper_1710_10769_amd.autograd import concord_smooth
+    p, n, lam2 = 400, 300, 0.1
+    _say(f"autograd buffers fp32 p={p} n={n} seed=59")
+    _, om, X = _case(p, n, 59, deg=10)
+    alloc = TorchAllocator(torch.cuda.current_device())
+    s = Solver(p, n, variant="obs", precision="fp32", allocator=alloc)
+    rp, cl, v = _csr_tensors(torch, om, torch.float32)
+    v.requires_grad_(True)
+    x = torch.from_numpy(X).to("cuda", torch.float32).requires_grad_(True)
+    f = concord_smooth(v, x, rp, cl, lam2, s)
+    live_after_forward = dict(alloc.live)
+    dense = (-(-p // 256) * 256) * (-(-n // 64) * 64) * 4   # rows padded to 256, K to 64
+    # the handle holds X^T in its dense layout and no second such buffer for Y
+    assert sum(1 for b in live_after_forward.values() if b == dense) == 1
+    n_before = alloc.n_alloc
+    f.backward()
+    assert alloc.n_alloc > n_before                 # Y, Omega Y and the halves, this call only
+    assert alloc.live == live_after_forward         # all of them returned
+    f_ref, G_ref, dX_ref = oc.smooth_value_and_grads(om, X.astype(np.float32).astype(np.float64),
+                                                     lam2)
+    assert abs(f.item() - f_ref) <= 2e-5 * abs(f_ref)
+    dx = x.grad.double().cpu().numpy()
+    assert np.abs(dx - dX_ref).max() <= 1e-4 * np.abs(dX_ref).max()
     s.close()
 
 

@@ -6,7 +6,7 @@ import pytest
 
 import datagen
 from oracle import concord as oc
-from tests.gpu_common import max_abs_diff, support_mismatch
+from tests.gpu_common import check_support, max_abs_diff, oracle_grad_fn
 
 pytestmark = pytest.mark.gpu
 
@@ -33,6 +33,7 @@ def test_c3_two_iterations(c3, precision):
     print(f"[case] c3 {precision} replay {[r.trials for r in ref.log]}", flush=True)
     s = Solver(w.p, w.n, variant="cov", precision=precision)
     s.set_data(torch.from_numpy(X).to("cuda", torch.float64 if precision == "fp64" else torch.float32))
+    prev = s.get_omega_scipy()
     for it, rec in enumerate(ref.log):
         info = s.step_replay(w.lam1, w.lam2, rec.trials)
         got = s.get_omega_scipy()
@@ -41,8 +42,10 @@ def test_c3_two_iterations(c3, precision):
         scale = np.abs(want.data).max()
         tol = 1e-6 if precision == "fp64" else 1e-4 * scale
         assert err <= tol, (it, err, tol)
-        mism = support_mismatch(got, want)
-        assert len(mism) <= (0 if precision == "fp64" else max(10, want.nnz // 10000)), (it, len(mism))
+        check_support(f"c3 it={it}", precision, w.lam1, rec.tau, got, want, prev,
+                      ref.iterates[it], s.get_candidates_scipy(),
+                      oracle_grad_fn(ref.iterates[it], X, w.lam2))
+        prev = got
         assert abs(info.F - rec.F) <= (1e-9 if precision == "fp64" else 1e-5) * abs(rec.F)
         assert info.nnz > w.p
     s.close()

@@ -8,7 +8,7 @@ import pytest
 
 import datagen
 from oracle import concord as oc
-from tests.gpu_common import max_abs_diff, support_mismatch
+from tests.gpu_common import check_support, max_abs_diff, oracle_grad_fn
 
 pytestmark = pytest.mark.gpu
 
@@ -30,11 +30,15 @@ def test_fmri_shaped_cov_replay(lam1):
     assert max(r.nnz for r in ref.log) > p, "case must grow the support"
     s = Solver(p, n, variant="cov", precision="fp32")
     s.set_data(torch.from_numpy(X.astype(np.float32)).cuda())
+    prev = s.get_omega_scipy()
     for it, rec in enumerate(ref.log):
         info = s.step_replay(lam1, lam2, rec.trials)
         got, want = s.get_omega_scipy(), ref.iterates[it + 1]
         err = max_abs_diff(got, want)
         assert err <= 1e-4 * np.abs(want.data).max(), (it, err)
-        assert len(support_mismatch(got, want)) <= 2, it   # only threshold-band entries
+        check_support(f"fmri lam1={lam1} it={it}", "fp32", lam1, rec.tau, got, want, prev,
+                      ref.iterates[it], s.get_candidates_scipy(),
+                      oracle_grad_fn(ref.iterates[it], X, lam2))
+        prev = got
         assert abs(info.F - rec.F) <= 1e-5 * abs(rec.F)
     s.close()
