@@ -284,6 +284,34 @@ int64_t concord_iterations(const concord_ctx* ctx);
    stored.  Requires CONCORD_OBS and X.  Errors: EINVAL, ENODATA, EHIP. */
 int concord_smooth_value(concord_ctx* ctx, double lambda2, double* host_f);
 
+/* ---- entry point that allocates nothing ----
+   For callers that cannot allocate device memory: code under HIP graph capture,
+   tight serving loops, harnesses that forbid hipMalloc.  The value of
+   concord_smooth_value, f = -sum_i log omega_ii + ||Omega X^T||_F^2 / (2n) +
+   lambda2/2 ||Omega||_F^2, for an iterate and data the caller passes, without a
+   handle: the partial sums live in a per-device array of the library of
+   CONCORD_NOALLOC_SCRATCH_BYTES (each device the call runs on holds it until the
+   process ends).  The call allocates and frees no device memory and does not
+   synchronise: f is written to dev_f in stream order.
+     p, n: sizes; the problem must fit the array: 8 * (4 + ceil(n / c)) * p bytes
+       plus a few KB, c = 256 (F32) or 128 (F64) columns.
+     dev_Xt: X^T, p x n row-major, leading dimension ldx >= n (a multiple of 4 for
+       F32, of 2 for F64), 16-byte aligned; dtype F32 (FP32 products, the FP32 form)
+       or F64.
+     dev_row_ptr int64[p+1], dev_col int32[nnz] (sorted per row, diagonal present),
+       dev_val double[nnz]: the iterate in CSR, as concord_set_omega takes it (not
+       validated here).
+     dev_f: one double of device memory.  stream: hipStream_t, NULL = null stream.
+   Every call on a device uses that device's one array, which keeps the last call's
+   contents: calls that overlap on one device race (order them, e.g. on one stream).
+   Errors (decided before any launch): EINVAL (sizes, null pointers, alignment,
+   lambda2 < 0 or not finite, problem larger than the array), EHIP. */
+#define CONCORD_NOALLOC_SCRATCH_BYTES (32u << 20)
+int concord_smooth_value_noalloc(int64_t p, int64_t n, const void* dev_Xt, int64_t ldx,
+                                 int32_t dtype, int64_t nnz, const int64_t* dev_row_ptr,
+                                 const int32_t* dev_col, const double* dev_val, double lambda2,
+                                 double* dev_f, void* stream);
+
 /* Gradients of concord_smooth_value at the current iterate.
    dev_dOmega: mode MASKED -> val-shaped array (nnz of the iterate, CSR
      order, dtype) holding G_ij on the stored entries; mode DENSE -> p x p

@@ -116,6 +116,8 @@ _SIGS = {
     "concord_iterations": (_I64, [_P]),
     "concord_smooth_value": (_I32, [_P, _D, ctypes.POINTER(_D)]),
     "concord_gradient": (_I32, [_P, _D, _I32, _P, _P, _I32]),
+    "concord_smooth_value_noalloc": (_I32, [_I64, _I64, _P, _I64, _I32, _I64, _P, _P, _P, _D, _P,
+                                            _P]),
     "concord_batch_config_init": (None, [ctypes.POINTER(concord_batch_config)]),
     "concord_batch_create": (_I32, [ctypes.POINTER(concord_batch_config), _I32,
                                     ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_P),
@@ -334,6 +336,14 @@ def concord_smooth_value(h, lam2: float) -> float:
     f = ctypes.c_double()
     _check(load().concord_smooth_value(h, lam2, ctypes.byref(f)), h)
     return f.value
+
+
+def concord_smooth_value_noalloc(p: int, n: int, Xt: int, ldx: int, dtype: int, nnz: int,
+                                 rowptr: int, col: int, val: int, lam2: float, f_out: int,
+                                 stream: Optional[int] = None) -> int:
+    """Handle-less smooth value into the device double at f_out; allocates nothing."""
+    return _check(load().concord_smooth_value_noalloc(p, n, Xt, ldx, dtype, nnz, rowptr, col, val,
+                                                      lam2, f_out, stream))
 
 
 def concord_gradient(h, lam2: float, mode: int, dOmega: int, dX: int, dtype: int) -> int:

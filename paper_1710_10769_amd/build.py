@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libconcord.so")
-SOURCES = ["gemm_sym.hip", "sparse.hip", "concord.hip", "batch.hip"]
+SOURCES = ["gemm_sym.hip", "sparse.hip", "concord.hip", "batch.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("CONCORD_OFFLOAD_ARCH", "gfx950")
