@@ -185,6 +185,26 @@ def bench_c1(args, torch, np, datagen):
         s.close()
         out[g] = (iters, float(np.median(times)))
         log(f"graph={g}: {iters} iterations in {out[g][1] * 1e3:.3f} ms")
+    # the same solve on the device-resident batched path (a batch of one): the iteration
+    # control stays on the device, the host reads two counters per replay of K iterations
+    from paper_1710_10769_amd import Batch
+    dev = {}
+    for K in (4, 8):
+        b = Batch([X], [w.lam1], precision="fp64", iters_per_launch=K)
+        times = []
+        for rep in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            iters_b, _, _ = b.solve(w.lam2, w.tol, w.max_iter)
+            torch.cuda.synchronize()
+            if rep >= args.warmup:
+                times.append(time.perf_counter() - t0)
+        st = b.stats()
+        b.close()
+        dev[K] = {"iters_per_s": iters_b[0] / float(np.median(times)),
+                  "ms_per_solve": float(np.median(times)) * 1e3, "iterations": iters_b[0],
+                  "replays": st["launches"], "host_syncs": st["host_syncs"]}
+        log(f"device loop K={K}: {dev[K]}")
     it, sec = out[True]
     line = {
         "metric": "prox-grad iters/sec, Cov FP64 p=200 (launch-latency bound)",
@@ -194,6 +214,7 @@ def bench_c1(args, torch, np, datagen):
         "config": {"workload": "cov_chain_p200_n100", "p": w.p, "n": w.n, "lam1": w.lam1,
                    "lam2": w.lam2, "iterations": it},
         "without_graph": {"value": out[False][0] / out[False][1], "ms_per_solve": out[False][1] * 1e3},
+        "device_loop": {f"iters_per_launch_{k}": v for k, v in dev.items()},
     }
     print(json.dumps(line), flush=True)
 

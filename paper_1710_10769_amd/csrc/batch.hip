@@ -28,7 +28,7 @@ namespace {
 
 constexpr int MAXQ_B = 8;    // step sizes per trial batch at most (the trial kernels' MAXQ)
 constexpr int NSIDE = 4;     // streams forming the instances' S concurrently
-constexpr int GRID = 2048;   // blocks of every phase kernel (they loop over work items)
+constexpr int GRID_MAX = 2048;   // blocks of a phase kernel at most (they loop over work items)
 
 struct Block {
     void* ptr = nullptr;
@@ -57,6 +57,7 @@ struct concord_batch {
     int count = 0, n_l1 = 0, nsolve = 0;
     int sstore = ST_F32, dstore = ST_F32, gkind = GK_F32;
     int maxT = 1;
+    int grid = 64;                  // blocks of every phase kernel: the row blocks of all solves, capped
     std::vector<int64_t> p, n, ld;
     std::vector<const void*> X;
     std::vector<double> lambda1;
@@ -378,6 +379,9 @@ int concord_batch_create(const concord_batch_config* cfg_in, int32_t count, cons
             o.tmask = L.add((size_t)T * ((T + 63) / 64) * 8);
         }
     }
+    int64_t row_blocks = 0;
+    for (int i = 0; i < count; ++i) row_blocks += (int64_t)n_l1 * ((b->p[i] + 3) / 4);
+    b->grid = (int)std::min<int64_t>(GRID_MAX, std::max<int64_t>(64, row_blocks));
     const size_t o_st = L.add((size_t)N * sizeof(DevState));
     const size_t o_ctl = L.add((size_t)N * sizeof(SolveCtl));
     const size_t o_act = L.add((size_t)N * 4);
@@ -424,7 +428,7 @@ int concord_batch_create(const concord_batch_config* cfg_in, int32_t count, cons
             d.T = (int)T;
             d.inst = i;
             d.screen = id.screen;
-            d.grouped = p >= 4096 ? 1 : 0;   // the single solver's switch to 8 lanes per row
+            d.grouped = p >= COV_TRIAL_GROUP_MIN_P ? 1 : 0;   // the single solver's choice
             d.S = A + io[i].S;
             d.lds = round_up(p, 64);
             d.smax = (const double*)(A + io[i].smax);
@@ -500,7 +504,7 @@ int concord_batch_solve(concord_batch* b, double lambda2, double tol, int64_t ma
     a.tol = tol;
     a.tau0 = b->cfg.tau0;
     a.shrink = b->cfg.shrink;
-    BHIP(b, launch_batch_iteration(b->dsd, b->did, b->plan, a, true, GRID, b->work));
+    BHIP(b, launch_batch_iteration(b->dsd, b->did, b->plan, a, true, b->grid, b->work));
     const int K = b->cfg.iters_per_launch;
     bool graph = b->cfg.use_graph != 0;
     if (graph && (!b->gexec || std::memcmp(&b->gargs, &a, sizeof(a)) != 0 || b->g_iters != K)) {
@@ -512,7 +516,7 @@ int concord_batch_solve(concord_batch* b, double lambda2, double tol, int64_t ma
         BHIP(b, hipStreamBeginCapture(b->work, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
         for (int k = 0; k < K && e == hipSuccess; ++k)
-            e = launch_batch_iteration(b->dsd, b->did, b->plan, a, false, GRID, b->work);
+            e = launch_batch_iteration(b->dsd, b->did, b->plan, a, false, b->grid, b->work);
         const hipError_t ec = hipStreamEndCapture(b->work, &g);
         if (e != hipSuccess || ec != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
@@ -533,7 +537,7 @@ int concord_batch_solve(concord_batch* b, double lambda2, double tol, int64_t ma
             BHIP(b, hipGraphLaunch(b->gexec, b->work));
         } else {
             for (int k = 0; k < K; ++k)
-                BHIP(b, launch_batch_iteration(b->dsd, b->did, b->plan, a, false, GRID, b->work));
+                BHIP(b, launch_batch_iteration(b->dsd, b->did, b->plan, a, false, b->grid, b->work));
         }
         launched += K;
         b->stats.launches += 1;

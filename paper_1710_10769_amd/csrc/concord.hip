@@ -501,15 +501,16 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
         const uint64_t* tm = cov && screen_now(c) ? c->rws.tmask : nullptr;
         if (merge || cov)
             HIPCK(c, launch_cand_merge(c->om[c->cur], p, c->bitmap, c->nwords, c->cnt, c->stream,
-                                       tm));
+                                       tm, cov && p >= COV_TRIAL_GROUP_MIN_P));
         else
             HIPCK(c, launch_cand_count(c->M, c->dstore, c->ldp, c->om[c->cur], p, lam1,
                                        c->bitmap, c->nwords, c->cnt, c->stream));
         HIPCK(c, launch_scan(c->cnt, p, c->A.rowptr, c->a_cap, &c->st->overflow, c->scan_ws,
                              c->stream, &c->st->n_cand));
+        // a contraction that wrote the threshold words stored M's upper triangle only
         HIPCK(c, launch_cand_fill(cov ? nullptr : c->M, c->dstore, c->ldp, c->om[c->cur], p, lam2,
                                   c->bitmap, c->nwords, c->A, c->a_cap, &c->st->overflow,
-                                  c->stream, tm));
+                                  c->stream, tm, !cov && merge));
         if (cov)
             HIPCK(c, launch_cand_grad_cov(c->om[c->cur], p, c->S, c->sstore, c->ldp, lam2, c->A,
                                           &c->st->overflow, c->stream));
@@ -529,10 +530,11 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
                                       c->stream));
         prof_end(c);
         prof_begin(c, CONCORD_PROF_EMIT);
-        HIPCK(c, launch_emit_count(c->A, p, lam1, c->st, c->cnt, c->stream));
+        const bool grp = c->variant == CONCORD_COV && p >= COV_TRIAL_GROUP_MIN_P;
+        HIPCK(c, launch_emit_count(c->A, p, lam1, c->st, c->cnt, c->stream, grp));
         HIPCK(c, launch_scan(c->cnt, p, c->om[nxt].rowptr, c->om_cap[nxt], nullptr, c->scan_ws,
                              c->stream, &c->st->nnz_next));
-        HIPCK(c, launch_emit_fill(c->A, p, lam1, c->st, c->om[nxt], c->stream));
+        HIPCK(c, launch_emit_fill(c->A, p, lam1, c->st, c->om[nxt], c->stream, grp));
         prof_end(c);
         int rc2 = products_at(c, nxt, &c->st->accepted,
                               c->variant == CONCORD_COV ? lam1 : -1.0);
@@ -1252,16 +1254,14 @@ int concord_gradient(concord_ctx* c, double lam2, int32_t mode, void* dev_dOmega
     const int64_t p = c->p, nnz = c->nnz;
     const size_t dense_bytes = (size_t)c->prow * c->ldk * elem_bytes(c->dstore);
     // Buffers of this call only (returned before it ends): Y when the handle holds none,
-    // Omega Y before its transpose, and the two halves of every masked entry.
+    // Omega Y before its transpose, and the half d_ij of every masked entry.
     void* ybuf = nullptr;
     void* oy = nullptr;
     double* D = nullptr;
-    double* E = nullptr;
     auto done = [&](int rc) {
         dfree(c, ybuf);
         dfree(c, oy);
         dfree(c, D);
-        dfree(c, E);
         return rc;
     };
     int rc;
@@ -1278,14 +1278,14 @@ int concord_gradient(concord_ctx* c, double lam2, int32_t mode, void* dev_dOmega
     }
     if (dev_dX && (rc = dalloc(c, &oy, dense_bytes, true))) return done(rc);
     if (dev_dOmega && mode == CONCORD_GRAD_MASKED) {
-        // both halves of every entry and, when d f / d X is wanted too, Omega Y, from one
+        // the half d_ij of every entry and, when d f / d X is wanted too, Omega Y, from one
         // gather of the rows Y_j
         const int ncb = grad_col_blocks(c->dstore, c->n);
         const size_t len = (size_t)std::max<int64_t>(nnz, 1) * ncb;
-        if ((rc = dalloc_t(c, &D, len)) || (rc = dalloc_t(c, &E, len))) return done(rc);
-        HIPCK(c, launch_grad_rows(O, p, nnz, Y, c->Xt, c->dstore, c->ldk, c->n, D, E, oy,
+        if ((rc = dalloc_t(c, &D, len))) return done(rc);
+        HIPCK(c, launch_grad_rows(O, p, nnz, Y, c->Xt, c->dstore, c->ldk, c->n, D, oy,
                                   c->stream));
-        HIPCK(c, launch_grad_combine(O, p, nnz, ncb, D, E, c->n, lam2, dev_dOmega, out64,
+        HIPCK(c, launch_grad_combine(O, p, nnz, ncb, D, c->n, lam2, dev_dOmega, out64,
                                      c->stream));
     } else {
         if (dev_dOmega) {   // dense G: the contraction of Algorithm 3 at the current iterate

@@ -537,6 +537,10 @@ __device__ __forceinline__ void store_tile_256(const f32x16_t (&acc)[dma::MB][dm
         write_thresh_bits<MB, NB>(acc, I == J, rowI0, rowJ0, wm * 64, wn * 128, lane, p, alpha,
                                   out_store, th);
 
+    // With the threshold words written, the candidate pass reads M only at candidates and
+    // takes M_ij from the upper triangle (the pair's stored value), so the mirrored
+    // (column-strided) stores are skipped.
+    const bool mirror = th.bits == nullptr;
     if (I != J && out_store != ST_F64) {
 #pragma unroll
         for (int i = 0; i < MB; ++i)
@@ -559,7 +563,7 @@ __device__ __forceinline__ void store_tile_256(const f32x16_t (&acc)[dma::MB][dm
                         }
                         if (gj < p && gi0 + t < p) ((uint32_t*)C)[(gi0 + t) * ldc + gj] = w[t];
                     }
-                    if (gj < p) {
+                    if (mirror && gj < p) {
                         if (gi0 + 3 < p) {
                             *(u32x4_t*)((uint32_t*)C + gj * ldc + gi0) = u32x4_t{w[0], w[1], w[2], w[3]};
                         } else {
@@ -585,7 +589,7 @@ __device__ __forceinline__ void store_tile_256(const f32x16_t (&acc)[dma::MB][dm
                 if (I == J && gi > gj) continue;
                 const double v = alpha * (double)acc[i][j][r];
                 store_val(C, out_store, gi * ldc + gj, v);
-                if (gi != gj) store_val(C, out_store, gj * ldc + gi, v);
+                if (mirror && gi != gj) store_val(C, out_store, gj * ldc + gi, v);
             }
 }
 
@@ -974,6 +978,10 @@ gemm_bf16x3_ar_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
     store_tile_256(acc, I, J, rowI0, rowJ0, wm, wn, lane, p, alpha, C, out_store, ldc, th);
 }
 
+hipError_t launch_bf16x3_dma(bool syr2k, const void* P0, const void* P1, const void* Q0,
+                             const void* Q1, int64_t ldk, int64_t p, double alpha, void* C,
+                             int out_store, int64_t ldc, hipStream_t stream, ThreshOut th);
+
 hipError_t launch_bf16x3_ar(bool syr2k, const void* P0, const void* P1, const void* Q0,
                             const void* Q1, int64_t ldk, int64_t p, double alpha, void* C,
                             int out_store, int64_t ldc, hipStream_t stream, ThreshOut th) {
@@ -983,7 +991,209 @@ hipError_t launch_bf16x3_ar(bool syr2k, const void* P0, const void* P1, const vo
     const int T = (int)((p + dma::BT - 1) / dma::BT);
     const int ntiles = T * (T + 1) / 2;
     if (ntiles == 0 || nk == 0) return hipSuccess;
+    if ((syr2k ? 2 * nk : nk) < 4)   // the prologue issues four stages; the ring kernel
+        return launch_bf16x3_dma(syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc,
+                                 stream, th);   // takes fewer (bitwise the same result)
     hipLaunchKernelGGL(gemm_bf16x3_ar_kernel, dim3(ntiles), dim3(dma::NT), 0, stream,
+                       (const char*)P0, (const char*)P1, (const char*)(syr2k ? Q0 : P0),
+                       (const char*)(syr2k ? Q1 : P1), round_up(p, ROW_PAD) * dma::ROW, nk,
+                       syr2k ? 1 : 0, (int)p, T, ntiles, alpha, C, out_store, ldc, th);
+    return hipGetLastError();
+}
+
+// ---- BF16-split contraction: A in registers, B fragments read one stage ahead ----
+//
+// The kernel above reads a stage's B fragments from LDS after the stage's barrier and
+// waits for them before its first MFMA, so every wave of the workgroup stalls on the
+// same burst of LDS reads (32 KB per stage) with the matrix cores idle.  Here the B
+// fragments of stage k + 1 are read while the MFMAs of stage k run: the second and
+// third split products of stage k are each one asm block that first issues four
+// fragment reads of stage k + 1, then the eight MFMAs, and waits for the reads at its
+// end (the results are in registers before the block ends).  Stage k + 1 must then be
+// in LDS one stage earlier: the wait at the top of stage k covers this wave's loads of
+// B(k + 1) and A(k), and the barrier after it publishes every wave's share.  B is still
+// issued three stages ahead (the slot of B(k), read by every wave during stage k - 1, is
+// refilled with B(k + 4)), A two stages ahead in three register sets.  Per accumulator
+// the products keep the order lo*hi, hi*lo, hi*hi of every other variant, so the
+// result is bitwise the same.
+namespace arp {
+// eight MFMAs acc[i][j] += a[i] * b[j] of one split product, with the four fragment
+// reads at `ad` (+1024 per 32-row block) issued first and complete when the block ends
+__device__ inline void mfma8_read4(f32x16_t (&c)[dma::MB][dma::NB], const bf16x8_t (&a)[dma::MB],
+                                   const bf16x8_t (&b)[dma::NB], u32x4_t (&nx)[4], uint32_t ad) {
+    asm volatile(
+        "ds_read_b128 %[n0], %[ad]\n\t"
+        "ds_read_b128 %[n1], %[ad] offset:1024\n\t"
+        "ds_read_b128 %[n2], %[ad] offset:2048\n\t"
+        "ds_read_b128 %[n3], %[ad] offset:3072\n\t"
+        "v_mfma_f32_32x32x16_bf16 %[c00], %[a0], %[b0], %[c00]\n\t"
+        "v_mfma_f32_32x32x16_bf16 %[c01], %[a0], %[b1], %[c01]\n\t"
+        "v_mfma_f32_32x32x16_bf16 %[c02], %[a0], %[b2], %[c02]\n\t"
+        "v_mfma_f32_32x32x16_bf16 %[c03], %[a0], %[b3], %[c03]\n\t"
+        "v_mfma_f32_32x32x16_bf16 %[c10], %[a1], %[b0], %[c10]\n\t"
+        "v_mfma_f32_32x32x16_bf16 %[c11], %[a1], %[b1], %[c11]\n\t"
+        "v_mfma_f32_32x32x16_bf16 %[c12], %[a1], %[b2], %[c12]\n\t"
+        "v_mfma_f32_32x32x16_bf16 %[c13], %[a1], %[b3], %[c13]\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : [c00] "+v"(c[0][0]), [c01] "+v"(c[0][1]), [c02] "+v"(c[0][2]), [c03] "+v"(c[0][3]),
+          [c10] "+v"(c[1][0]), [c11] "+v"(c[1][1]), [c12] "+v"(c[1][2]), [c13] "+v"(c[1][3]),
+          [n0] "=&v"(nx[0]), [n1] "=&v"(nx[1]), [n2] "=&v"(nx[2]), [n3] "=&v"(nx[3])
+        : [a0] "v"(a[0]), [a1] "v"(a[1]), [b0] "v"(b[0]), [b1] "v"(b[1]), [b2] "v"(b[2]),
+          [b3] "v"(b[3]), [ad] "v"(ad)
+        : "memory");
+}
+// the four fragment reads at `ad` alone, complete when the block ends
+__device__ inline void read4(u32x4_t (&nx)[4], uint32_t ad) {
+    asm volatile(
+        "ds_read_b128 %0, %4\n\t"
+        "ds_read_b128 %1, %4 offset:1024\n\t"
+        "ds_read_b128 %2, %4 offset:2048\n\t"
+        "ds_read_b128 %3, %4 offset:3072\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(nx[0]), "=&v"(nx[1]), "=&v"(nx[2]), "=&v"(nx[3])
+        : "v"(ad)
+        : "memory");
+}
+template <int N> __device__ inline void as_bf16(const u32x4_t (&u)[N], bf16x8_t (&b)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) b[i] = __builtin_bit_cast(bf16x8_t, u[i]);
+}
+}  // namespace arp
+
+__global__ void __launch_bounds__(dma::NT)
+gemm_bf16x3_arp_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
+                       const char* __restrict__ Q0, const char* __restrict__ Q1,
+                       int64_t kbs, int nk, int syr2k, int p, int T, int ntiles,
+                       double alpha, void* __restrict__ C, int out_store, int64_t ldc,
+                       ThreshOut th) {
+    using namespace dma;
+    using ar::BSLOT;
+    __shared__ __attribute__((aligned(16))) char ring[4 * BSLOT];
+
+    int I, J;
+    tile_of(blockIdx.x, ntiles, T, I, J);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave / WN, wn = wave % WN;
+    const int64_t rowI0 = (int64_t)I * BT, rowJ0 = (int64_t)J * BT;
+    const int nkt = syr2k ? 2 * nk : nk;
+    const int r32 = lane & 31, hk = lane >> 5;
+
+    // B side: as gemm_bf16x3_ar_kernel (2 loads per wave per stage)
+    const int bpl = wave >> 2;
+    const char* bsrc1 = syr2k ? (bpl ? Q1 : Q0) : (bpl ? P1 : P0);
+    const char* bsrc2 = bpl ? P1 : P0;
+    const int64_t brow = rowJ0 + (wave & 3) * 64 + (lane >> 1);
+    const int bsw = (lane & 1) ^ (((lane >> 1) >> 3) & 1);
+    auto issue_b = [&](int slot_kt, int kt) {
+        char* slot = ring + (slot_kt & 3) * BSLOT + bpl * PS + (wave & 3) * 2048;
+        const bool second = kt >= nk;
+        const char* g = (second ? bsrc2 : bsrc1) + (int64_t)(second ? kt - nk : kt) * kbs +
+                        brow * ROW + bsw * 16;
+        __builtin_amdgcn_global_load_lds((gbl_t*)g, (lds_t*)slot, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((gbl_t*)(g + 32 * ROW), (lds_t*)(slot + 1024), 16, 0, 0);
+    };
+    // A side: 4 loads per wave per stage (hi, lo of two 32-row blocks)
+    const int64_t arow = (rowI0 + wm * 64 + r32) * ROW + hk * 16;
+    auto load_a = [&](int kt, u32x4_t (&a)[4]) {
+        const bool second = kt >= nk;
+        const int64_t o = (int64_t)(second ? kt - nk : kt) * kbs + arow;
+        const char* ah = second ? Q0 : P0;
+        const char* al = second ? Q1 : P1;
+        a[0] = *(const u32x4_t*)(ah + o);
+        a[1] = *(const u32x4_t*)(ah + o + 32 * ROW);
+        a[2] = *(const u32x4_t*)(al + o);
+        a[3] = *(const u32x4_t*)(al + o + 32 * ROW);
+    };
+
+    f32x16_t acc[MB][NB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    const uint32_t lds_b = (uint32_t)(uintptr_t)(lds_t*)ring + off(wn * 128 + r32, hk);
+    const int last = nkt - 1;
+    // Issue order: B(0), B(1), A(0), B(2), A(1), B(3), then per stage k: A(k + 2),
+    // B(k + 4) (past the last stage they re-read stage nkt - 1 into a register set or a
+    // slot nothing reads again).  At the top of stage k, eight operations were issued
+    // after A(k) (B(k + 2), A(k + 1), B(k + 3)) and twelve after B(k + 1); nkt >= 4.
+    u32x4_t a0[4], a1[4], a2[4];
+    u32x4_t bh0[4], bl0[4], bh1[4], bl1[4];   // B fragments of two consecutive stages
+    issue_b(0, 0);
+    issue_b(1, 1);
+    load_a(0, a0);
+    issue_b(2, 2);
+    load_a(1, a1);
+    issue_b(3, 3);
+    __builtin_amdgcn_s_waitcnt(0x0f7e);   // vmcnt(14): this wave's share of B(0) landed
+    order();
+    __builtin_amdgcn_s_barrier();
+    order();
+    arp::read4(bh0, lds_b);
+    arp::read4(bl0, lds_b + PS);
+
+    // stage k: A(k) in acur, B(k) in (bh, bl); reads B(k + 1) into (nh, nl)
+    auto step = [&](int k, u32x4_t (&acur)[4], u32x4_t (&anext)[4], const u32x4_t (&bh)[4],
+                    const u32x4_t (&bl)[4], u32x4_t (&nh)[4], u32x4_t (&nl)[4]) {
+        __builtin_amdgcn_s_waitcnt(0x0f78);   // vmcnt(8): A(k), this wave's B(k + 1) landed
+        order();
+        __builtin_amdgcn_s_barrier();         // every wave's B(k + 1); slot of B(k) free
+        order();
+        load_a(k + 2 < last ? k + 2 : last, anext);
+        issue_b(k + 4, k + 4 < last ? k + 4 : last);
+        const uint32_t nb = lds_b + ((k + 1) & 3) * BSLOT;
+        bf16x8_t ah[MB], al[MB], bhv[NB], blv[NB];
+        ah[0] = __builtin_bit_cast(bf16x8_t, acur[0]);
+        ah[1] = __builtin_bit_cast(bf16x8_t, acur[1]);
+        al[0] = __builtin_bit_cast(bf16x8_t, acur[2]);
+        al[1] = __builtin_bit_cast(bf16x8_t, acur[3]);
+        arp::as_bf16(bh, bhv);
+        arp::as_bf16(bl, blv);
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bhv[j], acc[i][j], 0, 0, 0);
+        arp::mfma8_read4(acc, ah, blv, nh, nb);        // hi * lo; reads B(k + 1) hi
+        arp::mfma8_read4(acc, ah, bhv, nl, nb + PS);   // hi * hi; reads B(k + 1) lo
+    };
+    int kt = 0;
+    for (; kt + 6 <= nkt; kt += 6) {
+        step(kt + 0, a0, a2, bh0, bl0, bh1, bl1);
+        step(kt + 1, a1, a0, bh1, bl1, bh0, bl0);
+        step(kt + 2, a2, a1, bh0, bl0, bh1, bl1);
+        step(kt + 3, a0, a2, bh1, bl1, bh0, bl0);
+        step(kt + 4, a1, a0, bh0, bl0, bh1, bl1);
+        step(kt + 5, a2, a1, bh1, bl1, bh0, bl0);
+    }
+    if (kt + 0 < nkt) step(kt + 0, a0, a2, bh0, bl0, bh1, bl1);
+    if (kt + 1 < nkt) step(kt + 1, a1, a0, bh1, bl1, bh0, bl0);
+    if (kt + 2 < nkt) step(kt + 2, a2, a1, bh0, bl0, bh1, bl1);
+    if (kt + 3 < nkt) step(kt + 3, a0, a2, bh1, bl1, bh0, bl0);
+    if (kt + 4 < nkt) step(kt + 4, a1, a0, bh0, bl0, bh1, bl1);
+    wait_vm(0);
+    // the last MFMAs were issued from asm, where the compiler inserts no hazard wait:
+    // 24 wait states before any instruction reads their results
+    asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7" ::: "memory");
+    store_tile_256(acc, I, J, rowI0, rowJ0, wm, wn, lane, p, alpha, C, out_store, ldc, th);
+}
+
+hipError_t launch_bf16x3_arp(bool syr2k, const void* P0, const void* P1, const void* Q0,
+                             const void* Q1, int64_t ldk, int64_t p, double alpha, void* C,
+                             int out_store, int64_t ldc, hipStream_t stream, ThreshOut th) {
+    const int64_t ldk_bytes = ldk * 2;
+    if (ldk_bytes % dma::ROW) return hipErrorInvalidValue;
+    const int nk = (int)(ldk_bytes / dma::ROW);
+    const int T = (int)((p + dma::BT - 1) / dma::BT);
+    const int ntiles = T * (T + 1) / 2;
+    if (ntiles == 0 || nk == 0) return hipSuccess;
+    if ((syr2k ? 2 * nk : nk) < 4)   // the issue pattern needs four stages
+        return launch_bf16x3_dma(syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc,
+                                 stream, th);
+    hipLaunchKernelGGL(gemm_bf16x3_arp_kernel, dim3(ntiles), dim3(dma::NT), 0, stream,
                        (const char*)P0, (const char*)P1, (const char*)(syr2k ? Q0 : P0),
                        (const char*)(syr2k ? Q1 : P1), round_up(p, ROW_PAD) * dma::ROW, nk,
                        syr2k ? 1 : 0, (int)p, T, ntiles, alpha, C, out_store, ldc, th);
@@ -1097,6 +1307,7 @@ const Variant* variants(int kind, int* count) {
         {"bf16x3_256x256_w8_persistent", launch_kind<GK_BF16X3, 256, 4, 2, true>, false},
         {"bf16x3_256x256_w8_pingpong", launch_bf16x3_pp, true},
         {"bf16x3_256x256_w8_ldsring_aregs", launch_bf16x3_ar, true},
+        {"bf16x3_256x256_w8_ldsring_aregs_pipe", launch_bf16x3_arp, true},
     };
     static const Variant f32[] = {
         {"f32_256x256_w8", launch_kind<GK_F32, 256, 4, 2>, false},
@@ -1107,7 +1318,7 @@ const Variant* variants(int kind, int* count) {
         {"f64_128x128_w4", launch_kind<GK_F64, 128, 2, 2>, false},
     };
     switch (kind) {
-        case GK_BF16X3: *count = 6; return bf;
+        case GK_BF16X3: *count = 7; return bf;
         case GK_F32: *count = 3; return f32;
         default: *count = 1; return f64;
     }

@@ -51,7 +51,9 @@ __host__ __device__ inline int64_t kblk_index(int64_t row, int64_t k, int64_t st
 // set (p x nwords uint64, nwords = ceil(p/64)); bit j of word w of row i is set iff
 // i == j or |C_ij| > lam1 for the stored value.  bits == nullptr: not requested.
 // Only the direct-to-LDS BF16-split variants write it; *wrote (host, optional) tells
-// whether the variant that ran did (else the caller runs the full candidate pass).
+// whether the variant that ran did (else the caller runs the full candidate pass).  A
+// variant that writes the words stores C's upper triangle only (i <= j; the lower one is
+// not written): the candidate pass then reads C_ij as C[min(i,j)][max(i,j)].
 struct ThreshOut {
     double lam1 = 0.0;
     uint64_t* bits = nullptr;
@@ -119,7 +121,8 @@ struct Cand {
 // the words of kept tiles and the support's words are read; words outside both are stale
 // and never read.
 hipError_t launch_cand_merge(const Csr& om, int64_t p, uint64_t* bitmap, int64_t nwords,
-                             int64_t* cnt, hipStream_t stream, const uint64_t* tmask = nullptr);
+                             int64_t* cnt, hipStream_t stream, const uint64_t* tmask = nullptr,
+                             bool grouped = false);
 
 // Count pass: for every row, A_i = {j != i : |M_ij| > lam1} U supp(Omega_i) U {i}.
 // Writes the candidate bitmap (p x nwords64 uint64, row-major, word w bit b
@@ -129,11 +132,12 @@ hipError_t launch_cand_count(const void* M, int mstore, int64_t ldm, const Csr& 
                              hipStream_t stream);
 // Fill pass: writes A (sorted columns) with omega and G = M + lam2*omega - [i==j]/omega_ii.
 // With M null (Cov form) it writes the columns and omega only; launch_cand_grad_cov then
-// writes G.
+// writes G.  m_upper: only M's upper triangle is stored (M_ij read at [min][max]).
 hipError_t launch_cand_fill(const void* M, int mstore, int64_t ldm, const Csr& om, int64_t p,
                             double lam2, const uint64_t* bitmap, int64_t nwords,
                             const Cand& A, int64_t cap, const int* overflow,
-                            hipStream_t stream, const uint64_t* tmask = nullptr);
+                            hipStream_t stream, const uint64_t* tmask = nullptr,
+                            bool m_upper = false);
 
 // Cov form: G on the candidates of A (filled for the same iterate), with M_ij gathered
 // from S and the CSR rows i and j of Omega; bitwise the value the Cov refresh tests.
@@ -151,6 +155,9 @@ hipError_t launch_scan(const int64_t* cnt, int64_t p, int64_t* out, int64_t cap,
 int64_t scan_ws_len(int64_t p);
 
 struct DevState;
+// Cov trials of problems with at least this many rows run 8 lanes per row (8 rows per
+// wave); smaller ones a wave per row.  The batched solver makes the same choice per solve.
+constexpr int64_t COV_TRIAL_GROUP_MIN_P = 1024;
 // Column splits of the Obs quadratic term in launch_trial (1 for Cov).
 int trial_splits(int variant, int bstore, int64_t ncols);
 // Trial evaluation for `m` step sizes tau_q = tau0 * shrink^q (q < m) at once (tau_q
@@ -179,10 +186,12 @@ hipError_t launch_colsum_obj(const double* in, int64_t rows, int ncol, double* o
                              int nysq, const int* gate, DevState* st, hipStream_t stream);
 
 // Emission: new CSR from A at the chosen step (state->accepted_q).
+// grouped: 8 lanes per row (Cov problems of at least COV_TRIAL_GROUP_MIN_P rows; same
+// results as a wave per row).
 hipError_t launch_emit_count(const Cand& A, int64_t p, double lam1, const DevState* st,
-                             int64_t* cnt, hipStream_t stream);
+                             int64_t* cnt, hipStream_t stream, bool grouped = false);
 hipError_t launch_emit_fill(const Cand& A, int64_t p, double lam1, const DevState* st,
-                            const Csr& out, hipStream_t stream);
+                            const Csr& out, hipStream_t stream, bool grouped = false);
 
 // Objective partials of a CSR iterate.  part[t * p + row]: t = 0 sum of log
 // of the diagonal, 1 sum of squares, 2 off-diagonal sum of |v|, 3 sum of
@@ -242,18 +251,18 @@ hipError_t launch_tile_max(const void* S, int sstore, int64_t p, int64_t lds, do
 
 // Differentiation form.
 // Masked gradient on the stored entries and Omega Y (d f / d X^T times n) in one row
-// pass (Y = Omega X^T, p x ld rows): d_ij = <Y_j, Xt_i> goes to D at entry (i, j) and to E
-// at its mirror (j, i), per column block cb at offset cb * nnz (grad_col_blocks(store, n)
-// blocks; D and E hold that many times nnz doubles); oy (p x ld, may be null) receives
-// Omega Y.  launch_grad_combine then writes G_ij = (d_ij + d_ji) / (2n) + lam2 w_ij -
+// pass (Y = Omega X^T, p x ld rows): d_ij = <Y_j, Xt_i> goes to D at entry (i, j), per
+// column block cb at offset cb * nnz (grad_col_blocks(store, n) blocks; D holds that many
+// times nnz doubles); oy (p x ld, may be null) receives Omega Y.  launch_grad_combine
+// then finds d_ji at the mirror entry and writes G_ij = (d_ij + d_ji) / (2n) + lam2 w_ij -
 // [i == j] / w_ii to out (nnz, FP64 or FP32).  The pattern must be symmetric (an entry
 // whose mirror is not stored gets an unspecified value).
 int grad_col_blocks(int store, int64_t n);
 hipError_t launch_grad_rows(const Csr& om, int64_t p, int64_t nnz, const void* Y, const void* Xt,
-                            int store, int64_t ld, int64_t n, double* D, double* E, void* oy,
+                            int store, int64_t ld, int64_t n, double* D, void* oy,
                             hipStream_t stream);
 hipError_t launch_grad_combine(const Csr& om, int64_t p, int64_t nnz, int ncb, const double* D,
-                               const double* E, int64_t n, double lam2, void* out, int out_f64,
+                               int64_t n, double lam2, void* out, int out_f64,
                                hipStream_t stream);
 hipError_t launch_gather_dense_grad(const void* M, int mstore, int64_t ldm, const Csr& om,
                                     int64_t p, double lam2, void* out, int out_f64,

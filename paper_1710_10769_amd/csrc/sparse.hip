@@ -342,7 +342,7 @@ __device__ __forceinline__ void cand_fill_body(int64_t bx_, const void* __restri
                  double lam2, const uint64_t* __restrict__ bitmap, int64_t nwords,
                  const int64_t* __restrict__ arow, int32_t* __restrict__ acol,
                  double* __restrict__ aom, double* __restrict__ agr, const int* overflow,
-                 const uint64_t* __restrict__ tmask) {
+                 const uint64_t* __restrict__ tmask, bool m_upper = false) {
     if (*overflow) return;
     typedef typename Chunk<MS>::T E;
     extern __shared__ uint64_t swords[];   // with a tile mask: the row's words holding support
@@ -428,7 +428,8 @@ __device__ __forceinline__ void cand_fill_body(int64_t bx_, const void* __restri
             acol[pos] = (int32_t)j;
             aom[pos] = om;
             if (M) {
-                double gval = (double)Mrow[j] + lam2 * om;
+                const E mij = m_upper && j < row ? ((const E*)M)[j * ldm + row] : Mrow[j];
+                double gval = (double)mij + lam2 * om;
                 if (j == row) gval -= 1.0 / om;
                 agr[pos] = gval;
             }
@@ -445,8 +446,8 @@ cand_fill_kernel(const void* __restrict__ M, int64_t ldm, const int64_t* __restr
                  double lam2, const uint64_t* __restrict__ bitmap, int64_t nwords,
                  const int64_t* __restrict__ arow, int32_t* __restrict__ acol,
                  double* __restrict__ aom, double* __restrict__ agr, const int* overflow,
-                 const uint64_t* __restrict__ tmask) {
-    cand_fill_body<MS>(blockIdx.x, M, ldm, rowptr, col, val, p, lam2, bitmap, nwords, arow, acol, aom, agr, overflow, tmask);
+                 const uint64_t* __restrict__ tmask, bool m_upper) {
+    cand_fill_body<MS>(blockIdx.x, M, ldm, rowptr, col, val, p, lam2, bitmap, nwords, arow, acol, aom, agr, overflow, tmask, m_upper);
 }
 
 // Cov form: the gradient on the candidates, G_ij = M_ij + lam2 omega_ij - [i == j] / omega_ii,
@@ -817,7 +818,7 @@ trial_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
 // reduce-scatter (16 + 8 + 4 shuffles), after which lane g of the group holds the four
 // sums of step size q = g.
 constexpr int TG = 8;
-constexpr int64_t COV_GROUP_MIN_P = 4096;
+constexpr int64_t COV_GROUP_MIN_P = COV_TRIAL_GROUP_MIN_P;
 template <int BS>
 __device__ __forceinline__ void trial_cov_body(int64_t bx_, const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
                  const double* __restrict__ aom, const double* __restrict__ agr, int64_t p,
@@ -1636,13 +1637,15 @@ __device__ __forceinline__ void cand_merge_body(int64_t bx_, const int64_t* __re
         __builtin_amdgcn_s_waitcnt(0);
     }
     // the support bits go in by atomic OR on the few words they touch (the row's other
-    // words are only read); the count reads after every OR has completed (the line is
-    // in no L1: this kernel reads the row only after its ORs)
+    // words are only read); the count reads after every OR has completed, and after an
+    // acquire fence that drops the CU's L1 (another wave may have pulled a line shared
+    // with a neighbouring row into it before the ORs reached L2)
     for (int64_t k = s + lane; k < e; k += 64) {
         const int32_t c = col[k];
         atomicOr((unsigned long long*)&rw[c >> 6], 1ull << (c & 63));
     }
     __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     int64_t total = extra;   // each such entry is one bit of a word counted nowhere else
     if (mrow) {
         // only the 64-word blocks whose mask word is nonzero: the mask row is read 64
@@ -1671,6 +1674,234 @@ cand_merge_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict_
                   uint64_t* __restrict__ bitmap, int64_t nwords, int64_t* __restrict__ cnt,
                   const uint64_t* __restrict__ tmask) {
     cand_merge_body(blockIdx.x, rowptr, col, p, bitmap, nwords, cnt, tmask);
+}
+
+// ---- Cov per-row kernels with 8 lanes per row (8 rows per wave) --------------------
+// For Cov problems of at least COV_TRIAL_GROUP_MIN_P rows (the trials make the same
+// choice): a Cov row holds a few entries, so a wave per row leaves most lanes idle and,
+// with many rows, the kernels run latency bound with too few rows in flight.  The
+// candidate merge, the gradient on the candidates and the emission give the same results
+// as their wave-per-row forms (integer work; per-entry values formed by one lane as
+// before); the objective partials are sums over the row's 8 lanes (lane g takes entries
+// g, g + 8, ...) and a fixed butterfly, so they are reproducible but not bitwise those of
+// the wave-per-row form, which is why the choice is made by the problem size alone.
+__device__ inline int64_t group_row(int64_t bx) {
+    return (bx * WPB + (threadIdx.x >> 6)) * (64 / TG) + (lane_id() / TG);
+}
+// sum over the 8 lanes of a row group (butterfly within the group)
+__device__ inline double group_sum(double v) {
+#pragma unroll
+    for (int o = TG / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ void cand_merge_g_body(int64_t bx, const int64_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ col, int64_t p,
+                                                  uint64_t* __restrict__ bitmap, int64_t nwords,
+                                                  int64_t* __restrict__ cnt,
+                                                  const uint64_t* __restrict__ tmask) {
+    const int g = lane_id() & (TG - 1);
+    const int64_t row = group_row(bx);
+    const bool act = row < p;
+    const int64_t s = act ? rowptr[row] : 0, e = act ? rowptr[row + 1] : 0;
+    uint64_t* rw = bitmap + (act ? row : 0) * nwords;
+    const int64_t TW = (nwords + 63) / 64;
+    const uint64_t* mrow = tmask && act ? tmask + (row >> 6) * TW : nullptr;
+    int64_t total = 0;
+    // as cand_merge_body: support words outside the kept tiles are cleared first (each such
+    // entry is one bit counted nowhere else), then the support bits go in by atomic OR
+    if (mrow) {
+        for (int64_t k = s + g; k < e; k += TG) {
+            const int64_t w = col[k] >> 6;
+            if (!((mrow[w >> 6] >> (w & 63)) & 1ull)) {
+                rw[w] = 0ull;
+                ++total;
+            }
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    for (int64_t k = s + g; k < e; k += TG) {
+        const int32_t c = col[k];
+        atomicOr((unsigned long long*)&rw[c >> 6], 1ull << (c & 63));
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (mrow) {
+        for (int64_t m = g; m < TW; m += TG) {
+            uint64_t mk = mrow[m];
+            while (mk) {
+                const int b = __builtin_ctzll(mk);
+                mk &= mk - 1ull;
+                const int64_t w = m * 64 + b;
+                if (w < nwords) total += __popcll(rw[w]);
+            }
+        }
+    } else if (act) {
+        for (int64_t w = g; w < nwords; w += TG) total += __popcll(rw[w]);
+    }
+    const double tt = group_sum((double)total);
+    if (act && g == 0) cnt[row] = (int64_t)tt;
+}
+
+template <int BS>
+__device__ __forceinline__ void cand_grad_cov_g_body(int64_t bx, const int64_t* __restrict__ rowptr,
+                                                     const int32_t* __restrict__ col,
+                                                     const double* __restrict__ val, int64_t p,
+                                                     const void* __restrict__ S, int64_t lds,
+                                                     double lam2, const int64_t* __restrict__ arow,
+                                                     const int32_t* __restrict__ acol,
+                                                     const double* __restrict__ aom,
+                                                     double* __restrict__ agr, const int* overflow) {
+    if (*overflow) return;
+    const int g = lane_id() & (TG - 1);
+    const int64_t row = group_row(bx);
+    if (row >= p) return;
+    const int64_t s = arow[row], e = arow[row + 1];
+    for (int64_t k = s + g; k < e; k += TG) {
+        const int64_t j = acol[k];
+        const double m = m_entry<BS>(rowptr, col, val, S, lds, row, j);
+        const double om = aom[k];
+        double gr = m + lam2 * om;
+        if (j == row) gr -= 1.0 / om;
+        agr[k] = gr;
+    }
+}
+
+__device__ __forceinline__ void emit_count_g_body(int64_t bx, const int64_t* __restrict__ arow,
+                                                  const int32_t* __restrict__ acol,
+                                                  const double* __restrict__ aom,
+                                                  const double* __restrict__ agr, int64_t p,
+                                                  double lam1, const DevState* st,
+                                                  int64_t* __restrict__ cnt) {
+    if (st->accepted_q < 0 || st->nonpos) return;
+    const double tau = st->tau;
+    const int g = lane_id() & (TG - 1);
+    const int64_t row = group_row(bx);
+    const bool act = row < p;
+    int c = 0;
+    if (act) {
+        const int64_t s = arow[row], e = arow[row + 1];
+        for (int64_t k = s + g; k < e; k += TG) {
+            const bool diag = acol[k] == row;
+            const double wp = prox_one(aom[k], agr[k], tau, tau * lam1, diag);
+            c += (wp != 0.0 || diag) ? 1 : 0;
+        }
+    }
+#pragma unroll
+    for (int o = TG / 2; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+    if (act && g == 0) cnt[row] = c;
+}
+
+__device__ __forceinline__ void emit_fill_g_body(int64_t bx, const int64_t* __restrict__ arow,
+                                                 const int32_t* __restrict__ acol,
+                                                 const double* __restrict__ aom,
+                                                 const double* __restrict__ agr, int64_t p,
+                                                 double lam1, const DevState* st,
+                                                 const int64_t* __restrict__ orow,
+                                                 int32_t* __restrict__ ocol,
+                                                 double* __restrict__ oval) {
+    if (st->accepted_q < 0 || st->nonpos) return;
+    const double tau = st->tau;
+    const int lane = lane_id(), g = lane & (TG - 1), grp = lane / TG;
+    const int64_t row = group_row(bx);
+    const bool act = row < p;
+    const int64_t s = act ? arow[row] : 0, e = act ? arow[row + 1] : 0;
+    int64_t out = act ? orow[row] : 0;
+    // every lane runs the wave's longest row (the ballot needs the whole wave)
+    int len = (int)(e - s);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const int x = __shfl_xor(len, o, 64);
+        len = x > len ? x : len;
+    }
+    for (int k0 = 0; k0 < len; k0 += TG) {
+        const int64_t k = s + k0 + g;
+        bool keep = false;
+        double wp = 0.0;
+        int32_t j = 0;
+        if (k < e) {
+            j = acol[k];
+            const bool diag = j == row;
+            wp = prox_one(aom[k], agr[k], tau, tau * lam1, diag);
+            keep = wp != 0.0 || diag;
+        }
+        const uint32_t gm = (uint32_t)(__ballot(keep) >> (grp * TG)) & ((1u << TG) - 1u);
+        if (keep) {
+            const int64_t pos = out + __popc(gm & ((1u << g) - 1u));
+            ocol[pos] = j;
+            oval[pos] = wp;
+        }
+        out += __popc(gm);
+    }
+}
+
+template <int BS>
+__device__ __forceinline__ void obj_parts_cov_g_body(int64_t bx, const int64_t* __restrict__ rowptr,
+                                                     const int32_t* __restrict__ col,
+                                                     const double* __restrict__ val, int64_t p,
+                                                     const void* __restrict__ S, int64_t lds,
+                                                     double* __restrict__ part, const int* gate) {
+    if (gate && *gate == 0) return;
+    const int g = lane_id() & (TG - 1);
+    const int64_t row = group_row(bx);
+    const bool act = row < p;
+    double lg = 0, sq = 0, l1 = 0, wv = 0;
+    if (act) {
+        const int64_t s = rowptr[row], e = rowptr[row + 1];
+        for (int64_t k = s + g; k < e; k += TG) {
+            const int64_t j = col[k];
+            const double m = m_entry<BS>(rowptr, col, val, S, lds, row, j);
+            const double v = val[k];
+            sq += v * v;
+            if (j == row) lg += log(v);
+            else l1 += fabs(v);
+            wv = fma(m, v, wv);
+        }
+    }
+    lg = group_sum(lg); sq = group_sum(sq); l1 = group_sum(l1); wv = group_sum(wv);
+    if (act && g == 0) {
+        part[0 * p + row] = lg;
+        part[1 * p + row] = sq;
+        part[2 * p + row] = l1;
+        part[3 * p + row] = wv;
+    }
+}
+
+__global__ void __launch_bounds__(NT)
+cand_merge_g_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col, int64_t p,
+                    uint64_t* __restrict__ bitmap, int64_t nwords, int64_t* __restrict__ cnt,
+                    const uint64_t* __restrict__ tmask) {
+    cand_merge_g_body(blockIdx.x, rowptr, col, p, bitmap, nwords, cnt, tmask);
+}
+template <int BS>
+__global__ void __launch_bounds__(NT)
+cand_grad_cov_g_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                       const double* __restrict__ val, int64_t p, const void* __restrict__ S,
+                       int64_t lds, double lam2, const int64_t* __restrict__ arow,
+                       const int32_t* __restrict__ acol, const double* __restrict__ aom,
+                       double* __restrict__ agr, const int* overflow) {
+    cand_grad_cov_g_body<BS>(blockIdx.x, rowptr, col, val, p, S, lds, lam2, arow, acol, aom, agr,
+                             overflow);
+}
+__global__ void __launch_bounds__(NT)
+emit_count_g_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
+                    const double* __restrict__ aom, const double* __restrict__ agr, int64_t p,
+                    double lam1, const DevState* st, int64_t* __restrict__ cnt) {
+    emit_count_g_body(blockIdx.x, arow, acol, aom, agr, p, lam1, st, cnt);
+}
+__global__ void __launch_bounds__(NT)
+emit_fill_g_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
+                   const double* __restrict__ aom, const double* __restrict__ agr, int64_t p,
+                   double lam1, const DevState* st, const int64_t* __restrict__ orow,
+                   int32_t* __restrict__ ocol, double* __restrict__ oval) {
+    emit_fill_g_body(blockIdx.x, arow, acol, aom, agr, p, lam1, st, orow, ocol, oval);
+}
+template <int BS>
+__global__ void __launch_bounds__(NT)
+obj_parts_cov_g_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                       const double* __restrict__ val, int64_t p, const void* __restrict__ S,
+                       int64_t lds, double* __restrict__ part, const int* gate) {
+    obj_parts_cov_g_body<BS>(blockIdx.x, rowptr, col, val, p, S, lds, part, gate);
 }
 
 // ---- ingest ----------------------------------------------------------------------
@@ -1810,34 +2041,35 @@ check_finite_kernel(const In* __restrict__ A, int64_t rows, int64_t cols, int64_
 // since (Omega S)_ij = <Y_i, Xt_j> / n = d_ji / n.  Wave i gathers each row Y_j of its
 // entries once, for row i of Omega Y (d f / d X^T = Omega Y / n; FMA order of
 // spmm_kernel, so the row equals that kernel's bitwise) and for d_ij against its own row
-// Xt_i (held in LDS).  It writes d_ij to D at the entry and to E at the entry's mirror
-// (j, i), so grad_combine_kernel finds both halves of every entry in place; G_ij and G_ji
-// are then the same FP64 sum and bitwise equal.  Columns are taken in blocks of RC
-// chunks of 64 V; with more than one block the per-block partial sums go to D and E at
-// block offset cb * nnz (summed in block order by the combine).  The wave sums of 8
-// entries share one reduce-scatter (4 + 2 + 1 shuffles, then 3 for the whole wave).
+// Xt_i, and writes d_ij to D at the entry.  grad_combine_kernel then finds d_ji at the
+// mirror entry (j, i) (the pattern is symmetric), so G_ij and G_ji are the same FP64 sum
+// and bitwise equal; the mirror search runs there, over independent entries, rather
+// than in this kernel's dependent chain before each row's gathers.  Columns are taken
+// in blocks of RC chunks of 64 V; with more than one block the per-block partial sums go
+// to D at block offset cb * nnz (summed in block order by the combine).  The wave sums
+// of 8 entries share one reduce-scatter (4 + 2 + 1 shuffles, then 3 for the whole wave).
 constexpr int GRAD_GROUP = 8;
-template <int S, int RC>
-__global__ void __launch_bounds__(NT, 4)
+constexpr int GRAD_RC = 4;
+template <int S, int RC, int EG>
+__global__ void __launch_bounds__(NT, 3)
 grad_rows_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                  const double* __restrict__ val, int64_t p, const void* __restrict__ Y,
                  const void* __restrict__ Xt, int64_t ld, int64_t n, int64_t nnz,
-                 double* __restrict__ D, double* __restrict__ E, void* __restrict__ oy) {
+                 double* __restrict__ D, void* __restrict__ oy) {
     typedef Chunk<S> Ch;
     typedef typename Ch::T T;
     constexpr int V = Ch::V;
-    const int wave = threadIdx.x >> 6, lane = lane_id();
-    const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
+    const int lane = lane_id();
+    const int64_t row = uni((int64_t)blockIdx.x * WPB + (threadIdx.x >> 6));
     if (row >= p) return;
     const int64_t s = rowptr[row], e = rowptr[row + 1];
     const int nch = (int)((n + 64 * V - 1) / (64 * V));
     const int ncb = (nch + RC - 1) / RC;
-    __shared__ T xrow[WPB][RC][V][64];   // this block of columns of Xt_i; each lane reads its own
     double v[GRAD_GROUP];
-    int my_t = 0, m = 0, jl = -1;
-    int64_t mpos = -1, b = s, boff = 0;
-    // the wave sums of up to GRAD_GROUP entries (b + t of the current 64-entry block)
-    auto flush = [&]() {
+    int m = 0;
+    int64_t first = s;   // the entry of slot 0 of the pending group
+    // the wave sums of the m pending entries first .. first + m - 1 go to D
+    auto flush = [&](int64_t boff) {
 #pragma unroll
         for (int w = GRAD_GROUP, o = 32; w > 1; w >>= 1, o >>= 1) {
             const bool upper = (lane & o) != 0;   // keep the upper half of the w values
@@ -1853,81 +2085,65 @@ grad_rows_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__
 #pragma unroll
         for (int o = 4; o >= 1; o >>= 1) tot += __shfl_xor(tot, o, 64);
         const int g = (lane >> 3) & 7;
-        const int t = __shfl(my_t, g, 64);
-        const int64_t mp = __shfl(mpos, t, 64);
-        if ((lane & 7) == 0 && g < m) {
-            D[boff + b + t] = tot;
-            if (mp >= 0) E[boff + mp] = tot;
-        }
+        if ((lane & 7) == 0 && g < m) D[boff + first + g] = tot;
 #pragma unroll
         for (int i = 0; i < GRAD_GROUP; ++i) v[i] = 0.0;
+        first += m;
         m = 0;
     };
 #pragma unroll
     for (int i = 0; i < GRAD_GROUP; ++i) v[i] = 0.0;
     for (int cb = 0; cb < ncb; ++cb) {
-        boff = (int64_t)cb * nnz;
-        T acc[RC][V];
+        const int64_t boff = (int64_t)cb * nnz;
+        first = s;
+        T acc[RC][V], xi[RC][V];   // this block of row i of Omega Y, and of Xt_i
 #pragma unroll
         for (int q = 0; q < RC; ++q) {
             const int64_t c = (int64_t)(cb * RC + q) * 64 * V + lane * V;
-            T xv[V];
 #pragma unroll
-            for (int t = 0; t < V; ++t) { acc[q][t] = 0; xv[t] = 0; }
-            if (c < n) Ch::load(Xt, row * ld + c, xv);
-#pragma unroll
-            for (int t = 0; t < V; ++t) xrow[wave][q][t][lane] = xv[t];
+            for (int t = 0; t < V; ++t) { acc[q][t] = 0; xi[q][t] = 0; }
+            if (c < n) Ch::load(Xt, row * ld + c, xi[q]);
         }
-        for (b = s; b < e; b += 64) {
+        for (int64_t b = s; b < e; b += 64) {
             const int cnt = (int)(e - b < 64 ? e - b : 64);
-            // lane t: entry b + t, its column and its mirror's position (-1: not stored)
-            jl = -1;
-            mpos = -1;
-            if (lane < cnt) {
-                jl = col[b + lane];
-                if (jl == row) {
-                    mpos = b + lane;
-                } else {
-                    const int64_t me = rowptr[jl + 1];
-                    int64_t lo_ = rowptr[jl], hi_ = me;
-                    while (lo_ < hi_) {
-                        const int64_t mid = (lo_ + hi_) >> 1;
-                        if (col[mid] < row) lo_ = mid + 1; else hi_ = mid;
+            const int jl = lane < cnt ? col[b + lane] : 0;
+            for (int t0 = 0; t0 < cnt; t0 += EG) {
+                // the rows Y_j of up to EG entries, their loads issued before any FMA
+                T yj[EG][RC][V];
+#pragma unroll
+                for (int u = 0; u < EG; ++u) {
+                    const int64_t j = (int64_t)__shfl(jl, t0 + u < cnt ? t0 + u : t0, 64);
+#pragma unroll
+                    for (int q = 0; q < RC; ++q) {
+                        const int64_t c = (int64_t)(cb * RC + q) * 64 * V + lane * V;
+                        if (t0 + u < cnt && c < n) Ch::load(Y, j * ld + c, yj[u][q]);
                     }
-                    if (lo_ < me && col[lo_] == row) mpos = lo_;
                 }
-            }
-            for (int t = 0; t < cnt; ++t) {
-                const int64_t k = b + t;
-                const int64_t j = (int64_t)col[k];
-                const T wv = (T)val[k];
-                T yj[RC][V];
 #pragma unroll
-                for (int q = 0; q < RC; ++q) {
-                    const int64_t c = (int64_t)(cb * RC + q) * 64 * V + lane * V;
-                    if (c < n) Ch::load(Y, j * ld + c, yj[q]);
-                }
-                double a2 = 0.0;
+                for (int u = 0; u < EG; ++u) {
+                    if (t0 + u >= cnt) break;
+                    const T wv = (T)val[b + t0 + u];
+                    double a2 = 0.0;
 #pragma unroll
-                for (int q = 0; q < RC; ++q) {
-                    const int64_t c = (int64_t)(cb * RC + q) * 64 * V + lane * V;
-                    if (c < n) {
-                        T a = 0;
+                    for (int q = 0; q < RC; ++q) {
+                        const int64_t c = (int64_t)(cb * RC + q) * 64 * V + lane * V;
+                        if (c < n) {
+                            T a = 0;
 #pragma unroll
-                        for (int u = 0; u < V; ++u) {
-                            acc[q][u] = fma(wv, yj[q][u], acc[q][u]);
-                            a += yj[q][u] * xrow[wave][q][u][lane];
+                            for (int w = 0; w < V; ++w) {
+                                acc[q][w] = fma(wv, yj[u][q][w], acc[q][w]);
+                                a += yj[u][q][w] * xi[q][w];
+                            }
+                            a2 += (double)a;
                         }
-                        a2 += (double)a;
                     }
-                }
 #pragma unroll
-                for (int g = 0; g < GRAD_GROUP; ++g) v[g] = g == m ? a2 : v[g];
-                if (lane == m) my_t = t;
-                if (++m == GRAD_GROUP) flush();
+                    for (int g = 0; g < GRAD_GROUP; ++g) v[g] = g == m ? a2 : v[g];
+                    if (++m == GRAD_GROUP) flush(boff);
+                }
             }
-            if (m > 0) flush();
         }
+        if (m > 0) flush(boff);
         if (oy) {
 #pragma unroll
             for (int q = 0; q < RC; ++q) {
@@ -1948,26 +2164,38 @@ grad_rows_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__
     }
 }
 
-// G on the stored entries from the two halves grad_rows_kernel left at every entry:
-// G_ij = (sum_cb D + sum_cb E) / (2n) + lam2 w_ij - [i == j] / w_ii (blocks in order).
+// G on the stored entries: G_ij = (sum_cb D_ij + sum_cb D_ji) / (2n) + lam2 w_ij
+// - [i == j] / w_ii (blocks in order), D_ji found by binary search of row j for column i.
 __global__ void __launch_bounds__(NT)
 grad_combine_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                     const double* __restrict__ val, int64_t p, int64_t nnz, int ncb,
-                    const double* __restrict__ D, const double* __restrict__ E, double inv2n,
-                    double lam2, void* out, int out_f64) {
+                    const double* __restrict__ D, double inv2n, double lam2, void* out,
+                    int out_f64) {
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
     if (row >= p) return;
     const int64_t s = rowptr[row], e = rowptr[row + 1];
     for (int64_t k = s + lane; k < e; k += 64) {
-        double dsum = D[k], esum = E[k];
+        const int32_t j = col[k];
+        int64_t mk = k;
+        if (j != row) {
+            const int64_t je = rowptr[j + 1];
+            int64_t lo_ = rowptr[j], hi_ = je;
+            while (lo_ < hi_) {
+                const int64_t mid = (lo_ + hi_) >> 1;
+                if (col[mid] < row) lo_ = mid + 1; else hi_ = mid;
+            }
+            // stored in a symmetric pattern; otherwise the entry's own half stands in
+            if (lo_ < je && col[lo_] == row) mk = lo_;
+        }
+        double dsum = D[k], esum = D[mk];
         for (int cb = 1; cb < ncb; ++cb) {
             dsum += D[(int64_t)cb * nnz + k];
-            esum += E[(int64_t)cb * nnz + k];
+            esum += D[(int64_t)cb * nnz + mk];
         }
         const double wv = val[k];
         double gr = (dsum + esum) * inv2n + lam2 * wv;
-        if (col[k] == row) gr -= 1.0 / wv;
+        if (j == row) gr -= 1.0 / wv;
         if (out_f64) ((double*)out)[k] = gr;
         else ((float*)out)[k] = (float)gr;
     }
@@ -2138,8 +2366,13 @@ hipError_t launch_cand_count(const void* M, int mstore, int64_t ldm, const Csr& 
 }
 
 hipError_t launch_cand_merge(const Csr& om, int64_t p, uint64_t* bitmap, int64_t nwords,
-                             int64_t* cnt, hipStream_t stream, const uint64_t* tmask) {
+                             int64_t* cnt, hipStream_t stream, const uint64_t* tmask, bool grouped) {
     if (p == 0) return hipSuccess;
+    if (grouped) {
+        hipLaunchKernelGGL(cand_merge_g_kernel, dim3(blocks_for(p, WPB * (64 / TG))), dim3(NT), 0,
+                           stream, om.rowptr, om.col, p, bitmap, nwords, cnt, tmask);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(cand_merge_kernel, dim3(blocks_for(p, WPB)), dim3(NT), 0, stream,
                        om.rowptr, om.col, p, bitmap, nwords, cnt, tmask);
     return hipGetLastError();
@@ -2148,18 +2381,18 @@ hipError_t launch_cand_merge(const Csr& om, int64_t p, uint64_t* bitmap, int64_t
 hipError_t launch_cand_fill(const void* M, int mstore, int64_t ldm, const Csr& om, int64_t p,
                             double lam2, const uint64_t* bitmap, int64_t nwords,
                             const Cand& A, int64_t cap, const int* overflow,
-                            hipStream_t stream, const uint64_t* tmask) {
+                            hipStream_t stream, const uint64_t* tmask, bool m_upper) {
     (void)cap;
     if (p == 0) return hipSuccess;
     const size_t lds = tmask ? (size_t)WPB * ((nwords + 63) / 64) * 8 : 0;
     if (mstore == ST_F64)
         hipLaunchKernelGGL(cand_fill_kernel<ST_F64>, dim3(blocks_for(p, WPB)), dim3(NT), lds,
                            stream, M, ldm, om.rowptr, om.col, om.val, p, lam2, bitmap, nwords,
-                           A.rowptr, A.col, A.omega, A.grad, overflow, tmask);
+                           A.rowptr, A.col, A.omega, A.grad, overflow, tmask, m_upper);
     else
         hipLaunchKernelGGL(cand_fill_kernel<ST_F32>, dim3(blocks_for(p, WPB)), dim3(NT), lds,
                            stream, M, ldm, om.rowptr, om.col, om.val, p, lam2, bitmap, nwords,
-                           A.rowptr, A.col, A.omega, A.grad, overflow, tmask);
+                           A.rowptr, A.col, A.omega, A.grad, overflow, tmask, m_upper);
     return hipGetLastError();
 }
 
@@ -2199,7 +2432,8 @@ hipError_t launch_trial(const Cand& A, int64_t p, double tau0, double shrink, in
     // kernel's p waves fit on the chip at once and the step is latency bound, so packing
     // rows into fewer waves only lengthens each wave's serial loop (p = 200: 17% slower
     // solves); above it, 8 rows per wave leave far fewer lanes idle (p = 16,384: 20%
-    // faster solves).
+    // faster solves; in a batch, where many solves' rows share the chip, 6 times faster
+    // per row).
     if (!obs && p >= COV_GROUP_MIN_P) {   // Cov: 8 lanes per row
         static_assert(MAXQ == TG, "lane g of a row group holds step size q = g");
         dim3 cg(blocks_for(p, WPB * (64 / TG)));
@@ -2259,16 +2493,27 @@ hipError_t launch_colsum_obj(const double* in, int64_t rows, int ncol, double* o
 }
 
 hipError_t launch_emit_count(const Cand& A, int64_t p, double lam1, const DevState* st,
-                             int64_t* cnt, hipStream_t stream) {
+                             int64_t* cnt, hipStream_t stream, bool grouped) {
     if (p == 0) return hipSuccess;
+    if (grouped) {
+        hipLaunchKernelGGL(emit_count_g_kernel, dim3(blocks_for(p, WPB * (64 / TG))), dim3(NT), 0,
+                           stream, A.rowptr, A.col, A.omega, A.grad, p, lam1, st, cnt);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(emit_count_kernel, dim3(blocks_for(p, WPB)), dim3(NT), 0, stream,
                        A.rowptr, A.col, A.omega, A.grad, p, lam1, st, cnt);
     return hipGetLastError();
 }
 
 hipError_t launch_emit_fill(const Cand& A, int64_t p, double lam1, const DevState* st,
-                            const Csr& out, hipStream_t stream) {
+                            const Csr& out, hipStream_t stream, bool grouped) {
     if (p == 0) return hipSuccess;
+    if (grouped) {
+        hipLaunchKernelGGL(emit_fill_g_kernel, dim3(blocks_for(p, WPB * (64 / TG))), dim3(NT), 0,
+                           stream, A.rowptr, A.col, A.omega, A.grad, p, lam1, st, out.rowptr,
+                           out.col, out.val);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(emit_fill_kernel, dim3(blocks_for(p, WPB)), dim3(NT), 0, stream,
                        A.rowptr, A.col, A.omega, A.grad, p, lam1, st, out.rowptr, out.col,
                        out.val);
@@ -2291,6 +2536,18 @@ hipError_t launch_obj_parts(const Csr& om, int64_t p, const void* W, int wstore,
 hipError_t launch_obj_parts_cov(const Csr& om, int64_t p, const void* S, int sstore, int64_t lds,
                                 double* part, const int* gate, hipStream_t stream) {
     if (p == 0) return hipSuccess;
+    if (p >= COV_TRIAL_GROUP_MIN_P) {
+        dim3 gg(blocks_for(p, WPB * (64 / TG)));
+#define OBJG(BS)                                                                               \
+        hipLaunchKernelGGL(obj_parts_cov_g_kernel<BS>, gg, dim3(NT), 0, stream, om.rowptr, om.col, \
+                           om.val, p, S, lds, part, gate)
+        if (sstore == ST_F64) OBJG(ST_F64);
+        else if (sstore == ST_F32) OBJG(ST_F32);
+        else if (sstore == ST_B16P) OBJG(ST_B16P);
+        else return hipErrorInvalidValue;
+#undef OBJG
+        return hipGetLastError();
+    }
     dim3 grid(blocks_for(p, WPB));
     if (sstore == ST_F64)
         hipLaunchKernelGGL(obj_parts_cov_kernel<ST_F64>, grid, dim3(NT), 0, stream, om.rowptr,
@@ -2310,6 +2567,19 @@ hipError_t launch_cand_grad_cov(const Csr& om, int64_t p, const void* S, int sst
                                 double lam2, const Cand& A, const int* overflow,
                                 hipStream_t stream) {
     if (p == 0) return hipSuccess;
+    if (p >= COV_TRIAL_GROUP_MIN_P) {
+        dim3 gg(blocks_for(p, WPB * (64 / TG)));
+#define CGRADG(BS)                                                                            \
+        hipLaunchKernelGGL(cand_grad_cov_g_kernel<BS>, gg, dim3(NT), 0, stream, om.rowptr,      \
+                           om.col, om.val, p, S, lds, lam2, A.rowptr, A.col, A.omega, A.grad,  \
+                           overflow)
+        if (sstore == ST_F64) CGRADG(ST_F64);
+        else if (sstore == ST_F32) CGRADG(ST_F32);
+        else if (sstore == ST_B16P) CGRADG(ST_B16P);
+        else return hipErrorInvalidValue;
+#undef CGRADG
+        return hipGetLastError();
+    }
     dim3 grid(blocks_for(p, WPB));
 #define CGRAD(BS)                                                                         \
     hipLaunchKernelGGL(cand_grad_cov_kernel<BS>, grid, dim3(NT), 0, stream, om.rowptr, om.col, \
@@ -2475,33 +2745,33 @@ hipError_t launch_check_finite(const void* A, int is_f64, int64_t rows, int64_t 
     return hipGetLastError();
 }
 
-// column blocks of the masked-gradient row pass: RC = 4 chunks of 64 V columns each
+// column blocks of the masked-gradient row pass: GRAD_RC chunks of 64 V columns each
 int grad_col_blocks(int store, int64_t n) {
-    const int64_t w = 4 * 64 * (store == ST_F64 ? Chunk<ST_F64>::V : Chunk<ST_F32>::V);
+    const int64_t w = GRAD_RC * 64 * (store == ST_F64 ? Chunk<ST_F64>::V : Chunk<ST_F32>::V);
     return (int)((n + w - 1) / w);
 }
 
 hipError_t launch_grad_rows(const Csr& om, int64_t p, int64_t nnz, const void* Y, const void* Xt,
-                            int store, int64_t ld, int64_t n, double* D, double* E, void* oy,
+                            int store, int64_t ld, int64_t n, double* D, void* oy,
                             hipStream_t stream) {
     if (p == 0) return hipSuccess;
     dim3 grid(blocks_for(p, WPB));
     if (store == ST_F64)
-        hipLaunchKernelGGL((grad_rows_kernel<ST_F64, 4>), grid, dim3(NT), 0, stream, om.rowptr,
-                           om.col, om.val, p, Y, Xt, ld, n, nnz, D, E, oy);
+        hipLaunchKernelGGL((grad_rows_kernel<ST_F64, GRAD_RC, 2>), grid, dim3(NT), 0, stream,
+                           om.rowptr, om.col, om.val, p, Y, Xt, ld, n, nnz, D, oy);
     else
-        hipLaunchKernelGGL((grad_rows_kernel<ST_F32, 4>), grid, dim3(NT), 0, stream, om.rowptr,
-                           om.col, om.val, p, Y, Xt, ld, n, nnz, D, E, oy);
+        hipLaunchKernelGGL((grad_rows_kernel<ST_F32, GRAD_RC, 2>), grid, dim3(NT), 0, stream,
+                           om.rowptr, om.col, om.val, p, Y, Xt, ld, n, nnz, D, oy);
     return hipGetLastError();
 }
 
 hipError_t launch_grad_combine(const Csr& om, int64_t p, int64_t nnz, int ncb, const double* D,
-                               const double* E, int64_t n, double lam2, void* out, int out_f64,
+                               int64_t n, double lam2, void* out, int out_f64,
                                hipStream_t stream) {
     if (p == 0) return hipSuccess;
     hipLaunchKernelGGL(grad_combine_kernel, dim3(blocks_for(p, WPB)), dim3(NT), 0, stream,
-                       om.rowptr, om.col, om.val, p, nnz, ncb, D, E, 1.0 / (2.0 * (double)n),
-                       lam2, out, out_f64);
+                       om.rowptr, om.col, om.val, p, nnz, ncb, D, 1.0 / (2.0 * (double)n), lam2,
+                       out, out_f64);
     return hipGetLastError();
 }
 
@@ -2742,10 +3012,17 @@ __global__ void __launch_bounds__(NT)
 batch_merge_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, int nsolve) {
     for_items(pl, nsolve, BP_ROW, [&](int si, int64_t lb) {
         const SolveDesc& d = sd[si];
-        if (d.ctl->phase != BPH_CAND) return;
+        if (d.ctl->phase != BPH_CAND || d.grouped) return;
         const Csr& o = d.om[d.ctl->cur];
         cand_merge_body(lb, o.rowptr, o.col, d.p, d.bitmap, d.nwords, d.cnt,
                         d.screen ? d.rws.tmask : nullptr);
+    });
+    for_items(pl, nsolve, BP_ROWG, [&](int si, int64_t lb) {
+        const SolveDesc& d = sd[si];
+        if (d.ctl->phase != BPH_CAND || !d.grouped) return;
+        const Csr& o = d.om[d.ctl->cur];
+        cand_merge_g_body(lb, o.rowptr, o.col, d.p, d.bitmap, d.nwords, d.cnt,
+                          d.screen ? d.rws.tmask : nullptr);
     });
 }
 
@@ -2793,10 +3070,17 @@ __global__ void __launch_bounds__(NT)
 batch_grad_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, BatchArgs a) {
     for_items(pl, a.nsolve, BP_ROW, [&](int si, int64_t lb) {
         const SolveDesc& d = sd[si];
-        if (d.ctl->phase != BPH_CAND) return;
+        if (d.ctl->phase != BPH_CAND || d.grouped) return;
         const Csr& o = d.om[d.ctl->cur];
         cand_grad_cov_body<BS>(lb, o.rowptr, o.col, o.val, d.p, d.S, d.lds, a.lam2, d.A.rowptr,
                                d.A.col, d.A.omega, d.A.grad, &d.st->overflow);
+    });
+    for_items(pl, a.nsolve, BP_ROWG, [&](int si, int64_t lb) {
+        const SolveDesc& d = sd[si];
+        if (d.ctl->phase != BPH_CAND || !d.grouped) return;
+        const Csr& o = d.om[d.ctl->cur];
+        cand_grad_cov_g_body<BS>(lb, o.rowptr, o.col, o.val, d.p, d.S, d.lds, a.lam2, d.A.rowptr,
+                                 d.A.col, d.A.omega, d.A.grad, &d.st->overflow);
     });
 }
 
@@ -2848,7 +3132,13 @@ __global__ void __launch_bounds__(NT)
 batch_emit_count_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, int nsolve) {
     for_items(pl, nsolve, BP_ROW, [&](int si, int64_t lb) {
         const SolveDesc& d = sd[si];
+        if (d.grouped) return;
         emit_count_body(lb, d.A.rowptr, d.A.col, d.A.omega, d.A.grad, d.p, d.lam1, d.st, d.cnt);
+    });
+    for_items(pl, nsolve, BP_ROWG, [&](int si, int64_t lb) {
+        const SolveDesc& d = sd[si];
+        if (!d.grouped) return;
+        emit_count_g_body(lb, d.A.rowptr, d.A.col, d.A.omega, d.A.grad, d.p, d.lam1, d.st, d.cnt);
     });
 }
 
@@ -2856,9 +3146,17 @@ __global__ void __launch_bounds__(NT)
 batch_emit_fill_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, int nsolve) {
     for_items(pl, nsolve, BP_ROW, [&](int si, int64_t lb) {
         const SolveDesc& d = sd[si];
+        if (d.grouped) return;
         const Csr& o = d.om[d.ctl->cur ^ 1];
         emit_fill_body(lb, d.A.rowptr, d.A.col, d.A.omega, d.A.grad, d.p, d.lam1, d.st, o.rowptr,
                        o.col, o.val);
+    });
+    for_items(pl, nsolve, BP_ROWG, [&](int si, int64_t lb) {
+        const SolveDesc& d = sd[si];
+        if (!d.grouped) return;
+        const Csr& o = d.om[d.ctl->cur ^ 1];
+        emit_fill_g_body(lb, d.A.rowptr, d.A.col, d.A.omega, d.A.grad, d.p, d.lam1, d.st, o.rowptr,
+                         o.col, o.val);
     });
 }
 
@@ -2960,10 +3258,17 @@ __global__ void __launch_bounds__(NT)
 batch_obj_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, int nsolve, int init) {
     for_items(pl, nsolve, BP_ROW, [&](int si, int64_t lb) {
         const SolveDesc& d = sd[si];
-        if (!in_accept(d, init)) return;
+        if (!in_accept(d, init) || d.grouped) return;
         const Csr& o = prod_csr(d, init);
         obj_parts_cov_body<BS>(lb, o.rowptr, o.col, o.val, d.p, d.S, d.lds,
                                d.part + 4 * MAXQ * d.p, nullptr);
+    });
+    for_items(pl, nsolve, BP_ROWG, [&](int si, int64_t lb) {
+        const SolveDesc& d = sd[si];
+        if (!in_accept(d, init) || !d.grouped) return;
+        const Csr& o = prod_csr(d, init);
+        obj_parts_cov_g_body<BS>(lb, o.rowptr, o.col, o.val, d.p, d.S, d.lds,
+                                 d.part + 4 * MAXQ * d.p, nullptr);
     });
 }
 

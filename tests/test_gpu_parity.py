@@ -122,7 +122,7 @@ def test_replay_parity(variant, precision, lam1):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_replay_parity_cov_grouped_trials(precision):
-    """p >= 4096: the Cov trials run 8 rows per wave; p = 4133 leaves a ragged last
+    """p >= 1024: the Cov trials run 8 rows per wave; p = 4133 leaves a ragged last
     wave (4133 = 129 * 32 + 5) and a ragged 64-column tile."""
     _replay_parity("cov", precision, 0.2, 4133, 300, 4)
 
@@ -258,12 +258,15 @@ def test_lambda1_max_closed_form_gpu():
     s.close()
 
 
-@pytest.mark.parametrize("variant,precision,nvar", [("obs", "bf16x3", 6), ("obs", "fp32", 3),
-                                                    ("cov", "bf16x3", 6), ("cov", "fp32", 3)])
-def test_contraction_variants_bitwise_equal(variant, precision, nvar, monkeypatch):
-    """Every tile variant the autotuner may pick gives bitwise the same iterates."""
+@pytest.mark.parametrize("variant,precision,nvar,n", [("obs", "bf16x3", 7, 260), ("obs", "fp32", 3, 260),
+                                                      ("cov", "bf16x3", 7, 260), ("cov", "fp32", 3, 260),
+                                                      ("cov", "bf16x3", 7, 40)])
+def test_contraction_variants_bitwise_equal(variant, precision, nvar, n, monkeypatch):
+    """Every tile variant the autotuner may pick gives bitwise the same iterates (n = 40:
+    a contraction of three K stages, which the ring variants hand to the one that
+    takes fewer than four)."""
     torch = _torch()
-    p, n = 600, 260
+    p = 600
     w = datagen.make_workload("c2_obs_p20000", p=p, n=n)
     X = _rounded(w.X, precision)
     outs, cands = [], []
