@@ -492,43 +492,50 @@ def bench_c5(args, torch, np, datagen):
 
 def bench_c4(args, torch, np, datagen):
     """Batched lambda path: 48 Cov instances (p in {1k, 2k, 4k, 8k}, n = p/2), each
-    solved at lambda1 in {0.2, 0.3, 0.5} from Omega = I (FP32 products, FP64
-    reductions, stop at relative F change < 1e-5 or 200 iterations), all 144 solves on
-    the device at once (graph replays of 4 iterations, device-side control).  A step is
-    one whole path from the data (S formation included); value = solves per second."""
+    solved at lambda1 in {0.2, 0.3, 0.5} from Omega = I (FP64 reductions, stop at
+    relative F change < 1e-5 or 200 iterations), all 144 solves on the device at once
+    (graph replays of 4 iterations, device-side control).  A step is one whole path from
+    the data (S formation included); value = solves per second with the BF16 split
+    products (the FP32 form beside it)."""
     from paper_1710_10769_amd import Batch
     l1s, lam2 = datagen.lambda_path_c4()
     log("generating 48 instances")
     inst = datagen.c4_instances(backend="torch", device="cuda")
     Xs = [torch.from_numpy(X.astype(np.float32)).cuda() for _, X, _ in inst]
     torch.cuda.synchronize()
-    times = []
-    iters = None
-    stats = None
-    for rep in range(args.warmup + args.steps):
-        b = Batch(Xs, l1s, iters_per_launch=args.iters_per_launch)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        iters, Fs, rc = b.solve(lam2, 1e-5, 200)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        stats = b.stats()
-        b.close()
-        if rep >= args.warmup:
-            times.append(t1 - t0)
-        log(f"path {rep}: {t1 - t0:.4f} s (S {stats['s_ms']:.1f} ms, iterations "
-            f"{stats['iterate_ms']:.1f} ms, {stats['launches']} replays), max iterations {max(iters)}")
-    sec = float(np.mean(times))
     nsolve = len(inst) * len(l1s)
+    res = {}
+    for form in args.c4_forms.split(","):
+        times = []
+        iters = None
+        stats = None
+        for rep in range(args.warmup + args.steps):
+            b = Batch(Xs, l1s, precision=form, iters_per_launch=args.iters_per_launch)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            iters, Fs, rc = b.solve(lam2, 1e-5, 200)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            stats = b.stats()
+            b.close()
+            if rep >= args.warmup:
+                times.append(t1 - t0)
+            log(f"{form} path {rep}: {t1 - t0:.4f} s (S {stats['s_ms']:.1f} ms, iterations "
+                f"{stats['iterate_ms']:.1f} ms, {stats['launches']} replays), max iterations {max(iters)}")
+        sec = float(np.mean(times))
+        res[form] = {"value": nsolve / sec, "ms_per_step": sec * 1e3,
+                     "mean_iterations": float(np.mean(iters)), "max_iterations": int(max(iters)),
+                     "total_iterations": int(np.sum(iters)), "last_path": stats}
+    head = list(res)[0]
     line = {
         "metric": "batched lambda-path solves/sec (48 Cov instances x 3 lambda1)",
-        "value": nsolve / sec, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "value": res[head]["value"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res[head]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": head, "data": "synthetic",
         "config": {"workload": "cov_batched_lambda_path_48x3", "instances": len(inst),
                    "p": [p for p, _, _ in inst], "lambda1": list(l1s), "lam2": lam2},
-        "mean_iterations": float(np.mean(iters)), "max_iterations": int(max(iters)),
-        "total_iterations": int(np.sum(iters)), "last_path": stats,
+        **{k: v for k, v in res[head].items() if k not in ("value", "ms_per_step")},
+        "other_forms": {k: v for k, v in res.items() if k != head},
     }
     print(json.dumps(line), flush=True)
 
@@ -539,6 +546,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--forms", default="bf16x3,fp32")
+    ap.add_argument("--c4-forms", default="bf16x3,fp32",
+                    help="c4: precision forms, the first one is the line's value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cov-context", action="store_true",
                     help="skip timing the Cov form on the same problem")

@@ -345,7 +345,8 @@ int concord_gradient(concord_ctx* ctx, double lambda2, int32_t mode, void* dev_d
    its shape) by the first concord_batch_solve and kept for later calls. */
 typedef struct concord_batch concord_batch;
 typedef struct concord_batch_config {
-    int32_t precision;        /* CONCORD_FP32 (default) or CONCORD_FP64 products */
+    int32_t precision;        /* CONCORD_FP32 (default), CONCORD_FP64 or CONCORD_BF16X3 products
+                                 (as concord_config.precision in the Cov form) */
     int32_t device;           /* -1 = the current device */
     void*   stream;           /* hipStream_t; NULL = null stream */
     int32_t max_backtracks;   /* 60 */

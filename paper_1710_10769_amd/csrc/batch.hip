@@ -131,14 +131,28 @@ int64_t tiles(int64_t p) { return (p + 63) / 64; }
 int form_s(concord_batch* b) {
     const auto t0 = std::chrono::steady_clock::now();
     const size_t eb = b->dstore == ST_F64 ? 8 : 4;
-    size_t xt_bytes = 0;
+    const bool split = b->gkind == GK_BF16X3;   // BF16 hi/lo planes of X^T for the product
+    size_t xt_elems = 0;
     for (int i = 0; i < b->count; ++i)
-        xt_bytes = std::max(xt_bytes, (size_t)round_up(b->p[i], ROW_PAD) *
-                                          (size_t)round_up(b->n[i], K_PAD) * eb);
+        xt_elems = std::max(xt_elems, (size_t)round_up(b->p[i], ROW_PAD) *
+                                          (size_t)round_up(b->n[i], K_PAD));
     void* xt[NSIDE] = {};
+    void* xh[NSIDE] = {};
+    void* xl[NSIDE] = {};
+    auto release = [&]() {
+        for (int s = 0; s < NSIDE; ++s) {
+            bfree(b, xt[s]);
+            bfree(b, xh[s]);
+            bfree(b, xl[s]);
+        }
+    };
     int rc;
     for (int s = 0; s < NSIDE; ++s)
-        if ((rc = balloc(b, &xt[s], xt_bytes))) return rc;
+        if ((rc = balloc(b, &xt[s], xt_elems * eb)) ||
+            (split && ((rc = balloc(b, &xh[s], xt_elems * 2)) || (rc = balloc(b, &xl[s], xt_elems * 2))))) {
+            release();
+            return rc;
+        }
     std::vector<int> order(b->count);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return b->p[a] > b->p[c]; });
@@ -152,11 +166,18 @@ int form_s(concord_batch* b) {
         const int64_t ldk = round_up(n, K_PAD), prow = round_up(p, ROW_PAD);
         const InstDesc& id = b->hid[i];
         const SolveDesc& d0 = b->hsd[id.first];
-        BHIP(b, hipMemsetAsync(xt[s], 0, (size_t)prow * ldk * eb, st));
+        const size_t ne = (size_t)prow * ldk;
+        BHIP(b, hipMemsetAsync(xt[s], 0, ne * eb, st));
+        if (split) {
+            BHIP(b, hipMemsetAsync(xh[s], 0, ne * 2, st));
+            BHIP(b, hipMemsetAsync(xl[s], 0, ne * 2, st));
+        }
         BHIP(b, launch_transpose_in(b->X[i], b->dstore == ST_F64, n, p, b->ld[i], xt[s], b->dstore,
-                                    ldk, nullptr, nullptr, 0, b->dflag + s, st));
-        BHIP(b, launch_gemm_sym(b->gkind, false, xt[s], nullptr, nullptr, nullptr, ldk, p,
-                                1.0 / (double)n, const_cast<void*>(d0.S), b->sstore, d0.lds, st));
+                                    ldk, (uint16_t*)xh[s], (uint16_t*)xl[s], kblk_stride(prow),
+                                    b->dflag + s, st));
+        BHIP(b, launch_gemm_sym(b->gkind, false, split ? xh[s] : xt[s], split ? xl[s] : nullptr,
+                                nullptr, nullptr, ldk, p, 1.0 / (double)n,
+                                const_cast<void*>(d0.S), b->sstore, d0.lds, st));
         BHIP(b, launch_tile_max(d0.S, b->sstore, p, d0.lds, const_cast<double*>(d0.smax), st));
     }
     for (int s = 0; s < NSIDE; ++s) {
@@ -166,7 +187,7 @@ int form_s(concord_batch* b) {
     int hflag[NSIDE] = {};
     BHIP(b, hipMemcpyAsync(hflag, b->dflag, sizeof(hflag), hipMemcpyDeviceToHost, b->work));
     BHIP(b, hipStreamSynchronize(b->work));
-    for (int s = 0; s < NSIDE; ++s) bfree(b, xt[s]);
+    release();
     for (int s = 0; s < NSIDE; ++s)
         if (hflag[s]) return bfail(b, CONCORD_ENONFINITE, "data holds NaN or Inf");
     b->s_ready = true;
@@ -287,7 +308,9 @@ int concord_batch_create(const concord_batch_config* cfg_in, int32_t count, cons
     else concord_batch_config_init(&cfg);
     if (count < 1 || n_l1 < 1 || !host_p || !host_n || !host_dev_X || !host_ld || !host_lambda1)
         return CONCORD_EINVAL;
-    if (cfg.precision != CONCORD_FP32 && cfg.precision != CONCORD_FP64) return CONCORD_EINVAL;
+    if (cfg.precision != CONCORD_FP32 && cfg.precision != CONCORD_FP64 &&
+        cfg.precision != CONCORD_BF16X3)
+        return CONCORD_EINVAL;
     if (cfg.trial_batch < 1 || cfg.trial_batch > MAXQ_B || cfg.max_backtracks < 0 ||
         cfg.max_backtracks > 1000 || cfg.iters_per_launch < 1 || cfg.iters_per_launch > 64)
         return CONCORD_EINVAL;
@@ -330,9 +353,12 @@ int concord_batch_create(const concord_batch_config* cfg_in, int32_t count, cons
     b->count = count;
     b->n_l1 = n_l1;
     b->nsolve = count * n_l1;
+    // the single solver's stores: X^T in FP64 or FP32, S in FP64, FP32 or BF16 hi/lo pairs
     const bool f64 = cfg.precision == CONCORD_FP64;
-    b->sstore = b->dstore = f64 ? ST_F64 : ST_F32;
-    b->gkind = f64 ? GK_F64 : GK_F32;
+    const bool split = cfg.precision == CONCORD_BF16X3;
+    b->dstore = f64 ? ST_F64 : ST_F32;
+    b->sstore = f64 ? ST_F64 : (split ? ST_B16P : ST_F32);
+    b->gkind = f64 ? GK_F64 : (split ? GK_BF16X3 : GK_F32);
     b->p.assign(host_p, host_p + count);
     b->n.assign(host_n, host_n + count);
     b->ld.assign(host_ld, host_ld + count);

@@ -501,7 +501,7 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
         const uint64_t* tm = cov && screen_now(c) ? c->rws.tmask : nullptr;
         if (merge || cov)
             HIPCK(c, launch_cand_merge(c->om[c->cur], p, c->bitmap, c->nwords, c->cnt, c->stream,
-                                       tm, cov && p >= COV_TRIAL_GROUP_MIN_P));
+                                       tm));
         else
             HIPCK(c, launch_cand_count(c->M, c->dstore, c->ldp, c->om[c->cur], p, lam1,
                                        c->bitmap, c->nwords, c->cnt, c->stream));

@@ -121,8 +121,7 @@ struct Cand {
 // the words of kept tiles and the support's words are read; words outside both are stale
 // and never read.
 hipError_t launch_cand_merge(const Csr& om, int64_t p, uint64_t* bitmap, int64_t nwords,
-                             int64_t* cnt, hipStream_t stream, const uint64_t* tmask = nullptr,
-                             bool grouped = false);
+                             int64_t* cnt, hipStream_t stream, const uint64_t* tmask = nullptr);
 
 // Count pass: for every row, A_i = {j != i : |M_ij| > lam1} U supp(Omega_i) U {i}.
 // Writes the candidate bitmap (p x nwords64 uint64, row-major, word w bit b

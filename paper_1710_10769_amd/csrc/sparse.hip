@@ -649,6 +649,41 @@ __device__ __forceinline__ void trial_body(int64_t bx_, int split, int nsplit, c
             }
         }
         const int64_t cstep = (int64_t)nsplit * 64 * V;
+        if (cnt == 1) {
+            // one candidate (a row whose only candidate is the diagonal): one row of B,
+            // read PD chunks ahead (the two-chunk pipeline below keeps too few bytes in
+            // flight for a single row); the same products and sums in the same order
+            constexpr int PD = 8;
+            T b1[PD][V];
+            const int64_t c00 = (int64_t)split * 64 * V;
+#pragma unroll
+            for (int d = 0; d < PD; ++d) {
+                const int64_t c = c00 + d * cstep + lane * V;
+                if (c < ncols) Ch::load(B, rb[0] + c, b1[d]);
+                else {
+#pragma unroll
+                    for (int t = 0; t < V; ++t) b1[d][t] = 0;
+                }
+            }
+            for (int64_t c0 = c00; c0 < ncols; c0 += PD * cstep) {
+#pragma unroll
+                for (int d = 0; d < PD; ++d) {
+                    if (c0 + d * cstep >= ncols) break;
+#pragma unroll
+                    for (int q = 0; q < MAXQ; ++q) {
+                        if (q < m) {
+#pragma unroll
+                            for (int t = 0; t < V; ++t) {
+                                const T a = fma(dq[0][q], b1[d][t], (T)0);
+                                squad[q] += (double)a * (double)a;
+                            }
+                        }
+                    }
+                    const int64_t c = c0 + (d + PD) * cstep + lane * V;
+                    if (c < ncols) Ch::load(B, rb[0] + c, b1[d]);
+                }
+            }
+        } else {
         auto fetch = [&](int64_t c0, T (&b)[4][V]) {
             const int64_t c = c0 + lane * V;
 #pragma unroll
@@ -692,6 +727,7 @@ __device__ __forceinline__ void trial_body(int64_t bx_, int split, int nsplit, c
             for (int u = 0; u < 4; ++u)
 #pragma unroll
                 for (int t = 0; t < V; ++t) bc[u][t] = bn[u][t];
+        }
         }
     } else if (OBS) {
         // ||Delta_i X^T||^2 over n columns: lanes over columns, loop over entries
@@ -1637,15 +1673,17 @@ __device__ __forceinline__ void cand_merge_body(int64_t bx_, const int64_t* __re
         __builtin_amdgcn_s_waitcnt(0);
     }
     // the support bits go in by atomic OR on the few words they touch (the row's other
-    // words are only read); the count reads after every OR has completed, and after an
-    // acquire fence that drops the CU's L1 (another wave may have pulled a line shared
-    // with a neighbouring row into it before the ORs reached L2)
+    // words are only read); the count reads after every OR has completed, with loads that
+    // bypass the CU's L1 (another wave may have pulled a line shared with a neighbouring
+    // row into it before the ORs reached L2)
     for (int64_t k = s + lane; k < e; k += 64) {
         const int32_t c = col[k];
         atomicOr((unsigned long long*)&rw[c >> 6], 1ull << (c & 63));
     }
     __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    auto word = [&](int64_t w) {
+        return __hip_atomic_load(&rw[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
     int64_t total = extra;   // each such entry is one bit of a word counted nowhere else
     if (mrow) {
         // only the 64-word blocks whose mask word is nonzero: the mask row is read 64
@@ -1658,11 +1696,11 @@ __device__ __forceinline__ void cand_merge_body(int64_t bx_, const int64_t* __re
                 nz &= nz - 1ull;
                 const uint64_t mk = __shfl(mw, t, 64);
                 const int64_t w = (m0 + t) * 64 + lane;
-                if (w < nwords && ((mk >> lane) & 1ull)) total += __popcll(rw[w]);
+                if (w < nwords && ((mk >> lane) & 1ull)) total += __popcll(word(w));
             }
         }
     } else {
-        for (int64_t w = lane; w < nwords; w += 64) total += __popcll(rw[w]);
+        for (int64_t w = lane; w < nwords; w += 64) total += __popcll(word(w));
     }
     double tt = (double)total;
     tt = wave_sum(tt);
@@ -1680,11 +1718,13 @@ cand_merge_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict_
 // For Cov problems of at least COV_TRIAL_GROUP_MIN_P rows (the trials make the same
 // choice): a Cov row holds a few entries, so a wave per row leaves most lanes idle and,
 // with many rows, the kernels run latency bound with too few rows in flight.  The
-// candidate merge, the gradient on the candidates and the emission give the same results
-// as their wave-per-row forms (integer work; per-entry values formed by one lane as
-// before); the objective partials are sums over the row's 8 lanes (lane g takes entries
-// g, g + 8, ...) and a fixed butterfly, so they are reproducible but not bitwise those of
-// the wave-per-row form, which is why the choice is made by the problem size alone.
+// gradient on the candidates and the emission give the same results as their
+// wave-per-row forms (integer work; per-entry values formed by one lane as before); the
+// objective partials are sums over the row's 8 lanes (lane g takes entries g, g + 8, ...)
+// and a fixed butterfly, so they are reproducible but not bitwise those of the
+// wave-per-row form, which is why the choice is made by the problem size alone.  (The
+// candidate merge stays a wave per row: its count walks the row's kept bitmap words,
+// 64 at a time across the wave, which 8 lanes would walk in long serial chains.)
 __device__ inline int64_t group_row(int64_t bx) {
     return (bx * WPB + (threadIdx.x >> 6)) * (64 / TG) + (lane_id() / TG);
 }
@@ -1693,54 +1733,6 @@ __device__ inline double group_sum(double v) {
 #pragma unroll
     for (int o = TG / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
-}
-
-__device__ __forceinline__ void cand_merge_g_body(int64_t bx, const int64_t* __restrict__ rowptr,
-                                                  const int32_t* __restrict__ col, int64_t p,
-                                                  uint64_t* __restrict__ bitmap, int64_t nwords,
-                                                  int64_t* __restrict__ cnt,
-                                                  const uint64_t* __restrict__ tmask) {
-    const int g = lane_id() & (TG - 1);
-    const int64_t row = group_row(bx);
-    const bool act = row < p;
-    const int64_t s = act ? rowptr[row] : 0, e = act ? rowptr[row + 1] : 0;
-    uint64_t* rw = bitmap + (act ? row : 0) * nwords;
-    const int64_t TW = (nwords + 63) / 64;
-    const uint64_t* mrow = tmask && act ? tmask + (row >> 6) * TW : nullptr;
-    int64_t total = 0;
-    // as cand_merge_body: support words outside the kept tiles are cleared first (each such
-    // entry is one bit counted nowhere else), then the support bits go in by atomic OR
-    if (mrow) {
-        for (int64_t k = s + g; k < e; k += TG) {
-            const int64_t w = col[k] >> 6;
-            if (!((mrow[w >> 6] >> (w & 63)) & 1ull)) {
-                rw[w] = 0ull;
-                ++total;
-            }
-        }
-    }
-    __builtin_amdgcn_s_waitcnt(0);
-    for (int64_t k = s + g; k < e; k += TG) {
-        const int32_t c = col[k];
-        atomicOr((unsigned long long*)&rw[c >> 6], 1ull << (c & 63));
-    }
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (mrow) {
-        for (int64_t m = g; m < TW; m += TG) {
-            uint64_t mk = mrow[m];
-            while (mk) {
-                const int b = __builtin_ctzll(mk);
-                mk &= mk - 1ull;
-                const int64_t w = m * 64 + b;
-                if (w < nwords) total += __popcll(rw[w]);
-            }
-        }
-    } else if (act) {
-        for (int64_t w = g; w < nwords; w += TG) total += __popcll(rw[w]);
-    }
-    const double tt = group_sum((double)total);
-    if (act && g == 0) cnt[row] = (int64_t)tt;
 }
 
 template <int BS>
@@ -1867,12 +1859,6 @@ __device__ __forceinline__ void obj_parts_cov_g_body(int64_t bx, const int64_t* 
     }
 }
 
-__global__ void __launch_bounds__(NT)
-cand_merge_g_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col, int64_t p,
-                    uint64_t* __restrict__ bitmap, int64_t nwords, int64_t* __restrict__ cnt,
-                    const uint64_t* __restrict__ tmask) {
-    cand_merge_g_body(blockIdx.x, rowptr, col, p, bitmap, nwords, cnt, tmask);
-}
 template <int BS>
 __global__ void __launch_bounds__(NT)
 cand_grad_cov_g_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
@@ -2366,13 +2352,8 @@ hipError_t launch_cand_count(const void* M, int mstore, int64_t ldm, const Csr& 
 }
 
 hipError_t launch_cand_merge(const Csr& om, int64_t p, uint64_t* bitmap, int64_t nwords,
-                             int64_t* cnt, hipStream_t stream, const uint64_t* tmask, bool grouped) {
+                             int64_t* cnt, hipStream_t stream, const uint64_t* tmask) {
     if (p == 0) return hipSuccess;
-    if (grouped) {
-        hipLaunchKernelGGL(cand_merge_g_kernel, dim3(blocks_for(p, WPB * (64 / TG))), dim3(NT), 0,
-                           stream, om.rowptr, om.col, p, bitmap, nwords, cnt, tmask);
-        return hipGetLastError();
-    }
     hipLaunchKernelGGL(cand_merge_kernel, dim3(blocks_for(p, WPB)), dim3(NT), 0, stream,
                        om.rowptr, om.col, p, bitmap, nwords, cnt, tmask);
     return hipGetLastError();
@@ -3012,17 +2993,10 @@ __global__ void __launch_bounds__(NT)
 batch_merge_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, int nsolve) {
     for_items(pl, nsolve, BP_ROW, [&](int si, int64_t lb) {
         const SolveDesc& d = sd[si];
-        if (d.ctl->phase != BPH_CAND || d.grouped) return;
+        if (d.ctl->phase != BPH_CAND) return;
         const Csr& o = d.om[d.ctl->cur];
         cand_merge_body(lb, o.rowptr, o.col, d.p, d.bitmap, d.nwords, d.cnt,
                         d.screen ? d.rws.tmask : nullptr);
-    });
-    for_items(pl, nsolve, BP_ROWG, [&](int si, int64_t lb) {
-        const SolveDesc& d = sd[si];
-        if (d.ctl->phase != BPH_CAND || !d.grouped) return;
-        const Csr& o = d.om[d.ctl->cur];
-        cand_merge_g_body(lb, o.rowptr, o.col, d.p, d.bitmap, d.nwords, d.cnt,
-                          d.screen ? d.rws.tmask : nullptr);
     });
 }
 
@@ -3355,15 +3329,14 @@ hipError_t launch_batch_iteration(const SolveDesc* sd, const InstDesc* idesc, co
         hipLaunchKernelGGL(batch_scan_apply_kernel<false>, g, b, 0, stream, sd, pl, N, 0);
         hipLaunchKernelGGL(batch_fill_kernel, g, b, (size_t)WPB * ((a.maxT + 63) / 64) * 8, stream,
                            sd, pl, N);
-        if (a.bstore == ST_F64) {
-            hipLaunchKernelGGL(batch_grad_kernel<ST_F64>, g, b, 0, stream, sd, pl, a);
-            hipLaunchKernelGGL(batch_trial_kernel<ST_F64>, g, b, 0, stream, sd, pl, a);
-            hipLaunchKernelGGL(batch_trial_grouped_kernel<ST_F64>, g, b, 0, stream, sd, pl, a);
-        } else {
-            hipLaunchKernelGGL(batch_grad_kernel<ST_F32>, g, b, 0, stream, sd, pl, a);
-            hipLaunchKernelGGL(batch_trial_kernel<ST_F32>, g, b, 0, stream, sd, pl, a);
-            hipLaunchKernelGGL(batch_trial_grouped_kernel<ST_F32>, g, b, 0, stream, sd, pl, a);
-        }
+#define BCAND(BS)                                                                            \
+        hipLaunchKernelGGL(batch_grad_kernel<BS>, g, b, 0, stream, sd, pl, a);                \
+        hipLaunchKernelGGL(batch_trial_kernel<BS>, g, b, 0, stream, sd, pl, a);               \
+        hipLaunchKernelGGL(batch_trial_grouped_kernel<BS>, g, b, 0, stream, sd, pl, a)
+        if (a.bstore == ST_F64) { BCAND(ST_F64); }
+        else if (a.bstore == ST_F32) { BCAND(ST_F32); }
+        else { BCAND(ST_B16P); }
+#undef BCAND
         hipLaunchKernelGGL(batch_decide_kernel, g, b, 0, stream, sd, pl, a);
         hipLaunchKernelGGL(batch_emit_count_kernel, g, b, 0, stream, sd, pl, N);
         hipLaunchKernelGGL(batch_scan_part_kernel<true>, g, b, 0, stream, sd, pl, N, 0);
@@ -3379,13 +3352,13 @@ hipError_t launch_batch_iteration(const SolveDesc* sd, const InstDesc* idesc, co
     }
     hipLaunchKernelGGL(batch_refresh_plan_kernel, dim3(1), dim3(SCAN_BLOCK), 0, stream, sd, idesc,
                        pl, a.ninst, ini);
-    if (a.bstore == ST_F64) {
-        hipLaunchKernelGGL(batch_refresh_kernel<ST_F64>, g, b, 0, stream, sd, idesc, pl, a.ninst, ini);
-        hipLaunchKernelGGL(batch_obj_kernel<ST_F64>, g, b, 0, stream, sd, pl, N, ini);
-    } else {
-        hipLaunchKernelGGL(batch_refresh_kernel<ST_F32>, g, b, 0, stream, sd, idesc, pl, a.ninst, ini);
-        hipLaunchKernelGGL(batch_obj_kernel<ST_F32>, g, b, 0, stream, sd, pl, N, ini);
-    }
+#define BREF(BS)                                                                              \
+    hipLaunchKernelGGL(batch_refresh_kernel<BS>, g, b, 0, stream, sd, idesc, pl, a.ninst, ini);  \
+    hipLaunchKernelGGL(batch_obj_kernel<BS>, g, b, 0, stream, sd, pl, N, ini)
+    if (a.bstore == ST_F64) { BREF(ST_F64); }
+    else if (a.bstore == ST_F32) { BREF(ST_F32); }
+    else { BREF(ST_B16P); }
+#undef BREF
     hipLaunchKernelGGL(batch_obj_sum_kernel, g, b, 0, stream, sd, pl, N, ini);
     hipLaunchKernelGGL(batch_finish_kernel, g, b, 0, stream, sd, pl, a, ini);
     return hipGetLastError();

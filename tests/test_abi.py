@@ -122,7 +122,7 @@ def test_batch_create_rejects_bad_args(lib):
     assert (cfg.precision, cfg.trial_batch, cfg.iters_per_launch, cfg.use_graph) == (_lib.FP32, 8, 4, 1)
     X = (ctypes.c_void_p * 1)(4096)
     l1 = (ctypes.c_double * 1)(0.2)
-    for field, value in (("precision", _lib.BF16X3), ("iters_per_launch", 0), ("trial_batch", 9),
+    for field, value in (("precision", 3), ("iters_per_launch", 0), ("trial_batch", 9),
                          ("shrink", 1.5)):
         bad = _lib.concord_batch_config()
         lib.concord_batch_config_init(ctypes.byref(bad))

@@ -72,11 +72,13 @@ def test_batch_matches_single_solves_and_oracle():
     b.close()
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64", "bf16x3"])
 def test_batch_graph_modes_and_regrowth(precision):
     """lambda1 small enough that the candidate sets outgrow their first capacity (the
     host regrows between replays); direct launches, one iteration per replay and four
-    give the same iterates, equal to the single solver's."""
+    give the same iterates, equal to the single solver's (in every precision form: the
+    BF16 split forms S from hi/lo planes and stores it as hi/lo pairs, as the single
+    solver does)."""
     import torch
     from paper_1710_10769_amd import Batch
     dt = torch.float64 if precision == "fp64" else torch.float32
