@@ -163,8 +163,8 @@ def cpu_baseline(X64, lam1, lam2):
 def bench_c1(args, torch, np, datagen):
     """Small Cov FP64 solve (p = 200, n = 100, chain graph; lambda1 0.3, lambda2 0.1,
     tol 1e-5 / 200 iterations): launch-latency bound, so it is reported with and
-    without graph replay.  A step is one whole solve; value = iterations/s with
-    graph replay."""
+    without graph replay and on the device-resident loop.  A step is one whole solve;
+    value = iterations/s of the handle's default (direct launches)."""
     from paper_1710_10769_amd import Solver
     w = datagen.make_workload("c1_cov_fp64_p200")
     X = torch.from_numpy(w.X).cuda()
@@ -205,7 +205,7 @@ def bench_c1(args, torch, np, datagen):
                   "ms_per_solve": float(np.median(times)) * 1e3, "iterations": iters_b[0],
                   "replays": st["launches"], "host_syncs": st["host_syncs"]}
         log(f"device loop K={K}: {dev[K]}")
-    it, sec = out[True]
+    it, sec = out[False]
     line = {
         "metric": "prox-grad iters/sec, Cov FP64 p=200 (launch-latency bound)",
         "value": it / sec, "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
@@ -213,7 +213,7 @@ def bench_c1(args, torch, np, datagen):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "cov_chain_p200_n100", "p": w.p, "n": w.n, "lam1": w.lam1,
                    "lam2": w.lam2, "iterations": it},
-        "without_graph": {"value": out[False][0] / out[False][1], "ms_per_solve": out[False][1] * 1e3},
+        "with_graph": {"value": out[True][0] / out[True][1], "ms_per_solve": out[True][1] * 1e3},
         "device_loop": {f"iters_per_launch_{k}": v for k, v in dev.items()},
     }
     print(json.dumps(line), flush=True)
@@ -495,8 +495,8 @@ def bench_c4(args, torch, np, datagen):
     solved at lambda1 in {0.2, 0.3, 0.5} from Omega = I (FP64 reductions, stop at
     relative F change < 1e-5 or 200 iterations), all 144 solves on the device at once
     (graph replays of 4 iterations, device-side control).  A step is one whole path from
-    the data (S formation included); value = solves per second with the BF16 split
-    products (the FP32 form beside it)."""
+    the data (S formation included); value = solves per second with FP32 products, the
+    workload's precision (the BF16 split form beside it)."""
     from paper_1710_10769_amd import Batch
     l1s, lam2 = datagen.lambda_path_c4()
     log("generating 48 instances")
@@ -546,7 +546,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--forms", default="bf16x3,fp32")
-    ap.add_argument("--c4-forms", default="bf16x3,fp32",
+    ap.add_argument("--c4-forms", default="fp32,bf16x3",
                     help="c4: precision forms, the first one is the line's value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cov-context", action="store_true",

@@ -175,6 +175,12 @@ int form_s(concord_batch* b) {
         BHIP(b, launch_transpose_in(b->X[i], b->dstore == ST_F64, n, p, b->ld[i], xt[s], b->dstore,
                                     ldk, (uint16_t*)xh[s], (uint16_t*)xl[s], kblk_stride(prow),
                                     b->dflag + s, st));
+        // the first contraction of a shape times the tile variants (events on its stream):
+        // the other streams are drained first so that their kernels do not share the chip
+        // with the timed runs
+        if (b->gkind != GK_F64 && gemm_sym_choice(b->gkind, false, p, ldk, nullptr) < 0)
+            for (int o = 0; o < NSIDE; ++o)
+                if (o != s) BHIP(b, hipStreamSynchronize(b->side[o]));
         BHIP(b, launch_gemm_sym(b->gkind, false, split ? xh[s] : xt[s], split ? xl[s] : nullptr,
                                 nullptr, nullptr, ldk, p, 1.0 / (double)n,
                                 const_cast<void*>(d0.S), b->sstore, d0.lds, st));

@@ -212,13 +212,17 @@ int dalloc(concord_ctx* c, void** out, size_t bytes, bool zero) {
 
 void dfree(concord_ctx* c, void* p) {
     if (!p) return;
-    for (auto& a : c->allocs)
-        if (a.ptr == p) {
+    for (size_t i = 0; i < c->allocs.size(); ++i)
+        if (c->allocs[i].ptr == p) {
             // work queued on the stream may still read the block (hipFree would wait for
             // the device; a caller's allocator need not)
             (void)hipStreamSynchronize(c->stream);
-            release(c, a);
-            a.ptr = nullptr;
+            release(c, c->allocs[i]);
+            // the record goes too: a handle that allocates per call (the differentiation
+            // form's backward) keeps a list as long as its live blocks, not its calls
+            c->allocs[i] = c->allocs.back();
+            c->allocs.pop_back();
+            return;
         }
 }
 
@@ -1253,36 +1257,46 @@ int concord_gradient(concord_ctx* c, double lam2, int32_t mode, void* dev_dOmega
     const int out64 = dtype == CONCORD_F64;
     const int64_t p = c->p, nnz = c->nnz;
     const size_t dense_bytes = (size_t)c->prow * c->ldk * elem_bytes(c->dstore);
-    // Buffers of this call only (returned before it ends): Y when the handle holds none,
-    // Omega Y before its transpose, and the half d_ij of every masked entry.
-    void* ybuf = nullptr;
-    void* oy = nullptr;
-    double* D = nullptr;
+    // Buffers of this call only, in one block from one allocation (returned before the
+    // call ends): Y when the handle holds none, Omega Y before its transpose, and the half
+    // d_ij of every masked entry.
+    const bool masked = dev_dOmega && mode == CONCORD_GRAD_MASKED;
+    const bool need_y = !(c->prod_valid && c->Y);
+    const int ncb = grad_col_blocks(c->dstore, c->n);
+    auto a256 = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t ya = need_y && !c->Y ? a256(dense_bytes) : 0;
+    const size_t oa = dev_dX ? a256(dense_bytes) : 0;
+    const size_t da = masked ? a256((size_t)std::max<int64_t>(nnz, 1) * ncb * sizeof(double)) : 0;
+    void* blk = nullptr;
     auto done = [&](int rc) {
-        dfree(c, ybuf);
-        dfree(c, oy);
-        dfree(c, D);
+        dfree(c, blk);
         return rc;
     };
     int rc;
+    if (ya + oa + da && (rc = dalloc(c, &blk, ya + oa + da, false))) return rc;
+    char* const base = (char*)blk;
+    void* ybuf = ya ? base : nullptr;
+    void* oy = oa ? base + ya : nullptr;
+    double* D = da ? (double*)(base + ya + oa) : nullptr;
     // Y = Omega X^T: kept only by a solver whose products are current; otherwise
-    // recomputed here (the forward pass reduces ||Y||^2 without storing Y)
+    // recomputed here (the forward pass reduces ||Y||^2 without storing Y).  Omega Y needs
+    // no clearing (every column that is read is written); a fresh Y gets zero columns
+    // n .. ldk - 1, which the row pass's last chunk and the dense contraction's K loop read.
     void* Y = c->Y;
-    if (!(c->prod_valid && c->Y)) {
+    if (need_y) {
         if (!Y) {
-            if ((rc = dalloc(c, &ybuf, dense_bytes, true))) return done(rc);
             Y = ybuf;
+            const size_t eb = elem_bytes(c->dstore);
+            if (c->ldk > c->n)
+                HIPCK(c, hipMemset2DAsync((char*)Y + (size_t)c->n * eb, (size_t)c->ldk * eb, 0,
+                                          (size_t)(c->ldk - c->n) * eb, (size_t)p, c->stream));
         }
         HIPCK(c, launch_spmm(O, p, c->Xt, c->dstore, c->ldk, c->ldk, Y, c->dstore, c->ldk, nullptr,
                              nullptr, 0, nullptr, c->d_one, c->stream));
     }
-    if (dev_dX && (rc = dalloc(c, &oy, dense_bytes, true))) return done(rc);
-    if (dev_dOmega && mode == CONCORD_GRAD_MASKED) {
+    if (masked) {
         // the half d_ij of every entry and, when d f / d X is wanted too, Omega Y, from one
         // gather of the rows Y_j
-        const int ncb = grad_col_blocks(c->dstore, c->n);
-        const size_t len = (size_t)std::max<int64_t>(nnz, 1) * ncb;
-        if ((rc = dalloc_t(c, &D, len))) return done(rc);
         HIPCK(c, launch_grad_rows(O, p, nnz, Y, c->Xt, c->dstore, c->ldk, c->n, D, oy,
                                   c->stream));
         HIPCK(c, launch_grad_combine(O, p, nnz, ncb, D, c->n, lam2, dev_dOmega, out64,

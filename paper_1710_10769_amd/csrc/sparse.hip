@@ -585,6 +585,51 @@ __device__ inline double prox_one(double om, double g, double tau, double thr, b
     return z > thr ? z - thr : (z < -thr ? z + thr : 0.0);
 }
 
+// Cov trials, the quadratic term of one candidate b of row `row`: squad[q] += Delta_a(q)
+// S[j_a][j_b] Delta_b(q) over the row's candidates a in order s .. e - 1.  The entries of
+// four candidates a, then their four S values, are loaded before any of their arithmetic
+// (a row's candidates are a chain of dependent loads otherwise); the products and their
+// order are those of one candidate at a time.
+template <int BS>
+__device__ __forceinline__ void cov_quad_b(const int32_t* __restrict__ acol,
+                                           const double* __restrict__ aom,
+                                           const double* __restrict__ agr, int64_t s, int64_t e,
+                                           int64_t row, int64_t jb, const void* __restrict__ B,
+                                           int64_t ldb, double tau0, double shrink, double lam1,
+                                           int m, const double (&db)[MAXQ], double (&squad)[MAXQ]) {
+    auto one = [&](int64_t ja, double oma, double ga, double sab) {
+        const bool diaga = ja == row;
+        double tau = tau0;
+#pragma unroll
+        for (int q = 0; q < MAXQ; ++q) {
+            if (q < m) {
+                const double da = prox_one(oma, ga, tau, tau * lam1, diaga) - oma;
+                squad[q] += da * sab * db[q];
+            }
+            tau *= shrink;
+        }
+    };
+    int64_t ka = s;
+    for (; ka + 4 <= e; ka += 4) {
+        int64_t ja[4];
+        double oma[4], ga[4], sab[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            ja[u] = acol[ka + u];
+            oma[u] = aom[ka + u];
+            ga[u] = agr[ka + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) sab[u] = load_one_d<BS>(B, ja[u] * ldb + jb);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) one(ja[u], oma[u], ga[u], sab[u]);
+    }
+    for (; ka < e; ++ka) {
+        const int64_t ja = acol[ka];
+        one(ja, aom[ka], agr[ka], load_one_d<BS>(B, ja * ldb + jb));
+    }
+}
+
 template <int BS, bool OBS>
 __device__ __forceinline__ void trial_body(int64_t bx_, int split, int nsplit, const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
              const double* __restrict__ aom, const double* __restrict__ agr, int64_t p,
@@ -794,21 +839,7 @@ __device__ __forceinline__ void trial_body(int64_t bx_, int split, int nsplit, c
                     tau *= shrink;
                 }
             }
-            for (int64_t ka = s; ka < e; ++ka) {
-                const int64_t ja = acol[ka];
-                const double oma = aom[ka], ga = agr[ka];
-                const bool diaga = ja == row;
-                const double sab = load_one_d<BS>(B, ja * ldb + jb);
-                double tau = tau0;
-#pragma unroll
-                for (int q = 0; q < MAXQ; ++q) {
-                    if (q < m) {
-                        const double da = prox_one(oma, ga, tau, tau * lam1, diaga) - oma;
-                        squad[q] += da * sab * db[q];
-                    }
-                    tau *= shrink;
-                }
-            }
+            cov_quad_b<BS>(acol, aom, agr, s, e, row, jb, B, ldb, tau0, shrink, lam1, m, db, squad);
         }
     }
     // The 4 * MAXQ = 32 lane partials (value k = 4q + t) summed over the wave by a
@@ -904,21 +935,7 @@ __device__ __forceinline__ void trial_cov_body(int64_t bx_, const int64_t* __res
                 tau *= shrink;
             }
         }
-        for (int64_t ka = s; ka < e; ++ka) {
-            const int64_t ja = acol[ka];
-            const double oma = aom[ka], ga = agr[ka];
-            const bool diaga = ja == row;
-            const double sab = load_one_d<BS>(B, ja * ldb + jb);
-            double tau = tau0;
-#pragma unroll
-            for (int q = 0; q < MAXQ; ++q) {
-                if (q < m) {
-                    const double da = prox_one(oma, ga, tau, tau * lam1, diaga) - oma;
-                    squad[q] += da * sab * db[q];
-                }
-                tau *= shrink;
-            }
-        }
+        cov_quad_b<BS>(acol, aom, agr, s, e, row, jb, B, ldb, tau0, shrink, lam1, m, db, squad);
     }
     double v[4 * MAXQ];
 #pragma unroll
@@ -1384,37 +1401,46 @@ __device__ __forceinline__ void refresh_pair(const int I, const int J,
             acc[q] = m < cnt_q ? f : acc[q];
         }
     };
+    // each step's entries are fetched while the previous step's S loads are in flight, so
+    // a step waits for one round trip (its S loads), not two
     if (PAIR) {
         const int steps = maxI > maxJ ? maxI : maxJ;
+        int cl = 0, cn = 0;
+        A v = (A)0, vn = (A)0;
+        if (steps > 0) fetch(0, cl, v);
         for (int m = 0; m < steps; ++m) {
-            int cl;
-            A v;
-            fetch(m, cl, v);
             A x[16], xj[16];
             issue(cl, 0, cj, x);
             issue(cl, 16, ci, xj);
+            if (m + 1 < steps) fetch(m + 1, cn, vn);
             __builtin_amdgcn_sched_barrier(0);   // keep the 32 loads ahead of their uses
             accum(m, 0, v, x, w);
             accum(m, 16, v, xj, wj);
+            cl = cn;
+            v = vn;
         }
     } else {
+        int cl = 0, cn = 0;
+        A v = (A)0, vn = (A)0;
+        if (maxJ > 0) fetch(0, cl, v);
         for (int m = 0; m < maxJ; ++m) {
-            int cl;
-            A v;
-            fetch(m, cl, v);
             A x[16];
             issue(cl, 16, ci, x);
+            if (m + 1 < maxJ) fetch(m + 1, cn, vn);
             __builtin_amdgcn_sched_barrier(0);   // keep the 16 loads ahead of their uses
             accum(m, 16, v, x, wj);
+            cl = cn;
+            v = vn;
         }
+        if (maxI > 0) fetch(0, cl, v);
         for (int m = 0; m < maxI; ++m) {
-            int cl;
-            A v;
-            fetch(m, cl, v);
             A x[16];
             issue(cl, 0, cj, x);
+            if (m + 1 < maxI) fetch(m + 1, cn, vn);
             __builtin_amdgcn_sched_barrier(0);
             accum(m, 0, v, x, w);
+            cl = cn;
+            v = vn;
         }
     }
 #pragma unroll

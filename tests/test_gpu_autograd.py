@@ -144,7 +144,7 @@ def test_forward_stores_no_y_and_backward_returns_its_buffers():
     assert sum(1 for b in live_after_forward.values() if b == dense) == 1
     n_before = alloc.n_alloc
     f.backward()
-    assert alloc.n_alloc > n_before                 # Y, Omega Y and the halves, this call only
+    assert alloc.n_alloc == n_before + 1            # one block: Y, Omega Y and the halves d_ij
     assert alloc.live == live_after_forward         # all of them returned
     f_ref, G_ref, dX_ref = oc.smooth_value_and_grads(om, X.astype(np.float32).astype(np.float64),
                                                      lam2)
