@@ -857,6 +857,8 @@ __device__ inline void read_frags_b(uint32_t b, u32x4_t (&f)[8]) {
 
 }  // namespace ar
 
+constexpr int vm_wait_imm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x70 | 0xf00; }
+
 __global__ void __launch_bounds__(dma::NT)
 gemm_bf16x3_ar_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
                       const char* __restrict__ Q0, const char* __restrict__ Q1,
@@ -920,8 +922,8 @@ gemm_bf16x3_ar_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
     // Every stage issues exactly 4 A loads and then 2 B loads (past the last stage they
     // re-read stage nkt - 1 into a register set / ring slot nothing reads again), and
     // the prologue issues the same pattern (A(-1) is a dummy), so the operation counts
-    // are the same on every path into the loop: when stage k starts, 12 operations
-    // were issued after B(k) (A(k), B(k+1), A(k+1), B(k+2)); nkt >= 4.
+    // are the same on every path into the loop: when stage k starts, 8 operations were
+    // issued after A(k) (B(k+1), A(k+1), B(k+2)), and B(k) came before A(k); nkt >= 4.
     u32x4_t a0[4], a1[4], a2[4];
     load_a(0, a2);
     issue_b(0, 0);
@@ -931,7 +933,10 @@ gemm_bf16x3_ar_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
     issue_b(2, 2);
     const int last = nkt - 1;
     auto step = [&](int k, u32x4_t (&acur)[4], u32x4_t (&anext)[4]) {
-        __builtin_amdgcn_s_waitcnt(0x0f7c);   // vmcnt(12): this wave's share of B(k) landed
+        // this wave's A(k) landed, and B(k) issued before it: with the wait stated here
+        // the compiler adds none of its own before the MFMAs (across the unrolled loop's
+        // back edge it would otherwise drain every load in flight)
+        __builtin_amdgcn_s_waitcnt(vm_wait_imm(8));
         order();
         __builtin_amdgcn_s_barrier();         // ... and every wave's; slot (k-1)&3 is free
         order();
@@ -967,13 +972,21 @@ gemm_bf16x3_ar_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
                 acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
     };
     int kt = 0;
-    for (; kt + 3 <= nkt; kt += 3) {
+    // six stages per trip (two turns of the three register sets): the compiler's own
+    // wait for a set loaded on the previous trip then comes once per six stages
+    for (; kt + 6 <= nkt; kt += 6) {
         step(kt + 0, a0, a2);
         step(kt + 1, a1, a0);
         step(kt + 2, a2, a1);
+        step(kt + 3, a0, a2);
+        step(kt + 4, a1, a0);
+        step(kt + 5, a2, a1);
     }
     if (kt < nkt) step(kt, a0, a2);
     if (kt + 1 < nkt) step(kt + 1, a1, a0);
+    if (kt + 2 < nkt) step(kt + 2, a2, a1);
+    if (kt + 3 < nkt) step(kt + 3, a0, a2);
+    if (kt + 4 < nkt) step(kt + 4, a1, a0);
     wait_vm(0);
     store_tile_256(acc, I, J, rowI0, rowJ0, wm, wn, lane, p, alpha, C, out_store, ldc, th);
 }
@@ -1001,74 +1014,28 @@ hipError_t launch_bf16x3_ar(bool syr2k, const void* P0, const void* P1, const vo
     return hipGetLastError();
 }
 
-// ---- BF16-split contraction: A in registers, B fragments read one stage ahead ----
+// ---- BF16-split contraction: A in registers, B fragments read by ordinary loads ----
 //
-// The kernel above reads a stage's B fragments from LDS after the stage's barrier and
-// waits for them before its first MFMA, so every wave of the workgroup stalls on the
-// same burst of LDS reads (32 KB per stage) with the matrix cores idle.  Here the B
-// fragments of stage k + 1 are read while the MFMAs of stage k run: the second and
-// third split products of stage k are each one asm block that first issues four
-// fragment reads of stage k + 1, then the eight MFMAs, and waits for the reads at its
-// end (the results are in registers before the block ends).  Stage k + 1 must then be
-// in LDS one stage earlier: the wait at the top of stage k covers this wave's loads of
-// B(k + 1) and A(k), and the barrier after it publishes every wave's share.  B is still
-// issued three stages ahead (the slot of B(k), read by every wave during stage k - 1, is
-// refilled with B(k + 4)), A two stages ahead in three register sets.  Per accumulator
-// the products keep the order lo*hi, hi*lo, hi*hi of every other variant, so the
-// result is bitwise the same.
-namespace arp {
-// eight MFMAs acc[i][j] += a[i] * b[j] of one split product, with the four fragment
-// reads at `ad` (+1024 per 32-row block) issued first and complete when the block ends
-__device__ inline void mfma8_read4(f32x16_t (&c)[dma::MB][dma::NB], const bf16x8_t (&a)[dma::MB],
-                                   const bf16x8_t (&b)[dma::NB], u32x4_t (&nx)[4], uint32_t ad) {
-    asm volatile(
-        "ds_read_b128 %[n0], %[ad]\n\t"
-        "ds_read_b128 %[n1], %[ad] offset:1024\n\t"
-        "ds_read_b128 %[n2], %[ad] offset:2048\n\t"
-        "ds_read_b128 %[n3], %[ad] offset:3072\n\t"
-        "v_mfma_f32_32x32x16_bf16 %[c00], %[a0], %[b0], %[c00]\n\t"
-        "v_mfma_f32_32x32x16_bf16 %[c01], %[a0], %[b1], %[c01]\n\t"
-        "v_mfma_f32_32x32x16_bf16 %[c02], %[a0], %[b2], %[c02]\n\t"
-        "v_mfma_f32_32x32x16_bf16 %[c03], %[a0], %[b3], %[c03]\n\t"
-        "v_mfma_f32_32x32x16_bf16 %[c10], %[a1], %[b0], %[c10]\n\t"
-        "v_mfma_f32_32x32x16_bf16 %[c11], %[a1], %[b1], %[c11]\n\t"
-        "v_mfma_f32_32x32x16_bf16 %[c12], %[a1], %[b2], %[c12]\n\t"
-        "v_mfma_f32_32x32x16_bf16 %[c13], %[a1], %[b3], %[c13]\n\t"
-        "s_waitcnt lgkmcnt(0)"
-        : [c00] "+v"(c[0][0]), [c01] "+v"(c[0][1]), [c02] "+v"(c[0][2]), [c03] "+v"(c[0][3]),
-          [c10] "+v"(c[1][0]), [c11] "+v"(c[1][1]), [c12] "+v"(c[1][2]), [c13] "+v"(c[1][3]),
-          [n0] "=&v"(nx[0]), [n1] "=&v"(nx[1]), [n2] "=&v"(nx[2]), [n3] "=&v"(nx[3])
-        : [a0] "v"(a[0]), [a1] "v"(a[1]), [b0] "v"(b[0]), [b1] "v"(b[1]), [b2] "v"(b[2]),
-          [b3] "v"(b[3]), [ad] "v"(ad)
-        : "memory");
-}
-// the four fragment reads at `ad` alone, complete when the block ends
-__device__ inline void read4(u32x4_t (&nx)[4], uint32_t ad) {
-    asm volatile(
-        "ds_read_b128 %0, %4\n\t"
-        "ds_read_b128 %1, %4 offset:1024\n\t"
-        "ds_read_b128 %2, %4 offset:2048\n\t"
-        "ds_read_b128 %3, %4 offset:3072\n\t"
-        "s_waitcnt lgkmcnt(0)"
-        : "=&v"(nx[0]), "=&v"(nx[1]), "=&v"(nx[2]), "=&v"(nx[3])
-        : "v"(ad)
-        : "memory");
-}
-template <int N> __device__ inline void as_bf16(const u32x4_t (&u)[N], bf16x8_t (&b)[N]) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) b[i] = __builtin_bit_cast(bf16x8_t, u[i]);
-}
-}  // namespace arp
-
+// The register-A ring kernel above with its B ring in four separate LDS arrays, one per
+// slot, and the loop unrolled over twelve stages (four slots x three register sets), so
+// that every stage names its slot at compile time.  The B fragments are then read with
+// ordinary LDS loads: the compiler knows that the direct-to-LDS loads in flight write
+// other arrays than the one being read, adds no wait for them, and places the waits for
+// the fragments itself: the first product (column block outer) starts once its four
+// fragments have arrived, and the second product's reads go out under it.  Same products
+// per accumulator in the same order.
 __global__ void __launch_bounds__(dma::NT)
-gemm_bf16x3_arp_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
+gemm_bf16x3_arl_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
                        const char* __restrict__ Q0, const char* __restrict__ Q1,
                        int64_t kbs, int nk, int syr2k, int p, int T, int ntiles,
                        double alpha, void* __restrict__ C, int out_store, int64_t ldc,
                        ThreshOut th) {
     using namespace dma;
     using ar::BSLOT;
-    __shared__ __attribute__((aligned(16))) char ring[4 * BSLOT];
+    __shared__ __attribute__((aligned(16))) char s0[BSLOT];
+    __shared__ __attribute__((aligned(16))) char s1[BSLOT];
+    __shared__ __attribute__((aligned(16))) char s2[BSLOT];
+    __shared__ __attribute__((aligned(16))) char s3[BSLOT];
 
     int I, J;
     tile_of(blockIdx.x, ntiles, T, I, J);
@@ -1085,15 +1052,14 @@ gemm_bf16x3_arp_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
     const char* bsrc2 = bpl ? P1 : P0;
     const int64_t brow = rowJ0 + (wave & 3) * 64 + (lane >> 1);
     const int bsw = (lane & 1) ^ (((lane >> 1) >> 3) & 1);
-    auto issue_b = [&](int slot_kt, int kt) {
-        char* slot = ring + (slot_kt & 3) * BSLOT + bpl * PS + (wave & 3) * 2048;
+    auto issue_b = [&](char* slot, int kt) {
+        char* d = slot + bpl * PS + (wave & 3) * 2048;
         const bool second = kt >= nk;
         const char* g = (second ? bsrc2 : bsrc1) + (int64_t)(second ? kt - nk : kt) * kbs +
                         brow * ROW + bsw * 16;
-        __builtin_amdgcn_global_load_lds((gbl_t*)g, (lds_t*)slot, 16, 0, 0);
-        __builtin_amdgcn_global_load_lds((gbl_t*)(g + 32 * ROW), (lds_t*)(slot + 1024), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((gbl_t*)g, (lds_t*)d, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((gbl_t*)(g + 32 * ROW), (lds_t*)(d + 1024), 16, 0, 0);
     };
-    // A side: 4 loads per wave per stage (hi, lo of two 32-row blocks)
     const int64_t arow = (rowI0 + wm * 64 + r32) * ROW + hk * 16;
     auto load_a = [&](int kt, u32x4_t (&a)[4]) {
         const bool second = kt >= nk;
@@ -1114,74 +1080,82 @@ gemm_bf16x3_arp_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-    const uint32_t lds_b = (uint32_t)(uintptr_t)(lds_t*)ring + off(wn * 128 + r32, hk);
+    const int fo = off(wn * 128 + r32, hk);   // this lane's fragment offset in a slot
     const int last = nkt - 1;
-    // Issue order: B(0), B(1), A(0), B(2), A(1), B(3), then per stage k: A(k + 2),
-    // B(k + 4) (past the last stage they re-read stage nkt - 1 into a register set or a
-    // slot nothing reads again).  At the top of stage k, eight operations were issued
-    // after A(k) (B(k + 2), A(k + 1), B(k + 3)) and twelve after B(k + 1); nkt >= 4.
+    // Issue order and counts as gemm_bf16x3_ar_kernel: when stage k starts, 8 operations
+    // were issued after A(k), and B(k) before it; nkt >= 4.
     u32x4_t a0[4], a1[4], a2[4];
-    u32x4_t bh0[4], bl0[4], bh1[4], bl1[4];   // B fragments of two consecutive stages
-    issue_b(0, 0);
-    issue_b(1, 1);
+    load_a(0, a2);
+    issue_b(s0, 0);
     load_a(0, a0);
-    issue_b(2, 2);
+    issue_b(s1, 1);
     load_a(1, a1);
-    issue_b(3, 3);
-    __builtin_amdgcn_s_waitcnt(0x0f7e);   // vmcnt(14): this wave's share of B(0) landed
-    order();
-    __builtin_amdgcn_s_barrier();
-    order();
-    arp::read4(bh0, lds_b);
-    arp::read4(bl0, lds_b + PS);
-
-    // stage k: A(k) in acur, B(k) in (bh, bl); reads B(k + 1) into (nh, nl)
-    auto step = [&](int k, u32x4_t (&acur)[4], u32x4_t (&anext)[4], const u32x4_t (&bh)[4],
-                    const u32x4_t (&bl)[4], u32x4_t (&nh)[4], u32x4_t (&nl)[4]) {
-        __builtin_amdgcn_s_waitcnt(0x0f78);   // vmcnt(8): A(k), this wave's B(k + 1) landed
+    issue_b(s2, 2);
+    auto step = [&](int k, const char* cur, char* nxt, u32x4_t (&acur)[4], u32x4_t (&anext)[4]) {
+        __builtin_amdgcn_s_waitcnt(vm_wait_imm(8));   // A(k) and this wave's B(k) landed
         order();
-        __builtin_amdgcn_s_barrier();         // every wave's B(k + 1); slot of B(k) free
+        __builtin_amdgcn_s_barrier();                 // every wave's B(k); slot of B(k-1) free
         order();
         load_a(k + 2 < last ? k + 2 : last, anext);
-        issue_b(k + 4, k + 4 < last ? k + 4 : last);
-        const uint32_t nb = lds_b + ((k + 1) & 3) * BSLOT;
-        bf16x8_t ah[MB], al[MB], bhv[NB], blv[NB];
-        ah[0] = __builtin_bit_cast(bf16x8_t, acur[0]);
-        ah[1] = __builtin_bit_cast(bf16x8_t, acur[1]);
-        al[0] = __builtin_bit_cast(bf16x8_t, acur[2]);
-        al[1] = __builtin_bit_cast(bf16x8_t, acur[3]);
-        arp::as_bf16(bh, bhv);
-        arp::as_bf16(bl, blv);
+        issue_b(nxt, k + 3 < last ? k + 3 : last);
+        bf16x8_t ah[MB], al[MB], bh[NB], bl[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) bh[j] = *(const bf16x8_t*)(cur + fo + j * 1024);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) bl[j] = *(const bf16x8_t*)(cur + PS + fo + j * 1024);
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            ah[i] = __builtin_bit_cast(bf16x8_t, acur[i]);
+            al[i] = __builtin_bit_cast(bf16x8_t, acur[2 + i]);
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
 #pragma unroll
         for (int i = 0; i < MB; ++i)
 #pragma unroll
             for (int j = 0; j < NB; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bhv[j], acc[i][j], 0, 0, 0);
-        arp::mfma8_read4(acc, ah, blv, nh, nb);        // hi * lo; reads B(k + 1) hi
-        arp::mfma8_read4(acc, ah, bhv, nl, nb + PS);   // hi * hi; reads B(k + 1) lo
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
     };
+    // stage k reads slot k % 4, refills slot (k + 3) % 4, uses register set k % 3
     int kt = 0;
-    for (; kt + 6 <= nkt; kt += 6) {
-        step(kt + 0, a0, a2, bh0, bl0, bh1, bl1);
-        step(kt + 1, a1, a0, bh1, bl1, bh0, bl0);
-        step(kt + 2, a2, a1, bh0, bl0, bh1, bl1);
-        step(kt + 3, a0, a2, bh1, bl1, bh0, bl0);
-        step(kt + 4, a1, a0, bh0, bl0, bh1, bl1);
-        step(kt + 5, a2, a1, bh1, bl1, bh0, bl0);
+    for (; kt + 12 <= nkt; kt += 12) {
+        step(kt + 0, s0, s3, a0, a2);
+        step(kt + 1, s1, s0, a1, a0);
+        step(kt + 2, s2, s1, a2, a1);
+        step(kt + 3, s3, s2, a0, a2);
+        step(kt + 4, s0, s3, a1, a0);
+        step(kt + 5, s1, s0, a2, a1);
+        step(kt + 6, s2, s1, a0, a2);
+        step(kt + 7, s3, s2, a1, a0);
+        step(kt + 8, s0, s3, a2, a1);
+        step(kt + 9, s1, s0, a0, a2);
+        step(kt + 10, s2, s1, a1, a0);
+        step(kt + 11, s3, s2, a2, a1);
     }
-    if (kt + 0 < nkt) step(kt + 0, a0, a2, bh0, bl0, bh1, bl1);
-    if (kt + 1 < nkt) step(kt + 1, a1, a0, bh1, bl1, bh0, bl0);
-    if (kt + 2 < nkt) step(kt + 2, a2, a1, bh0, bl0, bh1, bl1);
-    if (kt + 3 < nkt) step(kt + 3, a0, a2, bh1, bl1, bh0, bl0);
-    if (kt + 4 < nkt) step(kt + 4, a1, a0, bh0, bl0, bh1, bl1);
+    if (kt + 0 < nkt) step(kt + 0, s0, s3, a0, a2);
+    if (kt + 1 < nkt) step(kt + 1, s1, s0, a1, a0);
+    if (kt + 2 < nkt) step(kt + 2, s2, s1, a2, a1);
+    if (kt + 3 < nkt) step(kt + 3, s3, s2, a0, a2);
+    if (kt + 4 < nkt) step(kt + 4, s0, s3, a1, a0);
+    if (kt + 5 < nkt) step(kt + 5, s1, s0, a2, a1);
+    if (kt + 6 < nkt) step(kt + 6, s2, s1, a0, a2);
+    if (kt + 7 < nkt) step(kt + 7, s3, s2, a1, a0);
+    if (kt + 8 < nkt) step(kt + 8, s0, s3, a2, a1);
+    if (kt + 9 < nkt) step(kt + 9, s1, s0, a0, a2);
+    if (kt + 10 < nkt) step(kt + 10, s2, s1, a1, a0);
     wait_vm(0);
-    // the last MFMAs were issued from asm, where the compiler inserts no hazard wait:
-    // 24 wait states before any instruction reads their results
-    asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7" ::: "memory");
     store_tile_256(acc, I, J, rowI0, rowJ0, wm, wn, lane, p, alpha, C, out_store, ldc, th);
 }
 
-hipError_t launch_bf16x3_arp(bool syr2k, const void* P0, const void* P1, const void* Q0,
+hipError_t launch_bf16x3_arl(bool syr2k, const void* P0, const void* P1, const void* Q0,
                              const void* Q1, int64_t ldk, int64_t p, double alpha, void* C,
                              int out_store, int64_t ldc, hipStream_t stream, ThreshOut th) {
     const int64_t ldk_bytes = ldk * 2;
@@ -1190,10 +1164,10 @@ hipError_t launch_bf16x3_arp(bool syr2k, const void* P0, const void* P1, const v
     const int T = (int)((p + dma::BT - 1) / dma::BT);
     const int ntiles = T * (T + 1) / 2;
     if (ntiles == 0 || nk == 0) return hipSuccess;
-    if ((syr2k ? 2 * nk : nk) < 4)   // the issue pattern needs four stages
+    if ((syr2k ? 2 * nk : nk) < 4)   // the prologue issues four stages
         return launch_bf16x3_dma(syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc,
                                  stream, th);
-    hipLaunchKernelGGL(gemm_bf16x3_arp_kernel, dim3(ntiles), dim3(dma::NT), 0, stream,
+    hipLaunchKernelGGL(gemm_bf16x3_arl_kernel, dim3(ntiles), dim3(dma::NT), 0, stream,
                        (const char*)P0, (const char*)P1, (const char*)(syr2k ? Q0 : P0),
                        (const char*)(syr2k ? Q1 : P1), round_up(p, ROW_PAD) * dma::ROW, nk,
                        syr2k ? 1 : 0, (int)p, T, ntiles, alpha, C, out_store, ldc, th);
@@ -1282,7 +1256,8 @@ hipError_t launch_kind(bool syr2k, const void* P0, const void* P1, const void* Q
 // Variants per form: 256-wide tiles (8 waves, register-staged), 128-wide tiles (4
 // waves, register-staged), the 256-wide kernel as a persistent grid of one
 // workgroup per CU, and, for the BF16 split, the 256-wide direct-to-LDS ring, its
-// ping-pong schedule, and the ring with the A side in registers.  All variants of a
+// ping-pong schedule, the ring with the A side in registers, and that kernel with its
+// B fragments read by ordinary loads from per-slot arrays.  All variants of a
 // form produce bitwise-identical results (same per-accumulator order of the K steps
 // and of the three split products), so the choice only affects speed.  The first
 // contraction of a new shape key (form, syr2k, p rounded up to 256, K) times every
@@ -1307,7 +1282,7 @@ const Variant* variants(int kind, int* count) {
         {"bf16x3_256x256_w8_persistent", launch_kind<GK_BF16X3, 256, 4, 2, true>, false},
         {"bf16x3_256x256_w8_pingpong", launch_bf16x3_pp, true},
         {"bf16x3_256x256_w8_ldsring_aregs", launch_bf16x3_ar, true},
-        {"bf16x3_256x256_w8_ldsring_aregs_pipe", launch_bf16x3_arp, true},
+        {"bf16x3_256x256_w8_ldsring_aregs_loads", launch_bf16x3_arl, true},
     };
     static const Variant f32[] = {
         {"f32_256x256_w8", launch_kind<GK_F32, 256, 4, 2>, false},

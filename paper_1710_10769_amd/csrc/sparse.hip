@@ -1322,8 +1322,23 @@ __device__ __forceinline__ void refresh_pair(const int I, const int J,
     double rbound = 0.0;
     const bool screen = smax != nullptr;
     if (I != J && screen) {
+        // four entries' loads, then their tile maxima, before the sums (same order)
         const int64_t other = hl < 16 ? J : I;
-        for (int m = 0; m < my_cnt; ++m)
+        int m = 0;
+        for (; m + 4 <= my_cnt; m += 4) {
+            int32_t c[4];
+            double v[4], sm[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                c[u] = col[my_s0 + m + u];
+                v[u] = val[my_s0 + m + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) sm[u] = smax[(int64_t)(c[u] >> 6) * T + other];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) rbound += fabs(v[u]) * sm[u];
+        }
+        for (; m < my_cnt; ++m)
             rbound += fabs(val[my_s0 + m]) * smax[(int64_t)(col[my_s0 + m] >> 6) * T + other];
     }
     int mx = my_cnt;
