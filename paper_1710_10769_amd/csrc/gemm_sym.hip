@@ -59,18 +59,11 @@ __device__ inline uint16_t f2bf_rne(float f) {
 // segment, the swizzled chunk the slot inside it), i.e. no bank conflict.
 __device__ inline int swz(int row, int chunk) { return row * ROWB + ((chunk ^ ((row >> 2) & 3)) << 4); }
 
-__device__ inline void tile_of(int w, int ntiles, int T, int& I, int& J) {
-    // XCD-aware remap: hardware places workgroup w on XCD w % 8.  Give XCD x
-    // the contiguous range [start_x, start_x + count_x) of the tile order below,
-    // so the ~32 tiles resident on one XCD are consecutive in that order.
-    const int nx = 8;
-    const int x = w % nx, r = w / nx;
-    const int base = ntiles / nx, rem = ntiles % nx;
-    int t = x * base + (x < rem ? x : rem) + r;
-    // Tile order over the upper triangle (I <= J): bands of G tile-rows; inside a
-    // band, column by column.  G consecutive tiles share one B slab (rows J)
-    // and every tile of the band shares the band's G A slabs (rows I), so a run
-    // of 32 tiles touches G + 32/G slabs instead of 33.
+// Tile t of the order over the upper triangle (I <= J): bands of G tile-rows; inside a
+// band, column by column.  G consecutive tiles share one B slab (rows J) and every tile
+// of the band shares the band's G A slabs (rows I), so a run of 32 tiles touches
+// G + 32/G slabs instead of 33.
+__device__ inline void tile_in_order(int t, int T, int& I, int& J) {
     constexpr int G = 8;
     int i0 = 0;
     for (;;) {
@@ -92,6 +85,38 @@ __device__ inline void tile_of(int w, int ntiles, int T, int& I, int& J) {
         J = i0 + h + t / h;
         I = i0 + t % h;
     }
+}
+
+__device__ inline void tile_of(int w, int ntiles, int T, int& I, int& J) {
+    // XCD-aware remap: hardware places workgroup w on XCD w % 8.  Give XCD x
+    // the contiguous range [start_x, start_x + count_x) of the tile order,
+    // so the ~32 tiles resident on one XCD are consecutive in that order.
+    const int nx = 8;
+    const int x = w % nx, r = w / nx;
+    const int base = ntiles / nx, rem = ntiles % nx;
+    tile_in_order(x * base + (x < rem ? x : rem) + r, T, I, J);
+}
+
+// As tile_of, for a grid of ntiles + 8 * nsplit workgroups (0 <= nsplit <= ntiles / 8):
+// the last nsplit tiles of every XCD's range go out as two workgroups each, one per
+// 128-column half (half = 0, 1; -1 for a whole tile).  Workgroups reach an XCD in id
+// order, so the halves are the XCD's last round.
+__device__ inline void tile_of_split(int w, int ntiles, int T, int nsplit, int& I, int& J,
+                                     int& half) {
+    const int nx = 8;
+    const int x = w % nx, r = w / nx;
+    const int base = ntiles / nx, rem = ntiles % nx;
+    const int start = x * base + (x < rem ? x : rem);
+    const int nfull = base + (x < rem ? 1 : 0) - nsplit;
+    int t;
+    if (r < nfull) {
+        t = start + r;
+        half = -1;
+    } else {
+        t = start + nfull + ((r - nfull) >> 1);
+        half = (r - nfull) & 1;
+    }
+    tile_in_order(t, T, I, J);
 }
 
 // ---- per-form fragment math ------------------------------------------------
@@ -524,17 +549,18 @@ __device__ inline void read_frags(uint32_t a, uint32_t b, u32x4_t (&f)[12]) {
 }
 }  // namespace dma
 
-// Symmetric store of one 256 x 256 tile held as the 8 waves' 64 x 128 accumulators
-// (element layout of Form<GK_BF16X3>); shared by the direct-to-LDS kernels below.
-__device__ __forceinline__ void store_tile_256(const f32x16_t (&acc)[dma::MB][dma::NB], int I, int J,
-                                      int64_t rowI0, int64_t rowJ0, int wm, int wn, int lane,
-                                      int p, double alpha, void* __restrict__ C, int out_store,
-                                      int64_t ldc, const ThreshOut& th) {
-    using namespace dma;
+// Symmetric store of one wave's MB x NB blocks of 32 x 32 accumulators (element layout
+// of Form<GK_BF16X3>) at rows wr0.. and columns wc0.. of tile (I, J); shared by the
+// direct-to-LDS kernels below.
+template <int MB, int NB>
+__device__ __forceinline__ void store_tile(const f32x16_t (&acc)[MB][NB], int I, int J,
+                                           int64_t rowI0, int64_t rowJ0, int wr0, int wc0,
+                                           int lane, int p, double alpha, void* __restrict__ C,
+                                           int out_store, int64_t ldc, const ThreshOut& th) {
     typedef Form<GK_BF16X3> F;
-    const int64_t gr0 = rowI0 + wm * 64, gc0 = rowJ0 + wn * 128;
+    const int64_t gr0 = rowI0 + wr0, gc0 = rowJ0 + wc0;
     if (th.bits)
-        write_thresh_bits<MB, NB>(acc, I == J, rowI0, rowJ0, wm * 64, wn * 128, lane, p, alpha,
+        write_thresh_bits<MB, NB>(acc, I == J, rowI0, rowJ0, wr0, wc0, lane, p, alpha,
                                   out_store, th);
 
     // With the threshold words written, the candidate pass reads M only at candidates and
@@ -591,6 +617,16 @@ __device__ __forceinline__ void store_tile_256(const f32x16_t (&acc)[dma::MB][dm
                 store_val(C, out_store, gi * ldc + gj, v);
                 if (mirror && gi != gj) store_val(C, out_store, gj * ldc + gi, v);
             }
+}
+
+// the whole 256 x 256 tile: 8 waves of 64 x 128
+__device__ __forceinline__ void store_tile_256(const f32x16_t (&acc)[dma::MB][dma::NB], int I, int J,
+                                               int64_t rowI0, int64_t rowJ0, int wm, int wn,
+                                               int lane, int p, double alpha,
+                                               void* __restrict__ C, int out_store, int64_t ldc,
+                                               const ThreshOut& th) {
+    store_tile<dma::MB, dma::NB>(acc, I, J, rowI0, rowJ0, wm * 64, wn * 128, lane, p, alpha, C,
+                                 out_store, ldc, th);
 }
 
 __global__ void __launch_bounds__(dma::NT)
@@ -1024,21 +1060,31 @@ hipError_t launch_bf16x3_ar(bool syr2k, const void* P0, const void* P1, const vo
 // the fragments itself: the first product (column block outer) starts once its four
 // fragments have arrived, and the second product's reads go out under it.  Same products
 // per accumulator in the same order.
-__global__ void __launch_bounds__(dma::NT)
-gemm_bf16x3_arl_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
-                       const char* __restrict__ Q0, const char* __restrict__ Q1,
-                       int64_t kbs, int nk, int syr2k, int p, int T, int ntiles,
-                       double alpha, void* __restrict__ C, int out_store, int64_t ldc,
-                       ThreshOut th) {
-    using namespace dma;
-    using ar::BSLOT;
-    __shared__ __attribute__((aligned(16))) char s0[BSLOT];
-    __shared__ __attribute__((aligned(16))) char s1[BSLOT];
-    __shared__ __attribute__((aligned(16))) char s2[BSLOT];
-    __shared__ __attribute__((aligned(16))) char s3[BSLOT];
+//
+// With nsplit > 0 the last nsplit tiles of every XCD's range run as two workgroups of
+// one 256 x 128 half each (tile_of_split): the same 8 waves, 64 x 64 per wave, half the
+// B rows per stage.  An XCD's 32 CUs otherwise finish its ~12.3 rounds of tiles in 13
+// full-tile rounds; with the partial last round split, that round takes a half-tile's
+// time.  Each accumulator sees the same products in the same order, so the result is
+// bitwise that of the unsplit grid.
+namespace arl {
+// the B ring: one array per slot (file scope, so that both tile shapes name the same
+// four arrays)
+__shared__ __attribute__((aligned(16))) char s0[ar::BSLOT];
+__shared__ __attribute__((aligned(16))) char s1[ar::BSLOT];
+__shared__ __attribute__((aligned(16))) char s2[ar::BSLOT];
+__shared__ __attribute__((aligned(16))) char s3[ar::BSLOT];
 
-    int I, J;
-    tile_of(blockIdx.x, ntiles, T, I, J);
+// Columns cb0 .. cb0 + 64 * NBW - 1 of tile (I, J); each wave holds NBW 32-column
+// blocks (4: the whole tile, 2: one half).
+template <int NBW>
+__device__ __forceinline__ void tile(const char* __restrict__ P0, const char* __restrict__ P1,
+                                     const char* __restrict__ Q0, const char* __restrict__ Q1,
+                                     int64_t kbs, int nk, int syr2k, int p, int I, int J, int cb0,
+                                     double alpha, void* __restrict__ C, int out_store,
+                                     int64_t ldc, const ThreshOut& th) {
+    using namespace dma;
+    constexpr int BL = NBW / 2;   // B loads (32 rows each) per wave per stage
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave / WN, wn = wave % WN;
@@ -1046,19 +1092,21 @@ gemm_bf16x3_arl_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
     const int nkt = syr2k ? 2 * nk : nk;
     const int r32 = lane & 31, hk = lane >> 5;
 
-    // B side: as gemm_bf16x3_ar_kernel (2 loads per wave per stage)
+    // B side: waves 0-3 load the hi plane, 4-7 the lo plane, 32 * BL rows each
     const int bpl = wave >> 2;
     const char* bsrc1 = syr2k ? (bpl ? Q1 : Q0) : (bpl ? P1 : P0);
     const char* bsrc2 = bpl ? P1 : P0;
-    const int64_t brow = rowJ0 + (wave & 3) * 64 + (lane >> 1);
+    const int64_t brow = rowJ0 + cb0 + (wave & 3) * (32 * BL) + (lane >> 1);
     const int bsw = (lane & 1) ^ (((lane >> 1) >> 3) & 1);
     auto issue_b = [&](char* slot, int kt) {
-        char* d = slot + bpl * PS + (wave & 3) * 2048;
+        char* d = slot + bpl * PS + (wave & 3) * (1024 * BL);
         const bool second = kt >= nk;
         const char* g = (second ? bsrc2 : bsrc1) + (int64_t)(second ? kt - nk : kt) * kbs +
                         brow * ROW + bsw * 16;
-        __builtin_amdgcn_global_load_lds((gbl_t*)g, (lds_t*)d, 16, 0, 0);
-        __builtin_amdgcn_global_load_lds((gbl_t*)(g + 32 * ROW), (lds_t*)(d + 1024), 16, 0, 0);
+#pragma unroll
+        for (int q = 0; q < BL; ++q)
+            __builtin_amdgcn_global_load_lds((gbl_t*)(g + q * 32 * ROW), (lds_t*)(d + q * 1024),
+                                             16, 0, 0);
     };
     const int64_t arow = (rowI0 + wm * 64 + r32) * ROW + hk * 16;
     auto load_a = [&](int kt, u32x4_t (&a)[4]) {
@@ -1072,18 +1120,19 @@ gemm_bf16x3_arl_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
         a[3] = *(const u32x4_t*)(al + o + 32 * ROW);
     };
 
-    f32x16_t acc[MB][NB];
+    f32x16_t acc[MB][NBW];
 #pragma unroll
     for (int i = 0; i < MB; ++i)
 #pragma unroll
-        for (int j = 0; j < NB; ++j)
+        for (int j = 0; j < NBW; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-    const int fo = off(wn * 128 + r32, hk);   // this lane's fragment offset in a slot
+    const int fo = off(wn * 32 * NBW + r32, hk);   // this lane's fragment offset in a slot
     const int last = nkt - 1;
-    // Issue order and counts as gemm_bf16x3_ar_kernel: when stage k starts, 8 operations
-    // were issued after A(k), and B(k) before it; nkt >= 4.
+    // Issue order and counts as gemm_bf16x3_ar_kernel: when stage k starts, 4 + 2 BL
+    // operations were issued after A(k) (B(k+1), A(k+1), B(k+2)), and B(k) before it;
+    // nkt >= 4.
     u32x4_t a0[4], a1[4], a2[4];
     load_a(0, a2);
     issue_b(s0, 0);
@@ -1092,36 +1141,36 @@ gemm_bf16x3_arl_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
     load_a(1, a1);
     issue_b(s2, 2);
     auto step = [&](int k, const char* cur, char* nxt, u32x4_t (&acur)[4], u32x4_t (&anext)[4]) {
-        __builtin_amdgcn_s_waitcnt(vm_wait_imm(8));   // A(k) and this wave's B(k) landed
+        __builtin_amdgcn_s_waitcnt(vm_wait_imm(4 + 2 * BL));   // A(k), this wave's B(k)
         order();
-        __builtin_amdgcn_s_barrier();                 // every wave's B(k); slot of B(k-1) free
+        __builtin_amdgcn_s_barrier();   // every wave's B(k); slot of B(k-1) free
         order();
         load_a(k + 2 < last ? k + 2 : last, anext);
         issue_b(nxt, k + 3 < last ? k + 3 : last);
-        bf16x8_t ah[MB], al[MB], bh[NB], bl[NB];
+        bf16x8_t ah[MB], al[MB], bh[NBW], bl[NBW];
 #pragma unroll
-        for (int j = 0; j < NB; ++j) bh[j] = *(const bf16x8_t*)(cur + fo + j * 1024);
+        for (int j = 0; j < NBW; ++j) bh[j] = *(const bf16x8_t*)(cur + fo + j * 1024);
 #pragma unroll
-        for (int j = 0; j < NB; ++j) bl[j] = *(const bf16x8_t*)(cur + PS + fo + j * 1024);
+        for (int j = 0; j < NBW; ++j) bl[j] = *(const bf16x8_t*)(cur + PS + fo + j * 1024);
 #pragma unroll
         for (int i = 0; i < MB; ++i) {
             ah[i] = __builtin_bit_cast(bf16x8_t, acur[i]);
             al[i] = __builtin_bit_cast(bf16x8_t, acur[2 + i]);
         }
 #pragma unroll
-        for (int j = 0; j < NB; ++j)
+        for (int j = 0; j < NBW; ++j)
 #pragma unroll
             for (int i = 0; i < MB; ++i)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
 #pragma unroll
         for (int i = 0; i < MB; ++i)
 #pragma unroll
-            for (int j = 0; j < NB; ++j)
+            for (int j = 0; j < NBW; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
 #pragma unroll
         for (int i = 0; i < MB; ++i)
 #pragma unroll
-            for (int j = 0; j < NB; ++j)
+            for (int j = 0; j < NBW; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
     };
     // stage k reads slot k % 4, refills slot (k + 3) % 4, uses register set k % 3
@@ -1152,12 +1201,42 @@ gemm_bf16x3_arl_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
     if (kt + 9 < nkt) step(kt + 9, s1, s0, a0, a2);
     if (kt + 10 < nkt) step(kt + 10, s2, s1, a1, a0);
     wait_vm(0);
-    store_tile_256(acc, I, J, rowI0, rowJ0, wm, wn, lane, p, alpha, C, out_store, ldc, th);
+    store_tile<MB, NBW>(acc, I, J, rowI0, rowJ0, wm * 64, cb0 + wn * 32 * NBW, lane, p, alpha, C,
+                        out_store, ldc, th);
+}
+}  // namespace arl
+
+__global__ void __launch_bounds__(dma::NT)
+gemm_bf16x3_arl_kernel(const char* __restrict__ P0, const char* __restrict__ P1,
+                       const char* __restrict__ Q0, const char* __restrict__ Q1,
+                       int64_t kbs, int nk, int syr2k, int p, int T, int ntiles, int nsplit,
+                       double alpha, void* __restrict__ C, int out_store, int64_t ldc,
+                       ThreshOut th) {
+    int I, J, half;
+    tile_of_split(blockIdx.x, ntiles, T, nsplit, I, J, half);
+    if (half < 0)
+        arl::tile<dma::NB>(P0, P1, Q0, Q1, kbs, nk, syr2k, p, I, J, 0, alpha, C, out_store, ldc, th);
+    else
+        arl::tile<dma::NB / 2>(P0, P1, Q0, Q1, kbs, nk, syr2k, p, I, J, half * (dma::BT / 2), alpha,
+                               C, out_store, ldc, th);
 }
 
-hipError_t launch_bf16x3_arl(bool syr2k, const void* P0, const void* P1, const void* Q0,
-                             const void* Q1, int64_t ldk, int64_t p, double alpha, void* C,
-                             int out_store, int64_t ldc, hipStream_t stream, ThreshOut th) {
+int device_cus();
+
+// Tiles per XCD to split into halves: those of its last, partial round of one workgroup
+// per CU, when they fill at most half of it (their halves then still run side by side).
+int arl_split_tiles(int ntiles) {
+    const int per_xcd = device_cus() / 8;
+    const int base = ntiles / 8, rem = ntiles % 8;
+    if (per_xcd < 2) return 0;
+    const int tail = (base + (rem ? 1 : 0)) % per_xcd;
+    if (tail == 0 || 2 * tail > per_xcd) return 0;
+    return tail < base ? tail : base;
+}
+
+hipError_t launch_arl(bool split, bool syr2k, const void* P0, const void* P1, const void* Q0,
+                      const void* Q1, int64_t ldk, int64_t p, double alpha, void* C,
+                      int out_store, int64_t ldc, hipStream_t stream, ThreshOut th) {
     const int64_t ldk_bytes = ldk * 2;
     if (ldk_bytes % dma::ROW) return hipErrorInvalidValue;
     const int nk = (int)(ldk_bytes / dma::ROW);
@@ -1167,11 +1246,24 @@ hipError_t launch_bf16x3_arl(bool syr2k, const void* P0, const void* P1, const v
     if ((syr2k ? 2 * nk : nk) < 4)   // the prologue issues four stages
         return launch_bf16x3_dma(syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc,
                                  stream, th);
-    hipLaunchKernelGGL(gemm_bf16x3_arl_kernel, dim3(ntiles), dim3(dma::NT), 0, stream,
-                       (const char*)P0, (const char*)P1, (const char*)(syr2k ? Q0 : P0),
+    const int nsplit = split ? arl_split_tiles(ntiles) : 0;
+    hipLaunchKernelGGL(gemm_bf16x3_arl_kernel, dim3(ntiles + 8 * nsplit), dim3(dma::NT), 0,
+                       stream, (const char*)P0, (const char*)P1, (const char*)(syr2k ? Q0 : P0),
                        (const char*)(syr2k ? Q1 : P1), round_up(p, ROW_PAD) * dma::ROW, nk,
-                       syr2k ? 1 : 0, (int)p, T, ntiles, alpha, C, out_store, ldc, th);
+                       syr2k ? 1 : 0, (int)p, T, ntiles, nsplit, alpha, C, out_store, ldc, th);
     return hipGetLastError();
+}
+
+hipError_t launch_bf16x3_arl(bool syr2k, const void* P0, const void* P1, const void* Q0,
+                             const void* Q1, int64_t ldk, int64_t p, double alpha, void* C,
+                             int out_store, int64_t ldc, hipStream_t stream, ThreshOut th) {
+    return launch_arl(false, syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc, stream, th);
+}
+
+hipError_t launch_bf16x3_arl_split(bool syr2k, const void* P0, const void* P1, const void* Q0,
+                                   const void* Q1, int64_t ldk, int64_t p, double alpha, void* C,
+                                   int out_store, int64_t ldc, hipStream_t stream, ThreshOut th) {
+    return launch_arl(true, syr2k, P0, P1, Q0, Q1, ldk, p, alpha, C, out_store, ldc, stream, th);
 }
 
 hipError_t launch_bf16x3_pp(bool syr2k, const void* P0, const void* P1, const void* Q0,
@@ -1256,8 +1348,9 @@ hipError_t launch_kind(bool syr2k, const void* P0, const void* P1, const void* Q
 // Variants per form: 256-wide tiles (8 waves, register-staged), 128-wide tiles (4
 // waves, register-staged), the 256-wide kernel as a persistent grid of one
 // workgroup per CU, and, for the BF16 split, the 256-wide direct-to-LDS ring, its
-// ping-pong schedule, the ring with the A side in registers, and that kernel with its
-// B fragments read by ordinary loads from per-slot arrays.  All variants of a
+// ping-pong schedule, the ring with the A side in registers, that kernel with its
+// B fragments read by ordinary loads from per-slot arrays, and the last one with each
+// XCD's partial last round of tiles split into half tiles.  All variants of a
 // form produce bitwise-identical results (same per-accumulator order of the K steps
 // and of the three split products), so the choice only affects speed.  The first
 // contraction of a new shape key (form, syr2k, p rounded up to 256, K) times every
@@ -1283,6 +1376,7 @@ const Variant* variants(int kind, int* count) {
         {"bf16x3_256x256_w8_pingpong", launch_bf16x3_pp, true},
         {"bf16x3_256x256_w8_ldsring_aregs", launch_bf16x3_ar, true},
         {"bf16x3_256x256_w8_ldsring_aregs_loads", launch_bf16x3_arl, true},
+        {"bf16x3_256x256_w8_ldsring_aregs_loads_tailsplit", launch_bf16x3_arl_split, true},
     };
     static const Variant f32[] = {
         {"f32_256x256_w8", launch_kind<GK_F32, 256, 4, 2>, false},
@@ -1293,7 +1387,7 @@ const Variant* variants(int kind, int* count) {
         {"f64_128x128_w4", launch_kind<GK_F64, 128, 2, 2>, false},
     };
     switch (kind) {
-        case GK_BF16X3: *count = 7; return bf;
+        case GK_BF16X3: *count = 8; return bf;
         case GK_F32: *count = 3; return f32;
         default: *count = 1; return f64;
     }

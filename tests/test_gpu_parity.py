@@ -258,15 +258,16 @@ def test_lambda1_max_closed_form_gpu():
     s.close()
 
 
-@pytest.mark.parametrize("variant,precision,nvar,n", [("obs", "bf16x3", 7, 260), ("obs", "fp32", 3, 260),
-                                                      ("cov", "bf16x3", 7, 260), ("cov", "fp32", 3, 260),
-                                                      ("cov", "bf16x3", 7, 40)])
-def test_contraction_variants_bitwise_equal(variant, precision, nvar, n, monkeypatch):
+@pytest.mark.parametrize("variant,precision,nvar,n,p", [
+    ("obs", "bf16x3", 8, 260, 600), ("obs", "fp32", 3, 260, 600), ("cov", "bf16x3", 8, 260, 600),
+    ("cov", "fp32", 3, 260, 600), ("cov", "bf16x3", 8, 40, 600), ("obs", "bf16x3", 8, 260, 1800),
+    ("cov", "bf16x3", 8, 260, 1800)])
+def test_contraction_variants_bitwise_equal(variant, precision, nvar, n, p, monkeypatch):
     """Every tile variant the autotuner may pick gives bitwise the same iterates (n = 40:
     a contraction of three K stages, which the ring variants hand to the one that
-    takes fewer than four)."""
+    takes fewer than four; p = 1,800: 36 tiles, of which the tail-split variant runs
+    32 as half-tile pairs, diagonal and edge tiles among them)."""
     torch = _torch()
-    p = 600
     w = datagen.make_workload("c2_obs_p20000", p=p, n=n)
     X = _rounded(w.X, precision)
     outs, cands = [], []
