@@ -92,6 +92,8 @@ struct concord_ctx {
     unsigned long long* d_active = nullptr;   // screening statistics counter
     RefreshWs rws = {};                         // Cov refresh screening workspace
     void* M = nullptr;
+    double* xn2 = nullptr;     // Obs: squared row norms of Xt (FP64), for one-candidate trial rows
+    bool xn2_valid = false;
 
     Csr om[2] = {};
     int64_t om_cap[2] = {0, 0};
@@ -341,6 +343,12 @@ int ensure_dense(concord_ctx* c) {
         (rc = dalloc(c, &c->M, (size_t)c->p * c->ldp * elem_bytes(c->dstore), true)))
         return rc;
     if (!c->bitmap && (rc = dalloc_t(c, &c->bitmap, (size_t)c->p * c->nwords, true))) return rc;
+    if (c->variant == CONCORD_OBS && !c->xn2_valid) {
+        // once per data set, before any step (the differentiation form never needs them)
+        if (!c->xn2 && (rc = dalloc_t(c, &c->xn2, (size_t)c->p, false))) return rc;
+        HIPCK(c, launch_row_norm2(c->Xt, c->dstore, c->ldk, c->ldk, c->p, c->xn2, c->stream));
+        c->xn2_valid = true;
+    }
     return CONCORD_OK;
 }
 
@@ -527,7 +535,8 @@ int do_step(concord_ctx* c, double lam1, double lam2, int forced_trials, concord
         const double tau0 = step_size(c, q_base);
         prof_begin(c, CONCORD_PROF_TRIAL);
         HIPCK(c, launch_trial(c->A, p, tau0, c->shrink, m, lam1, c->variant, TB, tbstore, tld,
-                              c->variant == CONCORD_OBS ? c->ldk : 0, c->part, c->st, c->stream));
+                              c->variant == CONCORD_OBS ? c->ldk : 0, c->xn2, c->part, c->st,
+                              c->stream));
         const int S = trial_splits(c->variant, tbstore, c->variant == CONCORD_OBS ? c->ldk : 0);
         HIPCK(c, launch_colsum_decide(c->part, (int64_t)S * p, 4 * m, c->sums, c->colsum_ws, m,
                                       tau0, c->shrink, q_base, lam2, inv_n, forced_q, c->st,
@@ -960,6 +969,7 @@ int concord_set_data(concord_ctx* c, int32_t kind, const void* dev_data, int32_t
     hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, c->stream, c->d_flags, 0);
     if (kind == CONCORD_DATA_X) {
         const bool split = c->precision == CONCORD_BF16X3;
+        c->xn2_valid = false;
         HIPCK(c, launch_transpose_in(dev_data, is64, rows, cols, ld, c->Xt, c->dstore, c->ldk,
                                      split ? c->Xt_hi : nullptr, split ? c->Xt_lo : nullptr,
                                      kblk_stride(c->prow), c->d_flags, c->stream));

@@ -164,11 +164,18 @@ int trial_splits(int variant, int bstore, int64_t ncols);
 // Per row partials part[((q*4 + t) * S + s) * p + row] for column split s < S =
 // trial_splits(...), t = 0: sum x - log1p x over the
 // diagonal, 1: ||Delta_i||^2, 2: quadratic term of row i, 3: 1 if the
-// diagonal entry is <= 0.  Obs quadratic: ||Delta_i X^T||^2 (B = Xt, ncols = n);
-// Cov quadratic: sum_{j,k in A_i} Delta_ij S_jk Delta_ik (B = S).
+// diagonal entry is <= 0.  Obs quadratic: ||Delta_i X^T||^2 (B = Xt, ncols = n); a row
+// with a single candidate (i, j) takes it as delta^2 xn2[j] when xn2 (the squared row norms
+// of X^T, launch_row_norm2) is given.  Cov quadratic: sum_{j,k in A_i} Delta_ij S_jk
+// Delta_ik (B = S).
 hipError_t launch_trial(const Cand& A, int64_t p, double tau0, double shrink, int m, double lam1,
                         int variant, const void* B, int bstore, int64_t ldb, int64_t ncols,
-                        double* part, const struct DevState* st, hipStream_t stream);
+                        const double* xn2, double* part, const struct DevState* st,
+                        hipStream_t stream);
+// out[j] = sum_c B[j * ldb + c]^2 over c < ncols, in FP64 (B FP64 or FP32, row-major,
+// ldb and ncols multiples of 4).
+hipError_t launch_row_norm2(const void* B, int bstore, int64_t ldb, int64_t ncols, int64_t p,
+                            double* out, hipStream_t stream);
 
 // Deterministic FP64 column sums in[c * rows + r] -> out[c], c < ncol, and in the same
 // launch the step that uses them.  ws holds at least ncol * COLSUM_MAXSEG doubles

@@ -634,7 +634,8 @@ template <int BS, bool OBS>
 __device__ __forceinline__ void trial_body(int64_t bx_, int split, int nsplit, const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
              const double* __restrict__ aom, const double* __restrict__ agr, int64_t p,
              double tau0, double shrink, int m, double lam1, const void* __restrict__ B,
-             int64_t ldb, int64_t ncols, double* __restrict__ part, const DevState* st) {
+             int64_t ldb, int64_t ncols, const double* __restrict__ xn2, double* __restrict__ part,
+             const DevState* st) {
     if (st->overflow || st->accepted_q >= 0) return;   // capacity exceeded or already decided
     typedef Chunk<BS> Ch;
     typedef typename Ch::T T;
@@ -694,7 +695,18 @@ __device__ __forceinline__ void trial_body(int64_t bx_, int split, int nsplit, c
             }
         }
         const int64_t cstep = (int64_t)nsplit * 64 * V;
-        if (cnt == 1) {
+        if (cnt == 1 && xn2) {
+            // one candidate (i, j): Delta_i X^T = delta X^T_j, so the row's term is
+            // delta^2 ||X^T_j||^2, from the row norms of X^T (no pass over X^T)
+            if (split == 0 && lane == 0) {
+                const double nj = xn2[acol[s]];
+#pragma unroll
+                for (int q = 0; q < MAXQ; ++q) {
+                    const double d = (double)dq[0][q];
+                    if (q < m) squad[q] = d * d * nj;
+                }
+            }
+        } else if (cnt == 1) {
             // one candidate (a row whose only candidate is the diagonal): one row of B,
             // read PD chunks ahead (the two-chunk pipeline below keeps too few bytes in
             // flight for a single row); the same products and sums in the same order
@@ -875,8 +887,36 @@ __global__ void __launch_bounds__(NT)
 trial_kernel(const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
              const double* __restrict__ aom, const double* __restrict__ agr, int64_t p,
              double tau0, double shrink, int m, double lam1, const void* __restrict__ B,
-             int64_t ldb, int64_t ncols, double* __restrict__ part, const DevState* st) {
-    trial_body<BS, OBS>(blockIdx.x, blockIdx.y, gridDim.y, arow, acol, aom, agr, p, tau0, shrink, m, lam1, B, ldb, ncols, part, st);
+             int64_t ldb, int64_t ncols, const double* __restrict__ xn2,
+             double* __restrict__ part, const DevState* st) {
+    trial_body<BS, OBS>(blockIdx.x, blockIdx.y, gridDim.y, arow, acol, aom, agr, p, tau0, shrink,
+                        m, lam1, B, ldb, ncols, xn2, part, st);
+}
+
+// Squared norms of the rows of X^T (||X^T_j||^2 = n S_jj) in FP64: one wave per row,
+// lane l adds the squares of its chunks of columns in column order, then a butterfly over
+// the wave (every lane ends with the same sum).  Read by the Obs trials for rows with a
+// single candidate.
+template <int BS>
+__global__ void __launch_bounds__(NT)
+row_norm2_kernel(const void* __restrict__ B, int64_t ldb, int64_t ncols, int64_t p,
+                 double* __restrict__ out) {
+    typedef Chunk<BS> Ch;
+    typedef typename Ch::T T;
+    constexpr int V = Ch::V;
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int64_t row = uni((int64_t)blockIdx.x * WPB + wave);
+    if (row >= p) return;
+    double sum = 0.0;
+    for (int64_t c = (int64_t)lane * V; c < ncols; c += 64 * V) {
+        T v[V];
+        Ch::load(B, row * ldb + c, v);
+#pragma unroll
+        for (int t = 0; t < V; ++t) sum += (double)v[t] * (double)v[t];
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, 64);
+    if (lane == 0) out[row] = sum;
 }
 
 // Cov trials with 8 lanes per row (8 rows per wave): a Cov candidate row holds a few
@@ -2442,13 +2482,14 @@ int trial_splits(int variant, int bstore, int64_t ncols) {
 
 hipError_t launch_trial(const Cand& A, int64_t p, double tau0, double shrink, int m, double lam1,
                         int variant, const void* B, int bstore, int64_t ldb, int64_t ncols,
-                        double* part, const DevState* st, hipStream_t stream) {
+                        const double* xn2, double* part, const DevState* st, hipStream_t stream) {
     if (p == 0) return hipSuccess;
     if (m < 1 || m > MAXQ) return hipErrorInvalidValue;
     dim3 grid(blocks_for(p, WPB), trial_splits(variant, bstore, ncols));
 #define TRIAL(BS, OBS)                                                                       \
     hipLaunchKernelGGL((trial_kernel<BS, OBS>), grid, dim3(NT), 0, stream, A.rowptr, A.col,   \
-                       A.omega, A.grad, p, tau0, shrink, m, lam1, B, ldb, ncols, part, st)
+                       A.omega, A.grad, p, tau0, shrink, m, lam1, B, ldb, ncols,              \
+                       obs ? xn2 : nullptr, part, st)
     const bool obs = variant == 1;
     // Cov rows hold a few candidates each.  Below COV_GROUP_MIN_P rows the wave-per-row
     // kernel's p waves fit on the chip at once and the step is latency bound, so packing
@@ -2472,6 +2513,21 @@ hipError_t launch_trial(const Cand& A, int64_t p, double tau0, double shrink, in
     else if (bstore == ST_F32) { if (obs) TRIAL(ST_F32, true); else TRIAL(ST_F32, false); }
     else { if (obs) return hipErrorInvalidValue; TRIAL(ST_B16P, false); }
 #undef TRIAL
+    return hipGetLastError();
+}
+
+hipError_t launch_row_norm2(const void* B, int bstore, int64_t ldb, int64_t ncols, int64_t p,
+                            double* out, hipStream_t stream) {
+    if (p == 0) return hipSuccess;
+    if (ldb % 4 || ncols % 4 || ncols > ldb) return hipErrorInvalidValue;   // whole chunks
+    if (bstore == ST_F64)
+        hipLaunchKernelGGL(row_norm2_kernel<ST_F64>, dim3(blocks_for(p, WPB)), dim3(NT), 0, stream,
+                           B, ldb, ncols, p, out);
+    else if (bstore == ST_F32)
+        hipLaunchKernelGGL(row_norm2_kernel<ST_F32>, dim3(blocks_for(p, WPB)), dim3(NT), 0, stream,
+                           B, ldb, ncols, p, out);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -3109,7 +3165,8 @@ batch_trial_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, BatchArgs a) 
         const int q = d.ctl->q_base;
         const int m = a.tb < a.total - q ? a.tb : a.total - q;
         trial_body<BS, false>(lb, 0, 1, d.A.rowptr, d.A.col, d.A.omega, d.A.grad, d.p,
-                              batch_tau(a, q), a.shrink, m, d.lam1, d.S, d.lds, 0, d.part, d.st);
+                              batch_tau(a, q), a.shrink, m, d.lam1, d.S, d.lds, 0, nullptr, d.part,
+                              d.st);
     });
 }
 

@@ -65,5 +65,14 @@ def test_c2_two_iterations(c2, variant, precision):
         check_support(f"c2 {s.variant} it={it}", precision, w.lam1, rec.tau, got, want, prev,
                       ref.iterates[it], (om_c, g_c), grad_at)
         assert abs(info.F - rec.F) <= (1e-9 if precision == "fp64" else 1e-5) * abs(rec.F)
+        # the backtracking test's left side at the accepted step (trial sums; here nearly
+        # every Obs row has the diagonal as its only candidate)
+        # (FP64 to 1e-9 of the right side; in FP32 / BF16x3 the gradient's rounding enters the
+        # left side's first-order term, measured at 3.6e-4 of the right side, plus an
+        # absolute floor of the objective's rounding once the steps become tiny; a wrong
+        # quadratic term would be off by order one)
+        lhs_tol = (1e-9 * rec.rhs if precision == "fp64"
+                   else 1e-2 * rec.rhs + 1e-7 * abs(rec.F) / w.p)
+        assert abs(info.lhs - rec.lhs) <= lhs_tol, (it, info.lhs, rec.lhs, rec.rhs)
         prev = got
     s.close()

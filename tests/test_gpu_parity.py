@@ -151,6 +151,15 @@ def _replay_parity(variant, precision, lam1, p, n, iters):
                       prev, ref.iterates[it], s.get_candidates_scipy(),
                       oracle_grad_fn(ref.iterates[it], X, lam2))
         assert abs(info.F - rec.F) <= (1e-9 if precision == "fp64" else 1e-5) * abs(rec.F)
+        # the backtracking test's left side at the accepted step (the trial sums; Obs rows
+        # with one candidate take their quadratic term from the row norms of X^T)
+        # (FP64 to 1e-9 of the right side; in FP32 / BF16x3 the gradient's rounding enters the
+        # left side's first-order term, measured at 3.6e-4 of the right side, plus an
+        # absolute floor of the objective's rounding once the steps become tiny; a wrong
+        # quadratic term would be off by order one)
+        lhs_tol = (1e-9 * rec.rhs if precision == "fp64"
+                   else 1e-2 * rec.rhs + 1e-7 * abs(rec.F) / p)
+        assert abs(info.lhs - rec.lhs) <= lhs_tol, (it, info.lhs, rec.lhs, rec.rhs)
         prev = got
     s.close()
 
