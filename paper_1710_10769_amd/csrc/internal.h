@@ -373,7 +373,10 @@ struct InstDesc {
 // ph (a = 0 .. nact), for the static phases; roff[i] the same for the refresh over the
 // instances.  status[0] = solves still running, status[1] = solves asking for more
 // candidate capacity.
-enum { BP_ROW = 0, BP_ROWG, BP_SCAN, BP_COLT, BP_COLO, BP_SROWS, BP_SPAIRS, BP_SOLVE, BP_N };
+// Row phases: BP_ROW every solve's rows (WPB per item), BP_ROWU the same for the solves
+// whose per-row kernels run a wave per row, BP_ROWG 8 lanes per row (WPB * 8 rows per item)
+// for the others, so a phase of one form walks no items of the other.
+enum { BP_ROW = 0, BP_ROWU, BP_ROWG, BP_SCAN, BP_COLT, BP_COLO, BP_SROWS, BP_SPAIRS, BP_SOLVE, BP_N };
 struct BatchPlan {
     int nact;
     int* act;      // nsolve

@@ -3020,7 +3020,8 @@ batch_plan_kernel(const SolveDesc* __restrict__ sd, const InstDesc* __restrict__
                 int64_t seg;
                 colsum_shape(p, &nseg, &seg);
                 cnt[BP_ROW] = (int)((p + WPB - 1) / WPB);
-                cnt[BP_ROWG] = (int)((p + WPB * (64 / TG) - 1) / (WPB * (64 / TG)));
+                cnt[BP_ROWU] = d.grouped ? 0 : cnt[BP_ROW];
+                cnt[BP_ROWG] = d.grouped ? (int)((p + WPB * (64 / TG) - 1) / (WPB * (64 / TG))) : 0;
                 cnt[BP_SCAN] = (int)((p + SCAN_CHUNK - 1) / SCAN_CHUNK);
                 cnt[BP_COLT] = 4 * m * nseg;
                 cnt[BP_COLO] = 4 * nseg;
@@ -3139,7 +3140,7 @@ batch_fill_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, int nsolve) {
 template <int BS>
 __global__ void __launch_bounds__(NT)
 batch_grad_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, BatchArgs a) {
-    for_items(pl, a.nsolve, BP_ROW, [&](int si, int64_t lb) {
+    for_items(pl, a.nsolve, BP_ROWU, [&](int si, int64_t lb) {
         const SolveDesc& d = sd[si];
         if (d.ctl->phase != BPH_CAND || d.grouped) return;
         const Csr& o = d.om[d.ctl->cur];
@@ -3159,7 +3160,7 @@ batch_grad_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, BatchArgs a) {
 template <int BS>
 __global__ void __launch_bounds__(NT)
 batch_trial_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, BatchArgs a) {
-    for_items(pl, a.nsolve, BP_ROW, [&](int si, int64_t lb) {
+    for_items(pl, a.nsolve, BP_ROWU, [&](int si, int64_t lb) {
         const SolveDesc& d = sd[si];
         if (d.grouped) return;
         const int q = d.ctl->q_base;
@@ -3202,7 +3203,7 @@ batch_decide_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, BatchArgs a)
 // ---- emission of the accepted iterates ----
 __global__ void __launch_bounds__(NT)
 batch_emit_count_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, int nsolve) {
-    for_items(pl, nsolve, BP_ROW, [&](int si, int64_t lb) {
+    for_items(pl, nsolve, BP_ROWU, [&](int si, int64_t lb) {
         const SolveDesc& d = sd[si];
         if (d.grouped) return;
         emit_count_body(lb, d.A.rowptr, d.A.col, d.A.omega, d.A.grad, d.p, d.lam1, d.st, d.cnt);
@@ -3216,7 +3217,7 @@ batch_emit_count_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, int nsol
 
 __global__ void __launch_bounds__(NT)
 batch_emit_fill_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, int nsolve) {
-    for_items(pl, nsolve, BP_ROW, [&](int si, int64_t lb) {
+    for_items(pl, nsolve, BP_ROWU, [&](int si, int64_t lb) {
         const SolveDesc& d = sd[si];
         if (d.grouped) return;
         const Csr& o = d.om[d.ctl->cur ^ 1];
@@ -3328,7 +3329,7 @@ batch_refresh_kernel(const SolveDesc* __restrict__ sd, const InstDesc* __restric
 template <int BS>
 __global__ void __launch_bounds__(NT)
 batch_obj_kernel(const SolveDesc* __restrict__ sd, BatchPlan pl, int nsolve, int init) {
-    for_items(pl, nsolve, BP_ROW, [&](int si, int64_t lb) {
+    for_items(pl, nsolve, BP_ROWU, [&](int si, int64_t lb) {
         const SolveDesc& d = sd[si];
         if (!in_accept(d, init) || d.grouped) return;
         const Csr& o = prod_csr(d, init);
