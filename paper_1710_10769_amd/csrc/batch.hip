@@ -536,6 +536,13 @@ int concord_batch_solve(concord_batch* b, double lambda2, double tol, int64_t ma
     a.tol = tol;
     a.tau0 = b->cfg.tau0;
     a.shrink = b->cfg.shrink;
+    for (int s = 0; s < N; ++s) {
+        const SolveDesc& d = b->hsd[s];
+        a.any_rowu |= d.grouped ? 0 : 1;
+        a.any_rowg |= d.grouped ? 1 : 0;
+        a.any_screen |= d.screen ? 1 : 0;
+        a.any_multichunk |= d.p > SCAN_CHUNK ? 1 : 0;
+    }
     BHIP(b, launch_batch_iteration(b->dsd, b->did, b->plan, a, true, b->grid, b->work));
     const int K = b->cfg.iters_per_launch;
     bool graph = b->cfg.use_graph != 0;

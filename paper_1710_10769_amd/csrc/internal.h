@@ -144,6 +144,8 @@ hipError_t launch_cand_grad_cov(const Csr& om, int64_t p, const void* S, int sst
                                 double lam2, const Cand& A, const int* overflow,
                                 hipStream_t stream);
 
+constexpr int SCAN_CHUNK = 2048;   // entries per scan chunk (8 per thread of a 256-thread block)
+
 // Exclusive scan of cnt[0..p) into out[0..p] (out[p] = total); sets
 // *overflow = 1 if total > cap (overflow may be null), and copies the total to
 // *total_out (may be null).  Two launches (chunk sums into
@@ -387,6 +389,10 @@ struct BatchPlan {
 
 struct BatchArgs {
     int nsolve, ninst, maxT;   // maxT: largest tile-row count (dynamic LDS of two phases)
+    // which launches can have work at all (fixed at batch creation): solves with a wave per
+    // trial row, solves with 8 lanes per row, screened solves, solves of more than one
+    // scan chunk; an iteration leaves out the launches of a form no solve uses
+    int any_rowu, any_rowg, any_screen, any_multichunk;
     int bstore;            // S storage (ST_F64 or ST_F32)
     int tb, total;         // step sizes per trial batch, max_backtracks + 1
     int64_t max_iter;

@@ -491,7 +491,6 @@ cand_grad_cov_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restri
 // ---- scan ---------------------------------------------------------------------
 // Two-kernel exclusive scan: chunk sums, then each chunk adds the sums before it and
 // scans itself.  Integer sums, so the result does not depend on the split.
-constexpr int SCAN_CHUNK = 2048;   // 8 per thread
 
 __device__ inline int64_t block_sum_i64(int64_t v, int64_t* red) {
 #pragma unroll
@@ -3424,30 +3423,38 @@ hipError_t launch_batch_iteration(const SolveDesc* sd, const InstDesc* idesc, co
         hipLaunchKernelGGL(batch_identity_kernel, g, b, 0, stream, sd, pl, N);
     } else {
         hipLaunchKernelGGL(batch_merge_kernel, g, b, 0, stream, sd, pl, N);
-        hipLaunchKernelGGL(batch_scan_part_kernel<false>, g, b, 0, stream, sd, pl, N, 0);
+        // chunk sums: none needed while every solve fits one scan chunk (the apply of
+        // chunk 0 reads none)
+        if (a.any_multichunk)
+            hipLaunchKernelGGL(batch_scan_part_kernel<false>, g, b, 0, stream, sd, pl, N, 0);
         hipLaunchKernelGGL(batch_scan_apply_kernel<false>, g, b, 0, stream, sd, pl, N, 0);
         hipLaunchKernelGGL(batch_fill_kernel, g, b, (size_t)WPB * ((a.maxT + 63) / 64) * 8, stream,
                            sd, pl, N);
 #define BCAND(BS)                                                                            \
         hipLaunchKernelGGL(batch_grad_kernel<BS>, g, b, 0, stream, sd, pl, a);                \
-        hipLaunchKernelGGL(batch_trial_kernel<BS>, g, b, 0, stream, sd, pl, a);               \
-        hipLaunchKernelGGL(batch_trial_grouped_kernel<BS>, g, b, 0, stream, sd, pl, a)
+        if (a.any_rowu) hipLaunchKernelGGL(batch_trial_kernel<BS>, g, b, 0, stream, sd, pl, a); \
+        if (a.any_rowg)                                                                       \
+            hipLaunchKernelGGL(batch_trial_grouped_kernel<BS>, g, b, 0, stream, sd, pl, a)
         if (a.bstore == ST_F64) { BCAND(ST_F64); }
         else if (a.bstore == ST_F32) { BCAND(ST_F32); }
         else { BCAND(ST_B16P); }
 #undef BCAND
         hipLaunchKernelGGL(batch_decide_kernel, g, b, 0, stream, sd, pl, a);
         hipLaunchKernelGGL(batch_emit_count_kernel, g, b, 0, stream, sd, pl, N);
-        hipLaunchKernelGGL(batch_scan_part_kernel<true>, g, b, 0, stream, sd, pl, N, 0);
+        if (a.any_multichunk)
+            hipLaunchKernelGGL(batch_scan_part_kernel<true>, g, b, 0, stream, sd, pl, N, 0);
         hipLaunchKernelGGL(batch_scan_apply_kernel<true>, g, b, 0, stream, sd, pl, N, 0);
         hipLaunchKernelGGL(batch_emit_fill_kernel, g, b, 0, stream, sd, pl, N);
     }
-    hipLaunchKernelGGL(batch_screen_rows_kernel, dim3(grid * WPB), dim3(64), (size_t)8 * a.maxT,
-                       stream, sd, pl, N, ini);
-    if (a.bstore == ST_F64) {
-        hipLaunchKernelGGL(batch_screen_pairs_kernel<double>, g, b, 0, stream, sd, idesc, pl, N, ini);
-    } else {
-        hipLaunchKernelGGL(batch_screen_pairs_kernel<float>, g, b, 0, stream, sd, idesc, pl, N, ini);
+    if (a.any_screen) {
+        hipLaunchKernelGGL(batch_screen_rows_kernel, dim3(grid * WPB), dim3(64),
+                           (size_t)8 * a.maxT, stream, sd, pl, N, ini);
+        if (a.bstore == ST_F64)
+            hipLaunchKernelGGL(batch_screen_pairs_kernel<double>, g, b, 0, stream, sd, idesc, pl,
+                               N, ini);
+        else
+            hipLaunchKernelGGL(batch_screen_pairs_kernel<float>, g, b, 0, stream, sd, idesc, pl,
+                               N, ini);
     }
     hipLaunchKernelGGL(batch_refresh_plan_kernel, dim3(1), dim3(SCAN_BLOCK), 0, stream, sd, idesc,
                        pl, a.ninst, ini);
