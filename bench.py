@@ -111,14 +111,21 @@ def run_cov_context(torch, X32, p, n, lam1, lam2, steps, warmup):
     form_s = time.perf_counter() - t0
     for _ in range(warmup):
         s.step(lam1, lam2)
-    s.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = [s.step(lam1, lam2) for _ in range(steps)]
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
-    prof = s.profile()
     om = s.get_omega_scipy()
+    # the phase breakdown from the same steps replayed with the per-phase HIP events on
+    # (untimed: the events cost a few microseconds each, a large part of a 0.2 ms step)
+    s.reset()
+    for _ in range(warmup):
+        s.step(lam1, lam2)
+    s.set_profiling(True)
+    for _ in range(steps):
+        s.step(lam1, lam2)
+    prof = s.profile()
     s.close()
     log(f"cov context: {steps} steps in {sec:.3f} s, S formed in {form_s * 1e3:.1f} ms")
     return {"variant": "cov", "precision": "bf16x3", "value": steps / sec, "unit": "iters/s",
@@ -219,6 +226,29 @@ def bench_c1(args, torch, np, datagen):
     print(json.dumps(line), flush=True)
 
 
+def timed_solve(torch, s, lam1, lam2, tol, max_iter):
+    """A solve from Omega = I timed without profiling (the per-phase HIP events cost a few
+    microseconds each, a third of an iteration at p = 16,384), after an untimed one that
+    takes the handle's first-use allocations."""
+    s.solve(lam1, lam2, tol, max_iter)
+    s.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    si = s.solve(lam1, lam2, tol, max_iter)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, si
+
+
+def profiled_solve(s, lam1, lam2, tol, max_iter):
+    """The same solve once more with the per-phase HIP events on: the phase breakdown."""
+    s.reset()
+    s.set_profiling(True)
+    s.solve(lam1, lam2, tol, max_iter)
+    prof = s.profile()
+    s.set_profiling(False)
+    return prof
+
+
 def bench_c3(args, torch, np, datagen):
     """Cov precision forms at p = 16,384, n = 4,096 (random degree 8; lambda1 0.3,
     lambda2 0.1, tol 1e-5 / 200): S formed once on MFMA, then the solve.  Each
@@ -231,17 +261,13 @@ def bench_c3(args, torch, np, datagen):
     res, oms = {}, {}
     for form in ("fp64", "fp32", "bf16x3"):
         s = Solver(w.p, w.n, variant="cov", precision=form)
-        s.set_profiling(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.set_data(X64 if form == "fp64" else X32)
         torch.cuda.synchronize()
         t_s = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        si = s.solve(w.lam1, w.lam2, w.tol, w.max_iter)
-        torch.cuda.synchronize()
-        t_solve = time.perf_counter() - t0
-        prof = s.profile()
+        t_solve, si = timed_solve(torch, s, w.lam1, w.lam2, w.tol, w.max_iter)
+        prof = profiled_solve(s, w.lam1, w.lam2, w.tol, w.max_iter)
         oms[form] = s.get_omega_scipy()
         # untimed replay of the same iterates counting, for every refresh of the solve (one
         # at Omega = I, one per accepted step), the tile pairs that passed the screening
@@ -277,14 +303,9 @@ def bench_c3(args, torch, np, datagen):
     # the BF16x3 form once more with the screening off: the refresh then forms every tile
     # pair (the plain product of Algorithm 2), reading all of S each iteration
     s = Solver(w.p, w.n, variant="cov", precision="bf16x3", screen=False)
-    s.set_profiling(True)
     s.set_data(X32)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    si = s.solve(w.lam1, w.lam2, w.tol, w.max_iter)
-    torch.cuda.synchronize()
-    t_solve = time.perf_counter() - t0
-    prof = s.profile()
+    t_solve, si = timed_solve(torch, s, w.lam1, w.lam2, w.tol, w.max_iter)
+    prof = profiled_solve(s, w.lam1, w.lam2, w.tol, w.max_iter)
     same = bool((s.get_omega_scipy() != oms["bf16x3"]).nnz == 0)
     s.close()
     ref_ms = prof["refresh"][0] / max(prof["refresh"][1], 1)
@@ -378,15 +399,10 @@ def bench_c6(args, torch, np, datagen):
     est_first = None
     for lam1 in datagen.FMRI_LAMBDA1:
         s.reset()
-        s.set_profiling(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        si = s.solve(lam1, lam2, 1e-5, 200)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        dt, si = timed_solve(torch, s, lam1, lam2, 1e-5, 200)
         t_all += dt
-        prof = s.profile()
         est = s.get_omega_scipy()
+        prof = profiled_solve(s, lam1, lam2, 1e-5, 200)
         deg = average_degree(est)
         points.append({"lam1": lam1, "iters": si.iters, "seconds": dt, "nnz": si.nnz, "F": si.F,
                        "avg_degree": deg,
