@@ -543,6 +543,29 @@ def bench_c4(args, torch, np, datagen):
                      "mean_iterations": float(np.mean(iters)), "max_iterations": int(max(iters)),
                      "total_iterations": int(np.sum(iters)), "last_path": stats}
     head = list(res)[0]
+    # autotuned against fixed contraction tiles: one path with one variant forced for every
+    # instance shape (the tuner picks per shape key: form, p rounded to 256, K)
+    fixed = {}
+    if not args.no_fixed_tiles:
+        # variants 0 and 1 of the FP32 and BF16-split tables: the 256 x 256 tile on 8 waves
+        # and the 128 x 128 tile on 4 waves (the FP64 table has one variant)
+        for v in ((0,) if head == "fp64" else (0, 1)):
+            os.environ["CONCORD_GEMM_VARIANT"] = str(v)
+            try:
+                b = Batch(Xs, l1s, precision=head, iters_per_launch=args.iters_per_launch)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                b.solve(lam2, 1e-5, 200)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                st = b.stats()
+                b.close()
+            finally:
+                del os.environ["CONCORD_GEMM_VARIANT"]
+            name = f"variant_{v}"
+            fixed[name] = {"solves_per_s": nsolve / (t1 - t0), "s_ms": st["s_ms"],
+                           "iterate_ms": st["iterate_ms"]}
+            log(f"{head} fixed contraction {name}: {t1 - t0:.4f} s (S {st['s_ms']:.1f} ms)")
     line = {
         "metric": "batched lambda-path solves/sec (48 Cov instances x 3 lambda1)",
         "value": res[head]["value"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -552,6 +575,7 @@ def bench_c4(args, torch, np, datagen):
                    "p": [p for p, _, _ in inst], "lambda1": list(l1s), "lam2": lam2},
         **{k: v for k, v in res[head].items() if k not in ("value", "ms_per_step")},
         "other_forms": {k: v for k, v in res.items() if k != head},
+        "fixed_contraction_tiles": fixed,
     }
     print(json.dumps(line), flush=True)
 
@@ -567,6 +591,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cov-context", action="store_true",
                     help="skip timing the Cov form on the same problem")
+    ap.add_argument("--no-fixed-tiles", action="store_true",
+                    help="c4 only: skip the paths with one contraction variant forced")
     ap.add_argument("--iters-per-launch", type=int, default=4,
                     help="c4 only: iterations captured per graph replay")
     ap.add_argument("--p", type=int, default=20000)
