@@ -105,8 +105,7 @@ def test_screening_does_not_change_the_solve(precision, source):
     _say(f"screen on/off {precision} {source} p={p}")
     dt = torch.float64 if precision == "fp64" else torch.float32
     if source == "banded_S":
-        if precision == "bf16x3":
-            pytest.skip("a supplied S is stored in FP32 for BF16x3: covered by fp32")
+        # (a supplied S is held in FP32 by the BF16-split form as well)
         data = torch.from_numpy(np.ascontiguousarray(_banded_cov(p, 13))).to("cuda", dt)
         lam1, lam2, n = 0.45, 0.1, 1
     else:
