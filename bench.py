@@ -54,6 +54,16 @@ def stream_copy_gbps(torch, mib=2048, reps=5):
     return 2.0 * mib * 1048576 / (ms * 1e-3) / 1e9
 
 
+def environment(torch, seed):
+    """What the run was measured on: software versions, the device and the workload's seed
+    (the clocks under this load are in the headline profile's power section)."""
+    from paper_1710_10769_amd._lib import concord_version
+    prop = torch.cuda.get_device_properties(0)
+    return {"library": concord_version(), "torch": torch.__version__, "hip": torch.version.hip,
+            "device": getattr(prop, "gcnArchName", prop.name),
+            "compute_units": prop.multi_processor_count, "seed": seed}
+
+
 def run_form(torch, X32, p, n, lam1, lam2, form, steps, warmup):
     from paper_1710_10769_amd import Solver
     s = Solver(p, n, variant="obs", precision=form)
@@ -674,6 +684,7 @@ def main():
         scale = float(np.abs(b.data).max())
         line[f"final_omega_maxdiff_rel_{head}_vs_{f}"] = (float(np.abs(d.data).max()) if d.nnz else 0.0) / scale
     line["stream_copy_GBps"] = stream_copy_gbps(torch)
+    line["environment"] = environment(torch, w.seed)
     line["kernel_ms_per_step"] = out[head]["kernel_ms_per_step"]
     line["dense_kernel_avg_ms"] = out[head]["dense_kernel_avg_ms"]
     line["contraction_variant"] = out[head]["contraction_variant"]
